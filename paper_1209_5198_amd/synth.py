@@ -1,0 +1,119 @@
+"""Seeded synthetic GF(2) inputs, shared by the oracle side and the GPU side.
+
+This module holds random bits only -- none of the method's arithmetic.  A
+planted-rank matrix is returned as its two random factors; each side forms the
+product with its own code.
+
+Random source: the SplitMix64 generator of Steele, Lea and Flood ("Fast
+splittable pseudorandom number generators", OOPSLA 2014), used counter-style:
+the 64-bit output for (seed, stream, index) is the SplitMix64 mixing function
+applied to ``key(seed, stream) + (index + 1) * GAMMA`` with
+``GAMMA = 0x9E3779B97F4A7C15`` and
+``key(seed, stream) = mix(seed * GAMMA + stream)``.
+
+Layout of every matrix returned: numpy ``uint64`` array of plain row-major bit
+rows, ``ceil(cols/64)`` words per row, column c = bit (c % 64) of word c // 64,
+bits at or beyond ``cols`` zero (Section 3 of the paper: a_ij is bit r of word
+q with j = 64q + r; the unused high bits of the last word are padding).
+
+Workloads (shapes, value distributions and structure of the paper's tests):
+  * ``dense``      iid Bernoulli(1/2) entries -- the random dense matrices of
+                   the paper's timing tables (Section 7).
+  * ``bernoulli``  iid Bernoulli(p) entries, one 32-bit draw per entry,
+                   entry = draw < floor(p * 2^32).
+  * ``sparse_rows`` exactly ``k`` ones per row at distinct uniform positions
+                   (the shape of the low-rank sample S_n of Section 7).
+  * ``planted``    factors X (n x r), Y (r x m) of a rank-<=r product X*Y.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def _mix(z):
+    """SplitMix64 output function (vectorised over uint64 arrays)."""
+    with np.errstate(over="ignore"):
+        z = np.asarray(z, dtype=np.uint64)
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        return z ^ (z >> np.uint64(31))
+
+
+def key(seed: int, stream: int) -> np.uint64:
+    with np.errstate(over="ignore"):
+        return _mix(np.uint64(seed & 0xFFFFFFFFFFFFFFFF) * GAMMA + np.uint64(stream & 0xFFFFFFFFFFFFFFFF))[()]
+
+
+def words(seed: int, stream: int, start: int, count: int) -> np.ndarray:
+    """``count`` consecutive 64-bit outputs starting at counter ``start``."""
+    k = key(seed, stream)
+    idx = np.arange(start + 1, start + 1 + count, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        return _mix(k + idx * GAMMA)
+
+
+def wpr(bits: int) -> int:
+    return (int(bits) + 63) // 64
+
+
+def pad_mask(cols: int) -> np.uint64:
+    r = cols & 63
+    return np.uint64(0xFFFFFFFFFFFFFFFF) if r == 0 else np.uint64((1 << r) - 1)
+
+
+def dense(seed: int, stream: int, rows: int, cols: int, row0: int = 0, nrows=None) -> np.ndarray:
+    """Bernoulli(1/2) matrix rows [row0, row0+nrows) of a rows x cols matrix."""
+    nw = wpr(cols)
+    nrows = rows - row0 if nrows is None else nrows
+    out = words(seed, stream, row0 * nw, nrows * nw).reshape(nrows, nw)
+    if nw:
+        out[:, -1] &= pad_mask(cols)
+    return out
+
+
+def bernoulli(seed: int, stream: int, rows: int, cols: int, p: float) -> np.ndarray:
+    """iid Bernoulli(p) entries: entry (i, j) = draw_{i*cols+j} < floor(p * 2^32)."""
+    if p == 0.5:
+        return dense(seed, stream, rows, cols)
+    thr = np.uint64(min(int(p * 4294967296.0), 4294967296))
+    nw = wpr(cols)
+    out = np.zeros((rows, nw), dtype=np.uint64)
+    chunk = max(1, (1 << 22) // max(cols, 1))
+    for r0 in range(0, rows, chunk):
+        r1 = min(rows, r0 + chunk)
+        n = (r1 - r0) * cols
+        first = r0 * cols
+        w = words(seed, stream, first // 2, (n + (first & 1) + 1) // 2 + 1)
+        halves = np.empty(2 * w.size, dtype=np.uint64)
+        halves[0::2] = w & np.uint64(0xFFFFFFFF)
+        halves[1::2] = w >> np.uint64(32)
+        draws = halves[(first & 1):(first & 1) + n]
+        bits = (draws < thr).astype(np.uint8).reshape(r1 - r0, cols)
+        padded = np.zeros((r1 - r0, nw * 64), dtype=np.uint8)
+        padded[:, :cols] = bits
+        out[r0:r1] = np.packbits(padded, axis=1, bitorder="little").view("<u8").astype(np.uint64)
+    return out
+
+
+def sparse_rows(seed: int, stream: int, rows: int, cols: int, k: int) -> np.ndarray:
+    """Exactly k ones per row at distinct uniformly drawn positions."""
+    k = min(k, cols)
+    nw = wpr(cols)
+    out = np.zeros((rows, nw), dtype=np.uint64)
+    for i in range(rows):
+        keys = words(seed, stream, i * cols, cols)
+        pos = np.argsort(keys, kind="stable")[:k]
+        for c in pos:
+            out[i, c >> 6] |= np.uint64(1) << np.uint64(c & 63)
+    return out
+
+
+def planted(seed: int, stream: int, rows: int, cols: int, r: int, p: float = 0.5):
+    """Random factors (X: rows x r, Y: r x cols) of a planted rank-<=r product."""
+    X = bernoulli(seed, 2 * stream, rows, r, p)
+    Y = bernoulli(seed, 2 * stream + 1, r, cols, p)
+    return X, Y
