@@ -1,0 +1,136 @@
+/*
+ * gf2.h -- C ABI of libgf2: dense GF(2) matrix decomposition, rank, product
+ * and linear solve on one MI355X (gfx950) GPU.
+ *
+ * Method: Bertolazzi & Rimoldi, "Fast matrix decomposition in F2".  The
+ * decomposition is the column-swap-free P*A = L*E of Lemma 4.1 (Section 4),
+ * computed by the block method of Section 4 (panel factorization by the
+ * incremental pseudo-inverse of procedure buildZ, Sections 4.1-4.4; trailing
+ * Schur complement update eq. (Aj) by the Four-Russians product of Section 6).
+ *
+ * ---------------------------------------------------------------- storage
+ * A matrix is a caller-owned device buffer described by gf2_mat.  Element
+ * a_ij is bit (j mod 64) (weight 2^(j mod 64)) of 64-bit word q = j / 64 of
+ * row i -- the bit order of Section 3 (a_ij is bit r of word q, j = qb + r,
+ * b = 64).  Words are grouped in column blocks of w words (64*w columns);
+ * inside a block the words are row-major ("column blocks of row-major
+ * matrices", Section 3):
+ *
+ *     word (i, q)  at  data[(q / w) * ld * w + i * w + (q % w)]
+ *
+ * w = 1 is the column-major word order the paper prefers; w = ceil(cols/64)
+ * is plain row-major.  The buffer holds ceil(ceil(cols/64) / w) blocks of
+ * ld * w words.  Input bits at or beyond `cols` (padding) are ignored; on
+ * output they are written as zero, and rows in [rows, ld) are not touched.
+ *
+ * ---------------------------------------------------------------- calls
+ * Every call is asynchronous on `stream` (a hipStream_t; NULL = the default
+ * stream).  Pointer arguments other than the gf2_mat descriptors themselves
+ * are device pointers.  The library never frees caller memory.  It owns one
+ * workspace per device, grown on demand with hipMalloc (so these calls must
+ * not be captured into a graph) and released by gf2_release().  Calls that
+ * share a device must not run concurrently from several host threads.
+ *
+ * Return value: 0 on success, or a negative GF2_E* code; gf2_last_error()
+ * then returns a message (thread-local, valid until the next call).  An
+ * inconsistent linear system is not an error.
+ */
+#ifndef GF2_H
+#define GF2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GF2_OK 0
+#define GF2_EINVAL (-1) /* bad descriptor, shape mismatch or null pointer   */
+#define GF2_ENOMEM (-2) /* workspace allocation failed                      */
+#define GF2_EHIP (-3)   /* a HIP runtime call failed                        */
+
+typedef struct gf2_mat {
+  uint64_t *data; /* device pointer to the words                        */
+  int64_t rows;   /* number of rows (bits)                              */
+  int64_t cols;   /* number of columns (bits)                           */
+  int64_t w;      /* words per row inside one column block (>= 1)       */
+  int64_t ld;     /* rows allocated per block (>= rows)                 */
+} gf2_mat;
+
+/*
+ * C = A*B (accumulate == 0) or C ^= A*B (accumulate != 0) over GF(2).
+ * A: n x k, B: k x m, C: n x m.  C must not overlap A or B.
+ * Four-Russians product (Section 6, eq. (M4RM:cost)) with Strassen-Winograd
+ * recursion above a size cutoff (Section 6.2).
+ */
+int gf2_matmul(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B, int accumulate,
+               void *stream);
+
+/*
+ * Decomposition P*A = L*E of Lemma 4.1, no column exchanges.  A (n x m) is
+ * read only.  With kmin = min(n, m) and r = rank:
+ *   L       : n x kmin; unit lower trapezoidal in columns [0, r), zero beyond
+ *             (may be NULL)
+ *   E       : kmin x m; row echelon, E[t][pivcols[t]] = 1 and zero to its
+ *             left; rows [r, kmin) zero (may be NULL)
+ *   perm    : n int64; perm[i] = row of A that is row i of P*A
+ *   pivcols : kmin int64; pivcols[t] = pivot column of row t, -1 for t >= r
+ *   rank    : 1 int64
+ * The pivot of each column is the first row, in the current order, at or
+ * below the next free position whose reduced entry is 1 (procedure buildZ,
+ * Section 4.4), exchanged by a transposition; this makes P unique and equal to
+ * that of plain elimination (b = 1, Remark after Lemma 4.1).
+ */
+int gf2_decompose(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t *perm,
+                  int64_t *pivcols, int64_t *rank, void *stream);
+
+/* rank(A) = number of rows of E = sum of the panel ranks r_j (Lemma 4.1). */
+int gf2_rank(const gf2_mat *A, int64_t *rank, void *stream);
+
+/*
+ * Solve A*X = B for k right-hand sides at once (column c of B is one system).
+ * A: n x m (read only), B: n x k, X: m x k (written).
+ * consistent: ceil(k/64) uint64 words, bit c set iff system c is solvable.
+ * X column c is the solution whose free (non-pivot) variables are zero, or
+ * zero when system c is inconsistent.  rank may be NULL.
+ * Method: y = L_top^{-1} (P b)_top; consistent iff L_bot y = (P b)_bot;
+ * back-substitution with E (uses of the decomposition, Section 1).
+ */
+int gf2_solve(const gf2_mat *A, const gf2_mat *B, const gf2_mat *X, uint64_t *consistent,
+              int64_t *rank, void *stream);
+
+/*
+ * Tuning knobs (no knob changes any result):
+ *   "panel_words"     : s, sub-panels of 64 columns per trailing-update panel (1..8)
+ *   "strassen_cutoff" : smallest dimension (bits) at which gf2_matmul recurses
+ *                       with Strassen-Winograd instead of a single product
+ * Returns 0, or GF2_EINVAL for an unknown name or out-of-range value.
+ */
+int gf2_set_param(const char *name, int64_t value);
+
+/*
+ * Timing of the dominant kernel (the trailing-update product, the hot path of
+ * Section 6.3).  While enabled, the library brackets each of its launches with
+ * HIP events on the launch stream; gf2_profile_read() synchronizes them and
+ * returns the summed kernel time (ms), the number of launches and the summed
+ * algorithmic work in table lookups (one 64-bit lookup-XOR per 8 bits of the
+ * inner dimension per output word).  Enabling resets the counters.
+ */
+int gf2_profile(int enable);
+int gf2_profile_read(double *ms, int64_t *launches, double *lookups);
+
+/* Free the workspace of every device.  Safe to call at any time between calls. */
+int gf2_release(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *gf2_last_error(void);
+
+/* Library version string. */
+const char *gf2_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GF2_H */

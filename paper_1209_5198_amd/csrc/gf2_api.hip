@@ -1,0 +1,413 @@
+// gf2_api.hip -- C ABI of libgf2 (include/gf2.h): validation, workspace and the
+// host-side sequence of kernels for each call.
+//
+// Decomposition driver (Section 4, non-recursive block loop): the columns are
+// processed in trailing-update panels of s sub-panels of 64 columns.  For each
+// sub-panel the panel kernel selects the pivots (buildZ, Sections 4.2-4.4) and
+// the rows kernel stores the multipliers and updates the rest of the panel;
+// then the panel's row exchanges are applied to every other column (P^(j)),
+// the pivot rows are brought to echelon form right of the panel (k_trsm), and
+// the Schur complement A^(j+1) = E xor Y*C (eq. (Aj)) is formed by the
+// Four-Russians product (Section 6).  Every size that depends on the data (the
+// rank so far, the number of pivots of a sub-panel) stays on the device: the
+// host enqueues a fixed sequence of launches and only the caller reads results.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "gf2_internal.h"
+
+namespace gf2 {
+namespace {
+
+thread_local std::string g_err;
+int g_panel_words = 8;
+int64_t g_strassen_cutoff = 0;  // 0: never recurse
+
+struct Workspace {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+struct ProfState {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  unsigned long long *work_dev = nullptr;
+  int64_t launches = 0;
+} g_prof;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return GF2_EHIP;
+}
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #x);  \
+  } while (0)
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int check_mat(const gf2_mat *M, const char *name) {
+  if (!M) return fail(GF2_EINVAL, std::string(name) + ": null descriptor");
+  if (M->rows < 0 || M->cols < 0) return fail(GF2_EINVAL, std::string(name) + ": negative shape");
+  if (M->w < 1) return fail(GF2_EINVAL, std::string(name) + ": w must be >= 1");
+  if (M->ld < M->rows) return fail(GF2_EINVAL, std::string(name) + ": ld < rows");
+  if (M->rows > 0 && M->cols > 0 && !M->data) return fail(GF2_EINVAL, std::string(name) + ": null data");
+  if (M->rows >= (1ll << 31)) return fail(GF2_EINVAL, std::string(name) + ": rows must be < 2^31");
+  return GF2_OK;
+}
+
+// Workspace of (device, stream), grown on demand.  Growing synchronises the
+// device before the old buffer is released.
+int get_workspace(hipStream_t s, size_t bytes, void **out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Workspace &w = g_ws[std::make_pair(dev, s)];
+  if (w.bytes < bytes) {
+    if (w.ptr) {
+      HIPCHK(hipDeviceSynchronize());
+      HIPCHK(hipFree(w.ptr));
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    size_t want = align256(bytes + bytes / 8);
+    if (hipMalloc(&w.ptr, want) != hipSuccess) {
+      (void)hipGetLastError();
+      w.ptr = nullptr;
+      if (hipMalloc(&w.ptr, align256(bytes)) != hipSuccess) {
+        (void)hipGetLastError();
+        w.ptr = nullptr;
+        return fail(GF2_ENOMEM, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
+      }
+      want = align256(bytes);
+    }
+    w.bytes = want;
+  }
+  *out = w.ptr;
+  return GF2_OK;
+}
+
+struct Carver {
+  char *base;
+  size_t off = 0;
+  explicit Carver(void *b) : base((char *)b) {}
+  template <typename T>
+  T *take(size_t count) {
+    T *p = (T *)(base + off);
+    off += align256(count * sizeof(T));
+    return p;
+  }
+};
+
+size_t decomp_bytes(int64_t n, int64_t m, int64_t ldw, int64_t Mw, int64_t NB) {
+  size_t b = 0;
+  b += align256((size_t)NB * ldw * TW * 8);
+  b += align256(sizeof(DecState));
+  b += align256((size_t)Mw * sizeof(SubInfo));
+  b += 2 * align256((size_t)Mw * 64 * 8);
+  b += align256((size_t)n * 8);
+  b += align256((size_t)Mw * 64 * 8);
+  b += 2 * align256((size_t)n * 4);
+  b += align256((size_t)kMaxPanelWords * 64 * 2 * 4);
+  b += align256((size_t)Mw * 4);
+  (void)m;
+  return b;
+}
+
+void carve_decomp(Carver &c, DecWork &w) {
+  w.W = c.take<uint64_t>((size_t)w.NB * w.ldw * TW);
+  w.st = c.take<DecState>(1);
+  w.sub = c.take<SubInfo>(w.Mw);
+  w.Zc = c.take<uint64_t>((size_t)w.Mw * 64);
+  w.Linv = c.take<uint64_t>((size_t)w.Mw * 64);
+  w.perm = c.take<int64_t>(w.n);
+  w.pivcols = c.take<int64_t>((size_t)w.Mw * 64);
+  w.bp_src = c.take<int32_t>(w.n);
+  w.bp_mark = c.take<int32_t>(w.n);
+  w.bp_list = c.take<int32_t>((size_t)kMaxPanelWords * 64 * 2);
+  w.nzflag = c.take<uint32_t>(w.Mw);
+}
+
+int profile_begin(hipStream_t s, hipEvent_t *a) {
+  if (!g_prof.on) return GF2_OK;
+  HIPCHK(hipEventCreate(a));
+  HIPCHK(hipEventRecord(*a, s));
+  return GF2_OK;
+}
+
+int profile_end(hipStream_t s, hipEvent_t a) {
+  if (!g_prof.on) return GF2_OK;
+  hipEvent_t b;
+  HIPCHK(hipEventCreate(&b));
+  HIPCHK(hipEventRecord(b, s));
+  g_prof.ev.emplace_back(a, b);
+  g_prof.launches += 1;
+  return GF2_OK;
+}
+
+int run_gemm(GemmArgs &a, int64_t nrows_max, hipStream_t s) {
+  hipEvent_t e0 = nullptr;
+  int rc = profile_begin(s, &e0);
+  if (rc) return rc;
+  a.work = g_prof.on ? g_prof.work_dev : nullptr;
+  HIPCHK(launch_gemm(a, nrows_max, s));
+  return profile_end(s, e0);
+}
+
+// Factor A into the working state w (which the caller sized with decomp_bytes).
+int factor(const gf2_mat *A, DecWork &w, hipStream_t s) {
+  HIPCHK(launch_init_state(w, s));
+  HIPCHK(launch_pack(*A, w.W, w.ldw, w.n, w.m, w.NB, s));
+  const int S = g_panel_words;
+  int prev = -1;
+  for (int q0 = 0; q0 < w.Mw; q0 += S) {
+    const int s_eff = (w.Mw - q0) < S ? (w.Mw - q0) : S;
+    for (int b = 0; b < s_eff; ++b) {
+      HIPCHK(launch_panel(w, q0 + b, q0, s_eff, prev, s));
+      HIPCHK(launch_rows_update(w, q0 + b, q0, s_eff, s));
+    }
+    HIPCHK(launch_swap(w, q0, s_eff, s));
+    if (q0 + s_eff < w.Mw) {
+      HIPCHK(launch_trsm(w, q0, s_eff, s));
+      GemmArgs a;
+      memset(&a, 0, sizeof(a));
+      a.A = w.W; a.ldA = w.ldw; a.a_word0 = q0;
+      a.B = w.W; a.ldB = w.ldw; a.b_rows = 0; a.bsub = w.sub + q0;
+      a.C = w.W; a.ldC = w.ldw;
+      a.row_tile0 = 0; a.row_end = w.n; a.row_begin_dev = &w.st->R;
+      a.kwords = s_eff;
+      a.qc0 = q0 + s_eff; a.qc1 = w.Mw;
+      a.accumulate = 1;
+      a.nzflag = w.nzflag + q0;
+      a.skip_flag = prev >= 0 ? w.nzflag + prev : nullptr;
+      int rc = run_gemm(a, w.n, s);
+      if (rc) return rc;
+    }
+    prev = q0;
+  }
+  return GF2_OK;
+}
+
+int prepare_decomp(const gf2_mat *A, hipStream_t s, DecWork &w, size_t extra, void **extra_ptr) {
+  const int64_t n = A->rows, m = A->cols;
+  memset(&w, 0, sizeof(w));
+  w.n = n;
+  w.m = m;
+  w.Mw = (int32_t)ceil_div(m, 64);
+  w.NB = (int32_t)ceil_div(w.Mw, TW);
+  w.ldw = ceil_div(n > 0 ? n : 1, 256) * 256;
+  const size_t need = decomp_bytes(n, m, w.ldw, w.Mw, w.NB) + align256(extra);
+  void *ws = nullptr;
+  int rc = get_workspace(s, need, &ws);
+  if (rc) return rc;
+  Carver c(ws);
+  carve_decomp(c, w);
+  if (extra_ptr) *extra_ptr = c.take<char>(extra);
+  return GF2_OK;
+}
+
+}  // namespace
+}  // namespace gf2
+
+using namespace gf2;
+
+extern "C" {
+
+const char *gf2_version(void) { return "libgf2 0.1 (gfx950)"; }
+
+const char *gf2_last_error(void) { return g_err.c_str(); }
+
+int gf2_set_param(const char *name, int64_t value) {
+  if (!name) return fail(GF2_EINVAL, "null parameter name");
+  if (!strcmp(name, "panel_words")) {
+    if (value < 1 || value > kMaxPanelWords) return fail(GF2_EINVAL, "panel_words must be in 1..8");
+    g_panel_words = (int)value;
+    return GF2_OK;
+  }
+  if (!strcmp(name, "strassen_cutoff")) {
+    if (value < 0) return fail(GF2_EINVAL, "strassen_cutoff must be >= 0");
+    g_strassen_cutoff = value;
+    return GF2_OK;
+  }
+  return fail(GF2_EINVAL, std::string("unknown parameter ") + name);
+}
+
+int gf2_profile(int enable) {
+  for (auto &p : g_prof.ev) {
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  g_prof.ev.clear();
+  g_prof.launches = 0;
+  if (enable && !g_prof.work_dev) {
+    HIPCHK(hipMalloc((void **)&g_prof.work_dev, sizeof(unsigned long long)));
+  }
+  if (g_prof.work_dev) HIPCHK(hipMemset(g_prof.work_dev, 0, sizeof(unsigned long long)));
+  g_prof.on = enable != 0;
+  return GF2_OK;
+}
+
+int gf2_profile_read(double *ms, int64_t *launches, double *lookups) {
+  double total = 0.0;
+  for (auto &p : g_prof.ev) {
+    HIPCHK(hipEventSynchronize(p.second));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, p.first, p.second));
+    total += t;
+  }
+  unsigned long long work = 0;
+  if (g_prof.work_dev) HIPCHK(hipMemcpy(&work, g_prof.work_dev, sizeof(work), hipMemcpyDeviceToHost));
+  if (ms) *ms = total;
+  if (launches) *launches = g_prof.launches;
+  if (lookups) *lookups = (double)work;
+  return GF2_OK;
+}
+
+int gf2_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  for (auto &kv : g_ws) {
+    if (kv.second.ptr) {
+      HIPCHK(hipSetDevice(kv.first.first));
+      HIPCHK(hipDeviceSynchronize());
+      HIPCHK(hipFree(kv.second.ptr));
+    }
+  }
+  g_ws.clear();
+  HIPCHK(hipSetDevice(cur));
+  return GF2_OK;
+}
+
+int gf2_matmul(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B, int accumulate, void *stream) {
+  int rc;
+  if ((rc = check_mat(C, "C")) || (rc = check_mat(A, "A")) || (rc = check_mat(B, "B"))) return rc;
+  if (A->cols != B->rows || C->rows != A->rows || C->cols != B->cols)
+    return fail(GF2_EINVAL, "gf2_matmul: shapes do not match (C n x m, A n x k, B k x m)");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = A->rows, k = A->cols, m = B->cols;
+  if (n == 0 || m == 0) return GF2_OK;
+  const int64_t Kw = ceil_div(k, 64), Mw = ceil_div(m, 64);
+  const int64_t NBa = ceil_div(Kw > 0 ? Kw : 1, TW), NBb = ceil_div(Mw, TW);
+  const int64_t lda = ceil_div(n, 256) * 256, ldb = ceil_div(k > 0 ? k : 1, 256) * 256;
+  const size_t ba = align256((size_t)NBa * lda * TW * 8), bb = align256((size_t)NBb * ldb * TW * 8),
+               bc = align256((size_t)NBb * lda * TW * 8);
+  void *ws = nullptr;
+  if ((rc = get_workspace(s, ba + bb + bc, &ws))) return rc;
+  uint64_t *Aw = (uint64_t *)ws, *Bw = (uint64_t *)((char *)ws + ba), *Cw = (uint64_t *)((char *)ws + ba + bb);
+  HIPCHK(launch_pack(*A, Aw, lda, n, k, (int32_t)NBa, s));
+  HIPCHK(launch_pack(*B, Bw, ldb, k, m, (int32_t)NBb, s));
+  if (accumulate) HIPCHK(launch_pack(*C, Cw, lda, n, m, (int32_t)NBb, s));
+  if (k > 0 || accumulate) {
+    GemmArgs a;
+    memset(&a, 0, sizeof(a));
+    a.A = Aw; a.ldA = lda; a.a_word0 = 0;
+    a.B = Bw; a.ldB = ldb; a.b_rows = k; a.bsub = nullptr;
+    a.C = Cw; a.ldC = lda;
+    a.row_tile0 = 0; a.row_end = n; a.row_begin_dev = nullptr;
+    a.kwords = (int32_t)Kw;
+    a.qc0 = 0; a.qc1 = (int32_t)Mw;
+    a.accumulate = accumulate ? 1 : 0;
+    if ((rc = run_gemm(a, n, s))) return rc;
+  } else {
+    HIPCHK(hipMemsetAsync(Cw, 0, bc, s));
+  }
+  HIPCHK(launch_unpack(Cw, lda, *C, s));
+  return GF2_OK;
+}
+
+int gf2_decompose(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t *perm,
+                  int64_t *pivcols, int64_t *rank, void *stream) {
+  int rc;
+  if ((rc = check_mat(A, "A"))) return rc;
+  const int64_t n = A->rows, m = A->cols, kmin = n < m ? n : m;
+  if (L) {
+    if ((rc = check_mat(L, "L"))) return rc;
+    if (L->rows != n || L->cols != kmin) return fail(GF2_EINVAL, "gf2_decompose: L must be n x min(n,m)");
+  }
+  if (E) {
+    if ((rc = check_mat(E, "E"))) return rc;
+    if (E->rows != kmin || E->cols != m) return fail(GF2_EINVAL, "gf2_decompose: E must be min(n,m) x m");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (n == 0 || m == 0) {
+    if (rank) HIPCHK(hipMemsetAsync(rank, 0, sizeof(int64_t), s));
+    if (perm && n > 0) {
+      std::vector<int64_t> id(n);
+      for (int64_t i = 0; i < n; ++i) id[i] = i;
+      HIPCHK(hipMemcpyAsync(perm, id.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    if (L && n > 0 && kmin > 0) HIPCHK(hipMemsetAsync(L->data, 0, 8 * (size_t)L->ld * L->w * ceil_div(ceil_div(kmin, 64), L->w), s));
+    return GF2_OK;
+  }
+  DecWork w;
+  if ((rc = prepare_decomp(A, s, w, 0, nullptr))) return rc;
+  if ((rc = factor(A, w, s))) return rc;
+  if (E) HIPCHK(launch_extract_E(w, *E, s));
+  if (L) HIPCHK(launch_extract_L(w, *L, s));
+  HIPCHK(launch_finish(w, perm, pivcols, rank, s));
+  return GF2_OK;
+}
+
+int gf2_rank(const gf2_mat *A, int64_t *rank, void *stream) {
+  int rc;
+  if ((rc = check_mat(A, "A"))) return rc;
+  if (!rank) return fail(GF2_EINVAL, "gf2_rank: null rank pointer");
+  hipStream_t s = (hipStream_t)stream;
+  if (A->rows == 0 || A->cols == 0) {
+    HIPCHK(hipMemsetAsync(rank, 0, sizeof(int64_t), s));
+    return GF2_OK;
+  }
+  DecWork w;
+  if ((rc = prepare_decomp(A, s, w, 0, nullptr))) return rc;
+  if ((rc = factor(A, w, s))) return rc;
+  HIPCHK(launch_finish(w, nullptr, nullptr, rank, s));
+  return GF2_OK;
+}
+
+int gf2_solve(const gf2_mat *A, const gf2_mat *B, const gf2_mat *X, uint64_t *consistent,
+              int64_t *rank, void *stream) {
+  int rc;
+  if ((rc = check_mat(A, "A")) || (rc = check_mat(B, "B")) || (rc = check_mat(X, "X"))) return rc;
+  if (!consistent) return fail(GF2_EINVAL, "gf2_solve: null consistent pointer");
+  const int64_t n = A->rows, m = A->cols, k = B->cols;
+  if (B->rows != n || X->rows != m || X->cols != k)
+    return fail(GF2_EINVAL, "gf2_solve: shapes do not match (A n x m, B n x k, X m x k)");
+  if (n == 0 || m == 0 || k == 0)
+    return fail(GF2_EINVAL, "gf2_solve: empty systems are not supported");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t kw = ceil_div(k, 64);
+  const size_t ybytes = align256((size_t)n * kw * 8) + align256((size_t)kw * 8);
+  DecWork w;
+  void *extra = nullptr;
+  if ((rc = prepare_decomp(A, s, w, ybytes, &extra))) return rc;
+  if ((rc = factor(A, w, s))) return rc;
+  SolveWork sw;
+  sw.Y = (uint64_t *)extra;
+  sw.kw = kw;
+  sw.k = k;
+  sw.bad = (uint64_t *)((char *)extra + align256((size_t)n * kw * 8));
+  HIPCHK(launch_solve(w, *B, *X, sw, consistent, s));
+  HIPCHK(launch_finish(w, nullptr, nullptr, rank, s));
+  return GF2_OK;
+}
+
+}  // extern "C"

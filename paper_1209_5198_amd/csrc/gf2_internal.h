@@ -1,0 +1,120 @@
+// gf2_internal.h -- internal layout, device state and launcher declarations of
+// libgf2 (gfx950).  Not installed; the public ABI is include/gf2.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gf2.h"
+
+namespace gf2 {
+
+// ---------------------------------------------------------------- working layout
+// The library's working matrices use the paper's column-blocked row-major
+// storage (Section 3) with a fixed block of TW = 16 words (1024 columns):
+// word (i, q) lives at base[((q / 16) * ldw + i) * 16 + q % 16].  A 16-word
+// block row is 128 contiguous bytes, so a 16-lane group of a wave reads or
+// writes one block row in a single coalesced 128-byte access, and a 64-row
+// tile of one block is 8 KB contiguous.
+constexpr int TW = 16;
+
+__host__ __device__ inline size_t widx(int64_t ldw, int64_t i, int64_t q) {
+  return ((size_t)(q >> 4) * (size_t)ldw + (size_t)i) * TW + (size_t)(q & 15);
+}
+
+// word (i, q) of a caller matrix described by gf2_mat
+__host__ __device__ inline size_t uidx(int64_t w, int64_t ld, int64_t i, int64_t q) {
+  return ((size_t)(q / w) * (size_t)ld + (size_t)i) * (size_t)w + (size_t)(q % w);
+}
+
+__host__ __device__ inline uint64_t pad_mask(int64_t cols, int64_t q) {
+  int64_t valid = cols - 64 * q;
+  if (valid >= 64) return ~0ull;
+  if (valid <= 0) return 0ull;
+  return (1ull << valid) - 1ull;
+}
+
+// ---------------------------------------------------------------- decomposition state
+// Per 64-column sub-panel q: rank before it (R), its number of pivots (r) and
+// the bit positions of its pivot columns inside word q.
+struct SubInfo {
+  int64_t R;
+  int32_t r;
+  int32_t pad;
+  uint64_t pivmask;
+};
+
+struct DecState {
+  int64_t R;         // rank found so far
+  int32_t bp_count;  // positions listed in bp_list for the current panel
+  int32_t pad0;
+};
+
+// Everything the decomposition kernels address; all pointers are device memory.
+struct DecWork {
+  uint64_t *W;       // working matrix, (NB * ldw * 16) words
+  int64_t ldw;       // rows per block (>= n, multiple of 256)
+  int64_t n, m;      // rows, cols (bits)
+  int32_t Mw;        // ceil(m / 64) word columns
+  int32_t NB;        // ceil(Mw / 16) blocks
+  DecState *st;
+  SubInfo *sub;      // [Mw]
+  uint64_t *Zc;      // [Mw * 64]  coefficient map of each sub-panel
+  uint64_t *Linv;    // [Mw * 64]  inverse of each sub-panel's unit lower block
+  int64_t *perm;     // [n]
+  int64_t *pivcols;  // [Mw * 64]
+  int32_t *bp_src;   // [n]  position at panel start of the row now at position p
+  int32_t *bp_mark;  // [n]  1 if p is listed in bp_list
+  int32_t *bp_list;  // [kMaxPanelWords * 64 * 2]
+  uint32_t *nzflag;  // [Mw]  trailing-update nonzero flag per panel
+};
+
+constexpr int kMaxPanelWords = 8;       // s <= 8 sub-panels per trailing-update panel
+constexpr int kWin = 128;               // window rows examined by the panel kernel
+
+// ---------------------------------------------------------------- product arguments
+struct GemmArgs {
+  const uint64_t *A; int64_t ldA; int32_t a_word0;   // A words [a_word0, a_word0 + kwords)
+  const uint64_t *B; int64_t ldB; int64_t b_rows;    // plain B: row k for k < b_rows
+  const SubInfo *bsub;                               // mapped B: row (kw, t) -> bsub[kw].R + t, t < bsub[kw].r
+  uint64_t *C; int64_t ldC;
+  int64_t row_tile0;                                 // first row of tile 0
+  int64_t row_end;                                   // rows < row_end
+  const int64_t *row_begin_dev;                      // optional device lower bound: rows >= *ptr
+  int32_t kwords;
+  int32_t qc0, qc1;                                  // C word columns [qc0, qc1)
+  int32_t accumulate;
+  uint32_t *nzflag;                                  // optional: OR of all written words != 0
+  const uint32_t *skip_flag;                         // optional: skip the launch when *skip_flag == 0
+  unsigned long long *work;                          // optional: += table lookups performed
+};
+
+// ---------------------------------------------------------------- launchers (one per kernel file)
+hipError_t launch_init_state(const DecWork &w, hipStream_t s);
+hipError_t launch_pack(const gf2_mat &src, uint64_t *W, int64_t ldw, int64_t n, int64_t m,
+                       int32_t NB, hipStream_t s);
+hipError_t launch_unpack(const uint64_t *W, int64_t ldw, const gf2_mat &dst, hipStream_t s);
+hipError_t launch_extract_E(const DecWork &w, const gf2_mat &E, hipStream_t s);
+hipError_t launch_extract_L(const DecWork &w, const gf2_mat &L, hipStream_t s);
+hipError_t launch_finish(const DecWork &w, int64_t *perm, int64_t *pivcols, int64_t *rank,
+                         hipStream_t s);
+
+hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, hipStream_t s);
+
+hipError_t launch_panel(const DecWork &w, int q, int q0, int s_eff, int prev_q0, hipStream_t s);
+hipError_t launch_rows_update(const DecWork &w, int q, int q0, int s_eff, hipStream_t s);
+hipError_t launch_swap(const DecWork &w, int q0, int s_eff, hipStream_t s);
+hipError_t launch_trsm(const DecWork &w, int q0, int s_eff, hipStream_t s);
+hipError_t launch_xor(uint64_t *dst, const uint64_t *a, const uint64_t *b, size_t nwords,
+                      hipStream_t s);
+
+struct SolveWork {
+  uint64_t *Y;       // n x kw words, row-major (right-hand sides after P, then Y)
+  int64_t kw;        // words per RHS row
+  int64_t k;         // number of right-hand sides
+  uint64_t *bad;     // [kw] OR of residual rows
+};
+hipError_t launch_solve(const DecWork &w, const gf2_mat &B, const gf2_mat &X,
+                        const SolveWork &sw, uint64_t *consistent, hipStream_t s);
+
+}  // namespace gf2

@@ -1,0 +1,217 @@
+// k_layout.hip -- state initialisation, layout conversion and extraction of
+// L and E from the in-place working matrix.
+//
+// In-place form kept by the decomposition (the L\U picture of Fig. 1, with
+// the L part stored compressed per 64-column sub-panel): after sub-panel q
+// (rank R_q before it, r_q pivots at bit positions pos_0 < ... inside word q)
+//   * pivot row R_q + t holds, in word q, the echelon row E_t restricted to
+//     word q (bits >= pos_t) together with its multipliers for the earlier
+//     pivots of the same sub-panel in bits [0, t);
+//   * every later row holds, in word q, its multipliers for the r_q pivots of
+//     the sub-panel in bits [0, r_q).
+// So column R_q + t of L is bit t of word q, and row t of E is the working row
+// t with the bits left of its pivot cleared.
+#include "gf2_internal.h"
+
+namespace gf2 {
+
+__global__ void k_init_state(DecWork w) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = g; i < w.n; i += stride) {
+    w.perm[i] = i;
+    w.bp_src[i] = (int32_t)i;
+    w.bp_mark[i] = 0;
+  }
+  for (int64_t i = g; i < (int64_t)w.Mw * 64; i += stride) w.pivcols[i] = -1;
+  for (int64_t i = g; i < w.Mw; i += stride) {
+    w.nzflag[i] = 0;
+    w.sub[i].R = 0;
+    w.sub[i].r = 0;
+    w.sub[i].pad = 0;
+    w.sub[i].pivmask = 0;
+  }
+  if (g == 0) {
+    w.st->R = 0;
+    w.st->bp_count = 0;
+    w.st->pad0 = 0;
+  }
+}
+
+hipError_t launch_init_state(const DecWork &w, hipStream_t s) {
+  int64_t work = w.n > (int64_t)w.Mw * 64 ? w.n : (int64_t)w.Mw * 64;
+  int blocks = (int)((work + 255) / 256);
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_init_state, dim3(blocks), dim3(256), 0, s, w);
+  return hipGetLastError();
+}
+
+// caller layout -> working layout; pads rows [n, ldw) and words [Mw, 16*NB) with 0
+__global__ void k_pack(gf2_mat src, uint64_t *W, int64_t ldw, int64_t n, int64_t m, int32_t NB) {
+  const int64_t Mw = (m + 63) / 64;
+  const int64_t total = (int64_t)NB * ldw * TW;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t blk = e / (ldw * TW);
+    const int64_t rem = e - blk * ldw * TW;
+    const int64_t i = rem / TW;
+    const int64_t q = blk * TW + (rem % TW);
+    uint64_t v = 0;
+    if (i < n && q < Mw) v = src.data[uidx(src.w, src.ld, i, q)] & pad_mask(m, q);
+    W[e] = v;
+  }
+}
+
+hipError_t launch_pack(const gf2_mat &src, uint64_t *W, int64_t ldw, int64_t n, int64_t m,
+                       int32_t NB, hipStream_t s) {
+  int64_t total = (int64_t)NB * ldw * TW;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_pack, dim3((unsigned)blocks), dim3(256), 0, s, src, W, ldw, n, m, NB);
+  return hipGetLastError();
+}
+
+// working layout -> caller layout (rows [0, rows), words [0, ceil(cols/64)))
+__global__ void k_unpack(const uint64_t *W, int64_t ldw, gf2_mat dst) {
+  const int64_t Mw = (dst.cols + 63) / 64;
+  const int64_t total = dst.rows * Mw;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t i = e / Mw;
+    const int64_t q = e - i * Mw;
+    dst.data[uidx(dst.w, dst.ld, i, q)] = W[widx(ldw, i, q)] & pad_mask(dst.cols, q);
+  }
+}
+
+hipError_t launch_unpack(const uint64_t *W, int64_t ldw, const gf2_mat &dst, hipStream_t s) {
+  int64_t total = dst.rows * ((dst.cols + 63) / 64);
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_unpack, dim3((unsigned)blocks), dim3(256), 0, s, W, ldw, dst);
+  return hipGetLastError();
+}
+
+// E (kmin x m): row t < rank = working row t with the bits left of its pivot cleared
+__global__ void k_extract_E(DecWork w, gf2_mat E) {
+  const int64_t Mw = w.Mw;
+  const int64_t total = E.rows * Mw;
+  const int64_t rank = w.st->R;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t t = e / Mw;
+    const int64_t q = e - t * Mw;
+    uint64_t v = 0;
+    if (t < rank) {
+      const int64_t pc = w.pivcols[t];
+      const int64_t qt = pc >> 6;
+      if (q > qt) v = w.W[widx(w.ldw, t, q)];
+      else if (q == qt) v = w.W[widx(w.ldw, t, q)] & (~0ull << (pc & 63));
+    }
+    E.data[uidx(E.w, E.ld, t, q)] = v & pad_mask(E.cols, q);
+  }
+}
+
+hipError_t launch_extract_E(const DecWork &w, const gf2_mat &E, hipStream_t s) {
+  int64_t total = E.rows * (int64_t)w.Mw;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_extract_E, dim3((unsigned)blocks), dim3(256), 0, s, w, E);
+  return hipGetLastError();
+}
+
+// index of the sub-panel whose pivot range [R_q, R_q + r_q) contains t (t < rank)
+__device__ inline int find_sub(const SubInfo *sub, int Mw, int64_t t) {
+  int lo = 0, hi = Mw - 1;  // last q with sub[q].R <= t
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (sub[mid].R <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// L (n x kmin): column t < rank of L is bit (t - R_q) of word q of the working
+// matrix (q = sub-panel of pivot t), below the diagonal; 1 on it; 0 above.
+__global__ void k_extract_L(DecWork w, gf2_mat L) {
+  const int64_t Lw = (L.cols + 63) / 64;
+  const int64_t total = L.rows * Lw;
+  const int64_t rank = w.st->R;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t i = e / Lw;
+    const int64_t u = e - i * Lw;
+    const int64_t t0 = 64 * u;
+    int64_t tend = t0 + 64;
+    if (tend > rank) tend = rank;
+    if (i < rank && tend > i) tend = i;  // strictly below the diagonal
+    uint64_t out = 0;
+    int64_t t = t0;
+    if (t < tend) {
+      int q = find_sub(w.sub, w.Mw, t);
+      while (t < tend) {
+        while (q < w.Mw && (w.sub[q].r == 0 || w.sub[q].R + w.sub[q].r <= t)) ++q;
+        if (q >= w.Mw) break;
+        const int64_t Rq = w.sub[q].R;
+        const int64_t end = Rq + w.sub[q].r < tend ? Rq + w.sub[q].r : tend;
+        const int nb = (int)(end - t);
+        const uint64_t word = w.W[widx(w.ldw, i, q)] >> (t - Rq);
+        const uint64_t mask = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
+        out |= (word & mask) << (t - t0);
+        t = end;
+        ++q;
+      }
+    }
+    if (i < rank && i >= t0 && i < t0 + 64) out |= 1ull << (i - t0);  // unit diagonal
+    L.data[uidx(L.w, L.ld, i, u)] = out & pad_mask(L.cols, u);
+  }
+}
+
+hipError_t launch_extract_L(const DecWork &w, const gf2_mat &L, hipStream_t s) {
+  int64_t total = L.rows * ((L.cols + 63) / 64);
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_extract_L, dim3((unsigned)blocks), dim3(256), 0, s, w, L);
+  return hipGetLastError();
+}
+
+__global__ void k_finish(DecWork w, int64_t *perm, int64_t *pivcols, int64_t *rank, int64_t kmin) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (perm)
+    for (int64_t i = g; i < w.n; i += stride) perm[i] = w.perm[i];
+  if (pivcols)
+    for (int64_t i = g; i < kmin; i += stride) pivcols[i] = w.pivcols[i];
+  if (rank && g == 0) *rank = w.st->R;
+}
+
+hipError_t launch_finish(const DecWork &w, int64_t *perm, int64_t *pivcols, int64_t *rank,
+                         hipStream_t s) {
+  int64_t kmin = w.n < w.m ? w.n : w.m;
+  int64_t work = w.n > kmin ? w.n : kmin;
+  int blocks = (int)((work + 255) / 256);
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_finish, dim3(blocks), dim3(256), 0, s, w, perm, pivcols, rank, kmin);
+  return hipGetLastError();
+}
+
+__global__ void k_xor(uint64_t *dst, const uint64_t *a, const uint64_t *b, size_t nwords) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nwords; e += stride)
+    dst[e] = a[e] ^ b[e];
+}
+
+hipError_t launch_xor(uint64_t *dst, const uint64_t *a, const uint64_t *b, size_t nwords,
+                      hipStream_t s) {
+  size_t blocks = (nwords + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_xor, dim3((unsigned)blocks), dim3(256), 0, s, dst, a, b, nwords);
+  return hipGetLastError();
+}
+
+}  // namespace gf2

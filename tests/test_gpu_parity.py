@@ -1,0 +1,219 @@
+"""GPU parity: every output of libgf2 equals the CPU oracle's, bit for bit.
+
+Inputs come from the shared seeded generator; the oracle and the GPU each form
+planted products with their own code.  Shapes span several 1024-row x
+1024-column product tiles, 512-column panels and ragged tails, plus the
+degenerate cases (1 x 1, one row, one column, zero, identity, all ones,
+duplicate rows, widths not a multiple of 64).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1209_5198_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def g():
+    _need_gpu()
+    from paper_1209_5198_amd import gf2
+
+    gf2.load()
+    return gf2
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_decompose(g, words, n, m, w=None):
+    A = g.Mat.from_rowmajor(words, n, m, w=w)
+    out = g.decompose(A)
+    import torch
+
+    torch.cuda.synchronize()
+    return dict(rank=int(out["rank"].item()), perm=out["perm"].cpu().numpy(),
+                pivcols=out["pivcols"].cpu().numpy(), L=out["L"].to_rowmajor(), E=out["E"].to_rowmajor())
+
+
+def assert_same_ple(got, ref, tag):
+    assert got["rank"] == ref["rank"], (tag, got["rank"], ref["rank"])
+    assert np.array_equal(got["perm"], ref["perm"]), (tag, "perm")
+    assert np.array_equal(got["pivcols"], ref["pivcols"]), (tag, "pivcols")
+    assert np.array_equal(got["E"], ref["E"]), (tag, "E")
+    assert np.array_equal(got["L"], ref["L"]), (tag, "L")
+
+
+def planted_words(orc, seed, n, m, r, p=0.5):
+    X, Y = synth.planted(seed, 9, n, m, r, p)
+    return orc.matmul(X, Y, n, r, m)
+
+
+# ---------------------------------------------------------------- product
+MATMUL_SHAPES = [(1, 1, 1), (5, 70, 3), (64, 64, 64), (100, 200, 300), (1030, 130, 1100),
+                 (2100, 1500, 2500), (300, 2049, 77)]
+
+
+@pytest.mark.parametrize("n,k,m", MATMUL_SHAPES)
+def test_matmul_parity(g, orc, n, k, m):
+    say("matmul", n, k, m)
+    A = synth.dense(21, 1, n, k)
+    B = synth.dense(21, 2, k, m)
+    ref = orc.matmul(A, B, n, k, m)
+    C = g.matmul(g.Mat.from_rowmajor(A, n, k), g.Mat.from_rowmajor(B, k, m))
+    assert np.array_equal(C.to_rowmajor(), ref)
+
+
+@pytest.mark.parametrize("wa,wb,wc", [(1, 1, 1), (3, 2, 5), (None, 1, None)])
+def test_matmul_layouts_and_accumulate(g, orc, wa, wb, wc):
+    n, k, m = 700, 650, 900
+    say("matmul layouts", wa, wb, wc)
+    A = synth.dense(22, 1, n, k)
+    B = synth.bernoulli(22, 2, k, m, 0.2)
+    C0 = synth.dense(22, 3, n, m)
+    ref = orc.matmul(A, B, n, k, m, C=C0)
+    Cg = g.Mat.from_rowmajor(C0, n, m, w=wc, ld=n + 5)
+    g.gf2_matmul(Cg, g.Mat.from_rowmajor(A, n, k, w=wa, ld=n + 3), g.Mat.from_rowmajor(B, k, m, w=wb),
+                 accumulate=True)
+    assert np.array_equal(Cg.to_rowmajor(), ref)
+
+
+# ---------------------------------------------------------------- decomposition
+DEC_CASES = [
+    ("dense", 1, 1), ("dense", 1, 200), ("dense", 200, 1), ("dense", 64, 64), ("dense", 65, 63),
+    ("dense", 63, 65), ("dense", 300, 300), ("dense", 700, 520), ("dense", 520, 700),
+    ("dense", 2048, 2048), ("dense", 2500, 1900), ("dense", 1900, 2500), ("dense", 1200, 4200),
+    ("sparse", 1500, 1500), ("sparse", 600, 2000), ("planted", 1800, 1600), ("planted", 1000, 3000),
+    ("planted", 3000, 1000),
+]
+
+
+@pytest.mark.parametrize("kind,n,m", DEC_CASES)
+def test_decompose_parity(g, orc, kind, n, m):
+    say("decompose", kind, n, m)
+    seed = 31 * n + m
+    if kind == "dense":
+        A = synth.dense(seed, 1, n, m)
+    elif kind == "sparse":
+        A = synth.bernoulli(seed, 1, n, m, 0.002)
+    else:
+        A = planted_words(orc, seed, n, m, min(n, m) // 3)
+    ref = orc.ple(A, n, m)
+    got = gpu_decompose(g, A, n, m)
+    assert_same_ple(got, ref, (kind, n, m))
+
+
+@pytest.mark.parametrize("panel_words", [1, 2, 3, 8])
+def test_decompose_panel_width_invariant(g, orc, panel_words):
+    """No tuning parameter changes a result (P is independent of the panel width)."""
+    n, m = 1300, 1700
+    say("panel width", panel_words)
+    A = planted_words(orc, 5, n, m, 900)
+    ref = orc.ple(A, n, m)
+    g.gf2_set_param("panel_words", panel_words)
+    try:
+        got = gpu_decompose(g, A, n, m)
+    finally:
+        g.gf2_set_param("panel_words", 8)
+    assert_same_ple(got, ref, panel_words)
+
+
+def test_decompose_special(g, orc):
+    for n, m in [(1, 1), (5, 9), (64, 64), (130, 70), (700, 1300)]:
+        say("special", n, m)
+        k = min(n, m)
+        cases = {
+            "zero": np.zeros((n, orc.wpr(m)), np.uint64),
+            "eye": orc.pack_bits(np.eye(n, m, dtype=np.uint8)),
+            "ones": orc.pack_bits(np.ones((n, m), np.uint8)),
+            "antieye": orc.pack_bits(np.eye(n, m, dtype=np.uint8)[::-1].copy()),
+        }
+        rng = np.random.default_rng(n + m)
+        base = rng.integers(0, 2, size=(max(1, n // 3), m), dtype=np.uint8)
+        dup = np.concatenate([base] * 3 + [base[:1]] * 3)[:n]
+        cases["dup"] = orc.pack_bits(dup)
+        for name, A in cases.items():
+            ref = orc.ple(A, n, m)
+            got = gpu_decompose(g, A, n, m)
+            assert_same_ple(got, ref, (name, n, m, k))
+
+
+@pytest.mark.parametrize("w", [1, 2, 5])
+def test_decompose_input_layouts(g, orc, w):
+    n, m = 900, 1000
+    say("layout", w)
+    A = synth.dense(8, 1, n, m)
+    ref = orc.ple(A, n, m)
+    got = gpu_decompose(g, A, n, m, w=w)
+    assert_same_ple(got, ref, w)
+
+
+def test_decompose_repeatable(g, orc):
+    """Bit-exact repeat runs (a race in LDS or in the row lists would show here)."""
+    n, m = 1500, 1500
+    A = synth.dense(99, 1, n, m)
+    first = gpu_decompose(g, A, n, m)
+    for _ in range(3):
+        again = gpu_decompose(g, A, n, m)
+        assert_same_ple(again, first, "repeat")
+
+
+@pytest.mark.parametrize("kind,n,m", [("dense", 2048, 2048), ("planted", 1500, 2200), ("dense", 3000, 500)])
+def test_rank_parity(g, orc, kind, n, m):
+    import torch
+
+    say("rank", kind, n, m)
+    A = synth.dense(3, 1, n, m) if kind == "dense" else planted_words(orc, 3, n, m, 777)
+    r = torch.empty(1, dtype=torch.int64, device="cuda")
+    g.gf2_rank(g.Mat.from_rowmajor(A, n, m), r)
+    assert int(r.item()) == orc.rank(A, n, m)
+
+
+# ---------------------------------------------------------------- solve
+@pytest.mark.parametrize("kind,n,m,k", [("dense", 2048, 2048, 1), ("dense", 1000, 700, 64),
+                                        ("dense", 700, 1000, 70), ("planted", 1200, 1200, 130),
+                                        ("planted", 300, 900, 5)])
+def test_solve_parity(g, orc, kind, n, m, k):
+    say("solve", kind, n, m, k)
+    A = synth.dense(4, 1, n, m) if kind == "dense" else planted_words(orc, 4, n, m, min(n, m) // 2)
+    B = synth.dense(4, 2, n, k)
+    # half of the systems consistent by construction: b = A x0
+    x0 = synth.dense(4, 3, m, k)
+    AX = orc.matmul(A, x0, n, m, k)
+    bits = orc.unpack_bits(B, k)
+    bits[:, ::2] = orc.unpack_bits(AX, k)[:, ::2]
+    B = orc.pack_bits(bits)
+    ref = orc.solve(A, B, n, m, k)
+    out = g.solve(g.Mat.from_rowmajor(A, n, m), g.Mat.from_rowmajor(B, n, k))
+    import torch
+
+    torch.cuda.synchronize()
+    assert int(out["rank"].item()) == ref["rank"]
+    assert np.array_equal(out["consistent"].cpu().numpy().view(np.uint64), ref["consistent"])
+    assert np.array_equal(out["X"].to_rowmajor(), ref["X"])
+
+
+def test_errors_are_reported(g):
+    import torch
+
+    A = g.Mat.zeros(10, 20)
+    B = g.Mat.zeros(30, 5)
+    C = g.Mat.zeros(10, 5)
+    with pytest.raises(g.Gf2Error):
+        g.gf2_matmul(C, A, B)
+    with pytest.raises(g.Gf2Error):
+        g.gf2_set_param("panel_words", 99)
+    r = torch.empty(1, dtype=torch.int64, device="cuda")
+    g.gf2_rank(A, r)
+    assert int(r.item()) == 0
