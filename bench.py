@@ -1,0 +1,155 @@
+"""Benchmark: effective GF(2) bit-ops/s of the 65536 x 65536 decomposition on one MI355X.
+
+One step = one call of gf2_decompose on a device-resident 65536 x 65536
+Bernoulli(1/2) matrix (512 MB bit-packed), writing L, E, the permutation, the
+pivot columns and the rank.  Effective bit-ops = 2 * sum_t (n-1-t)(m-1-p_t)
+(one AND and one XOR per multiply-add of textbook elimination, from the pivot
+columns p_t the run returns); value = effective bit-ops / seconds per step.
+
+Roofline of the dominant kernel (the trailing-update Four-Russians product):
+its launches are bracketed by HIP events inside the library on the launch
+stream during the timed steps; its algorithmic work is one 8-byte LDS table
+read and one 64-bit XOR per table lookup (one lookup per output word per 8
+inner bits); the bound is the on-chip table-read rate (LDS: 128 B/clk/CU x 256
+CUs x 2.4 GHz).
+
+cpu_baseline: the CPU oracle (plain elimination, OpenMP) timed on a bounded
+sample of the same workload (a smaller dense matrix of the same distribution),
+expressed in the same unit.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "effective GF(2) bit-ops/s for 65536² decompose; batched solves/s + p99 latency"
+PAPER_BITOPS_PER_S = 1.876e14 / 86.156   # paper's best 65536^2 time (Table 4, b = 128, recursive), context
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12   # 78.6 TB/s
+SEED = 65536
+
+
+def eff_bitops(n: int, m: int, pivcols: np.ndarray) -> float:
+    p = pivcols[pivcols >= 0].astype(np.float64)
+    t = np.arange(p.size, dtype=np.float64)
+    return float(2.0 * np.sum((n - 1 - t) * (m - 1 - p)))
+
+
+def cpu_baseline(budget_s: float = 12.0):
+    """Time the oracle on a dense sample sized to roughly budget_s seconds."""
+    import oracle
+    from paper_1209_5198_amd import synth
+
+    oracle.build()
+    n = 2048
+    last = None
+    while True:
+        A = synth.dense(SEED, 7, n, n)
+        t0 = time.perf_counter()
+        res = oracle.ple(A, n, n, want_le=False)
+        dt = time.perf_counter() - t0
+        last = (n, dt, res)
+        if dt * 8 > budget_s or n >= 32768:
+            break
+        n *= 2
+    n, dt, res = last
+    ops = eff_bitops(n, n, res["pivcols"])
+    return {"value": ops / dt, "unit": "bit-ops/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"oracle PLE (plain elimination) of one {n}x{n} Bernoulli(1/2) matrix, "
+                      f"{dt:.2f} s, rank {res['rank']}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1209_5198_amd import gf2, synth
+
+    torch.cuda.set_device(0)
+    n = m = args.n
+    print(f"# generating {n}x{m} Bernoulli(1/2) input (seed {SEED})", file=sys.stderr, flush=True)
+    words = synth.dense(SEED, 1, n, m)
+    A = gf2.Mat.from_rowmajor(words, n, m)
+    del words
+    kmin = min(n, m)
+    L = gf2.Mat.zeros(n, kmin)
+    E = gf2.Mat.zeros(kmin, m)
+    perm = torch.empty(n, dtype=torch.int64, device="cuda")
+    piv = torch.empty(kmin, dtype=torch.int64, device="cuda")
+    rank = torch.empty(1, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        gf2.gf2_decompose(A, L, E, perm, piv, rank, stream)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"# warmup {i} done", file=sys.stderr, flush=True)
+    gf2.gf2_profile(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    kms, klaunch, lookups = gf2.gf2_profile_read()
+    gf2.gf2_profile(False)
+    print(f"# timed {args.steps} steps: wall {wall*1e3:.1f} ms, events {gpu_ms:.1f} ms", file=sys.stderr, flush=True)
+
+    r = int(rank.item())
+    pc = piv.cpu().numpy()
+    ops = eff_bitops(n, m, pc)
+    ms_per_step = wall * 1e3 / args.steps
+    value = ops / (ms_per_step / 1e3)
+
+    per_launch_ms = kms / max(klaunch, 1)
+    lookups_per_launch = lookups / max(klaunch, 1)
+    achieved_tbs = (8.0 * lookups_per_launch) / (per_launch_ms / 1e3) / 1e12 if per_launch_ms > 0 else 0.0
+    roof = {"bound": "alu", "achieved": achieved_tbs, "peak": LDS_PEAK_TBS, "unit": "TB/s",
+            "frac": achieved_tbs / LDS_PEAK_TBS, "traffic": None,
+            "kernel": "k_gemm_m4rm (trailing-update Four-Russians product)",
+            "work_per_launch": {"lookups": lookups_per_launch, "lds_bytes": 8.0 * lookups_per_launch},
+            "avg_launch_ms": per_launch_ms, "launches": klaunch,
+            "kernel_share_of_step": (kms / args.steps) / ms_per_step if ms_per_step > 0 else None}
+
+    out = {"metric": METRIC, "value": value, "unit": "bit-ops/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": value / PAPER_BITOPS_PER_S if n == 65536 else None,
+           "dtype": "u64", "data": "synthetic",
+           "config": {"workload": f"gf2_decompose {n}x{m} Bernoulli(1/2), P*A=L*E with L, E, perm, pivcols, rank",
+                      "n": n, "m": m, "seed": SEED, "rank": r, "eff_bitops_per_step": ops,
+                      "panel_words": 8},
+           "roofline": roof}
+    if not args.no_cpu:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

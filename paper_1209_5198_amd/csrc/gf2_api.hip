@@ -29,6 +29,21 @@ namespace {
 thread_local std::string g_err;
 int g_panel_words = 8;
 int64_t g_strassen_cutoff = 0;  // 0: never recurse
+int g_gemm_variant = 0;         // product-kernel variant for gf2_matmul
+int g_panel_gemm_variant = 2;   // product-kernel variant for the trailing update
+int g_chain_cus = 8;            // CUs reserved for the pivot chain (look-ahead); 0 = no look-ahead
+
+// Per device: the two internal streams of the look-ahead pipeline.  The pivot
+// chain of panel J+1 (panel and row kernels) runs on `chain`, restricted to a
+// few CUs, while the bulk of panel J's trailing update runs on `gemm`, which
+// owns the other CUs; events order the two.
+struct Pipe {
+  hipStream_t gemm = nullptr, chain = nullptr;
+  std::vector<hipEvent_t> ring;
+  size_t next = 0;
+  int chain_cus = -1;
+};
+std::map<int, Pipe> g_pipes;
 
 struct Workspace {
   void *ptr = nullptr;
@@ -162,47 +177,119 @@ int profile_end(hipStream_t s, hipEvent_t a) {
   return GF2_OK;
 }
 
-int run_gemm(GemmArgs &a, int64_t nrows_max, hipStream_t s) {
+int run_gemm(GemmArgs &a, int64_t nrows_max, int variant, hipStream_t s) {
   hipEvent_t e0 = nullptr;
   int rc = profile_begin(s, &e0);
   if (rc) return rc;
   a.work = g_prof.on ? g_prof.work_dev : nullptr;
-  HIPCHK(launch_gemm(a, nrows_max, s));
+  HIPCHK(launch_gemm(a, nrows_max, variant, s));
   return profile_end(s, e0);
 }
 
+int get_pipe(Pipe **out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Pipe &p = g_pipes[dev];
+  if (p.gemm && p.chain_cus != g_chain_cus) {  // re-create on a changed split
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipStreamDestroy(p.gemm));
+    HIPCHK(hipStreamDestroy(p.chain));
+    p.gemm = p.chain = nullptr;
+  }
+  if (!p.gemm) {
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    const int ncu = prop.multiProcessorCount;
+    const int nchain = (g_chain_cus > 0 && g_chain_cus < ncu) ? g_chain_cus : 0;
+    if (nchain == 0) {
+      HIPCHK(hipStreamCreateWithFlags(&p.gemm, hipStreamNonBlocking));
+      HIPCHK(hipStreamCreateWithFlags(&p.chain, hipStreamNonBlocking));
+    } else {
+      const int nw = (ncu + 31) / 32;
+      std::vector<uint32_t> mg(nw, 0u), mc(nw, 0u);
+      for (int c = 0; c < ncu; ++c) {
+        if (c < nchain) mc[c >> 5] |= 1u << (c & 31);
+        else mg[c >> 5] |= 1u << (c & 31);
+      }
+      HIPCHK(hipExtStreamCreateWithCUMask(&p.gemm, (uint32_t)nw, mg.data()));
+      HIPCHK(hipExtStreamCreateWithCUMask(&p.chain, (uint32_t)nw, mc.data()));
+    }
+    p.chain_cus = g_chain_cus;
+    p.ring.resize(64);
+    for (auto &e : p.ring) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  *out = &p;
+  return GF2_OK;
+}
+
+// make `waiter` wait for everything enqueued so far on `signaller`
+int link(Pipe *p, hipStream_t signaller, hipStream_t waiter) {
+  hipEvent_t e = p->ring[p->next++ % p->ring.size()];
+  HIPCHK(hipEventRecord(e, signaller));
+  HIPCHK(hipStreamWaitEvent(waiter, e, 0));
+  return GF2_OK;
+}
+
+int trailing_gemm(DecWork &w, int q0, int s_eff, int prev, int qc0, int qc1, hipStream_t s) {
+  if (qc1 <= qc0) return GF2_OK;
+  GemmArgs a;
+  memset(&a, 0, sizeof(a));
+  a.A = w.W; a.ldA = w.ldw; a.a_word0 = q0;
+  a.B = w.W; a.ldB = w.ldw; a.b_rows = 0; a.bsub = w.sub + q0;
+  a.C = w.W; a.ldC = w.ldw;
+  a.row_tile0 = 0; a.row_end = w.n;
+  a.kwords = s_eff;
+  a.qc0 = qc0; a.qc1 = qc1;
+  a.accumulate = 1;
+  a.nzflag = w.nzflag + q0;
+  a.skip_flag = prev >= 0 ? w.nzflag + prev : nullptr;
+  return run_gemm(a, w.n, g_panel_gemm_variant, s);
+}
+
+int chain(DecWork &w, int q0, int s_eff, int flag_q0, hipStream_t s) {
+  for (int b = 0; b < s_eff; ++b) {
+    HIPCHK(launch_panel(w, q0 + b, q0, s_eff, flag_q0, s));
+    HIPCHK(launch_rows_update(w, q0 + b, q0, s_eff, s));
+  }
+  return GF2_OK;
+}
+
 // Factor A into the working state w (which the caller sized with decomp_bytes).
-int factor(const gf2_mat *A, DecWork &w, hipStream_t s) {
-  HIPCHK(launch_init_state(w, s));
-  HIPCHK(launch_pack(*A, w.W, w.ldw, w.n, w.m, w.NB, s));
+// Look-ahead: once panel J's row exchanges, pivot rows and the columns of panel
+// J+1 are updated, the pivot chain of panel J+1 starts on the chain stream while
+// the rest of panel J's trailing update runs on the gemm stream.  The zero-tail
+// test of a panel's chain reads the flag of the panel two steps back, the last
+// one whose trailing update is certainly complete.  Returns with `user` ordered
+// after all the work.
+int factor(const gf2_mat *A, DecWork &w, hipStream_t user) {
+  Pipe *P = nullptr;
+  int rc = get_pipe(&P);
+  if (rc) return rc;
+  hipStream_t G = P->gemm, Cs = P->chain;
+  if ((rc = link(P, user, G))) return rc;
+  HIPCHK(launch_init_state(w, G));
+  HIPCHK(launch_pack(*A, w.W, w.ldw, w.n, w.m, w.NB, G));
   const int S = g_panel_words;
+  if ((rc = link(P, G, Cs))) return rc;
+  if ((rc = chain(w, 0, w.Mw < S ? w.Mw : S, -1, Cs))) return rc;
   int prev = -1;
   for (int q0 = 0; q0 < w.Mw; q0 += S) {
     const int s_eff = (w.Mw - q0) < S ? (w.Mw - q0) : S;
-    for (int b = 0; b < s_eff; ++b) {
-      HIPCHK(launch_panel(w, q0 + b, q0, s_eff, prev, s));
-      HIPCHK(launch_rows_update(w, q0 + b, q0, s_eff, s));
-    }
-    HIPCHK(launch_swap(w, q0, s_eff, s));
-    if (q0 + s_eff < w.Mw) {
-      HIPCHK(launch_trsm(w, q0, s_eff, s));
-      GemmArgs a;
-      memset(&a, 0, sizeof(a));
-      a.A = w.W; a.ldA = w.ldw; a.a_word0 = q0;
-      a.B = w.W; a.ldB = w.ldw; a.b_rows = 0; a.bsub = w.sub + q0;
-      a.C = w.W; a.ldC = w.ldw;
-      a.row_tile0 = 0; a.row_end = w.n; a.row_begin_dev = &w.st->R;
-      a.kwords = s_eff;
-      a.qc0 = q0 + s_eff; a.qc1 = w.Mw;
-      a.accumulate = 1;
-      a.nzflag = w.nzflag + q0;
-      a.skip_flag = prev >= 0 ? w.nzflag + prev : nullptr;
-      int rc = run_gemm(a, w.n, s);
-      if (rc) return rc;
+    if ((rc = link(P, Cs, G))) return rc;  // panel J's chain is done
+    HIPCHK(launch_swap(w, q0, s_eff, G));
+    const int nq0 = q0 + s_eff;
+    if (nq0 < w.Mw) {
+      const int ns = (w.Mw - nq0) < S ? (w.Mw - nq0) : S;
+      HIPCHK(launch_trsm(w, q0, s_eff, G));
+      if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0, nq0 + ns, G))) return rc;  // next panel's columns
+      if ((rc = link(P, G, Cs))) return rc;
+      if ((rc = chain(w, nq0, ns, prev, Cs))) return rc;                          // look-ahead
+      if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0 + ns, w.Mw, G))) return rc; // the rest
     }
     prev = q0;
   }
-  return GF2_OK;
+  return link(P, G, user);
 }
 
 int prepare_decomp(const gf2_mat *A, hipStream_t s, DecWork &w, size_t extra, void **extra_ptr) {
@@ -239,6 +326,21 @@ int gf2_set_param(const char *name, int64_t value) {
   if (!strcmp(name, "panel_words")) {
     if (value < 1 || value > kMaxPanelWords) return fail(GF2_EINVAL, "panel_words must be in 1..8");
     g_panel_words = (int)value;
+    return GF2_OK;
+  }
+  if (!strcmp(name, "gemm_variant")) {
+    if (value < 0 || value > 4) return fail(GF2_EINVAL, "gemm_variant must be in 0..4");
+    g_gemm_variant = (int)value;
+    return GF2_OK;
+  }
+  if (!strcmp(name, "panel_gemm_variant")) {
+    if (value < 0 || value > 4) return fail(GF2_EINVAL, "panel_gemm_variant must be in 0..4");
+    g_panel_gemm_variant = (int)value;
+    return GF2_OK;
+  }
+  if (!strcmp(name, "chain_cus")) {
+    if (value < 0 || value > 128) return fail(GF2_EINVAL, "chain_cus must be in 0..128");
+    g_chain_cus = (int)value;
     return GF2_OK;
   }
   if (!strcmp(name, "strassen_cutoff")) {
@@ -321,11 +423,11 @@ int gf2_matmul(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B, int accumul
     a.A = Aw; a.ldA = lda; a.a_word0 = 0;
     a.B = Bw; a.ldB = ldb; a.b_rows = k; a.bsub = nullptr;
     a.C = Cw; a.ldC = lda;
-    a.row_tile0 = 0; a.row_end = n; a.row_begin_dev = nullptr;
+    a.row_tile0 = 0; a.row_end = n;
     a.kwords = (int32_t)Kw;
     a.qc0 = 0; a.qc1 = (int32_t)Mw;
     a.accumulate = accumulate ? 1 : 0;
-    if ((rc = run_gemm(a, n, s))) return rc;
+    if ((rc = run_gemm(a, n, g_gemm_variant, s))) return rc;
   } else {
     HIPCHK(hipMemsetAsync(Cw, 0, bc, s));
   }

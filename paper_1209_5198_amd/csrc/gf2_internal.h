@@ -76,11 +76,11 @@ constexpr int kWin = 128;               // window rows examined by the panel ker
 struct GemmArgs {
   const uint64_t *A; int64_t ldA; int32_t a_word0;   // A words [a_word0, a_word0 + kwords)
   const uint64_t *B; int64_t ldB; int64_t b_rows;    // plain B: row k for k < b_rows
-  const SubInfo *bsub;                               // mapped B: row (kw, t) -> bsub[kw].R + t, t < bsub[kw].r
+  const SubInfo *bsub;                               // mapped B: row (kw, t) -> bsub[kw].R + t, t < bsub[kw].r;
+                                                     // then also rows >= bsub[kwords-1].R + bsub[kwords-1].r
   uint64_t *C; int64_t ldC;
   int64_t row_tile0;                                 // first row of tile 0
   int64_t row_end;                                   // rows < row_end
-  const int64_t *row_begin_dev;                      // optional device lower bound: rows >= *ptr
   int32_t kwords;
   int32_t qc0, qc1;                                  // C word columns [qc0, qc1)
   int32_t accumulate;
@@ -99,7 +99,7 @@ hipError_t launch_extract_L(const DecWork &w, const gf2_mat &L, hipStream_t s);
 hipError_t launch_finish(const DecWork &w, int64_t *perm, int64_t *pivcols, int64_t *rank,
                          hipStream_t s);
 
-hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, hipStream_t s);
+hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int variant, hipStream_t s);
 
 hipError_t launch_panel(const DecWork &w, int q, int q0, int s_eff, int prev_q0, hipStream_t s);
 hipError_t launch_rows_update(const DecWork &w, int q, int q0, int s_eff, hipStream_t s);

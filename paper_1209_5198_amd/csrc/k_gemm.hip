@@ -11,32 +11,45 @@
 // on one row at a time and lane l of the group owns word l of the block row,
 // so the table index (a byte of the row's A word) is uniform in the group and
 // every lookup reads one contiguous 128-byte table entry: 512 bytes per wave
-// instruction with no LDS bank conflicts.  Four tables (32 inner bits, 128 KB
-// of LDS) are live at a time.  Accumulators stay in registers for the whole
-// inner loop, so C is read and written once per launch.
+// instruction with no LDS bank conflicts.  The inner dimension advances in
+// stages of 16 bits (two tables); tables are double-buffered (2 x 64 KB), so
+// the build of stage i+1 overlaps the lookups of stage i with one barrier per
+// stage, and the B rows / A words of later stages are prefetched into
+// registers.  Accumulators stay in registers for the whole inner loop, so C
+// is read and written once per launch.
 #include "gf2_internal.h"
 
 namespace gf2 {
 
+// Four tables (32 inner bits) per step, two barriers per step.
 template <int NT, int TM>
-__global__ __launch_bounds__(NT) void k_gemm_m4rm(GemmArgs a) {
+__global__ __launch_bounds__(NT) void k_gemm_quad(GemmArgs a) {
   constexpr int NW = NT / 64;          // waves
   constexpr int RPL = TM / (4 * NW);   // rows per lane
-  static_assert(RPL * 4 * NW == TM, "tile");
-  __shared__ uint64_t T[4][256][TW];   // 4 tables x 256 entries x 16 words = 128 KB
-  __shared__ uint64_t As[TM];          // the tile's A word for the current 64 inner bits
+  constexpr int JOBS = NT / 16;        // table-build jobs (16 threads each, one per word)
+  constexpr int EPJ = 4 * 256 / JOBS;  // entries per job
+  constexpr int LOGE = EPJ == 16 ? 4 : 5;
+  static_assert(RPL * 4 * NW == TM && RPL % 4 == 0, "tile");
+  static_assert(EPJ == 16 || EPJ == 32, "build split");
+  static_assert(TM % NT == 0, "A staging");
+  // Four tables of 256 entries x 16 words (128 KB).  Tables g = 2p + s are stored
+  // as T[p][idx][s][word], so the byte address of entry idx of table g for word
+  // wl is p*65536 + idx*256 + s*128 + wl*8: byte 1 of the address is the index
+  // itself, and one byte permute of (A bits, lane base) yields the address.
+  __shared__ uint64_t T[2][256][2][TW];
+  __shared__ uint32_t As[2 * TM];      // the tile's A word for the current 64 inner bits
 
+  if (a.skip_flag && *a.skip_flag == 0u) return;  // the Schur complement is already zero
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6, h = lane >> 4, wl = lane & 15;
   const int blk = blockIdx.y + (a.qc0 >> 4);
   const int64_t q = (int64_t)blk * TW + wl;
   const bool qok = q >= a.qc0 && q < a.qc1;
 
-  if (a.skip_flag && *a.skip_flag == 0u) return;  // the Schur complement is already zero
   const int64_t tile0 = a.row_tile0 + (int64_t)blockIdx.x * TM;
   int64_t rb = tile0;
-  if (a.row_begin_dev) {
-    int64_t d = *a.row_begin_dev;
+  if (a.bsub) {  // rows below the panel's pivots: first row after the last sub-panel's pivots
+    const int64_t d = a.bsub[a.kwords - 1].R + a.bsub[a.kwords - 1].r;
     if (d > rb) rb = d;
   }
   int64_t re = tile0 + TM < a.row_end ? tile0 + TM : a.row_end;
@@ -50,54 +63,87 @@ __global__ __launch_bounds__(NT) void k_gemm_m4rm(GemmArgs a) {
     if (a.accumulate && qok && i >= rb && i < re) acc[u] = a.C[widx(a.ldC, i, q)];
   }
 
-  // table-build role of this thread: word bw of the block, tables g, entries [32*uu, 32*uu+32)
   const int bw = tid & 15;
+  const int job = tid >> 4;
+  const int g_b = job / (256 / EPJ), uu = job % (256 / EPJ);
   const int64_t bq = (int64_t)blk * TW + bw;
   const bool bq_ok = bq >= a.qc0 && bq < a.qc1;
 
-  for (int kw = 0; kw < a.kwords; ++kw) {
-    __syncthreads();
-    for (int j = tid; j < TM; j += NT) {
-      const int64_t i = tile0 + j;
-      As[j] = (i >= rb && i < re) ? a.A[widx(a.ldA, i, a.a_word0 + kw)] : 0ull;
-    }
-    int64_t browR = 64ll * kw;  // B row of inner bit 64*kw + t is browR + t when t < blim
+  auto load_b = [&](int hh, uint64_t (&bv)[8]) {
+    const int kw = hh >> 1, half = hh & 1;
+    int64_t browR = 64ll * kw;
     int blim;
     if (a.bsub) {
       browR = a.bsub[kw].R;
       blim = a.bsub[kw].r;
     } else {
-      int64_t left = a.b_rows - 64ll * kw;
+      const int64_t left = a.b_rows - 64ll * kw;
       blim = left >= 64 ? 64 : (left > 0 ? (int)left : 0);
     }
-#pragma unroll 1
-    for (int half = 0; half < 2; ++half) {
-      if (half) __syncthreads();
-      // ---- build 4 tables for inner bits [64kw + 32half, +32)
-      for (int job = tid >> 4; job < 32; job += NT / 16) {
-        const int g = job >> 3, uu = job & 7;
-        uint64_t bv[8];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const int t = 32 * half + 8 * g + b;
-          bv[b] = (bq_ok && t < blim) ? a.B[widx(a.ldB, browR + t, bq)] : 0ull;
-        }
-        uint64_t cur = ((uu & 1) ? bv[5] : 0ull) ^ ((uu & 2) ? bv[6] : 0ull) ^ ((uu & 4) ? bv[7] : 0ull);
+    for (int b = 0; b < 8; ++b) {
+      const int t = 32 * half + 8 * g_b + b;
+      bv[b] = (bq_ok && t < blim) ? a.B[widx(a.ldB, browR + t, bq)] : 0ull;
+    }
+  };
+  constexpr int APT = TM / NT;
+  auto load_a = [&](int kw, uint64_t (&av)[APT]) {
 #pragma unroll
-        for (int j = 0; j < 32; ++j) {
-          const int gj = j ^ (j >> 1);
-          T[g][32 * uu + gj][bw] = cur;
-          if (j < 31) cur ^= bv[__builtin_ctz(j + 1)];
-        }
+    for (int j = 0; j < APT; ++j) {
+      const int64_t i = tile0 + tid + (int64_t)j * NT;
+      av[j] = (i >= rb && i < re) ? a.A[widx(a.ldA, i, a.a_word0 + kw)] : 0ull;
+    }
+  };
+
+  uint64_t bv[8], av[APT];
+  load_b(0, bv);
+  load_a(0, av);
+  const char *Tb = (const char *)&T[0][0][0][0];
+  uint32_t lbase[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) lbase[g] = ((uint32_t)(g >> 1) << 16) | ((uint32_t)(g & 1) << 7) | ((uint32_t)wl << 3);
+  const int nh = 2 * a.kwords;
+  for (int hh = 0; hh < nh; ++hh) {
+    const int half = hh & 1;
+    __syncthreads();  // previous lookups finished: T and As are free
+    if (half == 0) {
+#pragma unroll
+      for (int j = 0; j < APT; ++j) {
+        As[2 * (tid + j * NT)] = (uint32_t)av[j];
+        As[2 * (tid + j * NT) + 1] = (uint32_t)(av[j] >> 32);
       }
-      __syncthreads();
-      // ---- lookups: one 8-byte read and one XOR per 8 inner bits per output word
+    }
+    {
+      uint64_t cur = 0ull;
 #pragma unroll
-      for (int u = 0; u < RPL; ++u) {
-        const uint32_t a32 = (uint32_t)(As[4 * (wv + NW * u) + h] >> (32 * half));
-        acc[u] ^= T[0][a32 & 255u][wl] ^ T[1][(a32 >> 8) & 255u][wl] ^
-                  T[2][(a32 >> 16) & 255u][wl] ^ T[3][a32 >> 24][wl];
+      for (int b = LOGE; b < 8; ++b)
+        if ((uu >> (b - LOGE)) & 1) cur ^= bv[b];
+#pragma unroll
+      for (int j = 0; j < EPJ; ++j) {
+        const int gj = j ^ (j >> 1);
+        T[g_b >> 1][EPJ * uu + gj][g_b & 1][bw] = cur;
+        if (j < EPJ - 1) cur ^= bv[__builtin_ctz(j + 1)];
       }
+    }
+    if (hh + 1 < nh) load_b(hh + 1, bv);  // in flight during the lookups
+    if (half == 0 && (hh >> 1) + 1 < a.kwords) load_a((hh >> 1) + 1, av);
+    __syncthreads();
+#pragma unroll
+    for (int u0 = 0; u0 < RPL; u0 += 4) {
+      uint32_t a32[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a32[v] = As[2 * (4 * (wv + NW * (u0 + v)) + h) + half];
+      uint64_t t[4][4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          // address bytes: [lane base | byte g of a32 | table pair | 0]
+          const uint32_t addr = __builtin_amdgcn_perm(a32[v], lbase[g], 0x0C020000u | ((4u + g) << 8));
+          t[v][g] = *(const uint64_t *)(Tb + addr);
+        }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u0 + v] ^= (t[v][0] ^ t[v][1]) ^ (t[v][2] ^ t[v][3]);
     }
   }
 
@@ -122,13 +168,187 @@ __global__ __launch_bounds__(NT) void k_gemm_m4rm(GemmArgs a) {
   }
 }
 
-hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, hipStream_t s) {
-  constexpr int NT = 512, TM = 1024;
+template <int NT, int TM>
+__global__ __launch_bounds__(NT) void k_gemm_db(GemmArgs a) {
+  constexpr int NW = NT / 64;          // waves
+  constexpr int RPL = TM / (4 * NW);   // rows per lane
+  constexpr int EPT = 2 * 256 * TW / NT;  // table entries built per thread per stage
+  constexpr int LOGE = EPT == 8 ? 3 : (EPT == 16 ? 4 : 5);
+  static_assert(RPL * 4 * NW == TM && RPL % 4 == 0, "tile");
+  static_assert(EPT == 8 || EPT == 16 || EPT == 32, "build split");
+  static_assert(TM % NT == 0, "A staging");
+  // Two buffers of two tables (256 entries x 16 words each).  Entry idx of table
+  // s in buffer b, word wl, sits at byte b*65536 + idx*256 + s*128 + wl*8: byte 1
+  // of the address is the index, so one byte permute of (A bits, lane base)
+  // forms the address.
+  __shared__ uint64_t T[2][256][2][TW];
+  __shared__ uint32_t As[2][2 * TM];   // A word of each row, double-buffered by 64-bit step
+
+  if (a.skip_flag && *a.skip_flag == 0u) return;  // the Schur complement is already zero
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, h = lane >> 4, wl = lane & 15;
+  const int blk = blockIdx.y + (a.qc0 >> 4);
+  const int64_t q = (int64_t)blk * TW + wl;
+  const bool qok = q >= a.qc0 && q < a.qc1;
+
+  const int64_t tile0 = a.row_tile0 + (int64_t)blockIdx.x * TM;
+  int64_t rb = tile0;
+  if (a.bsub) {  // rows below the panel's pivots: first row after the last sub-panel's pivots
+    const int64_t d = a.bsub[a.kwords - 1].R + a.bsub[a.kwords - 1].r;
+    if (d > rb) rb = d;
+  }
+  int64_t re = tile0 + TM < a.row_end ? tile0 + TM : a.row_end;
+  if (rb >= re) return;
+
+  uint64_t acc[RPL];
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const int64_t i = tile0 + 4 * (wv + NW * u) + h;
+    acc[u] = 0;
+    if (a.accumulate && qok && i >= rb && i < re) acc[u] = a.C[widx(a.ldC, i, q)];
+  }
+
+  // table-build role: table sb of the stage, word bw, entries [EPT*uu, EPT*uu + EPT)
+  const int bw = tid & 15;
+  const int sb = tid / (NT / 2);
+  const int uu = (tid >> 4) % (256 / EPT);
+  const int64_t bq = (int64_t)blk * TW + bw;
+  const bool bq_ok = bq >= a.qc0 && bq < a.qc1;
+
+  // B rows of table sb of stage st (inner bits [16 st + 8 sb, +8))
+  auto load_b = [&](int st, uint64_t (&bv)[8]) {
+    const int kw = st >> 2;
+    int64_t browR = 64ll * kw;
+    int blim;
+    if (a.bsub) {
+      browR = a.bsub[kw].R;
+      blim = a.bsub[kw].r;
+    } else {
+      const int64_t left = a.b_rows - 64ll * kw;
+      blim = left >= 64 ? 64 : (left > 0 ? (int)left : 0);
+    }
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int t = 16 * (st & 3) + 8 * sb + b;
+      bv[b] = (bq_ok && t < blim) ? a.B[widx(a.ldB, browR + t, bq)] : 0ull;
+    }
+  };
+  constexpr int APT = TM / NT;  // A rows staged per thread
+  auto load_a = [&](int kw, uint64_t (&av)[APT]) {
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+      const int64_t i = tile0 + tid + (int64_t)j * NT;
+      av[j] = (i >= rb && i < re) ? a.A[widx(a.ldA, i, a.a_word0 + kw)] : 0ull;
+    }
+  };
+  auto build = [&](int buf, const uint64_t (&bv)[8]) {
+    uint64_t cur = 0ull;
+#pragma unroll
+    for (int b = LOGE; b < 8; ++b)
+      if ((uu >> (b - LOGE)) & 1) cur ^= bv[b];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int gj = j ^ (j >> 1);
+      T[buf][EPT * uu + gj][sb][bw] = cur;
+      if (j < EPT - 1) cur ^= bv[__builtin_ctz(j + 1)];
+    }
+  };
+  auto stage_a = [&](int buf, const uint64_t (&av)[APT]) {
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+      As[buf][2 * (tid + j * NT)] = (uint32_t)av[j];
+      As[buf][2 * (tid + j * NT) + 1] = (uint32_t)(av[j] >> 32);
+    }
+  };
+
+  const char *Tb = (const char *)&T[0][0][0][0];
+  uint32_t lbase[2];
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2) lbase[s2] = ((uint32_t)s2 << 7) | ((uint32_t)wl << 3);
+
+  const int nst = 4 * a.kwords;  // stages of 16 inner bits
+  uint64_t bv[8], av[APT];
+  load_b(0, bv);
+  load_a(0, av);
+  stage_a(0, av);
+  build(0, bv);
+  if (nst > 1) load_b(1, bv);
+  if (a.kwords > 1) load_a(1, av);
+  for (int st = 0; st < nst; ++st) {
+    __syncthreads();  // stage st's tables and A words are complete; buffer st+1 is free
+    if (st + 1 < nst) {
+      if (((st + 1) & 3) == 0) stage_a(((st + 1) >> 2) & 1, av);
+      build((st + 1) & 1, bv);
+      if (st + 2 < nst) load_b(st + 2, bv);
+      if (((st + 1) & 3) == 0 && ((st + 1) >> 2) + 1 < a.kwords) load_a(((st + 1) >> 2) + 1, av);
+    }
+    // ---- lookups of stage st: two 8-byte reads and two XORs per output word
+    const uint32_t *Ast = As[(st >> 2) & 1];
+    const int sh = 16 * (st & 1);           // 16-bit half of the 32-bit A half
+    const int ah = (st >> 1) & 1;           // which 32-bit half of the A word
+    const uint32_t bbase = (uint32_t)(st & 1) << 16;
+#pragma unroll
+    for (int u0 = 0; u0 < RPL; u0 += 4) {
+      uint32_t a16[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a16[v] = Ast[2 * (4 * (wv + NW * (u0 + v)) + h) + ah] >> sh;
+      uint64_t t[4][2];
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+          // address bytes: [lane base | byte s2 of the 16 A bits | buffer | 0]
+          const uint32_t addr = __builtin_amdgcn_perm(a16[v], lbase[s2] | bbase, 0x0C020000u | ((4u + s2) << 8));
+          t[v][s2] = *(const uint64_t *)(Tb + addr);
+        }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u0 + v] ^= t[v][0] ^ t[v][1];
+    }
+  }
+
+  uint64_t any = 0;
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const int64_t i = tile0 + 4 * (wv + NW * u) + h;
+    if (qok && i >= rb && i < re) {
+      a.C[widx(a.ldC, i, q)] = acc[u];
+      any |= acc[u];
+    }
+  }
+  if (a.nzflag) {
+    if (__ballot(any != 0ull) != 0ull && lane == 0) atomicOr(a.nzflag, 1u);
+  }
+  if (a.work && tid == 0) {
+    int64_t lo = (int64_t)blk * TW, hi = lo + TW;
+    if (lo < a.qc0) lo = a.qc0;
+    if (hi > a.qc1) hi = a.qc1;
+    const unsigned long long words = hi > lo ? (unsigned long long)(hi - lo) : 0ull;
+    atomicAdd(a.work, (unsigned long long)(re - rb) * words * (unsigned long long)a.kwords * 8ull);
+  }
+}
+
+
+// Product-kernel variants (same results; chosen per call by the tuning knob):
+//   0: four tables / 32 inner bits, 1024 threads, 1024-row tiles
+//   1: four tables, 512 threads, 1024-row tiles
+//   2: four tables, 512 threads, 2048-row tiles
+//   3: double-buffered table pairs, 1024 threads, 1024-row tiles
+//   4: double-buffered table pairs, 512 threads, 2048-row tiles
+int gemm_tile_rows(int v) { return (v == 2 || v == 4) ? 2048 : 1024; }
+
+hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t s) {
   if (nrows_max <= 0 || a.qc1 <= a.qc0) return hipSuccess;
+  const int TM = gemm_tile_rows(v);
   const int64_t tiles = (nrows_max + TM - 1) / TM;
   const int blocks_y = ((a.qc1 - 1) >> 4) - (a.qc0 >> 4) + 1;
-  hipLaunchKernelGGL((k_gemm_m4rm<NT, TM>), dim3((unsigned)tiles, (unsigned)blocks_y), dim3(NT), 0,
-                     s, a);
+  const dim3 grid((unsigned)tiles, (unsigned)blocks_y);
+  switch (v) {
+    case 1: hipLaunchKernelGGL((k_gemm_quad<512, 1024>), grid, dim3(512), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_gemm_quad<512, 2048>), grid, dim3(512), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_gemm_db<1024, 1024>), grid, dim3(1024), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_gemm_db<512, 2048>), grid, dim3(512), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_gemm_quad<1024, 1024>), grid, dim3(1024), 0, s, a); break;
+  }
   return hipGetLastError();
 }
 

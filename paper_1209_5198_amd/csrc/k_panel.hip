@@ -40,21 +40,25 @@ __device__ inline uint64_t rdl64(uint64_t v, int l) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// slot s of a 128-slot window held as two registers per lane (slot = 64*g + lane)
+// slot s of a 128-slot window held as two registers per lane (slot = 64*g + lane).
+// Value selects only (no references or pointer selects), so the window stays in
+// registers instead of being lowered to a dynamically indexed private array.
 __device__ inline uint64_t rdslot(uint64_t a0, uint64_t a1, int s) {
-  return s < 64 ? rdl64(a0, s) : rdl64(a1, s - 64);
+  const uint64_t u0 = rdl64(a0, s & 63), u1 = rdl64(a1, s & 63);
+  return s < 64 ? u0 : u1;
 }
 __device__ inline int rdslot_i(int a0, int a1, int s) {
-  return s < 64 ? __builtin_amdgcn_readlane(a0, s) : __builtin_amdgcn_readlane(a1, s - 64);
+  const int u0 = __builtin_amdgcn_readlane(a0, s & 63), u1 = __builtin_amdgcn_readlane(a1, s & 63);
+  return s < 64 ? u0 : u1;
 }
-template <typename V>
-__device__ inline void wrslot(V &a0, V &a1, int s, V v, int lane) {
-  if (s < 64) {
-    if (lane == s) a0 = v;
-  } else {
-    if (lane == s - 64) a1 = v;
-  }
+__device__ inline uint64_t wrslot0(uint64_t a0, int s, uint64_t v, int lane) {
+  return (s < 64 && lane == s) ? v : a0;
 }
+__device__ inline uint64_t wrslot1(uint64_t a1, int s, uint64_t v, int lane) {
+  return (s >= 64 && lane == s - 64) ? v : a1;
+}
+__device__ inline int wrslot0i(int a0, int s, int v, int lane) { return (s < 64 && lane == s) ? v : a0; }
+__device__ inline int wrslot1i(int a1, int s, int v, int lane) { return (s >= 64 && lane == s - 64) ? v : a1; }
 // lanes l with base + l >= ib
 __device__ inline uint64_t geq_mask(int ib, int base) {
   if (ib <= base) return ~0ull;
@@ -79,6 +83,8 @@ __global__ __launch_bounds__(256) void k_panel(DecWork w, int q, int q0, int s_e
   __shared__ int ptag[64];
   __shared__ int64_t gperm[kWin + 64];
   __shared__ int gbp[kWin + 64];
+  __shared__ int wave_new[4];
+  __shared__ int list_base;
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t n = w.n, ldw = w.ldw;
@@ -134,12 +140,18 @@ __global__ __launch_bounds__(256) void k_panel(DecWork w, int q, int q0, int s_e
       if (sp != ib) {
         const uint64_t xi = rdslot(x0, x1, ib), xri = rdslot(xr0, xr1, ib);
         const int ti = rdslot_i(tag0, tag1, ib);
-        wrslot(x0, x1, sp, xi, lane);
-        wrslot(xr0, xr1, sp, xri, lane);
-        wrslot(tag0, tag1, sp, ti, lane);
-        wrslot(x0, x1, ib, xs, lane);
-        wrslot(xr0, xr1, ib, xrs, lane);
-        wrslot(tag0, tag1, ib, ts, lane);
+        x0 = wrslot0(x0, sp, xi, lane);
+        x1 = wrslot1(x1, sp, xi, lane);
+        xr0 = wrslot0(xr0, sp, xri, lane);
+        xr1 = wrslot1(xr1, sp, xri, lane);
+        tag0 = wrslot0i(tag0, sp, ti, lane);
+        tag1 = wrslot1i(tag1, sp, ti, lane);
+        x0 = wrslot0(x0, ib, xs, lane);
+        x1 = wrslot1(x1, ib, xs, lane);
+        xr0 = wrslot0(xr0, ib, xrs, lane);
+        xr1 = wrslot1(xr1, ib, xrs, lane);
+        tag0 = wrslot0i(tag0, ib, ts, lane);
+        tag1 = wrslot1i(tag1, ib, ts, lane);
       }
       Mnew = xrs;
     } else {
@@ -200,9 +212,12 @@ __global__ __launch_bounds__(256) void k_panel(DecWork w, int q, int q0, int s_e
         bl_tag[j] = to;
       }
       __syncthreads();
-      wrslot(x0, x1, ib, xp, lane);
-      wrslot(xr0, xr1, ib, xrp, lane);
-      wrslot(tag0, tag1, ib, tp, lane);
+      x0 = wrslot0(x0, ib, xp, lane);
+      x1 = wrslot1(x1, ib, xp, lane);
+      xr0 = wrslot0(xr0, ib, xrp, lane);
+      xr1 = wrslot1(xr1, ib, xrp, lane);
+      tag0 = wrslot0i(tag0, ib, tp, lane);
+      tag1 = wrslot1i(tag1, ib, tp, lane);
       F |= xro;
       Mnew = xrp;
     }
@@ -300,15 +315,25 @@ __global__ __launch_bounds__(256) void k_panel(DecWork w, int q, int q0, int s_e
     if (j > jq && dst - R < r) continue;  // pivot rows right of q: written below
     W[widx(ldw, dst, q0 + j)] = G[mvi][j];
   }
-  for (int e = tid; e < cnt; e += 256) {
-    const int dst = mv_dst[e];
-    w.perm[dst] = gperm[e];
-    w.bp_src[dst] = gbp[e];
-    if (!w.bp_mark[dst]) {
-      w.bp_mark[dst] = 1;
-      const int at = atomicAdd(&w.st->bp_count, 1);
-      w.bp_list[at] = dst;
+  {
+    // cnt <= 128 (two positions per transposition, at most 64 of them)
+    int dst = 0;
+    bool fresh = false;
+    if (tid < cnt) {
+      dst = mv_dst[tid];
+      w.perm[dst] = gperm[tid];
+      w.bp_src[dst] = gbp[tid];
+      fresh = w.bp_mark[dst] == 0;
+      if (fresh) w.bp_mark[dst] = 1;
     }
+    const uint64_t fm = __ballot(fresh);
+    if (lane == 0) wave_new[wv] = __popcll(fm);
+    __syncthreads();
+    if (tid == 0) list_base = atomicAdd(&w.st->bp_count, wave_new[0] + wave_new[1] + wave_new[2] + wave_new[3]);
+    __syncthreads();
+    int at = list_base + __popcll(fm & ((1ull << lane) - 1ull));
+    for (int v = 0; v < wv; ++v) at += wave_new[v];
+    if (fresh) w.bp_list[at] = dst;
   }
   if (wv == 0) {
     // word q: pivot rows get E_t | multipliers of earlier pivots; moved rows their raw word
@@ -425,9 +450,13 @@ hipError_t launch_swap(const DecWork &w, int q0, int s_eff, hipStream_t s) {
 //   E_b = Linv_b * X_b, then X_c ^= L_cb * E_b for later sub-panels c,
 // with L_cb = word q0+b of the pivot rows of sub-panel c (their multipliers for
 // the pivots of sub-panel b).  16-lane groups over a 16-word block, 4-bit tables.
-__global__ __launch_bounds__(256) void k_trsm(DecWork w, int q0, int s_eff) {
-  __shared__ uint64_t X[kMaxPanelWords * 64][TW];
-  __shared__ uint64_t T[16][16][TW];
+constexpr int kTrsmThreads = 1024;
+__global__ __launch_bounds__(kTrsmThreads) void k_trsm(DecWork w, int q0, int s_eff) {
+  __shared__ uint64_t X[kMaxPanelWords * 64][TW];           // 64 KB: pivot rows, this block
+  __shared__ uint64_t T[16][16][TW];                        // 32 KB: 4-bit tables
+  __shared__ uint64_t Cf[kMaxPanelWords * 64][kMaxPanelWords];  // 32 KB: multipliers L_cb
+  __shared__ uint64_t Li[kMaxPanelWords][64];               // 4 KB: Linv_b
+  __shared__ SubInfo Sb[kMaxPanelWords];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, h = lane >> 4, wl = lane & 15;
   const int qc0 = q0 + s_eff;
   const int blk = blockIdx.x + (qc0 >> 4);
@@ -435,20 +464,27 @@ __global__ __launch_bounds__(256) void k_trsm(DecWork w, int q0, int s_eff) {
   const bool qok = qw >= qc0 && qw < w.Mw;
   const int64_t ldw = w.ldw;
   uint64_t *W = w.W;
+  if (tid < s_eff) Sb[tid] = w.sub[q0 + tid];
+  __syncthreads();
   int rtot = 0;
-  for (int b = 0; b < s_eff; ++b) rtot += w.sub[q0 + b].r;
+  for (int b = 0; b < s_eff; ++b) rtot += Sb[b].r;
   if (rtot == 0) return;
-  for (int ri = tid >> 4; ri < 64 * s_eff; ri += 16) {
+  for (int ri = tid >> 4; ri < 64 * s_eff; ri += kTrsmThreads / 16) {
     const int b = ri >> 6, t = ri & 63;
-    const SubInfo sb = w.sub[q0 + b];
-    X[ri][wl] = (qok && t < sb.r) ? W[widx(ldw, sb.R + t, qw)] : 0ull;
+    X[ri][wl] = (qok && t < Sb[b].r) ? W[widx(ldw, Sb[b].R + t, qw)] : 0ull;
   }
+  for (int e = tid; e < 64 * s_eff * s_eff; e += kTrsmThreads) {
+    const int ri = e / s_eff, b = e - ri * s_eff;
+    const int c = ri >> 6, t = ri & 63;
+    Cf[ri][b] = (b < c && t < Sb[c].r) ? W[widx(ldw, Sb[c].R + t, q0 + b)] : 0ull;
+  }
+  for (int e = tid; e < 64 * s_eff; e += kTrsmThreads) Li[e >> 6][e & 63] = w.Linv[(size_t)(q0 + (e >> 6)) * 64 + (e & 63)];
   __syncthreads();
   for (int b = 0; b < s_eff; ++b) {
-    const int rb = w.sub[q0 + b].r;
+    const int rb = Sb[b].r;
     if (rb == 0) continue;
     // tables over the rows of X_b
-    {
+    if (tid < 256) {
       const int g = tid >> 4, c = tid & 15;
       uint64_t v[4];
       for (int j = 0; j < 4; ++j) v[j] = X[64 * b + 4 * g + j][c];
@@ -459,10 +495,10 @@ __global__ __launch_bounds__(256) void k_trsm(DecWork w, int q0, int s_eff) {
       }
     }
     __syncthreads();
-    for (int u = 0; u < 4; ++u) {
-      const int t = 4 * (wv + 4 * u) + h;
+    {
+      const int t = 4 * wv + h;  // 16 waves x 4 groups = 64 rows
       if (t < rb) {
-        const uint64_t l = w.Linv[(size_t)(q0 + b) * 64 + t];
+        const uint64_t l = Li[b][t];
         uint64_t v = 0ull;
 #pragma unroll
         for (int g = 0; g < 16; ++g) v ^= T[g][(l >> (4 * g)) & 15u][wl];
@@ -471,7 +507,7 @@ __global__ __launch_bounds__(256) void k_trsm(DecWork w, int q0, int s_eff) {
     }
     __syncthreads();
     if (b == s_eff - 1) break;
-    {
+    if (tid < 256) {
       const int g = tid >> 4, c = tid & 15;
       uint64_t v[4];
       for (int j = 0; j < 4; ++j) v[j] = X[64 * b + 4 * g + j][c];
@@ -482,25 +518,22 @@ __global__ __launch_bounds__(256) void k_trsm(DecWork w, int q0, int s_eff) {
       }
     }
     __syncthreads();
-    const int ngb = (rb + 3) >> 2;
-    for (int c = b + 1; c < s_eff; ++c) {
-      const SubInfo sc = w.sub[q0 + c];
-      for (int u = 0; u < 4; ++u) {
-        const int t = 4 * (wv + 4 * u) + h;
-        if (t < sc.r) {
-          const uint64_t l = W[widx(ldw, sc.R + t, q0 + b)];
-          uint64_t v = 0ull;
-          for (int g = 0; g < ngb; ++g) v ^= T[g][(l >> (4 * g)) & 15u][wl];
-          X[64 * c + t][wl] ^= v;
-        }
+    // multipliers have no bits at or beyond rb, so unused tables contribute entry 0 = 0
+    for (int ri = 64 * (b + 1) + 4 * wv + h; ri < 64 * s_eff; ri += kTrsmThreads / 16) {
+      const int c = ri >> 6, t = ri & 63;
+      if (t < Sb[c].r) {
+        const uint64_t l = Cf[ri][b];
+        uint64_t v = 0ull;
+#pragma unroll
+        for (int g = 0; g < 16; ++g) v ^= T[g][(l >> (4 * g)) & 15u][wl];
+        X[ri][wl] ^= v;
       }
     }
     __syncthreads();
   }
-  for (int ri = tid >> 4; ri < 64 * s_eff; ri += 16) {
+  for (int ri = tid >> 4; ri < 64 * s_eff; ri += kTrsmThreads / 16) {
     const int b = ri >> 6, t = ri & 63;
-    const SubInfo sb = w.sub[q0 + b];
-    if (qok && t < sb.r) W[widx(ldw, sb.R + t, qw)] = X[ri][wl];
+    if (qok && t < Sb[b].r) W[widx(ldw, Sb[b].R + t, qw)] = X[ri][wl];
   }
 }
 
@@ -508,7 +541,7 @@ hipError_t launch_trsm(const DecWork &w, int q0, int s_eff, hipStream_t s) {
   const int qc0 = q0 + s_eff;
   if (qc0 >= w.Mw) return hipSuccess;
   const int blocks = ((w.Mw - 1) >> 4) - (qc0 >> 4) + 1;
-  hipLaunchKernelGGL(k_trsm, dim3((unsigned)blocks), dim3(256), 0, s, w, q0, s_eff);
+  hipLaunchKernelGGL(k_trsm, dim3((unsigned)blocks), dim3(kTrsmThreads), 0, s, w, q0, s_eff);
   return hipGetLastError();
 }
 
