@@ -29,8 +29,8 @@ namespace {
 thread_local std::string g_err;
 int g_panel_words = 8;
 int64_t g_strassen_cutoff = 0;  // 0: never recurse
-int g_gemm_variant = 0;         // product-kernel variant for gf2_matmul
-int g_panel_gemm_variant = 2;   // product-kernel variant for the trailing update
+int g_gemm_variant = -1;        // product-kernel variant for gf2_matmul (-1: automatic)
+int g_panel_gemm_variant = -1;  // product-kernel variant for the trailing update (-1: automatic)
 int g_chain_cus = 8;            // CUs reserved for the pivot chain (look-ahead); 0 = no look-ahead
 
 // Per device: the two internal streams of the look-ahead pipeline.  The pivot
@@ -142,6 +142,7 @@ size_t decomp_bytes(int64_t n, int64_t m, int64_t ldw, int64_t Mw, int64_t NB) {
   b += 2 * align256((size_t)n * 4);
   b += align256((size_t)kMaxPanelWords * 64 * 2 * 4);
   b += align256((size_t)Mw * 4);
+  b += align256((size_t)n * 4);
   (void)m;
   return b;
 }
@@ -158,6 +159,7 @@ void carve_decomp(Carver &c, DecWork &w) {
   w.bp_mark = c.take<int32_t>(w.n);
   w.bp_list = c.take<int32_t>((size_t)kMaxPanelWords * 64 * 2);
   w.nzflag = c.take<uint32_t>(w.Mw);
+  w.lvl = c.take<int32_t>(w.n);
 }
 
 int profile_begin(hipStream_t s, hipEvent_t *a) {
@@ -177,7 +179,24 @@ int profile_end(hipStream_t s, hipEvent_t a) {
   return GF2_OK;
 }
 
-int run_gemm(GemmArgs &a, int64_t nrows_max, int variant, hipStream_t s) {
+int device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
+    cached[dev] = prop.multiProcessorCount;
+  }
+  return cached[dev];
+}
+
+// active_rows: rows expected to do work (used only to pick a tile size)
+int run_gemm(GemmArgs &a, int64_t nrows_max, int variant, int64_t active_rows, hipStream_t s) {
+  if (variant < 0) {
+    const int blocks_y = ((a.qc1 - 1) >> 4) - (a.qc0 >> 4) + 1;
+    variant = gemm_auto_variant(active_rows, blocks_y, device_cus());
+  }
   hipEvent_t e0 = nullptr;
   int rc = profile_begin(s, &e0);
   if (rc) return rc;
@@ -244,14 +263,14 @@ int trailing_gemm(DecWork &w, int q0, int s_eff, int prev, int qc0, int qc1, hip
   a.accumulate = 1;
   a.nzflag = w.nzflag + q0;
   a.skip_flag = prev >= 0 ? w.nzflag + prev : nullptr;
-  return run_gemm(a, w.n, g_panel_gemm_variant, s);
+  // at most 64 pivots per sub-panel so far: a lower bound on the rows left
+  int64_t active = w.n - 64ll * (q0 + s_eff);
+  if (active < 1) active = 1;
+  return run_gemm(a, w.n, g_panel_gemm_variant, active, s);
 }
 
 int chain(DecWork &w, int q0, int s_eff, int flag_q0, hipStream_t s) {
-  for (int b = 0; b < s_eff; ++b) {
-    HIPCHK(launch_panel(w, q0 + b, q0, s_eff, flag_q0, s));
-    HIPCHK(launch_rows_update(w, q0 + b, q0, s_eff, s));
-  }
+  for (int b = 0; b < s_eff; ++b) HIPCHK(launch_panel(w, q0 + b, q0, s_eff, flag_q0, s));
   return GF2_OK;
 }
 
@@ -278,6 +297,7 @@ int factor(const gf2_mat *A, DecWork &w, hipStream_t user) {
     const int s_eff = (w.Mw - q0) < S ? (w.Mw - q0) : S;
     if ((rc = link(P, Cs, G))) return rc;  // panel J's chain is done
     HIPCHK(launch_swap(w, q0, s_eff, G));
+    HIPCHK(launch_rows_panel(w, q0, s_eff, G));
     const int nq0 = q0 + s_eff;
     if (nq0 < w.Mw) {
       const int ns = (w.Mw - nq0) < S ? (w.Mw - nq0) : S;
@@ -329,12 +349,12 @@ int gf2_set_param(const char *name, int64_t value) {
     return GF2_OK;
   }
   if (!strcmp(name, "gemm_variant")) {
-    if (value < 0 || value > 4) return fail(GF2_EINVAL, "gemm_variant must be in 0..4");
+    if (value < -1 || value > 6) return fail(GF2_EINVAL, "gemm_variant must be in -1..6");
     g_gemm_variant = (int)value;
     return GF2_OK;
   }
   if (!strcmp(name, "panel_gemm_variant")) {
-    if (value < 0 || value > 4) return fail(GF2_EINVAL, "panel_gemm_variant must be in 0..4");
+    if (value < -1 || value > 6) return fail(GF2_EINVAL, "panel_gemm_variant must be in -1..6");
     g_panel_gemm_variant = (int)value;
     return GF2_OK;
   }
@@ -427,7 +447,7 @@ int gf2_matmul(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B, int accumul
     a.kwords = (int32_t)Kw;
     a.qc0 = 0; a.qc1 = (int32_t)Mw;
     a.accumulate = accumulate ? 1 : 0;
-    if ((rc = run_gemm(a, n, g_gemm_variant, s))) return rc;
+    if ((rc = run_gemm(a, n, g_gemm_variant, n, s))) return rc;
   } else {
     HIPCHK(hipMemsetAsync(Cw, 0, bc, s));
   }

@@ -67,6 +67,7 @@ struct DecWork {
   int32_t *bp_mark;  // [n]  1 if p is listed in bp_list
   int32_t *bp_list;  // [kMaxPanelWords * 64 * 2]
   uint32_t *nzflag;  // [Mw]  trailing-update nonzero flag per panel
+  int32_t *lvl;      // [n]   16*q0 + L: sub-panels 0..L-1 of the panel at q0 applied to row p
 };
 
 constexpr int kMaxPanelWords = 8;       // s <= 8 sub-panels per trailing-update panel
@@ -100,9 +101,10 @@ hipError_t launch_finish(const DecWork &w, int64_t *perm, int64_t *pivcols, int6
                          hipStream_t s);
 
 hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int variant, hipStream_t s);
+int gemm_auto_variant(int64_t active_rows, int blocks_y, int ncu);  // variant for a launch shape
 
 hipError_t launch_panel(const DecWork &w, int q, int q0, int s_eff, int prev_q0, hipStream_t s);
-hipError_t launch_rows_update(const DecWork &w, int q, int q0, int s_eff, hipStream_t s);
+hipError_t launch_rows_panel(const DecWork &w, int q0, int s_eff, hipStream_t s);
 hipError_t launch_swap(const DecWork &w, int q0, int s_eff, hipStream_t s);
 hipError_t launch_trsm(const DecWork &w, int q0, int s_eff, hipStream_t s);
 hipError_t launch_xor(uint64_t *dst, const uint64_t *a, const uint64_t *b, size_t nwords,

@@ -28,9 +28,9 @@ __global__ __launch_bounds__(NT) void k_gemm_quad(GemmArgs a) {
   constexpr int RPL = TM / (4 * NW);   // rows per lane
   constexpr int JOBS = NT / 16;        // table-build jobs (16 threads each, one per word)
   constexpr int EPJ = 4 * 256 / JOBS;  // entries per job
-  constexpr int LOGE = EPJ == 16 ? 4 : 5;
+  constexpr int LOGE = EPJ == 16 ? 4 : (EPJ == 32 ? 5 : 6);
   static_assert(RPL * 4 * NW == TM && RPL % 4 == 0, "tile");
-  static_assert(EPJ == 16 || EPJ == 32, "build split");
+  static_assert(EPJ == 16 || EPJ == 32 || EPJ == 64, "build split");
   static_assert(TM % NT == 0, "A staging");
   // Four tables of 256 entries x 16 words (128 KB).  Tables g = 2p + s are stored
   // as T[p][idx][s][word], so the byte address of entry idx of table g for word
@@ -328,13 +328,35 @@ __global__ __launch_bounds__(NT) void k_gemm_db(GemmArgs a) {
 }
 
 
-// Product-kernel variants (same results; chosen per call by the tuning knob):
+// Product-kernel variants (same results; chosen per call by a tuning knob, or
+// automatically when the knob is -1):
 //   0: four tables / 32 inner bits, 1024 threads, 1024-row tiles
 //   1: four tables, 512 threads, 1024-row tiles
 //   2: four tables, 512 threads, 2048-row tiles
 //   3: double-buffered table pairs, 1024 threads, 1024-row tiles
 //   4: double-buffered table pairs, 512 threads, 2048-row tiles
-int gemm_tile_rows(int v) { return (v == 2 || v == 4) ? 2048 : 1024; }
+//   5: four tables, 256 threads, 512-row tiles
+//   6: four tables, 256 threads, 256-row tiles
+// Automatic choice: the largest tile that still gives at least one workgroup
+// per CU for the rows expected to be active; small launches get small tiles.
+int gemm_tile_rows(int v) {
+  switch (v) {
+    case 2: case 4: return 2048;
+    case 5: return 512;
+    case 6: return 256;
+    default: return 1024;
+  }
+}
+
+int gemm_auto_variant(int64_t active_rows, int blocks_y, int ncu) {
+  const int64_t want = ncu;
+  const int order[4] = {2, 0, 5, 6};
+  for (int i = 0; i < 4; ++i) {
+    const int tm = gemm_tile_rows(order[i]);
+    if (((active_rows + tm - 1) / tm) * (int64_t)blocks_y >= want) return order[i];
+  }
+  return 6;
+}
 
 hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t s) {
   if (nrows_max <= 0 || a.qc1 <= a.qc0) return hipSuccess;
@@ -347,6 +369,8 @@ hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t 
     case 2: hipLaunchKernelGGL((k_gemm_quad<512, 2048>), grid, dim3(512), 0, s, a); break;
     case 3: hipLaunchKernelGGL((k_gemm_db<1024, 1024>), grid, dim3(1024), 0, s, a); break;
     case 4: hipLaunchKernelGGL((k_gemm_db<512, 2048>), grid, dim3(512), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_gemm_quad<256, 512>), grid, dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_gemm_quad<256, 256>), grid, dim3(256), 0, s, a); break;
     default: hipLaunchKernelGGL((k_gemm_quad<1024, 1024>), grid, dim3(1024), 0, s, a); break;
   }
   return hipGetLastError();

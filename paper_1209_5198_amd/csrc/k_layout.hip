@@ -22,6 +22,7 @@ __global__ void k_init_state(DecWork w) {
     w.perm[i] = i;
     w.bp_src[i] = (int32_t)i;
     w.bp_mark[i] = 0;
+    w.lvl[i] = -1;
   }
   for (int64_t i = g; i < (int64_t)w.Mw * 64; i += stride) w.pivcols[i] = -1;
   for (int64_t i = g; i < w.Mw; i += stride) {

@@ -130,14 +130,16 @@ def test_decompose_panel_width_invariant(g, orc, panel_words):
 
 
 @pytest.mark.parametrize("knob,value", [("chain_cus", 0), ("chain_cus", 32), ("panel_gemm_variant", 0),
-                                        ("panel_gemm_variant", 3), ("panel_gemm_variant", 4)])
+                                        ("panel_gemm_variant", 2), ("panel_gemm_variant", 3),
+                                        ("panel_gemm_variant", 4), ("panel_gemm_variant", 5),
+                                        ("panel_gemm_variant", 6)])
 def test_decompose_tuning_invariant(g, orc, knob, value):
     """Look-ahead split and product-kernel variant do not change any result."""
     n, m = 2300, 2900
     say("tuning", knob, value)
     A = synth.dense(17, 1, n, m)
     ref = orc.ple(A, n, m)
-    defaults = {"chain_cus": 8, "panel_gemm_variant": 2}
+    defaults = {"chain_cus": 8, "panel_gemm_variant": -1}
     g.gf2_set_param(knob, value)
     try:
         got = gpu_decompose(g, A, n, m)
@@ -146,7 +148,7 @@ def test_decompose_tuning_invariant(g, orc, knob, value):
     assert_same_ple(got, ref, (knob, value))
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
 def test_matmul_variants(g, orc, variant):
     n, k, m = 2100, 1300, 2500
     say("matmul variant", variant)
@@ -157,7 +159,7 @@ def test_matmul_variants(g, orc, variant):
     try:
         C = g.matmul(g.Mat.from_rowmajor(A, n, k), g.Mat.from_rowmajor(B, k, m))
     finally:
-        g.gf2_set_param("gemm_variant", 0)
+        g.gf2_set_param("gemm_variant", -1)
     assert np.array_equal(C.to_rowmajor(), ref)
 
 
