@@ -17,7 +17,12 @@ cpu_baseline: the CPU oracle (plain elimination, OpenMP) timed on a bounded
 sample of the same workload (a smaller dense matrix of the same distribution),
 expressed in the same unit.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N]
+HBM traffic of that kernel is read from rocprofv3 counters (FETCH_SIZE and
+WRITE_SIZE, separate runs); --copy-calibration runs only a plain 1 GiB device
+copy, whose counter readings give the scale factor between counter units and
+bytes.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -75,6 +80,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
@@ -85,6 +92,16 @@ def main():
     from paper_1209_5198_amd import gf2, synth
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes, "copies": 3}}),
+              flush=True)
+        return
     n = m = args.n
     print(f"# generating {n}x{m} Bernoulli(1/2) input (seed {SEED})", file=sys.stderr, flush=True)
     words = synth.dense(SEED, 1, n, m)

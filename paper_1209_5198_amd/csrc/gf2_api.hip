@@ -270,7 +270,7 @@ int trailing_gemm(DecWork &w, int q0, int s_eff, int prev, int qc0, int qc1, hip
 }
 
 int chain(DecWork &w, int q0, int s_eff, int flag_q0, hipStream_t s) {
-  for (int b = 0; b < s_eff; ++b) HIPCHK(launch_panel(w, q0 + b, q0, s_eff, flag_q0, s));
+  HIPCHK(launch_panel(w, q0, s_eff, flag_q0, s));
   return GF2_OK;
 }
 

@@ -71,7 +71,7 @@ struct DecWork {
 };
 
 constexpr int kMaxPanelWords = 8;       // s <= 8 sub-panels per trailing-update panel
-constexpr int kWin = 128;               // window rows examined by the panel kernel
+constexpr int kWin = 128;               // window rows examined per sub-panel
 
 // ---------------------------------------------------------------- product arguments
 struct GemmArgs {
@@ -103,7 +103,7 @@ hipError_t launch_finish(const DecWork &w, int64_t *perm, int64_t *pivcols, int6
 hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int variant, hipStream_t s);
 int gemm_auto_variant(int64_t active_rows, int blocks_y, int ncu);  // variant for a launch shape
 
-hipError_t launch_panel(const DecWork &w, int q, int q0, int s_eff, int prev_q0, hipStream_t s);
+hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, hipStream_t s);
 hipError_t launch_rows_panel(const DecWork &w, int q0, int s_eff, hipStream_t s);
 hipError_t launch_swap(const DecWork &w, int q0, int s_eff, hipStream_t s);
 hipError_t launch_trsm(const DecWork &w, int q0, int s_eff, hipStream_t s);

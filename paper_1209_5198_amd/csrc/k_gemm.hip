@@ -21,6 +21,47 @@
 
 namespace gf2 {
 
+// Rows owned by one lane of a product tile: tile0 + l0 + S*u for u in [0, RPL)
+// (l0 = 4 * wave + group, S = 4 * waves).  [ulo, uhi) are the u whose row lies
+// in [rb, re).  Row u of the lane's column word sits at Cl + u*S*16 with
+// Cl = &C[(blk * ldC + tile0 + l0) * 16 + word].  The base pointer passes
+// through an empty asm statement so that the compiler forms the 64 per-row
+// addresses next to their loads and stores instead of keeping them alive
+// across the inner loop (which spilled registers to scratch).
+template <int RPL, int S>
+__device__ inline void lane_rows(int64_t tile0, int l0, int64_t rb, int64_t re, int &ulo, int &uhi) {
+  const int64_t b = tile0 + l0;
+  int64_t lo = rb - b, hi = re - b;
+  lo = lo <= 0 ? 0 : (lo + S - 1) / S;
+  hi = hi <= 0 ? 0 : (hi + S - 1) / S;
+  ulo = (int)(lo < RPL ? lo : RPL);
+  uhi = (int)(hi < RPL ? hi : RPL);
+}
+
+__device__ inline uint64_t *lane_c_base(const GemmArgs &a, int blk, int64_t tile0, int l0, int wl) {
+  uint64_t *C = a.C;
+  asm volatile("" : "+s"(C));
+  return C + (((int64_t)blk * a.ldC + tile0 + l0) * TW + wl);
+}
+
+template <int RPL, int S>
+__device__ inline void load_acc(uint64_t (&acc)[RPL], const uint64_t *Cl, bool on, int ulo, int uhi) {
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) acc[u] = (on && u >= ulo && u < uhi) ? Cl[(int64_t)u * S * TW] : 0ull;
+}
+
+template <int RPL, int S>
+__device__ inline uint64_t store_acc(const uint64_t (&acc)[RPL], uint64_t *Cl, bool on, int ulo, int uhi) {
+  uint64_t any = 0;
+#pragma unroll
+  for (int u = 0; u < RPL; ++u)
+    if (on && u >= ulo && u < uhi) {
+      Cl[(int64_t)u * S * TW] = acc[u];
+      any |= acc[u];
+    }
+  return any;
+}
+
 // Four tables (32 inner bits) per step, two barriers per step.
 template <int NT, int TM>
 __global__ __launch_bounds__(NT) void k_gemm_quad(GemmArgs a) {
@@ -55,13 +96,10 @@ __global__ __launch_bounds__(NT) void k_gemm_quad(GemmArgs a) {
   int64_t re = tile0 + TM < a.row_end ? tile0 + TM : a.row_end;
   if (rb >= re) return;
 
+  int ulo, uhi;
+  lane_rows<RPL, 4 * NW>(tile0, 4 * wv + h, rb, re, ulo, uhi);
   uint64_t acc[RPL];
-#pragma unroll
-  for (int u = 0; u < RPL; ++u) {
-    const int64_t i = tile0 + 4 * (wv + NW * u) + h;
-    acc[u] = 0;
-    if (a.accumulate && qok && i >= rb && i < re) acc[u] = a.C[widx(a.ldC, i, q)];
-  }
+  load_acc<RPL, 4 * NW>(acc, lane_c_base(a, blk, tile0, 4 * wv + h, wl), a.accumulate && qok, ulo, uhi);
 
   const int bw = tid & 15;
   const int job = tid >> 4;
@@ -147,15 +185,7 @@ __global__ __launch_bounds__(NT) void k_gemm_quad(GemmArgs a) {
     }
   }
 
-  uint64_t any = 0;
-#pragma unroll
-  for (int u = 0; u < RPL; ++u) {
-    const int64_t i = tile0 + 4 * (wv + NW * u) + h;
-    if (qok && i >= rb && i < re) {
-      a.C[widx(a.ldC, i, q)] = acc[u];
-      any |= acc[u];
-    }
-  }
+  const uint64_t any = store_acc<RPL, 4 * NW>(acc, lane_c_base(a, blk, tile0, 4 * wv + h, wl), qok, ulo, uhi);
   if (a.nzflag) {
     if (__ballot(any != 0ull) != 0ull && lane == 0) atomicOr(a.nzflag, 1u);
   }
@@ -200,13 +230,10 @@ __global__ __launch_bounds__(NT) void k_gemm_db(GemmArgs a) {
   int64_t re = tile0 + TM < a.row_end ? tile0 + TM : a.row_end;
   if (rb >= re) return;
 
+  int ulo, uhi;
+  lane_rows<RPL, 4 * NW>(tile0, 4 * wv + h, rb, re, ulo, uhi);
   uint64_t acc[RPL];
-#pragma unroll
-  for (int u = 0; u < RPL; ++u) {
-    const int64_t i = tile0 + 4 * (wv + NW * u) + h;
-    acc[u] = 0;
-    if (a.accumulate && qok && i >= rb && i < re) acc[u] = a.C[widx(a.ldC, i, q)];
-  }
+  load_acc<RPL, 4 * NW>(acc, lane_c_base(a, blk, tile0, 4 * wv + h, wl), a.accumulate && qok, ulo, uhi);
 
   // table-build role: table sb of the stage, word bw, entries [EPT*uu, EPT*uu + EPT)
   const int bw = tid & 15;
@@ -306,15 +333,7 @@ __global__ __launch_bounds__(NT) void k_gemm_db(GemmArgs a) {
     }
   }
 
-  uint64_t any = 0;
-#pragma unroll
-  for (int u = 0; u < RPL; ++u) {
-    const int64_t i = tile0 + 4 * (wv + NW * u) + h;
-    if (qok && i >= rb && i < re) {
-      a.C[widx(a.ldC, i, q)] = acc[u];
-      any |= acc[u];
-    }
-  }
+  const uint64_t any = store_acc<RPL, 4 * NW>(acc, lane_c_base(a, blk, tile0, 4 * wv + h, wl), qok, ulo, uhi);
   if (a.nzflag) {
     if (__ballot(any != 0ull) != 0ull && lane == 0) atomicOr(a.nzflag, 1u);
   }

@@ -1,18 +1,18 @@
 // k_panel.hip -- the per-panel steps of the block decomposition (Section 4).
 //
 // A trailing-update panel is s <= 8 consecutive 64-column sub-panels (words
-// q0 .. q0+s-1), factored left-looking:
-//   k_panel        per sub-panel q: brings the window rows up to date for the
-//                  panel's earlier sub-panels, then selects the pivots of the
-//                  64 columns of word q (procedure buildZ, Sections 4.2-4.4):
-//                  for each bit k in order, the first row at or below the next
-//                  free position whose reduced bit k is 1 becomes the pivot and
-//                  is exchanged with that position (a transposition).  It
-//                  produces the pivot columns, the coefficient map Zc (row j of
-//                  Zc gives the multipliers of bit j, so y = x * Zc are a row's
-//                  multipliers -- the role of Z in D*Z = Y, Section 4.1), the
-//                  inverse of the sub-panel's unit lower block, and writes back
-//                  the window rows (pivot rows in final form).
+// q0 .. q0+s-1):
+//   k_chain        one workgroup per panel: for each sub-panel q in order it
+//                  selects the pivots of the 64 columns of word q (procedure
+//                  buildZ, Sections 4.2-4.4): for each bit k in order, the first
+//                  row at or below the next free position whose reduced bit k is
+//                  1 becomes the pivot and is exchanged with that position (a
+//                  transposition).  It produces the pivot columns, the
+//                  coefficient map Zc (row j of Zc gives the multipliers of bit
+//                  j, so y = x * Zc are a row's multipliers -- the role of Z in
+//                  D*Z = Y, Section 4.1), the inverse of the sub-panel's unit
+//                  lower block and the pivot rows in final form, and applies the
+//                  sub-panel to the rows it holds in LDS.
 //   k_rows_panel   once per panel: every row below the pivots gets the
 //                  sub-panels it still lacks, so its panel words hold its
 //                  multipliers (eq. (Aj) restricted to the panel).
@@ -22,47 +22,32 @@
 //                  (block forward substitution over the sub-panels).
 // The trailing product (Schur complement, eq. (Aj)) is k_gemm.
 //
-// Reduced bit of a row.  The panel kernel keeps, for every pivot found so
+// Reduced bit of a row.  The chain kernel keeps, for every pivot found so
 // far, its fully reduced row M_j (indexed by the pivot's bit position j; rows
 // of M are the identity on pivot positions -- the words M of buildZ).  The
 // reduced form of any row x is Proj(x) = x xor sum_{pivot j} x_j M_j; its bit k
 // is the parity test popC(c AND x) of buildZ with c = e_k xor sum_j M_j[k] e_j.
 // Rows of a window (the first kWin free positions) are kept reduced in
 // registers; rows below the window are tested with Proj on demand.
+#include <type_traits>
+
 #include "gf2_internal.h"
 
+// v_writelane_b32 (lane `lane` of `old` receives the uniform value `val`): an
+// LLVM intrinsic that clang does not expose as a builtin.
+extern "C" __device__ int gf2_llvm_writelane(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 namespace gf2 {
+
+__device__ inline uint32_t wrlane(uint32_t val, int lane, uint32_t old) {
+  return (uint32_t)gf2_llvm_writelane((int)val, lane, (int)old);
+}
+__device__ inline int wrlane(int val, int lane, int old) { return gf2_llvm_writelane(val, lane, old); }
 
 __device__ inline uint64_t rdl64(uint64_t v, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
   return ((uint64_t)hi << 32) | lo;
-}
-
-// slot s of a 128-slot window held as two registers per lane (slot = 64*g + lane).
-// Value selects only (no references or pointer selects), so the window stays in
-// registers instead of being lowered to a dynamically indexed private array.
-__device__ inline uint64_t rdslot(uint64_t a0, uint64_t a1, int s) {
-  const uint64_t u0 = rdl64(a0, s & 63), u1 = rdl64(a1, s & 63);
-  return s < 64 ? u0 : u1;
-}
-__device__ inline int rdslot_i(int a0, int a1, int s) {
-  const int u0 = __builtin_amdgcn_readlane(a0, s & 63), u1 = __builtin_amdgcn_readlane(a1, s & 63);
-  return s < 64 ? u0 : u1;
-}
-__device__ inline uint64_t wrslot0(uint64_t a0, int s, uint64_t v, int lane) {
-  return (s < 64 && lane == s) ? v : a0;
-}
-__device__ inline uint64_t wrslot1(uint64_t a1, int s, uint64_t v, int lane) {
-  return (s >= 64 && lane == s - 64) ? v : a1;
-}
-__device__ inline int wrslot0i(int a0, int s, int v, int lane) { return (s < 64 && lane == s) ? v : a0; }
-__device__ inline int wrslot1i(int a1, int s, int v, int lane) { return (s >= 64 && lane == s - 64) ? v : a1; }
-// lanes l with base + l >= ib
-__device__ inline uint64_t geq_mask(int ib, int base) {
-  if (ib <= base) return ~0ull;
-  if (ib >= base + 64) return 0ull;
-  return ~0ull << (ib - base);
 }
 
 // ---------------------------------------------------------------- panel-local update
@@ -80,23 +65,23 @@ __host__ __device__ inline int pidx(int c, int wd) { return c * (2 * kMaxPanelWo
 struct PanelTables {
   uint64_t Tz[kMaxPanelWords][16][16];  // y = x * Zc_c
   uint64_t Te[kPairs][16][16];          // y * E_c[w]
-  uint64_t Src[kPairs + kMaxPanelWords][64];  // staged Zc_c rows and E_c[w] words
 };
+typedef uint64_t TableSrc[kPairs + kMaxPanelWords][64];  // staged Zc_c rows and E_c[w] words
 
 // Tables of sub-panels c in [0, cend) of the panel starting at q0 (all threads).
-__device__ void build_panel_tables(PanelTables &pt, const DecWork &w, int q0, int s_eff, int cend,
-                                   int tid, int nthr) {
+__device__ void build_panel_tables(PanelTables &pt, TableSrc &Src, const DecWork &w, int q0, int s_eff,
+                                   int cend, int tid, int nthr) {
   // stage: slot c*64+t of Src for Zc_c; slot (kMaxPanelWords + pidx)*64 + t for E_c[w]
   for (int e = tid; e < cend * 64; e += nthr) {
     const int c = e >> 6, t = e & 63;
-    pt.Src[c][t] = w.Zc[(size_t)(q0 + c) * 64 + t];
+    Src[c][t] = w.Zc[(size_t)(q0 + c) * 64 + t];
   }
   for (int c = 0; c < cend; ++c) {
     const SubInfo sc = w.sub[q0 + c];
     const int nwd = s_eff - 1 - c;
     for (int e = tid; e < nwd * 64; e += nthr) {
       const int wd = c + 1 + (e >> 6), t = e & 63;
-      pt.Src[kMaxPanelWords + pidx(c, wd)][t] = t < sc.r ? w.W[widx(w.ldw, sc.R + t, q0 + wd)] : 0ull;
+      Src[kMaxPanelWords + pidx(c, wd)][t] = t < sc.r ? w.W[widx(w.ldw, sc.R + t, q0 + wd)] : 0ull;
     }
   }
   __syncthreads();
@@ -105,7 +90,7 @@ __device__ void build_panel_tables(PanelTables &pt, const DecWork &w, int q0, in
     uint64_t acc = 0ull;
 #pragma unroll
     for (int b = 0; b < 4; ++b)
-      if (v & (1 << b)) acc ^= pt.Src[c][4 * g + b];
+      if (v & (1 << b)) acc ^= Src[c][4 * g + b];
     pt.Tz[c][g][v] = acc;
   }
   for (int c = 0; c < cend; ++c) {
@@ -116,7 +101,7 @@ __device__ void build_panel_tables(PanelTables &pt, const DecWork &w, int q0, in
       uint64_t acc = 0ull;
 #pragma unroll
       for (int b = 0; b < 4; ++b)
-        if (v & (1 << b)) acc ^= pt.Src[kMaxPanelWords + pi][4 * g + b];
+        if (v & (1 << b)) acc ^= Src[kMaxPanelWords + pi][4 * g + b];
       pt.Te[pi][g][v] = acc;
     }
   }
@@ -159,41 +144,64 @@ __device__ inline int row_level(const DecWork &w, int64_t p, int q0) {
 }
 
 // ---------------------------------------------------------------- pivot selection
-// One workgroup of 4 waves.  The window (the first kWin free positions) is
-// brought up to date for the panel's earlier sub-panels, then all four waves
-// hold the same reduced words of word q and take the same decisions (no
-// communication on the common path); the scan below the window and the
-// write-back use all 256 threads.  A slot carries an origin code: o < kWin is
-// the row that sat at window position o, o >= kWin the row kept in Xr[o-kWin]
-// (brought up from below the window).
-__global__ __launch_bounds__(256) void k_panel(DecWork w, int q, int q0, int s_eff, int flag_q0) {
-  __shared__ PanelTables pt;
-  __shared__ uint64_t Wl[kWin][kMaxPanelWords];  // window rows, panel words at level b
-  __shared__ uint64_t Xr[64][kMaxPanelWords];    // rows brought up from below the window
-  __shared__ int Xsrc[64];
-  __shared__ int nX;
-  __shared__ uint64_t Tp[8][256];                // Proj tables for the scan
-  __shared__ uint64_t Ms[64];
-  __shared__ int po_pos[64], po_org[64];         // positions below the window now holding a window row
-  __shared__ int npo;
-  __shared__ uint32_t po_bloom[128];
-  __shared__ int scan_best;
-  __shared__ unsigned long long scan_F;
-  __shared__ int sorg[kWin];
-  __shared__ uint64_t Praw[64][kMaxPanelWords];
-  __shared__ int wr_pos[kWin + 64], wr_org[kWin + 64];
-  __shared__ int nwr;
-  __shared__ int64_t gperm[kWin + 64];
-  __shared__ int gbp[kWin + 64];
-  __shared__ int wave_new[4];
-  __shared__ int list_base;
+// One workgroup of 4 waves factors a whole panel (s <= 8 sub-panels).  The rows
+// at positions [R0, R0 + 64 s + kWin) -- every position a window of this panel
+// can reach -- are held in LDS ("block") with their panel words, and are
+// brought up to date right-looking after each sub-panel (eq. (Aj) restricted
+// to the panel).  Rows further down stay in HBM at their level and are only
+// read by the rare scan below the window.
+//
+// Per sub-panel b (word q = q0 + b, rank Rb before it): the window is the kWin
+// positions from Rb; all four waves hold the same reduced words of word q of
+// the window (slot 64g + lane) and take the same decisions.  For each bit k the
+// candidates are one ballot per half ANDed with the scalar mask of free slots;
+// the first candidate becomes the pivot of position Rb + ib (a transposition),
+// and every other candidate is reduced by it.  The fully reduced pivot rows M_j
+// (lane j) and their coefficient map Zc are updated in the same step.  When no
+// window row has bit k, all threads scan the rows below the window with
+// Proj(x) = x xor sum_j x_j M_j and keep an over-approximation F of the bits
+// such rows can still have, so a zero tail costs one scan per sub-panel.
+constexpr int kBlkMax = 64 * kMaxPanelWords + kWin;  // block rows
+constexpr int kMbMax = 64 * kMaxPanelWords;          // rows moved below the block per panel
 
+struct ChainShared {
+  PanelTables pt;                            // tables of the panel's finished sub-panels
+  uint64_t blk[kBlkMax][kMaxPanelWords];     // block rows: panel words, level = current sub-panel
+  int bsrc[kBlkMax];                         // panel-start position of the row at block index i
+  uint64_t win[kWin][kMaxPanelWords];        // staging for window permutations and pivot rows
+  int wsrc[kWin];
+  int sorg[kWin];
+  uint64_t Tp[16][16];                       // 4-bit tables: Proj during a scan, then y = x * Zc
+  uint64_t Ms[64];
+  uint64_t Li[64];
+  int mb_pos[kMbMax], mb_src[kMbMax];        // positions below the block that received a block row
+  int mb_n;
+  int scan_best;
+  unsigned long long scan_F;
+  int nmv;
+};
+// end-of-panel staging, placed over the (then dead) tables
+struct ChainMoved {
+  int64_t perm[kBlkMax + kMbMax];
+  int pos[kBlkMax + kMbMax];
+  int src[kBlkMax + kMbMax];
+};
+static_assert(sizeof(ChainMoved) <= sizeof(PanelTables), "staging fits in the table area");
+
+__device__ inline uint64_t proj4(const uint64_t (&T)[16][16], uint64_t x) {
+  uint64_t r = 0ull;
+#pragma unroll
+  for (int g = 0; g < 16; ++g) r ^= T[g][(x >> (4 * g)) & 15u];
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_chain(DecWork w, int q0, int s_eff, int flag_q0) {
+  __shared__ ChainShared sh;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t n = w.n, ldw = w.ldw;
   uint64_t *W = w.W;
-  const int b = q - q0;
 
-  if (q == q0) {  // first sub-panel of a panel: forget the previous panel's row list
+  {  // forget the previous panel's row list
     const int cnt = w.st->bp_count;
     for (int j = tid; j < cnt; j += 256) {
       const int p = w.bp_list[j];
@@ -203,368 +211,394 @@ __global__ __launch_bounds__(256) void k_panel(DecWork w, int q, int q0, int s_e
     __syncthreads();
     if (tid == 0) w.st->bp_count = 0;
   }
-  const int64_t R = w.st->R;
-  int nbits = (int)(w.m - 64ll * q);
-  if (nbits > 64) nbits = 64;
-  bool skip = R >= n;
+  const int64_t R0 = w.st->R;
+  bool skip = R0 >= n;
   if (flag_q0 >= 0 && w.nzflag[flag_q0] == 0u) skip = true;  // Schur complement already zero
   if (skip) {
-    if (tid < 64) {
-      w.Zc[(size_t)q * 64 + tid] = 0ull;
-      w.Linv[(size_t)q * 64 + tid] = 0ull;
-    }
-    if (tid == 0) {
-      w.sub[q].R = R;
-      w.sub[q].r = 0;
-      w.sub[q].pivmask = 0;
+    for (int b = 0; b < s_eff; ++b) {
+      if (tid < 64) {
+        w.Zc[(size_t)(q0 + b) * 64 + tid] = 0ull;
+        w.Linv[(size_t)(q0 + b) * 64 + tid] = 0ull;
+      }
+      if (tid == 0) {
+        w.sub[q0 + b].R = R0;
+        w.sub[q0 + b].r = 0;
+        w.sub[q0 + b].pivmask = 0ull;
+      }
     }
     return;
   }
-
-  // ---- tables of the earlier sub-panels, window rows brought to level b
-  build_panel_tables(pt, w, q0, s_eff, b, tid, 256);
-  if (tid == 0) {
-    nX = 0;
-    npo = 0;
+  const int nblk = (int)((n - R0) < (int64_t)(64 * s_eff + kWin) ? (n - R0) : (int64_t)(64 * s_eff + kWin));
+  for (int e = tid; e < nblk * kMaxPanelWords; e += 256) {
+    const int i = e >> 3, j = e & 7;
+    sh.blk[i][j] = j < s_eff ? W[widx(ldw, R0 + i, q0 + j)] : 0ull;
   }
-  if (tid < 128) po_bloom[tid] = 0u;
-  if (tid < kWin) {
-    const int64_t p = R + tid;
-    uint64_t x[kMaxPanelWords];
-#pragma unroll
-    for (int j = 0; j < kMaxPanelWords; ++j) x[j] = (p < n && j < s_eff) ? W[widx(ldw, p, q0 + j)] : 0ull;
-    if (p < n) panel_update(x, row_level(w, p, q0), b, s_eff - 1, pt);
-#pragma unroll
-    for (int j = 0; j < kMaxPanelWords; ++j) Wl[tid][j] = x[j];
-  }
+  for (int i = tid; i < nblk; i += 256) sh.bsrc[i] = (int)(R0 + i);
+  if (tid == 0) sh.mb_n = 0;
   __syncthreads();
 
-  const bool v0 = R + lane < n, v1 = R + 64 + lane < n;
-  // Window state of this wave: slot 64g + lane holds reduced word (lo, hi) and origin.
-  uint32_t a_lo = (uint32_t)Wl[lane][b], a_hi = (uint32_t)(Wl[lane][b] >> 32);
-  uint32_t b_lo = (uint32_t)Wl[64 + lane][b], b_hi = (uint32_t)(Wl[64 + lane][b] >> 32);
-  int org0 = lane, org1 = 64 + lane;
-  // Slots still free (at or after the next pivot position), as scalar lane masks.
-  uint64_t act0 = __ballot(v0), act1 = __ballot(v1);
-  uint64_t Mrow = 0ull, yM = 0ull, pivmask = 0ull, F = 0ull;
-  bool Fknown = false;
-  int ib = 0;
+  int wb = 0;  // block index of position Rb
+  for (int b = 0; b < s_eff; ++b) {
+    const int q = q0 + b;
+    const int64_t Rb = R0 + wb;
+    int nbits = (int)(w.m - 64ll * q);
+    if (nbits > 64) nbits = 64;
 
-  for (int k = 0; k < nbits; ++k) {
-    const uint64_t kb = 1ull << k;
-    const uint32_t bit = 1u << (k & 31);
-    uint64_t c0, c1;
-    if (k < 32) {
-      c0 = __ballot((a_lo & bit) != 0u) & act0;
-      c1 = __ballot((b_lo & bit) != 0u) & act1;
-    } else {
-      c0 = __ballot((a_hi & bit) != 0u) & act0;
-      c1 = __ballot((b_hi & bit) != 0u) & act1;
-    }
-    int sp = -1;
-    if (c0) sp = __builtin_ctzll(c0);
-    else if (c1) sp = 64 + __builtin_ctzll(c1);
-    uint64_t Mnew;
-    uint64_t rs0 = 0ull, rs1 = 0ull;  // slots to reduce by the new pivot row
-    if (sp >= 0) {
-      uint32_t p_lo, p_hi;
-      int p_org;
-      if (sp < 64) {
-        p_lo = __builtin_amdgcn_readlane(a_lo, sp);
-        p_hi = __builtin_amdgcn_readlane(a_hi, sp);
-        p_org = __builtin_amdgcn_readlane(org0, sp);
-      } else {
-        p_lo = __builtin_amdgcn_readlane(b_lo, sp - 64);
-        p_hi = __builtin_amdgcn_readlane(b_hi, sp - 64);
-        p_org = __builtin_amdgcn_readlane(org1, sp - 64);
+    // ---- window registers
+    const bool v0 = wb + lane < nblk, v1 = wb + 64 + lane < nblk;
+    uint32_t a_lo = 0u, a_hi = 0u, b_lo = 0u, b_hi = 0u;
+    if (v0) { const uint64_t x = sh.blk[wb + lane][b]; a_lo = (uint32_t)x; a_hi = (uint32_t)(x >> 32); }
+    if (v1) { const uint64_t x = sh.blk[wb + 64 + lane][b]; b_lo = (uint32_t)x; b_hi = (uint32_t)(x >> 32); }
+    int org0 = lane, org1 = 64 + lane;
+    uint64_t act0 = __ballot(v0), act1 = __ballot(v1);
+    uint32_t m_lo = 0u, m_hi = 0u, y_lo = 0u, y_hi = 0u;  // M_j and Zc row j (lane j)
+    uint64_t pivmask = 0ull, F = 0ull;
+    bool Fknown = false;
+    int ib = 0;
+
+    // pivot t = ib for bit k with reduced row (p_lo, p_hi): bookkeeping rows M
+    // (RREF of the pivots so far) and the coefficient map, free slots.
+    // mm: lanes j of earlier pivots whose M_j has bit k.
+    auto commit = [&](int k, uint32_t p_lo, uint32_t p_hi, uint64_t mm) {
+      const bool up = __builtin_amdgcn_inverse_ballot_w64(mm);
+      const uint64_t tb = 1ull << ib;
+      const uint32_t t_lo = (uint32_t)tb, t_hi = (uint32_t)(tb >> 32);
+      const uint32_t xm_lo = m_lo ^ p_lo, xm_hi = m_hi ^ p_hi, xy_lo = y_lo ^ t_lo, xy_hi = y_hi ^ t_hi;
+      m_lo = wrlane(p_lo, k, up ? xm_lo : m_lo);
+      m_hi = wrlane(p_hi, k, up ? xm_hi : m_hi);
+      y_lo = wrlane(t_lo, k, up ? xy_lo : y_lo);
+      y_hi = wrlane(t_hi, k, up ? xy_hi : y_hi);
+      const uint64_t kb = 1ull << k;
+      pivmask |= kb;
+      act0 &= ~tb;
+      if (Fknown) {
+        if (F & kb) F |= ((uint64_t)p_hi << 32) | p_lo;
+        F &= ~kb;
       }
-      if (sp != ib) {  // transposition: the row at ib moves to sp, the pivot to ib
-        uint32_t i_lo, i_hi;
-        int i_org;
-        if (ib < 64) {
-          i_lo = __builtin_amdgcn_readlane(a_lo, ib);
-          i_hi = __builtin_amdgcn_readlane(a_hi, ib);
-          i_org = __builtin_amdgcn_readlane(org0, ib);
-        } else {
-          i_lo = __builtin_amdgcn_readlane(b_lo, ib - 64);
-          i_hi = __builtin_amdgcn_readlane(b_hi, ib - 64);
-          i_org = __builtin_amdgcn_readlane(org1, ib - 64);
-        }
-        const uint64_t msp0 = sp < 64 ? 1ull << sp : 0ull, msp1 = sp >= 64 ? 1ull << (sp - 64) : 0ull;
-        const uint64_t mib0 = ib < 64 ? 1ull << ib : 0ull, mib1 = ib >= 64 ? 1ull << (ib - 64) : 0ull;
-        if (msp0 | mib0) {
-          const bool ws = __builtin_amdgcn_inverse_ballot_w64(msp0), wi = __builtin_amdgcn_inverse_ballot_w64(mib0);
-          a_lo = ws ? i_lo : (wi ? p_lo : a_lo);
-          a_hi = ws ? i_hi : (wi ? p_hi : a_hi);
-          org0 = ws ? i_org : (wi ? p_org : org0);
-        }
-        if (msp1 | mib1) {
-          const bool ws = __builtin_amdgcn_inverse_ballot_w64(msp1), wi = __builtin_amdgcn_inverse_ballot_w64(mib1);
-          b_lo = ws ? i_lo : (wi ? p_lo : b_lo);
-          b_hi = ws ? i_hi : (wi ? p_hi : b_hi);
-          org1 = ws ? i_org : (wi ? p_org : org1);
-        }
+      ++ib;
+    };
+
+    // Bits [k, kend) whose word half is fixed, while the first half of the
+    // window has a candidate (the common case); returns at the first bit where
+    // it has none.  The candidates other than the pivot are reduced by it, then
+    // the pivot moves to slot ib and the row of slot ib to the pivot's slot.
+    auto run_bits = [&](auto hi_tag, int &k, int kend) {
+      constexpr bool HI = decltype(hi_tag)::value;
+      for (; k < kend; ++k) {
+        const uint32_t bit = 1u << (k & 31);
+        const uint64_t c0 = __ballot(((HI ? a_hi : a_lo) & bit) != 0u) & act0;
+        if (c0 == 0ull) return;
+        const uint64_t c1 = __ballot(((HI ? b_hi : b_lo) & bit) != 0u) & act1;
+        const int sp = __builtin_ctzll(c0);
+        const uint32_t p_lo = __builtin_amdgcn_readlane(a_lo, sp), p_hi = __builtin_amdgcn_readlane(a_hi, sp);
+        const int p_org = __builtin_amdgcn_readlane(org0, sp);
+        const uint32_t i_lo = __builtin_amdgcn_readlane(a_lo, ib), i_hi = __builtin_amdgcn_readlane(a_hi, ib);
+        const int i_org = __builtin_amdgcn_readlane(org0, ib);
+        const bool r0 = __builtin_amdgcn_inverse_ballot_w64(c0 & ~(1ull << sp));
+        const bool r1 = __builtin_amdgcn_inverse_ballot_w64(c1);
+        const uint32_t xa_lo = a_lo ^ p_lo, xa_hi = a_hi ^ p_hi, xb_lo = b_lo ^ p_lo, xb_hi = b_hi ^ p_hi;
+        a_lo = r0 ? xa_lo : a_lo;
+        a_hi = r0 ? xa_hi : a_hi;
+        b_lo = r1 ? xb_lo : b_lo;
+        b_hi = r1 ? xb_hi : b_hi;
+        // (slot ib holds no candidate unless ib == sp; then both writes store the pivot)
+        a_lo = wrlane(p_lo, ib, wrlane(i_lo, sp, a_lo));
+        a_hi = wrlane(p_hi, ib, wrlane(i_hi, sp, a_hi));
+        org0 = wrlane(p_org, ib, wrlane(i_org, sp, org0));
+        commit(k, p_lo, p_hi, __ballot(((HI ? m_hi : m_lo) & bit) != 0u));
       }
-      Mnew = ((uint64_t)p_hi << 32) | p_lo;
-      // candidates other than the pivot itself (the row now at sp has bit k clear)
-      rs0 = c0 & ~(sp < 64 ? 1ull << sp : 0ull);
-      rs1 = c1 & ~(sp >= 64 ? 1ull << (sp - 64) : 0ull);
-    } else {
-      if (Fknown && !(F & kb)) continue;  // no row below the window can have bit k
-      // ---- scan the rows below the window (all threads)
+    };
+
+    // window permutation of the registers applied to the block rows (all threads)
+    auto materialize = [&]() {
       __syncthreads();
-      if (wv == 0) Ms[lane] = Mrow;
+      if (wv == 0) {
+        sh.sorg[lane] = org0;
+        sh.sorg[64 + lane] = org1;
+      }
+      __syncthreads();
+      for (int e = tid; e < kWin * kMaxPanelWords; e += 256) {
+        const int s = e >> 3, j = e & 7;
+        if (wb + s < nblk) {
+          sh.win[s][j] = sh.blk[wb + sh.sorg[s]][j];
+          if (j == 0) sh.wsrc[s] = sh.bsrc[wb + sh.sorg[s]];
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < kWin * kMaxPanelWords; e += 256) {
+        const int s = e >> 3, j = e & 7;
+        if (wb + s < nblk) {
+          sh.blk[wb + s][j] = sh.win[s][j];
+          if (j == 0) sh.bsrc[wb + s] = sh.wsrc[s];
+        }
+      }
+      org0 = lane;
+      org1 = 64 + lane;
+      __syncthreads();
+    };
+
+    int k = 0;
+    while (true) {
+      if (k < 32) run_bits(std::false_type{}, k, nbits < 32 ? nbits : 32);
+      if (k >= 32 && k < nbits) run_bits(std::true_type{}, k, nbits);
+      if (k >= nbits) break;
+      // ---- bit k: no candidate in the first half of the window
+      const uint32_t bit = 1u << (k & 31);
+      const uint64_t c1 = __ballot(((k < 32 ? b_lo : b_hi) & bit) != 0u) & act1;
+      if (c1) {  // pivot from the second half
+        const int sp = __builtin_ctzll(c1);
+        const uint32_t p_lo = __builtin_amdgcn_readlane(b_lo, sp), p_hi = __builtin_amdgcn_readlane(b_hi, sp);
+        const int p_org = __builtin_amdgcn_readlane(org1, sp);
+        const uint32_t i_lo = __builtin_amdgcn_readlane(a_lo, ib), i_hi = __builtin_amdgcn_readlane(a_hi, ib);
+        const int i_org = __builtin_amdgcn_readlane(org0, ib);
+        const bool r1 = __builtin_amdgcn_inverse_ballot_w64(c1 & ~(1ull << sp));
+        b_lo = r1 ? b_lo ^ p_lo : b_lo;
+        b_hi = r1 ? b_hi ^ p_hi : b_hi;
+        b_lo = wrlane(i_lo, sp, b_lo);
+        b_hi = wrlane(i_hi, sp, b_hi);
+        org1 = wrlane(i_org, sp, org1);
+        a_lo = wrlane(p_lo, ib, a_lo);
+        a_hi = wrlane(p_hi, ib, a_hi);
+        org0 = wrlane(p_org, ib, org0);
+        commit(k, p_lo, p_hi, __ballot(((k < 32 ? m_lo : m_hi) & bit) != 0u));
+        ++k;
+        continue;
+      }
+      if (Fknown && !((F >> k) & 1ull)) {  // no row below the window can have bit k
+        ++k;
+        continue;
+      }
+      // ---- bit k: no window row has it; scan the rows below the window (all threads)
+      const uint64_t kb = 1ull << k;
+      materialize();
+      if (wv == 0) sh.Ms[lane] = ((uint64_t)m_hi << 32) | m_lo;
       if (tid == 0) {
-        scan_best = 0x7fffffff;
-        scan_F = 0ull;
+        sh.scan_best = 0x7fffffff;
+        sh.scan_F = 0ull;
       }
       __syncthreads();
-      for (int e = tid; e < 8 * 256; e += 256) {
-        const int g = e >> 8, idx = e & 255;
-        uint64_t v = 0ull;
+      {
+        const int g = tid >> 4, v = tid & 15;
+        uint64_t acc = 0ull;
 #pragma unroll
-        for (int bb = 0; bb < 8; ++bb)
-          if (idx & (1 << bb)) v ^= Ms[8 * g + bb];
-        Tp[g][idx] = v;
+        for (int bb = 0; bb < 4; ++bb)
+          if (v & (1 << bb)) acc ^= sh.Ms[4 * g + bb];
+        sh.Tp[g][v] = acc;
       }
       __syncthreads();
       int best = 0x7fffffff;
       uint64_t Floc = 0ull;
-      for (int64_t p = R + kWin + tid; p < n; p += 256) {
+      for (int64_t p = Rb + kWin + tid; p < n; p += 256) {
         uint64_t xq;
-        int o = -1;
-        if ((po_bloom[(p >> 5) & 127] >> (p & 31)) & 1u)
-          for (int j = 0; j < npo; ++j)
-            if (po_pos[j] == (int)p) o = po_org[j];
-        if (o >= 0) {
-          xq = o < kWin ? Wl[o][b] : Xr[o - kWin][b];
+        if (p - R0 < nblk) {
+          xq = sh.blk[p - R0][b];
         } else {
           uint64_t x[kMaxPanelWords];
 #pragma unroll
           for (int j = 0; j < kMaxPanelWords; ++j) x[j] = j <= b ? W[widx(ldw, p, q0 + j)] : 0ull;
-          panel_update(x, row_level(w, p, q0), b, b, pt);
+          panel_update(x, row_level(w, p, q0), b, b, sh.pt);
           xq = x[0];
 #pragma unroll
           for (int j = 1; j < kMaxPanelWords; ++j)
             if (j == b) xq = x[j];
         }
-        uint64_t pr = xq;
-#pragma unroll
-        for (int g = 0; g < 8; ++g) pr ^= Tp[g][(xq >> (8 * g)) & 255u];
+        const uint64_t pr = xq ^ proj4(sh.Tp, xq);
         Floc |= pr;
         if ((pr & kb) && (int)p < best) best = (int)p;
       }
-      if (best != 0x7fffffff) atomicMin(&scan_best, best);
-      if (Floc) atomicOr(&scan_F, (unsigned long long)Floc);
+      if (best != 0x7fffffff) atomicMin(&sh.scan_best, best);
+      if (Floc) atomicOr(&sh.scan_F, (unsigned long long)Floc);
       __syncthreads();
-      best = scan_best;
-      F = scan_F;
+      best = __builtin_amdgcn_readfirstlane(sh.scan_best);
+      {
+        const unsigned long long fv = sh.scan_F;
+        F = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(fv >> 32)) << 32) |
+            (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)fv);
+      }
       Fknown = true;
-      if (best == 0x7fffffff) continue;
-      // ---- bring the row at `best` into slot ib; the slot's row goes to position `best`
-      int oin = -1;
-      for (int j = 0; j < npo; ++j)
-        if (po_pos[j] == best) oin = po_org[j];
-      int oout;
-      uint64_t xro;
-      if (ib < 64) {
-        oout = __builtin_amdgcn_readlane(org0, ib);
-        xro = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(a_hi, ib) << 32) | (uint32_t)__builtin_amdgcn_readlane(a_lo, ib);
-      } else {
-        oout = __builtin_amdgcn_readlane(org1, ib - 64);
-        xro = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(b_hi, ib - 64) << 32) |
-              (uint32_t)__builtin_amdgcn_readlane(b_lo, ib - 64);
-      }
-      __syncthreads();
-      if (oin < 0 && tid == 0) {  // a row never seen: load it and bring it to level b
-        const int j = nX;
-        uint64_t x[kMaxPanelWords];
+      if (best != 0x7fffffff) {
+        // position `best` and slot ib (position Rb + ib) exchange their rows
+        const uint64_t xro = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(a_hi, ib) << 32) |
+                             (uint32_t)__builtin_amdgcn_readlane(a_lo, ib);
+        const int si = wb + ib;
+        if (best - R0 < nblk) {
+          const int bi = (int)(best - R0);
+          if (tid < kMaxPanelWords) {
+            const uint64_t t0 = sh.blk[bi][tid], t1 = sh.blk[si][tid];
+            sh.blk[bi][tid] = t1;
+            sh.blk[si][tid] = t0;
+          }
+          if (tid == 0) {
+            const int s0 = sh.bsrc[bi];
+            sh.bsrc[bi] = sh.bsrc[si];
+            sh.bsrc[si] = s0;
+          }
+        } else if (tid == 0) {
+          // a row below the block: bring it to level b; the slot's row takes its
+          // place in HBM at level b
+          uint64_t x[kMaxPanelWords];
 #pragma unroll
-        for (int jj = 0; jj < kMaxPanelWords; ++jj) x[jj] = jj < s_eff ? W[widx(ldw, best, q0 + jj)] : 0ull;
-        panel_update(x, row_level(w, best, q0), b, s_eff - 1, pt);
+          for (int j = 0; j < kMaxPanelWords; ++j) x[j] = j < s_eff ? W[widx(ldw, best, q0 + j)] : 0ull;
+          panel_update(x, row_level(w, best, q0), b, s_eff - 1, sh.pt);
+          for (int j = 0; j < s_eff; ++j) W[widx(ldw, best, q0 + j)] = sh.blk[si][j];
+          w.lvl[best] = (q0 << 4) | b;
+          int e = 0;
+          while (e < sh.mb_n && sh.mb_pos[e] != best) ++e;
+          const int src_in = e < sh.mb_n ? sh.mb_src[e] : best;
+          if (e == sh.mb_n) {
+            sh.mb_pos[e] = best;
+            sh.mb_n = e + 1;
+          }
+          sh.mb_src[e] = sh.bsrc[si];
 #pragma unroll
-        for (int jj = 0; jj < kMaxPanelWords; ++jj) Xr[j][jj] = x[jj];
-        Xsrc[j] = best;
-        nX = j + 1;
-      }
-      if (tid == 0) {
-        int j = 0;
-        while (j < npo && po_pos[j] != best) ++j;
-        if (j == npo) {
-          po_pos[j] = best;
-          npo = j + 1;
-          po_bloom[(best >> 5) & 127] |= 1u << (best & 31);
+          for (int j = 0; j < kMaxPanelWords; ++j) sh.blk[si][j] = x[j];
+          sh.bsrc[si] = src_in;
         }
-        po_org[j] = oout;
+        __syncthreads();
+        const uint64_t xin = sh.blk[si][b];
+        const uint64_t xrp = xin ^ proj4(sh.Tp, xin);
+        a_lo = wrlane((uint32_t)xrp, ib, a_lo);
+        a_hi = wrlane((uint32_t)(xrp >> 32), ib, a_hi);
+        F |= xro;
+        commit(k, (uint32_t)xrp, (uint32_t)(xrp >> 32),
+               __ballot(((k < 32 ? m_lo : m_hi) & (1u << (k & 31))) != 0u));
       }
-      __syncthreads();
-      if (oin < 0) oin = kWin + nX - 1;
-      const uint64_t xin = oin < kWin ? Wl[oin][b] : Xr[oin - kWin][b];
-      uint64_t xrp = xin;
-#pragma unroll
-      for (int g = 0; g < 8; ++g) xrp ^= Tp[g][(xin >> (8 * g)) & 255u];
-      if (ib < 64) {
-        if (lane == ib) { a_lo = (uint32_t)xrp; a_hi = (uint32_t)(xrp >> 32); org0 = oin; }
-      } else {
-        if (lane == ib - 64) { b_lo = (uint32_t)xrp; b_hi = (uint32_t)(xrp >> 32); org1 = oin; }
-      }
-      F |= xro;
-      Mnew = xrp;
+      ++k;
     }
-    // ---- pivot t = ib for bit k: bookkeeping rows (RREF), their multipliers, the window
-    pivmask |= kb;
-    const uint64_t tb = 1ull << ib;
-    {
-      const uint64_t mm = __ballot((Mrow & kb) != 0ull);  // earlier pivots with bit k set
-      const bool upd = __builtin_amdgcn_inverse_ballot_w64(mm);
-      const bool me = __builtin_amdgcn_inverse_ballot_w64(kb);  // lane k
-      Mrow = me ? Mnew : (upd ? Mrow ^ Mnew : Mrow);
-      yM = me ? tb : (upd ? yM ^ tb : yM);
-    }
-    {
-      const uint32_t n_lo = (uint32_t)Mnew, n_hi = (uint32_t)(Mnew >> 32);
-      if (rs0) {
-        const bool r0 = __builtin_amdgcn_inverse_ballot_w64(rs0);
-        a_lo = r0 ? a_lo ^ n_lo : a_lo;
-        a_hi = r0 ? a_hi ^ n_hi : a_hi;
-      }
-      if (rs1) {
-        const bool r1 = __builtin_amdgcn_inverse_ballot_w64(rs1);
-        b_lo = r1 ? b_lo ^ n_lo : b_lo;
-        b_hi = r1 ? b_hi ^ n_hi : b_hi;
-      }
-    }
-    if (ib < 64) act0 &= ~(1ull << ib);
-    else act1 &= ~(1ull << (ib - 64));
-    if (Fknown) {
-      if (F & kb) F |= Mnew;
-      F &= ~kb;
-    }
-    ++ib;
-  }
-  const int r = ib;
-  const uint64_t xr0 = ((uint64_t)a_hi << 32) | a_lo;  // lane t < r: E_t
+    const int r = ib;
+    const uint64_t yM = ((uint64_t)y_hi << 32) | y_lo;
+    const uint64_t xr0 = ((uint64_t)a_hi << 32) | a_lo;  // lane t < r: E_t restricted to word q
+    materialize();
 
-  // ---- multipliers of the pivot rows (unit lower block L_pp) from the coefficient
-  // map: the current word b of pivot row t is in the span of E_0..E_t, so
-  // y = word * Zc lists its multipliers (bit t set).  Then the block's inverse.
-  if (wv == 0) Ms[lane] = yM;
-  __syncthreads();
-  {
-    const int g = tid >> 4, v = tid & 15;
-    uint64_t acc = 0ull;
+    // ---- multipliers of the pivot rows (unit lower block L_pp) from the
+    // coefficient map: word q of pivot row t at level b lies in the span of
+    // E_0..E_t, so y = word * Zc lists its multipliers (bit t set).  Then the
+    // block's inverse.
+    if (wv == 0) sh.Ms[lane] = yM;
+    __syncthreads();
+    {
+      const int g = tid >> 4, v = tid & 15;
+      uint64_t acc = 0ull;
 #pragma unroll
-    for (int bb = 0; bb < 4; ++bb)
-      if (v & (1 << bb)) acc ^= Ms[4 * g + bb];
-    Tp[0][tid] = acc;  // table g = tid >> 4 of 16 entries
-  }
-  __syncthreads();
-  const int myorg = org0;
-  uint64_t yx = 0ull;
-  if (lane < r) {
-    const uint64_t xb = myorg < kWin ? Wl[myorg][b] : Xr[myorg - kWin][b];
-#pragma unroll
-    for (int g = 0; g < 16; ++g) yx ^= Tp[0][16 * g + ((xb >> (4 * g)) & 15u)];
-  }
-  uint64_t li = lane < r ? (1ull << lane) : 0ull;
-  for (int t = 0; t < r; ++t) {
-    const uint64_t row = rdl64(li, t);
-    if (lane > t && lane < r && ((yx >> t) & 1ull)) li ^= row;
-  }
-
-  // ---- rows to write back: every window position, then positions below it now
-  // holding a window row
-  if (wv == 0) {
-    if (v0) sorg[lane] = org0;
-    if (v1) sorg[64 + lane] = org1;
-    w.Zc[(size_t)q * 64 + lane] = yM;
-    w.Linv[(size_t)q * 64 + lane] = li;
-    if ((pivmask >> lane) & 1ull) {
-      const int t = __popcll(pivmask & ((1ull << lane) - 1ull));
-      w.pivcols[R + t] = 64ll * q + lane;
+      for (int bb = 0; bb < 4; ++bb)
+        if (v & (1 << bb)) acc ^= sh.Ms[4 * g + bb];
+      sh.Tp[g][v] = acc;
     }
-  }
-  __syncthreads();
-  {
-    const int nvalid = (n - R) < kWin ? (int)(n - R) : kWin;
-    if (tid < nvalid) {
-      wr_pos[tid] = (int)(R + tid);
-      wr_org[tid] = sorg[tid];
-    }
-    if (tid < npo) {
-      wr_pos[nvalid + tid] = po_pos[tid];
-      wr_org[nvalid + tid] = po_org[tid];
-    }
-    if (tid == 0) nwr = nvalid + npo;
-  }
-  for (int e = tid; e < r * kMaxPanelWords; e += 256) {
-    const int t = e / kMaxPanelWords, j = e % kMaxPanelWords;
-    const int o = sorg[t];
-    Praw[t][j] = o < kWin ? Wl[o][j] : Xr[o - kWin][j];
-  }
-  __syncthreads();
-  const int nw = nwr;
-  // perm / panel-start positions of the rows that moved (gather, then scatter)
-  for (int e = tid; e < nw; e += 256) {
-    const int o = wr_org[e];
-    const int src = o < kWin ? (int)(R + o) : Xsrc[o - kWin];
-    gperm[e] = w.perm[src];
-    gbp[e] = w.bp_src[src];
-  }
-  __syncthreads();
-  {
-    int dst = 0;
-    bool fresh = false;
-    if (tid < nw) {
-      const int o = wr_org[tid];
-      const int src = o < kWin ? (int)(R + o) : Xsrc[o - kWin];
-      dst = wr_pos[tid];
-      if (src != dst) {
-        w.perm[dst] = gperm[tid];
-        w.bp_src[dst] = gbp[tid];
-        fresh = w.bp_mark[dst] == 0;
-        if (fresh) w.bp_mark[dst] = 1;
+    __syncthreads();
+    uint64_t yx = 0ull, li = 0ull;
+    if (wv == 0) {
+      if (lane < r) yx = proj4(sh.Tp, sh.blk[wb + lane][b]);
+      li = lane < r ? (1ull << lane) : 0ull;
+      for (int t = 0; t < r; ++t) {
+        const uint64_t row = rdl64(li, t);
+        if (lane > t && lane < r && ((yx >> t) & 1ull)) li ^= row;
+      }
+      sh.Li[lane] = li;
+      w.Zc[(size_t)q * 64 + lane] = yM;
+      w.Linv[(size_t)q * 64 + lane] = li;
+      if ((pivmask >> lane) & 1ull) {
+        const int t = __popcll(pivmask & ((1ull << lane) - 1ull));
+        w.pivcols[Rb + t] = 64ll * q + lane;
+      }
+      if (lane == 0) {
+        w.sub[q].R = Rb;
+        w.sub[q].r = r;
+        w.sub[q].pivmask = pivmask;
       }
     }
-    const uint64_t fm = __ballot(fresh);
-    if (lane == 0) wave_new[wv] = __popcll(fm);
     __syncthreads();
-    if (tid == 0) list_base = atomicAdd(&w.st->bp_count, wave_new[0] + wave_new[1] + wave_new[2] + wave_new[3]);
+    // ---- pivot rows in final form: word q = E_t | L_pp bits left of t; later
+    // panel words = L_pp^{-1} * (pivot rows at level b)
+    for (int e = tid; e < r * kMaxPanelWords; e += 256) {
+      const int t = e >> 3, j = e & 7;
+      if (j > b && j < s_eff) {
+        const uint64_t l = sh.Li[t];
+        uint64_t acc = 0ull;
+        for (int u = 0; u < r; ++u)
+          if ((l >> u) & 1ull) acc ^= sh.blk[wb + u][j];
+        sh.win[t][j] = acc;
+      }
+    }
     __syncthreads();
-    int at = list_base + __popcll(fm & ((1ull << lane) - 1ull));
-    for (int v = 0; v < wv; ++v) at += wave_new[v];
-    if (fresh) w.bp_list[at] = dst;
+    for (int e = tid; e < r * kMaxPanelWords; e += 256) {
+      const int t = e >> 3, j = e & 7;
+      if (j > b && j < s_eff) sh.blk[wb + t][j] = sh.win[t][j];
+    }
+    if (wv == 0 && lane < r) sh.blk[wb + lane][b] = xr0 | (yx & ((1ull << lane) - 1ull));
+    __syncthreads();
+    // ---- tables of sub-panel b, then every block row below its pivots gets it
+    {
+      const int g = tid >> 4, v = tid & 15;
+      uint64_t acc = 0ull;
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+        if (v & (1 << bb)) acc ^= sh.Ms[4 * g + bb];
+      sh.pt.Tz[b][g][v] = acc;
+    }
+    for (int e = tid; e < (s_eff - 1 - b) * 256; e += 256) {
+      const int wd = b + 1 + (e >> 8), g = (e >> 4) & 15, v = e & 15;
+      uint64_t acc = 0ull;
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+        if ((v & (1 << bb)) && 4 * g + bb < r) acc ^= sh.blk[wb + 4 * g + bb][wd];
+      sh.pt.Te[pidx(b, wd)][g][v] = acc;
+    }
+    __syncthreads();
+    for (int i = wb + r + tid; i < nblk; i += 256) {
+      uint64_t x[kMaxPanelWords];
+#pragma unroll
+      for (int j = 0; j < kMaxPanelWords; ++j) x[j] = sh.blk[i][j];
+      panel_update(x, b, b + 1, s_eff - 1, sh.pt);
+#pragma unroll
+      for (int j = 0; j < kMaxPanelWords; ++j) sh.blk[i][j] = x[j];
+    }
+    __syncthreads();
+    wb += r;
   }
-  // panel words of every written row; pivot rows: multipliers left of b, E | L_pp at b,
-  // echelon words right of b
-  for (int e = tid; e < nw * s_eff; e += 256) {
-    const int i = e / s_eff, j = e - i * s_eff;
-    const int dst = wr_pos[i];
-    const int o = wr_org[i];
-    if (dst - R < r && j >= b) continue;  // pivot rows, words b.. written below
-    W[widx(ldw, dst, q0 + j)] = o < kWin ? Wl[o][j] : Xr[o - kWin][j];
+
+  // ---- block rows back to HBM; every row below the pivots is at level s
+  for (int e = tid; e < nblk * kMaxPanelWords; e += 256) {
+    const int i = e >> 3, j = e & 7;
+    if (j < s_eff) W[widx(ldw, R0 + i, q0 + j)] = sh.blk[i][j];
   }
-  for (int e = tid; e < nw; e += 256) {
-    const int dst = wr_pos[e];
-    w.lvl[dst] = dst - R < r ? (q0 << 4) | 15 : (q0 << 4) | b;
+  for (int i = tid; i < nblk; i += 256) w.lvl[R0 + i] = i < wb ? (q0 << 4) | 15 : (q0 << 4) | s_eff;
+  // ---- permutation bookkeeping of every position whose row changed
+  ChainMoved &mv = *reinterpret_cast<ChainMoved *>(&sh.pt);
+  if (tid == 0) sh.nmv = 0;
+  __syncthreads();
+  for (int i = tid; i < nblk + sh.mb_n; i += 256) {
+    int pos, src;
+    if (i < nblk) {
+      pos = (int)(R0 + i);
+      src = sh.bsrc[i];
+    } else {
+      pos = sh.mb_pos[i - nblk];
+      src = sh.mb_src[i - nblk];
+    }
+    if (pos != src) {
+      const int e = atomicAdd(&sh.nmv, 1);
+      mv.pos[e] = pos;
+      mv.src[e] = src;
+      mv.perm[e] = w.perm[src];
+    }
   }
-  if (wv == 0 && lane < r) W[widx(ldw, R + lane, q)] = xr0 | (yx & ((1ull << lane) - 1ull));
-  for (int j = b + 1 + wv; j < s_eff; j += 4) {
-    uint64_t acc = 0ull;
-    for (int t = 0; t < r; ++t)
-      if ((li >> t) & 1ull) acc ^= Praw[t][j];
-    if (lane < r) W[widx(ldw, R + lane, q0 + j)] = acc;
+  __syncthreads();
+  const int nmv = sh.nmv;
+  for (int e = tid; e < nmv; e += 256) {
+    const int pos = mv.pos[e];
+    w.perm[pos] = mv.perm[e];
+    w.bp_src[pos] = mv.src[e];
+    w.bp_mark[pos] = 1;
+    w.bp_list[e] = pos;
   }
   if (tid == 0) {
-    w.sub[q].R = R;
-    w.sub[q].r = r;
-    w.sub[q].pivmask = pivmask;
-    w.st->R = R + r;
+    w.st->bp_count = nmv;
+    w.st->R = R0 + wb;
   }
 }
 
-hipError_t launch_panel(const DecWork &w, int q, int q0, int s_eff, int flag_q0, hipStream_t s) {
-  hipLaunchKernelGGL(k_panel, dim3(1), dim3(256), 0, s, w, q, q0, s_eff, flag_q0);
+hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, hipStream_t s) {
+  hipLaunchKernelGGL(k_chain, dim3(1), dim3(256), 0, s, w, q0, s_eff, flag_q0);
   return hipGetLastError();
 }
 
@@ -575,11 +609,12 @@ constexpr int kRowsThreads = 256;
 constexpr int kRowsPerThread = 2;
 __global__ __launch_bounds__(kRowsThreads) void k_rows_panel(DecWork w, int q0, int s_eff) {
   __shared__ PanelTables pt;
+  __shared__ TableSrc src;
   const SubInfo last = w.sub[q0 + s_eff - 1];
   const int64_t rowbeg = last.R + last.r;
   const int64_t blk0 = (int64_t)blockIdx.x * kRowsThreads * kRowsPerThread;
   if (blk0 + kRowsThreads * kRowsPerThread <= rowbeg || blk0 >= w.n) return;
-  build_panel_tables(pt, w, q0, s_eff, s_eff, threadIdx.x, kRowsThreads);
+  build_panel_tables(pt, src, w, q0, s_eff, s_eff, threadIdx.x, kRowsThreads);
   for (int u = 0; u < kRowsPerThread; ++u) {
     const int64_t i = blk0 + (int64_t)u * kRowsThreads + threadIdx.x;
     if (i < rowbeg || i >= w.n) continue;
