@@ -28,6 +28,14 @@ namespace gf2 {
 // through an empty asm statement so that the compiler forms the 64 per-row
 // addresses next to their loads and stores instead of keeping them alive
 // across the inner loop (which spilled registers to scratch).
+// x ^ y ^ z on each 32-bit half with one three-input bitwise instruction
+// (truth table 0x96 is the three-way exclusive or).
+__device__ inline uint64_t xor3(uint64_t x, uint64_t y, uint64_t z) {
+  const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)x, (uint32_t)y, (uint32_t)z, 0x96);
+  const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(x >> 32), (uint32_t)(y >> 32), (uint32_t)(z >> 32), 0x96);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 template <int RPL, int S>
 __device__ inline void lane_rows(int64_t tile0, int l0, int64_t rb, int64_t re, int &ulo, int &uhi) {
   const int64_t b = tile0 + l0;
@@ -181,7 +189,7 @@ __global__ __launch_bounds__(NT) void k_gemm_quad(GemmArgs a) {
           t[v][g] = *(const uint64_t *)(Tb + addr);
         }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u0 + v] ^= (t[v][0] ^ t[v][1]) ^ (t[v][2] ^ t[v][3]);
+      for (int v = 0; v < 4; ++v) acc[u0 + v] = xor3(xor3(acc[u0 + v], t[v][0], t[v][1]), t[v][2], t[v][3]);
     }
   }
 
@@ -329,7 +337,7 @@ __global__ __launch_bounds__(NT) void k_gemm_db(GemmArgs a) {
           t[v][s2] = *(const uint64_t *)(Tb + addr);
         }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u0 + v] ^= t[v][0] ^ t[v][1];
+      for (int v = 0; v < 4; ++v) acc[u0 + v] = xor3(acc[u0 + v], t[v][0], t[v][1]);
     }
   }
 

@@ -163,15 +163,18 @@ __device__ inline int row_level(const DecWork &w, int64_t p, int q0) {
 // such rows can still have, so a zero tail costs one scan per sub-panel.
 constexpr int kBlkMax = 64 * kMaxPanelWords + kWin;  // block rows
 constexpr int kMbMax = 64 * kMaxPanelWords;          // rows moved below the block per panel
+constexpr int kChainThreads = 512;
 
 struct ChainShared {
   PanelTables pt;                            // tables of the panel's finished sub-panels
   uint64_t blk[kBlkMax][kMaxPanelWords];     // block rows: panel words, level = current sub-panel
   int bsrc[kBlkMax];                         // panel-start position of the row at block index i
   uint64_t win[kWin][kMaxPanelWords];        // staging for window permutations and pivot rows
+  uint64_t Pt[kMaxPanelWords - 1][16][16];   // 4-bit tables of the pivot rows before the solve
   int wsrc[kWin];
   int sorg[kWin];
   uint64_t Tp[16][16];                       // 4-bit tables: Proj during a scan, then y = x * Zc
+  uint64_t Tw[16][16];                       // Proj tables private to the pivot wave
   uint64_t Ms[64];
   uint64_t Li[64];
   int mb_pos[kMbMax], mb_src[kMbMax];        // positions below the block that received a block row
@@ -179,6 +182,7 @@ struct ChainShared {
   int scan_best;
   unsigned long long scan_F;
   int nmv;
+  int ctl_need, ctl_k, ctl_ib;
 };
 // end-of-panel staging, placed over the (then dead) tables
 struct ChainMoved {
@@ -195,26 +199,37 @@ __device__ inline uint64_t proj4(const uint64_t (&T)[16][16], uint64_t x) {
   return r;
 }
 
-__global__ __launch_bounds__(256) void k_chain(DecWork w, int q0, int s_eff, int flag_q0) {
+// 16 tables of 16 entries over the 64 words src[0..63] (entry v of table g = XOR
+// of src[4g + bit] for the set bits of v); one entry per thread of the range.
+__device__ inline uint64_t table4_entry(const uint64_t *src, int e) {
+  const int g = e >> 4, v = e & 15;
+  uint64_t acc = 0ull;
+#pragma unroll
+  for (int bb = 0; bb < 4; ++bb)
+    if (v & (1 << bb)) acc ^= src[4 * g + bb];
+  return acc;
+}
+
+__global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int s_eff, int flag_q0) {
+  constexpr int NT = kChainThreads;
   __shared__ ChainShared sh;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // (wave index made visibly uniform, so the pivot wave's loop stays scalar)
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t n = w.n, ldw = w.ldw;
   uint64_t *W = w.W;
 
-  {  // forget the previous panel's row list
-    const int cnt = w.st->bp_count;
-    for (int j = tid; j < cnt; j += 256) {
-      const int p = w.bp_list[j];
-      w.bp_src[p] = p;
-      w.bp_mark[p] = 0;
-    }
+  const int64_t R0 = w.st->R;
+  const int cnt = w.st->bp_count;
+  const uint32_t nz = flag_q0 >= 0 ? w.nzflag[flag_q0] : 1u;
+  // forget the previous panel's row list
+  for (int j = tid; j < cnt; j += NT) {
+    const int p = w.bp_list[j];
+    w.bp_src[p] = p;
+    w.bp_mark[p] = 0;
+  }
+  if (R0 >= n || nz == 0u) {  // no rows left, or the Schur complement is already zero
     __syncthreads();
     if (tid == 0) w.st->bp_count = 0;
-  }
-  const int64_t R0 = w.st->R;
-  bool skip = R0 >= n;
-  if (flag_q0 >= 0 && w.nzflag[flag_q0] == 0u) skip = true;  // Schur complement already zero
-  if (skip) {
     for (int b = 0; b < s_eff; ++b) {
       if (tid < 64) {
         w.Zc[(size_t)(q0 + b) * 64 + tid] = 0ull;
@@ -229,13 +244,44 @@ __global__ __launch_bounds__(256) void k_chain(DecWork w, int q0, int s_eff, int
     return;
   }
   const int nblk = (int)((n - R0) < (int64_t)(64 * s_eff + kWin) ? (n - R0) : (int64_t)(64 * s_eff + kWin));
-  for (int e = tid; e < nblk * kMaxPanelWords; e += 256) {
-    const int i = e >> 3, j = e & 7;
-    sh.blk[i][j] = j < s_eff ? W[widx(ldw, R0 + i, q0 + j)] : 0ull;
+  {
+    constexpr int PER = kBlkMax * kMaxPanelWords / NT;
+    uint64_t v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * NT, i = e >> 3, j = e & 7;
+      v[u] = (i < nblk && j < s_eff) ? W[widx(ldw, R0 + i, q0 + j)] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * NT, i = e >> 3, j = e & 7;
+      if (i < nblk) sh.blk[i][j] = v[u];
+    }
   }
-  for (int i = tid; i < nblk; i += 256) sh.bsrc[i] = (int)(R0 + i);
+  for (int i = tid; i < nblk; i += NT) sh.bsrc[i] = (int)(R0 + i);
   if (tid == 0) sh.mb_n = 0;
   __syncthreads();
+  if (tid == 0) w.st->bp_count = 0;
+
+  // window permutation (sorg, written by the pivot wave) applied to the block rows
+  auto materialize = [&](int wb) {
+    for (int e = tid; e < kWin * kMaxPanelWords; e += NT) {
+      const int s = e >> 3, j = e & 7;
+      if (wb + s < nblk) {
+        sh.win[s][j] = sh.blk[wb + sh.sorg[s]][j];
+        if (j == 0) sh.wsrc[s] = sh.bsrc[wb + sh.sorg[s]];
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < kWin * kMaxPanelWords; e += NT) {
+      const int s = e >> 3, j = e & 7;
+      if (wb + s < nblk) {
+        sh.blk[wb + s][j] = sh.win[s][j];
+        if (j == 0) sh.bsrc[wb + s] = sh.wsrc[s];
+      }
+    }
+    __syncthreads();
+  };
 
   int wb = 0;  // block index of position Rb
   for (int b = 0; b < s_eff; ++b) {
@@ -244,17 +290,24 @@ __global__ __launch_bounds__(256) void k_chain(DecWork w, int q0, int s_eff, int
     int nbits = (int)(w.m - 64ll * q);
     if (nbits > 64) nbits = 64;
 
-    // ---- window registers
-    const bool v0 = wb + lane < nblk, v1 = wb + 64 + lane < nblk;
+    // ---- pivot-wave state.  Slot s of the window is position Rb + s; the
+    // first half (slots 0..63) is kept reduced by every pivot, the second half
+    // holds rows that are reduced on demand (Proj) when the first half has no
+    // candidate.
     uint32_t a_lo = 0u, a_hi = 0u, b_lo = 0u, b_hi = 0u;
-    if (v0) { const uint64_t x = sh.blk[wb + lane][b]; a_lo = (uint32_t)x; a_hi = (uint32_t)(x >> 32); }
-    if (v1) { const uint64_t x = sh.blk[wb + 64 + lane][b]; b_lo = (uint32_t)x; b_hi = (uint32_t)(x >> 32); }
     int org0 = lane, org1 = 64 + lane;
-    uint64_t act0 = __ballot(v0), act1 = __ballot(v1);
+    uint64_t act0 = 0ull, act1 = 0ull;
     uint32_t m_lo = 0u, m_hi = 0u, y_lo = 0u, y_hi = 0u;  // M_j and Zc row j (lane j)
     uint64_t pivmask = 0ull, F = 0ull;
     bool Fknown = false;
     int ib = 0;
+    if (wv == 0) {
+      const bool v0 = wb + lane < nblk, v1 = wb + 64 + lane < nblk;
+      if (v0) { const uint64_t x = sh.blk[wb + lane][b]; a_lo = (uint32_t)x; a_hi = (uint32_t)(x >> 32); }
+      if (v1) { const uint64_t x = sh.blk[wb + 64 + lane][b]; b_lo = (uint32_t)x; b_hi = (uint32_t)(x >> 32); }
+      act0 = __ballot(v0);
+      act1 = __ballot(v1);
+    }
 
     // pivot t = ib for bit k with reduced row (p_lo, p_hi): bookkeeping rows M
     // (RREF of the pivots so far) and the coefficient map, free slots.
@@ -288,19 +341,15 @@ __global__ __launch_bounds__(256) void k_chain(DecWork w, int q0, int s_eff, int
         const uint32_t bit = 1u << (k & 31);
         const uint64_t c0 = __ballot(((HI ? a_hi : a_lo) & bit) != 0u) & act0;
         if (c0 == 0ull) return;
-        const uint64_t c1 = __ballot(((HI ? b_hi : b_lo) & bit) != 0u) & act1;
         const int sp = __builtin_ctzll(c0);
         const uint32_t p_lo = __builtin_amdgcn_readlane(a_lo, sp), p_hi = __builtin_amdgcn_readlane(a_hi, sp);
         const int p_org = __builtin_amdgcn_readlane(org0, sp);
         const uint32_t i_lo = __builtin_amdgcn_readlane(a_lo, ib), i_hi = __builtin_amdgcn_readlane(a_hi, ib);
         const int i_org = __builtin_amdgcn_readlane(org0, ib);
         const bool r0 = __builtin_amdgcn_inverse_ballot_w64(c0 & ~(1ull << sp));
-        const bool r1 = __builtin_amdgcn_inverse_ballot_w64(c1);
-        const uint32_t xa_lo = a_lo ^ p_lo, xa_hi = a_hi ^ p_hi, xb_lo = b_lo ^ p_lo, xb_hi = b_hi ^ p_hi;
+        const uint32_t xa_lo = a_lo ^ p_lo, xa_hi = a_hi ^ p_hi;
         a_lo = r0 ? xa_lo : a_lo;
         a_hi = r0 ? xa_hi : a_hi;
-        b_lo = r1 ? xb_lo : b_lo;
-        b_hi = r1 ? xb_hi : b_hi;
         // (slot ib holds no candidate unless ib == sp; then both writes store the pivot)
         a_lo = wrlane(p_lo, ib, wrlane(i_lo, sp, a_lo));
         a_hi = wrlane(p_hi, ib, wrlane(i_hi, sp, a_hi));
@@ -309,86 +358,80 @@ __global__ __launch_bounds__(256) void k_chain(DecWork w, int q0, int s_eff, int
       }
     };
 
-    // window permutation of the registers applied to the block rows (all threads)
-    auto materialize = [&]() {
-      __syncthreads();
-      if (wv == 0) {
-        sh.sorg[lane] = org0;
-        sh.sorg[64 + lane] = org1;
-      }
-      __syncthreads();
-      for (int e = tid; e < kWin * kMaxPanelWords; e += 256) {
-        const int s = e >> 3, j = e & 7;
-        if (wb + s < nblk) {
-          sh.win[s][j] = sh.blk[wb + sh.sorg[s]][j];
-          if (j == 0) sh.wsrc[s] = sh.bsrc[wb + sh.sorg[s]];
+    // Pivot wave: bits from k on, until the end of the sub-panel or a bit that
+    // needs the scan below the window (returned true).
+    auto pivot_wave = [&](int &k) -> bool {
+      while (true) {
+        if (k < 32) run_bits(std::false_type{}, k, nbits < 32 ? nbits : 32);
+        if (k >= 32 && k < nbits) run_bits(std::true_type{}, k, nbits);
+        if (k >= nbits) return false;
+        // bit k: no candidate in the first half; reduce the second half (Proj)
+        const uint32_t bit = 1u << (k & 31);
+        sh.Ms[lane] = ((uint64_t)m_hi << 32) | m_lo;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sh.Tw[(lane >> 4) + 4 * u][lane & 15] = table4_entry(sh.Ms, lane + 64 * u);
+        __builtin_amdgcn_wave_barrier();
+        {
+          const uint64_t x = ((uint64_t)b_hi << 32) | b_lo;
+          const uint64_t xr = x ^ proj4(sh.Tw, x);
+          b_lo = (uint32_t)xr;
+          b_hi = (uint32_t)(xr >> 32);
         }
-      }
-      __syncthreads();
-      for (int e = tid; e < kWin * kMaxPanelWords; e += 256) {
-        const int s = e >> 3, j = e & 7;
-        if (wb + s < nblk) {
-          sh.blk[wb + s][j] = sh.win[s][j];
-          if (j == 0) sh.bsrc[wb + s] = sh.wsrc[s];
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t c1 = __ballot(((k < 32 ? b_lo : b_hi) & bit) != 0u) & act1;
+        if (c1) {  // pivot from the second half; the row of slot ib takes its slot
+          const int sp = __builtin_ctzll(c1);
+          const uint32_t p_lo = __builtin_amdgcn_readlane(b_lo, sp), p_hi = __builtin_amdgcn_readlane(b_hi, sp);
+          const int p_org = __builtin_amdgcn_readlane(org1, sp);
+          const uint32_t i_lo = __builtin_amdgcn_readlane(a_lo, ib), i_hi = __builtin_amdgcn_readlane(a_hi, ib);
+          const int i_org = __builtin_amdgcn_readlane(org0, ib);
+          b_lo = wrlane(i_lo, sp, b_lo);
+          b_hi = wrlane(i_hi, sp, b_hi);
+          org1 = wrlane(i_org, sp, org1);
+          a_lo = wrlane(p_lo, ib, a_lo);
+          a_hi = wrlane(p_hi, ib, a_hi);
+          org0 = wrlane(p_org, ib, org0);
+          commit(k, p_lo, p_hi, __ballot(((k < 32 ? m_lo : m_hi) & bit) != 0u));
+          ++k;
+          continue;
         }
+        if (Fknown && !((F >> k) & 1ull)) {  // no row below the window can have bit k
+          ++k;
+          continue;
+        }
+        return true;
       }
-      org0 = lane;
-      org1 = 64 + lane;
-      __syncthreads();
     };
 
     int k = 0;
     while (true) {
-      if (k < 32) run_bits(std::false_type{}, k, nbits < 32 ? nbits : 32);
-      if (k >= 32 && k < nbits) run_bits(std::true_type{}, k, nbits);
-      if (k >= nbits) break;
-      // ---- bit k: no candidate in the first half of the window
-      const uint32_t bit = 1u << (k & 31);
-      const uint64_t c1 = __ballot(((k < 32 ? b_lo : b_hi) & bit) != 0u) & act1;
-      if (c1) {  // pivot from the second half
-        const int sp = __builtin_ctzll(c1);
-        const uint32_t p_lo = __builtin_amdgcn_readlane(b_lo, sp), p_hi = __builtin_amdgcn_readlane(b_hi, sp);
-        const int p_org = __builtin_amdgcn_readlane(org1, sp);
-        const uint32_t i_lo = __builtin_amdgcn_readlane(a_lo, ib), i_hi = __builtin_amdgcn_readlane(a_hi, ib);
-        const int i_org = __builtin_amdgcn_readlane(org0, ib);
-        const bool r1 = __builtin_amdgcn_inverse_ballot_w64(c1 & ~(1ull << sp));
-        b_lo = r1 ? b_lo ^ p_lo : b_lo;
-        b_hi = r1 ? b_hi ^ p_hi : b_hi;
-        b_lo = wrlane(i_lo, sp, b_lo);
-        b_hi = wrlane(i_hi, sp, b_hi);
-        org1 = wrlane(i_org, sp, org1);
-        a_lo = wrlane(p_lo, ib, a_lo);
-        a_hi = wrlane(p_hi, ib, a_hi);
-        org0 = wrlane(p_org, ib, org0);
-        commit(k, p_lo, p_hi, __ballot(((k < 32 ? m_lo : m_hi) & bit) != 0u));
-        ++k;
-        continue;
+      if (wv == 0) {
+        const bool need = pivot_wave(k);
+        if (lane == 0) {
+          sh.ctl_need = need ? 1 : 0;
+          sh.ctl_k = k;
+          sh.ctl_ib = ib;
+        }
+        sh.sorg[lane] = org0;
+        sh.sorg[64 + lane] = org1;
+        sh.Ms[lane] = ((uint64_t)m_hi << 32) | m_lo;
       }
-      if (Fknown && !((F >> k) & 1ull)) {  // no row below the window can have bit k
-        ++k;
-        continue;
-      }
-      // ---- bit k: no window row has it; scan the rows below the window (all threads)
-      const uint64_t kb = 1ull << k;
-      materialize();
-      if (wv == 0) sh.Ms[lane] = ((uint64_t)m_hi << 32) | m_lo;
+      __syncthreads();
+      if (!sh.ctl_need) break;
+      // ---- bit kk: no window row has it; scan the rows below the window (all threads)
+      const int kk = sh.ctl_k, ibs = sh.ctl_ib;
+      const uint64_t kb = 1ull << kk;
+      materialize(wb);
+      if (tid < 256) sh.Tp[tid >> 4][tid & 15] = table4_entry(sh.Ms, tid);
       if (tid == 0) {
         sh.scan_best = 0x7fffffff;
         sh.scan_F = 0ull;
       }
       __syncthreads();
-      {
-        const int g = tid >> 4, v = tid & 15;
-        uint64_t acc = 0ull;
-#pragma unroll
-        for (int bb = 0; bb < 4; ++bb)
-          if (v & (1 << bb)) acc ^= sh.Ms[4 * g + bb];
-        sh.Tp[g][v] = acc;
-      }
-      __syncthreads();
       int best = 0x7fffffff;
       uint64_t Floc = 0ull;
-      for (int64_t p = Rb + kWin + tid; p < n; p += 256) {
+      for (int64_t p = Rb + kWin + tid; p < n; p += NT) {
         uint64_t xq;
         if (p - R0 < nblk) {
           xq = sh.blk[p - R0][b];
@@ -410,17 +453,9 @@ __global__ __launch_bounds__(256) void k_chain(DecWork w, int q0, int s_eff, int
       if (Floc) atomicOr(&sh.scan_F, (unsigned long long)Floc);
       __syncthreads();
       best = __builtin_amdgcn_readfirstlane(sh.scan_best);
-      {
-        const unsigned long long fv = sh.scan_F;
-        F = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(fv >> 32)) << 32) |
-            (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)fv);
-      }
-      Fknown = true;
+      const int si = wb + ibs;
       if (best != 0x7fffffff) {
         // position `best` and slot ib (position Rb + ib) exchange their rows
-        const uint64_t xro = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(a_hi, ib) << 32) |
-                             (uint32_t)__builtin_amdgcn_readlane(a_lo, ib);
-        const int si = wb + ib;
         if (best - R0 < nblk) {
           const int bi = (int)(best - R0);
           if (tid < kMaxPanelWords) {
@@ -455,40 +490,57 @@ __global__ __launch_bounds__(256) void k_chain(DecWork w, int q0, int s_eff, int
           sh.bsrc[si] = src_in;
         }
         __syncthreads();
-        const uint64_t xin = sh.blk[si][b];
-        const uint64_t xrp = xin ^ proj4(sh.Tp, xin);
-        a_lo = wrlane((uint32_t)xrp, ib, a_lo);
-        a_hi = wrlane((uint32_t)(xrp >> 32), ib, a_hi);
-        F |= xro;
-        commit(k, (uint32_t)xrp, (uint32_t)(xrp >> 32),
-               __ballot(((k < 32 ? m_lo : m_hi) & (1u << (k & 31))) != 0u));
       }
-      ++k;
+      if (wv == 0) {
+        org0 = lane;
+        org1 = 64 + lane;
+        {
+          const unsigned long long fv = sh.scan_F;
+          F = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(fv >> 32)) << 32) |
+              (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)fv);
+        }
+        Fknown = true;
+        if (best != 0x7fffffff) {
+          const uint64_t xro = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(a_hi, ib) << 32) |
+                               (uint32_t)__builtin_amdgcn_readlane(a_lo, ib);
+          const uint64_t xin = sh.blk[si][b];
+          const uint64_t xrp = xin ^ proj4(sh.Tp, xin);
+          a_lo = wrlane((uint32_t)xrp, ib, a_lo);
+          a_hi = wrlane((uint32_t)(xrp >> 32), ib, a_hi);
+          F |= xro;
+          commit(k, (uint32_t)xrp, (uint32_t)(xrp >> 32),
+                 __ballot(((k < 32 ? m_lo : m_hi) & (1u << (k & 31))) != 0u));
+        }
+        ++k;
+      }
+      __syncthreads();
     }
-    const int r = ib;
+    const int r = sh.ctl_ib;
+    // (pivot wave) lane t < r: word q of E_t, the coefficient map yM
     const uint64_t yM = ((uint64_t)y_hi << 32) | y_lo;
-    const uint64_t xr0 = ((uint64_t)a_hi << 32) | a_lo;  // lane t < r: E_t restricted to word q
-    materialize();
+    const uint64_t xr0 = ((uint64_t)a_hi << 32) | a_lo;
+    materialize(wb);
 
     // ---- multipliers of the pivot rows (unit lower block L_pp) from the
     // coefficient map: word q of pivot row t at level b lies in the span of
     // E_0..E_t, so y = word * Zc lists its multipliers (bit t set).  Then the
-    // block's inverse.
+    // block's inverse.  The pivot rows' later words get 4-bit tables.
     if (wv == 0) sh.Ms[lane] = yM;
     __syncthreads();
-    {
-      const int g = tid >> 4, v = tid & 15;
+    if (tid < 256) sh.Tp[tid >> 4][tid & 15] = table4_entry(sh.Ms, tid);
+    for (int e = tid; e < (s_eff - 1 - b) * 256; e += NT) {
+      const int wd = b + 1 + (e >> 8), g = (e >> 4) & 15, v = e & 15;
       uint64_t acc = 0ull;
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb)
-        if (v & (1 << bb)) acc ^= sh.Ms[4 * g + bb];
-      sh.Tp[g][v] = acc;
+        if ((v & (1 << bb)) && 4 * g + bb < r) acc ^= sh.blk[wb + 4 * g + bb][wd];
+      sh.Pt[wd - b - 1][g][v] = acc;
     }
     __syncthreads();
-    uint64_t yx = 0ull, li = 0ull;
+    uint64_t yx = 0ull;
     if (wv == 0) {
       if (lane < r) yx = proj4(sh.Tp, sh.blk[wb + lane][b]);
-      li = lane < r ? (1ull << lane) : 0ull;
+      uint64_t li = lane < r ? (1ull << lane) : 0ull;
       for (int t = 0; t < r; ++t) {
         const uint64_t row = rdl64(li, t);
         if (lane > t && lane < r && ((yx >> t) & 1ull)) li ^= row;
@@ -509,33 +561,23 @@ __global__ __launch_bounds__(256) void k_chain(DecWork w, int q0, int s_eff, int
     __syncthreads();
     // ---- pivot rows in final form: word q = E_t | L_pp bits left of t; later
     // panel words = L_pp^{-1} * (pivot rows at level b)
-    for (int e = tid; e < r * kMaxPanelWords; e += 256) {
-      const int t = e >> 3, j = e & 7;
-      if (j > b && j < s_eff) {
-        const uint64_t l = sh.Li[t];
-        uint64_t acc = 0ull;
-        for (int u = 0; u < r; ++u)
-          if ((l >> u) & 1ull) acc ^= sh.blk[wb + u][j];
-        sh.win[t][j] = acc;
+    {
+      const int nw = s_eff - 1 - b;
+      for (int e = tid; e < r * nw; e += NT) {
+        const int t = e / nw, wd = b + 1 + (e - t * nw);
+        sh.win[t][wd] = proj4(sh.Pt[wd - b - 1], sh.Li[t]);
       }
     }
     __syncthreads();
-    for (int e = tid; e < r * kMaxPanelWords; e += 256) {
+    for (int e = tid; e < r * kMaxPanelWords; e += NT) {
       const int t = e >> 3, j = e & 7;
       if (j > b && j < s_eff) sh.blk[wb + t][j] = sh.win[t][j];
     }
     if (wv == 0 && lane < r) sh.blk[wb + lane][b] = xr0 | (yx & ((1ull << lane) - 1ull));
     __syncthreads();
     // ---- tables of sub-panel b, then every block row below its pivots gets it
-    {
-      const int g = tid >> 4, v = tid & 15;
-      uint64_t acc = 0ull;
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb)
-        if (v & (1 << bb)) acc ^= sh.Ms[4 * g + bb];
-      sh.pt.Tz[b][g][v] = acc;
-    }
-    for (int e = tid; e < (s_eff - 1 - b) * 256; e += 256) {
+    if (tid < 256) sh.pt.Tz[b][tid >> 4][tid & 15] = table4_entry(sh.Ms, tid);
+    for (int e = tid; e < (s_eff - 1 - b) * 256; e += NT) {
       const int wd = b + 1 + (e >> 8), g = (e >> 4) & 15, v = e & 15;
       uint64_t acc = 0ull;
 #pragma unroll
@@ -544,7 +586,7 @@ __global__ __launch_bounds__(256) void k_chain(DecWork w, int q0, int s_eff, int
       sh.pt.Te[pidx(b, wd)][g][v] = acc;
     }
     __syncthreads();
-    for (int i = wb + r + tid; i < nblk; i += 256) {
+    for (int i = wb + r + tid; i < nblk; i += NT) {
       uint64_t x[kMaxPanelWords];
 #pragma unroll
       for (int j = 0; j < kMaxPanelWords; ++j) x[j] = sh.blk[i][j];
@@ -557,16 +599,20 @@ __global__ __launch_bounds__(256) void k_chain(DecWork w, int q0, int s_eff, int
   }
 
   // ---- block rows back to HBM; every row below the pivots is at level s
-  for (int e = tid; e < nblk * kMaxPanelWords; e += 256) {
-    const int i = e >> 3, j = e & 7;
-    if (j < s_eff) W[widx(ldw, R0 + i, q0 + j)] = sh.blk[i][j];
+  {
+    constexpr int PER = kBlkMax * kMaxPanelWords / NT;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * NT, i = e >> 3, j = e & 7;
+      if (i < nblk && j < s_eff) W[widx(ldw, R0 + i, q0 + j)] = sh.blk[i][j];
+    }
   }
-  for (int i = tid; i < nblk; i += 256) w.lvl[R0 + i] = i < wb ? (q0 << 4) | 15 : (q0 << 4) | s_eff;
+  for (int i = tid; i < nblk; i += NT) w.lvl[R0 + i] = i < wb ? (q0 << 4) | 15 : (q0 << 4) | s_eff;
   // ---- permutation bookkeeping of every position whose row changed
   ChainMoved &mv = *reinterpret_cast<ChainMoved *>(&sh.pt);
   if (tid == 0) sh.nmv = 0;
   __syncthreads();
-  for (int i = tid; i < nblk + sh.mb_n; i += 256) {
+  for (int i = tid; i < nblk + sh.mb_n; i += NT) {
     int pos, src;
     if (i < nblk) {
       pos = (int)(R0 + i);
@@ -584,7 +630,7 @@ __global__ __launch_bounds__(256) void k_chain(DecWork w, int q0, int s_eff, int
   }
   __syncthreads();
   const int nmv = sh.nmv;
-  for (int e = tid; e < nmv; e += 256) {
+  for (int e = tid; e < nmv; e += NT) {
     const int pos = mv.pos[e];
     w.perm[pos] = mv.perm[e];
     w.bp_src[pos] = mv.src[e];
@@ -598,7 +644,7 @@ __global__ __launch_bounds__(256) void k_chain(DecWork w, int q0, int s_eff, int
 }
 
 hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, hipStream_t s) {
-  hipLaunchKernelGGL(k_chain, dim3(1), dim3(256), 0, s, w, q0, s_eff, flag_q0);
+  hipLaunchKernelGGL(k_chain, dim3(1), dim3(kChainThreads), 0, s, w, q0, s_eff, flag_q0);
   return hipGetLastError();
 }
 
