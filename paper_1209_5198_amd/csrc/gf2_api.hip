@@ -349,12 +349,12 @@ int gf2_set_param(const char *name, int64_t value) {
     return GF2_OK;
   }
   if (!strcmp(name, "gemm_variant")) {
-    if (value < -1 || value > 6) return fail(GF2_EINVAL, "gemm_variant must be in -1..6");
+    if (value < -1 || value >= kGemmVariants) return fail(GF2_EINVAL, "gemm_variant out of range");
     g_gemm_variant = (int)value;
     return GF2_OK;
   }
   if (!strcmp(name, "panel_gemm_variant")) {
-    if (value < -1 || value > 6) return fail(GF2_EINVAL, "panel_gemm_variant must be in -1..6");
+    if (value < -1 || value >= kGemmVariants) return fail(GF2_EINVAL, "panel_gemm_variant out of range");
     g_panel_gemm_variant = (int)value;
     return GF2_OK;
   }

@@ -7,16 +7,21 @@
 // T = (b/c)(2^c - 1) XORs for the tables plus R = b/c XORs per row).
 //
 // gfx950 mapping.  A workgroup owns a tile of TM rows x one 16-word column
-// block of C (1024 columns).  A wave is four 16-lane groups; each group works
-// on one row at a time and lane l of the group owns word l of the block row,
-// so the table index (a byte of the row's A word) is uniform in the group and
-// every lookup reads one contiguous 128-byte table entry: 512 bytes per wave
-// instruction with no LDS bank conflicts.  The inner dimension advances in
-// stages of 16 bits (two tables); tables are double-buffered (2 x 64 KB), so
-// the build of stage i+1 overlaps the lookups of stage i with one barrier per
-// stage, and the B rows / A words of later stages are prefetched into
-// registers.  Accumulators stay in registers for the whole inner loop, so C
-// is read and written once per launch.
+// block of C (1024 columns); four tables (32 inner bits) are built per step in
+// LDS (128 KB) and every row of the tile then does its four lookups, with two
+// barriers per step.  B rows and A words of the next step are prefetched into
+// registers during the lookups, and the accumulators stay in registers for the
+// whole inner loop, so C is read and written once per launch.
+//   k_gemm_wide  (the default) eight 8-lane groups per wave; lane w2 of a
+//                group owns words 2*w2, 2*w2+1 of its group's row and one
+//                16-byte read fetches them from a 128-byte table entry.
+//                Adjacent groups read the two interleaved tables of a pair in
+//                the same instruction, so 16 lanes cover 256 contiguous bytes
+//                (no bank conflicts at the full 16-byte read rate).
+//   k_gemm_quad  four 16-lane groups per wave, one 8-byte read per lookup.
+//   k_gemm_db    two tables per stage, double-buffered.
+// The byte address of a table entry is formed by one byte permute of (A bits,
+// lane base), and the XORs use the three-input bitwise instruction.
 #include "gf2_internal.h"
 
 namespace gf2 {
@@ -355,6 +360,220 @@ __global__ __launch_bounds__(NT) void k_gemm_db(GemmArgs a) {
 }
 
 
+// Four tables per step like k_gemm_quad, read with 16-byte lookups: a wave is
+// eight 8-lane groups, lane w2 of a group owns words 2*w2 and 2*w2+1 of its
+// group's row, and one ds_read_b128 fetches 16 bytes of a 128-byte entry.
+// Adjacent groups read the two tables of a pair (entries 128 bytes apart) in
+// the same instruction, so every 16 lanes cover 256 contiguous bytes: the
+// conflict-free pattern that sustains the highest LDS read rate on gfx950.
+template <int RPL, int S>
+__device__ inline void load_acc2(uint64_t (&acc)[RPL][2], const uint64_t *Cl, bool ok0, bool ok1, int ulo,
+                                 int uhi) {
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    acc[u][0] = 0ull;
+    acc[u][1] = 0ull;
+    if (u >= ulo && u < uhi) {
+      const uint64_t *p = Cl + (int64_t)u * S * TW;
+      if (ok0 && ok1) {
+        const ulonglong2 v = *(const ulonglong2 *)p;
+        acc[u][0] = v.x;
+        acc[u][1] = v.y;
+      } else {
+        if (ok0) acc[u][0] = p[0];
+        if (ok1) acc[u][1] = p[1];
+      }
+    }
+  }
+}
+
+template <int RPL, int S>
+__device__ inline uint64_t store_acc2(const uint64_t (&acc)[RPL][2], uint64_t *Cl, bool ok0, bool ok1, int ulo,
+                                      int uhi) {
+  uint64_t any = 0;
+#pragma unroll
+  for (int u = 0; u < RPL; ++u)
+    if (u >= ulo && u < uhi) {
+      uint64_t *p = Cl + (int64_t)u * S * TW;
+      if (ok0 && ok1) {
+        *(ulonglong2 *)p = make_ulonglong2(acc[u][0], acc[u][1]);
+      } else {
+        if (ok0) p[0] = acc[u][0];
+        if (ok1) p[1] = acc[u][1];
+      }
+      any |= (ok0 ? acc[u][0] : 0ull) | (ok1 ? acc[u][1] : 0ull);
+    }
+  return any;
+}
+
+template <int NT, int TM>
+__global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
+  constexpr int NW = NT / 64;          // waves
+  constexpr int RPL = TM / (8 * NW);   // rows per lane
+  constexpr int JOBS = NT / 8;         // table-build jobs (8 threads each, one word pair per thread)
+  constexpr int EPJ = 4 * 256 / JOBS;  // entries per job
+  constexpr int LOGE = EPJ == 8 ? 3 : (EPJ == 16 ? 4 : (EPJ == 32 ? 5 : 6));
+  static_assert(RPL * 8 * NW == TM && RPL % 2 == 0, "tile");
+  static_assert(EPJ == 8 || EPJ == 16 || EPJ == 32 || EPJ == 64, "build split");
+  static_assert(TM % NT == 0, "A staging");
+  // Tables g = 2p + s stored as T[p][idx][s][word]: entry idx of table g, word w
+  // at byte p*65536 + idx*256 + s*128 + w*8.
+  __shared__ uint64_t T[2][256][2][TW];
+  __shared__ uint32_t As[2 * TM];      // the tile's A word for the current 64 inner bits
+
+  if (a.skip_flag && *a.skip_flag == 0u) return;  // the Schur complement is already zero
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, G = lane >> 3, w2 = lane & 7;
+  const int blk = blockIdx.y + (a.qc0 >> 4);
+  const int64_t qw = (int64_t)blk * TW + 2 * w2;
+  const bool ok0 = qw >= a.qc0 && qw < a.qc1, ok1 = qw + 1 >= a.qc0 && qw + 1 < a.qc1;
+
+  const int64_t tile0 = a.row_tile0 + (int64_t)blockIdx.x * TM;
+  int64_t rb = tile0;
+  if (a.bsub) {  // rows below the panel's pivots: first row after the last sub-panel's pivots
+    const int64_t d = a.bsub[a.kwords - 1].R + a.bsub[a.kwords - 1].r;
+    if (d > rb) rb = d;
+  }
+  int64_t re = tile0 + TM < a.row_end ? tile0 + TM : a.row_end;
+  if (rb >= re) return;
+
+  // rows of this lane: tile0 + 8*wv + G + 8*NW*u
+  int ulo, uhi;
+  lane_rows<RPL, 8 * NW>(tile0, 8 * wv + G, rb, re, ulo, uhi);
+  uint64_t acc[RPL][2];
+  {
+    uint64_t *C = a.C;
+    asm volatile("" : "+s"(C));
+    const uint64_t *Cl = C + (((int64_t)blk * a.ldC + tile0 + 8 * wv + G) * TW + 2 * w2);
+    load_acc2<RPL, 8 * NW>(acc, Cl, a.accumulate && ok0, a.accumulate && ok1, ulo, uhi);
+  }
+
+  const int bw2 = tid & 7;
+  const int job = tid >> 3;
+  const int g_b = job / (256 / EPJ), uu = job % (256 / EPJ);
+  const int64_t bq = (int64_t)blk * TW + 2 * bw2;
+  const bool bok0 = bq >= a.qc0 && bq < a.qc1, bok1 = bq + 1 >= a.qc0 && bq + 1 < a.qc1;
+
+  auto load_b = [&](int hh, uint64_t (&bv)[8][2]) {
+    const int kw = hh >> 1, half = hh & 1;
+    int64_t browR = 64ll * kw;
+    int blim;
+    if (a.bsub) {
+      browR = a.bsub[kw].R;
+      blim = a.bsub[kw].r;
+    } else {
+      const int64_t left = a.b_rows - 64ll * kw;
+      blim = left >= 64 ? 64 : (left > 0 ? (int)left : 0);
+    }
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int t = 32 * half + 8 * g_b + b;
+      const uint64_t *p = a.B + widx(a.ldB, browR + t, bq);
+      bv[b][0] = (bok0 && t < blim) ? p[0] : 0ull;
+      bv[b][1] = (bok1 && t < blim) ? p[1] : 0ull;
+    }
+  };
+  constexpr int APT = TM / NT;
+  auto load_a = [&](int kw, uint64_t (&av)[APT]) {
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+      const int64_t i = tile0 + tid + (int64_t)j * NT;
+      av[j] = (i >= rb && i < re) ? a.A[widx(a.ldA, i, a.a_word0 + kw)] : 0ull;
+    }
+  };
+
+  uint64_t bv[8][2], av[APT];
+  load_b(0, bv);
+  load_a(0, av);
+  const char *Tb = (const char *)&T[0][0][0][0];
+  // instruction g: odd groups read table g ^ 1 (the other table of the pair)
+  uint32_t lbase[4], sel[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int gg = g ^ (G & 1);
+    lbase[g] = ((uint32_t)(gg >> 1) << 16) | ((uint32_t)(gg & 1) << 7) | ((uint32_t)w2 << 4);
+    sel[g] = 0x0C020000u | ((4u + (uint32_t)gg) << 8);  // [lane base | byte gg of A | pair | 0]
+  }
+  const int nh = 2 * a.kwords;
+  for (int hh = 0; hh < nh; ++hh) {
+    const int half = hh & 1;
+    __syncthreads();  // previous lookups finished: T and As are free
+    if (half == 0) {
+#pragma unroll
+      for (int j = 0; j < APT; ++j) {
+        As[2 * (tid + j * NT)] = (uint32_t)av[j];
+        As[2 * (tid + j * NT) + 1] = (uint32_t)(av[j] >> 32);
+      }
+    }
+    {
+      uint64_t c0 = 0ull, c1 = 0ull;
+#pragma unroll
+      for (int b = LOGE; b < 8; ++b)
+        if ((uu >> (b - LOGE)) & 1) {
+          c0 ^= bv[b][0];
+          c1 ^= bv[b][1];
+        }
+#pragma unroll
+      for (int j = 0; j < EPJ; ++j) {
+        const int gj = j ^ (j >> 1);
+        *(ulonglong2 *)&T[g_b >> 1][EPJ * uu + gj][g_b & 1][2 * bw2] = make_ulonglong2(c0, c1);
+        if (j < EPJ - 1) {
+          c0 ^= bv[__builtin_ctz(j + 1)][0];
+          c1 ^= bv[__builtin_ctz(j + 1)][1];
+        }
+      }
+    }
+    if (hh + 1 < nh) load_b(hh + 1, bv);  // in flight during the lookups
+    if (half == 0 && (hh >> 1) + 1 < a.kwords) load_a((hh >> 1) + 1, av);
+    __syncthreads();
+#pragma unroll
+    for (int u0 = 0; u0 < RPL; u0 += 2) {
+      uint32_t a32[2];
+#pragma unroll
+      for (int v = 0; v < 2; ++v) a32[v] = As[2 * (8 * (wv + NW * (u0 + v)) + G) + half];
+      uint4 t[2][4];
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) t[v][g] = *(const uint4 *)(Tb + __builtin_amdgcn_perm(a32[v], lbase[g], sel[g]));
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        uint32_t x0 = (uint32_t)acc[u0 + v][0], x1 = (uint32_t)(acc[u0 + v][0] >> 32);
+        uint32_t x2 = (uint32_t)acc[u0 + v][1], x3 = (uint32_t)(acc[u0 + v][1] >> 32);
+        x0 = __builtin_amdgcn_bitop3_b32(x0, t[v][0].x, t[v][1].x, 0x96);
+        x1 = __builtin_amdgcn_bitop3_b32(x1, t[v][0].y, t[v][1].y, 0x96);
+        x2 = __builtin_amdgcn_bitop3_b32(x2, t[v][0].z, t[v][1].z, 0x96);
+        x3 = __builtin_amdgcn_bitop3_b32(x3, t[v][0].w, t[v][1].w, 0x96);
+        x0 = __builtin_amdgcn_bitop3_b32(x0, t[v][2].x, t[v][3].x, 0x96);
+        x1 = __builtin_amdgcn_bitop3_b32(x1, t[v][2].y, t[v][3].y, 0x96);
+        x2 = __builtin_amdgcn_bitop3_b32(x2, t[v][2].z, t[v][3].z, 0x96);
+        x3 = __builtin_amdgcn_bitop3_b32(x3, t[v][2].w, t[v][3].w, 0x96);
+        acc[u0 + v][0] = ((uint64_t)x1 << 32) | x0;
+        acc[u0 + v][1] = ((uint64_t)x3 << 32) | x2;
+      }
+    }
+  }
+
+  uint64_t any;
+  {
+    uint64_t *C = a.C;
+    asm volatile("" : "+s"(C));
+    uint64_t *Cl = C + (((int64_t)blk * a.ldC + tile0 + 8 * wv + G) * TW + 2 * w2);
+    any = store_acc2<RPL, 8 * NW>(acc, Cl, ok0, ok1, ulo, uhi);
+  }
+  if (a.nzflag) {
+    if (__ballot(any != 0ull) != 0ull && lane == 0) atomicOr(a.nzflag, 1u);
+  }
+  if (a.work && tid == 0) {
+    int64_t lo = (int64_t)blk * TW, hi = lo + TW;
+    if (lo < a.qc0) lo = a.qc0;
+    if (hi > a.qc1) hi = a.qc1;
+    const unsigned long long words = hi > lo ? (unsigned long long)(hi - lo) : 0ull;
+    atomicAdd(a.work, (unsigned long long)(re - rb) * words * (unsigned long long)a.kwords * 8ull);
+  }
+}
+
+
 // Product-kernel variants (same results; chosen per call by a tuning knob, or
 // automatically when the knob is -1):
 //   0: four tables / 32 inner bits, 1024 threads, 1024-row tiles
@@ -364,25 +583,29 @@ __global__ __launch_bounds__(NT) void k_gemm_db(GemmArgs a) {
 //   4: double-buffered table pairs, 512 threads, 2048-row tiles
 //   5: four tables, 256 threads, 512-row tiles
 //   6: four tables, 256 threads, 256-row tiles
+//   7: four tables with 16-byte lookups, 512 threads, 2048-row tiles
+//   8: four tables with 16-byte lookups, 512 threads, 1024-row tiles
+//   9: four tables with 16-byte lookups, 256 threads, 256-row tiles
+//  10: four tables with 16-byte lookups, 256 threads, 512-row tiles
 // Automatic choice: the largest tile that still gives at least one workgroup
 // per CU for the rows expected to be active; small launches get small tiles.
 int gemm_tile_rows(int v) {
   switch (v) {
-    case 2: case 4: return 2048;
-    case 5: return 512;
-    case 6: return 256;
+    case 2: case 4: case 7: return 2048;
+    case 5: case 10: return 512;
+    case 6: case 9: return 256;
     default: return 1024;
   }
 }
 
 int gemm_auto_variant(int64_t active_rows, int blocks_y, int ncu) {
   const int64_t want = ncu;
-  const int order[4] = {2, 0, 5, 6};
+  const int order[4] = {7, 8, 10, 9};
   for (int i = 0; i < 4; ++i) {
     const int tm = gemm_tile_rows(order[i]);
     if (((active_rows + tm - 1) / tm) * (int64_t)blocks_y >= want) return order[i];
   }
-  return 6;
+  return 9;
 }
 
 hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t s) {
@@ -398,6 +621,10 @@ hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t 
     case 4: hipLaunchKernelGGL((k_gemm_db<512, 2048>), grid, dim3(512), 0, s, a); break;
     case 5: hipLaunchKernelGGL((k_gemm_quad<256, 512>), grid, dim3(256), 0, s, a); break;
     case 6: hipLaunchKernelGGL((k_gemm_quad<256, 256>), grid, dim3(256), 0, s, a); break;
+    case 7: hipLaunchKernelGGL((k_gemm_wide<512, 2048>), grid, dim3(512), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_gemm_wide<512, 1024>), grid, dim3(512), 0, s, a); break;
+    case 9: hipLaunchKernelGGL((k_gemm_wide<256, 256>), grid, dim3(256), 0, s, a); break;
+    case 10: hipLaunchKernelGGL((k_gemm_wide<256, 512>), grid, dim3(256), 0, s, a); break;
     default: hipLaunchKernelGGL((k_gemm_quad<1024, 1024>), grid, dim3(1024), 0, s, a); break;
   }
   return hipGetLastError();

@@ -132,7 +132,9 @@ def test_decompose_panel_width_invariant(g, orc, panel_words):
 @pytest.mark.parametrize("knob,value", [("chain_cus", 0), ("chain_cus", 32), ("panel_gemm_variant", 0),
                                         ("panel_gemm_variant", 2), ("panel_gemm_variant", 3),
                                         ("panel_gemm_variant", 4), ("panel_gemm_variant", 5),
-                                        ("panel_gemm_variant", 6)])
+                                        ("panel_gemm_variant", 6), ("panel_gemm_variant", 7),
+                                        ("panel_gemm_variant", 8), ("panel_gemm_variant", 9),
+                                        ("panel_gemm_variant", 10)])
 def test_decompose_tuning_invariant(g, orc, knob, value):
     """Look-ahead split and product-kernel variant do not change any result."""
     n, m = 2300, 2900
@@ -148,7 +150,7 @@ def test_decompose_tuning_invariant(g, orc, knob, value):
     assert_same_ple(got, ref, (knob, value))
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", list(range(11)))
 def test_matmul_variants(g, orc, variant):
     n, k, m = 2100, 1300, 2500
     say("matmul variant", variant)
