@@ -101,10 +101,14 @@ int gf2_solve(const gf2_mat *A, const gf2_mat *B, const gf2_mat *X, uint64_t *co
               int64_t *rank, void *stream);
 
 /*
- * Tuning knobs (no knob changes any result):
- *   "panel_words"     : s, sub-panels of 64 columns per trailing-update panel (1..8)
- *   "strassen_cutoff" : smallest dimension (bits) at which gf2_matmul recurses
- *                       with Strassen-Winograd instead of a single product
+ * Tuning knobs, process-wide (no knob changes any result):
+ *   "panel_words"        : s, sub-panels of 64 columns per trailing-update panel (1..8)
+ *   "strassen_cutoff"    : smallest dimension (bits) at which gf2_matmul recurses
+ *                          with Strassen-Winograd instead of a single product
+ *   "gemm_variant"       : product-kernel variant for gf2_matmul (-1 = automatic)
+ *   "panel_gemm_variant" : product-kernel variant for the trailing update (-1 = automatic)
+ *   "chain_cus"          : CUs reserved for the pivot chain through CU-masked
+ *                          streams (0 = two unmasked streams, the default)
  * Returns 0, or GF2_EINVAL for an unknown name or out-of-range value.
  */
 int gf2_set_param(const char *name, int64_t value);

@@ -31,7 +31,10 @@ int g_panel_words = 8;
 int64_t g_strassen_cutoff = 0;  // 0: never recurse
 int g_gemm_variant = -1;        // product-kernel variant for gf2_matmul (-1: automatic)
 int g_panel_gemm_variant = -1;  // product-kernel variant for the trailing update (-1: automatic)
-int g_chain_cus = 8;            // CUs reserved for the pivot chain (look-ahead); 0 = no look-ahead
+// CUs reserved for the pivot chain through a CU-masked stream pair; 0 = two
+// plain streams (the default: measured faster, since a masked product launch
+// leaves the CUs of the reserved range idle and unbalances its XCD)
+int g_chain_cus = 0;
 
 // Per device: the two internal streams of the look-ahead pipeline.  The pivot
 // chain of panel J+1 (panel and row kernels) runs on `chain`, restricted to a

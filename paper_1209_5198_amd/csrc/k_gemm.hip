@@ -440,13 +440,44 @@ __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
   // rows of this lane: tile0 + 8*wv + G + 8*NW*u
   int ulo, uhi;
   lane_rows<RPL, 8 * NW>(tile0, 8 * wv + G, rb, re, ulo, uhi);
+  // With accumulation, C arrives in chunks of CH rows per lane, one chunk per
+  // step, so its HBM latency hides behind the lookups instead of stalling the
+  // prologue (one workgroup per CU leaves nothing else to overlap it with).
+  constexpr int CH = 2, NCH = RPL / CH;
+  const int nh = 2 * a.kwords;
+  const bool cstream = a.accumulate && nh >= NCH;
   uint64_t acc[RPL][2];
   {
     uint64_t *C = a.C;
     asm volatile("" : "+s"(C));
     const uint64_t *Cl = C + (((int64_t)blk * a.ldC + tile0 + 8 * wv + G) * TW + 2 * w2);
-    load_acc2<RPL, 8 * NW>(acc, Cl, a.accumulate && ok0, a.accumulate && ok1, ulo, uhi);
+    const bool pro = a.accumulate && !cstream;
+    load_acc2<RPL, 8 * NW>(acc, Cl, pro && ok0, pro && ok1, ulo, uhi);
   }
+  uint64_t cb[CH][2];
+  auto load_chunk = [&](int c) {
+    uint64_t *C = a.C;
+    asm volatile("" : "+s"(C));
+    const uint64_t *Cl = C + (((int64_t)blk * a.ldC + tile0 + 8 * wv + G) * TW + 2 * w2);
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int u = c * CH + i;
+      cb[i][0] = 0ull;
+      cb[i][1] = 0ull;
+      if (u >= ulo && u < uhi) {
+        const uint64_t *p = Cl + (int64_t)u * (8 * NW) * TW;
+        if (ok0 && ok1) {
+          const ulonglong2 v = *(const ulonglong2 *)p;
+          cb[i][0] = v.x;
+          cb[i][1] = v.y;
+        } else {
+          if (ok0) cb[i][0] = p[0];
+          if (ok1) cb[i][1] = p[1];
+        }
+      }
+    }
+  };
+  if (cstream) load_chunk(0);
 
   const int bw2 = tid & 7;
   const int job = tid >> 3;
@@ -494,9 +525,20 @@ __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
     lbase[g] = ((uint32_t)(gg >> 1) << 16) | ((uint32_t)(gg & 1) << 7) | ((uint32_t)w2 << 4);
     sel[g] = 0x0C020000u | ((4u + (uint32_t)gg) << 8);  // [lane base | byte gg of A | pair | 0]
   }
-  const int nh = 2 * a.kwords;
   for (int hh = 0; hh < nh; ++hh) {
     const int half = hh & 1;
+    if (cstream && hh < NCH) {  // chunk hh (requested one step earlier) joins its accumulators
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+        if (c == hh) {
+#pragma unroll
+          for (int i = 0; i < CH; ++i) {
+            acc[c * CH + i][0] ^= cb[i][0];
+            acc[c * CH + i][1] ^= cb[i][1];
+          }
+        }
+      if (hh + 1 < NCH) load_chunk(hh + 1);
+    }
     __syncthreads();  // previous lookups finished: T and As are free
     if (half == 0) {
 #pragma unroll

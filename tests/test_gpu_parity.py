@@ -129,7 +129,7 @@ def test_decompose_panel_width_invariant(g, orc, panel_words):
     assert_same_ple(got, ref, panel_words)
 
 
-@pytest.mark.parametrize("knob,value", [("chain_cus", 0), ("chain_cus", 32), ("panel_gemm_variant", 0),
+@pytest.mark.parametrize("knob,value", [("chain_cus", 8), ("chain_cus", 32), ("panel_gemm_variant", 0),
                                         ("panel_gemm_variant", 2), ("panel_gemm_variant", 3),
                                         ("panel_gemm_variant", 4), ("panel_gemm_variant", 5),
                                         ("panel_gemm_variant", 6), ("panel_gemm_variant", 7),
@@ -141,7 +141,7 @@ def test_decompose_tuning_invariant(g, orc, knob, value):
     say("tuning", knob, value)
     A = synth.dense(17, 1, n, m)
     ref = orc.ple(A, n, m)
-    defaults = {"chain_cus": 8, "panel_gemm_variant": -1}
+    defaults = {"chain_cus": 0, "panel_gemm_variant": -1}
     g.gf2_set_param(knob, value)
     try:
         got = gpu_decompose(g, A, n, m)
