@@ -299,12 +299,10 @@ int factor(const gf2_mat *A, DecWork &w, hipStream_t user) {
   for (int q0 = 0; q0 < w.Mw; q0 += S) {
     const int s_eff = (w.Mw - q0) < S ? (w.Mw - q0) : S;
     if ((rc = link(P, Cs, G))) return rc;  // panel J's chain is done
-    HIPCHK(launch_swap(w, q0, s_eff, G));
-    HIPCHK(launch_rows_panel(w, q0, s_eff, G));
+    HIPCHK(launch_post(w, q0, s_eff, G));  // row exchanges, multipliers, pivot rows in echelon form
     const int nq0 = q0 + s_eff;
     if (nq0 < w.Mw) {
       const int ns = (w.Mw - nq0) < S ? (w.Mw - nq0) : S;
-      HIPCHK(launch_trsm(w, q0, s_eff, G));
       if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0, nq0 + ns, G))) return rc;  // next panel's columns
       if ((rc = link(P, G, Cs))) return rc;
       if ((rc = chain(w, nq0, ns, prev, Cs))) return rc;                          // look-ahead

@@ -105,9 +105,7 @@ hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int variant, hipStr
 int gemm_auto_variant(int64_t active_rows, int blocks_y, int ncu);  // variant for a launch shape
 
 hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, hipStream_t s);
-hipError_t launch_rows_panel(const DecWork &w, int q0, int s_eff, hipStream_t s);
-hipError_t launch_swap(const DecWork &w, int q0, int s_eff, hipStream_t s);
-hipError_t launch_trsm(const DecWork &w, int q0, int s_eff, hipStream_t s);
+hipError_t launch_post(const DecWork &w, int q0, int s_eff, hipStream_t s);
 hipError_t launch_xor(uint64_t *dst, const uint64_t *a, const uint64_t *b, size_t nwords,
                       hipStream_t s);
 

@@ -648,165 +648,172 @@ hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, hipStr
   return hipGetLastError();
 }
 
-// All rows below the panel's pivots: apply the sub-panels each row still lacks
-// (from its level to the end of the panel), so every panel word holds the
-// row's multipliers y_c -- the Y of the paper's D*Z = Y, per sub-panel.
-constexpr int kRowsThreads = 256;
-constexpr int kRowsPerThread = 2;
-__global__ __launch_bounds__(kRowsThreads) void k_rows_panel(DecWork w, int q0, int s_eff) {
-  __shared__ PanelTables pt;
-  __shared__ TableSrc src;
+// ---------------------------------------------------------------- after the chain
+// One launch per panel, two kinds of workgroups (1024 threads each):
+//   * one per 16-word column block: the panel's net row permutation applied to
+//     the block's words outside the panel (P^(j) applied to all columns), then,
+//     for trailing words, the pivot rows in echelon form E = L_pp^{-1} * rows
+//     (block forward substitution over the sub-panels).  Both touch only the
+//     block's own words, so the permutation finishes before the solve reads.
+//   * one per 2048 rows: every row below the pivots gets the sub-panels it still
+//     lacks, so its panel words hold its multipliers y_c (the Y of D*Z = Y,
+//     eq. (Aj) restricted to the panel).  These touch only panel words.
+constexpr int kPostThreads = 1024;
+constexpr int kRowsPerWG = 2 * kPostThreads;
+
+struct TrsmShared {
+  uint64_t X[kMaxPanelWords * 64][TW];              // 64 KB: pivot rows, this block
+  uint64_t T[16][16][TW];                           // 32 KB: 4-bit tables
+  uint64_t Cf[kMaxPanelWords * 64][kMaxPanelWords]; // 32 KB: multipliers L_cb
+  uint64_t Li[kMaxPanelWords][64];                  // 4 KB: Linv_b
+  SubInfo Sb[kMaxPanelWords];
+};
+struct RowsShared {
+  PanelTables pt;
+  TableSrc src;
+};
+union PostShared {
+  TrsmShared t;
+  RowsShared r;
+};
+
+// the row now at listed position p comes from position bp_src[p] at the panel start
+__device__ void post_swap(const DecWork &w, int q0, int s_eff, int blk) {
+  const int cnt = w.st->bp_count;
+  if (cnt == 0) return;
+  const int tid = threadIdx.x, wl = tid & 15, e0 = tid >> 4;
+  const int64_t qw = (int64_t)blk * TW + wl;
+  const bool act = qw < w.Mw && !(qw >= q0 && qw < q0 + s_eff);
+  constexpr int PER = (kMaxPanelWords * 64 * 2) / (kPostThreads / 16);
+  uint64_t vals[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = e0 + (kPostThreads / 16) * u;
+    vals[u] = (act && e < cnt) ? w.W[widx(w.ldw, w.bp_src[w.bp_list[e]], qw)] : 0ull;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = e0 + (kPostThreads / 16) * u;
+    if (act && e < cnt) w.W[widx(w.ldw, w.bp_list[e], qw)] = vals[u];
+  }
+  __syncthreads();
+}
+
+// Pivot rows of the panel, words of column block blk right of the panel:
+//   E_b = Linv_b * X_b, then X_c ^= L_cb * E_b for later sub-panels c,
+// with L_cb = word q0+b of the pivot rows of sub-panel c (their multipliers for
+// the pivots of sub-panel b).  16-lane groups over the block, 4-bit tables.
+__device__ void post_trsm(const DecWork &w, int q0, int s_eff, int blk, TrsmShared &sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, h = lane >> 4, wl = lane & 15;
+  const int qc0 = q0 + s_eff;
+  const int64_t qw = (int64_t)blk * TW + wl;
+  const bool qok = qw >= qc0 && qw < w.Mw;
+  const int64_t ldw = w.ldw;
+  uint64_t *W = w.W;
+  if (tid < s_eff) sh.Sb[tid] = w.sub[q0 + tid];
+  __syncthreads();
+  int rtot = 0;
+  for (int b = 0; b < s_eff; ++b) rtot += sh.Sb[b].r;
+  if (rtot == 0) return;
+  for (int ri = tid >> 4; ri < 64 * s_eff; ri += kPostThreads / 16) {
+    const int b = ri >> 6, t = ri & 63;
+    sh.X[ri][wl] = (qok && t < sh.Sb[b].r) ? W[widx(ldw, sh.Sb[b].R + t, qw)] : 0ull;
+  }
+  for (int e = tid; e < 64 * s_eff * s_eff; e += kPostThreads) {
+    const int ri = e / s_eff, b = e - ri * s_eff;
+    const int c = ri >> 6, t = ri & 63;
+    sh.Cf[ri][b] = (b < c && t < sh.Sb[c].r) ? W[widx(ldw, sh.Sb[c].R + t, q0 + b)] : 0ull;
+  }
+  for (int e = tid; e < 64 * s_eff; e += kPostThreads)
+    sh.Li[e >> 6][e & 63] = w.Linv[(size_t)(q0 + (e >> 6)) * 64 + (e & 63)];
+  __syncthreads();
+  auto tables = [&](int b) {  // 16 tables of 16 entries over the 64 rows of X_b
+    if (tid < 256) {
+      const int g = tid >> 4, c = tid & 15;
+      uint64_t v[4];
+      for (int j = 0; j < 4; ++j) v[j] = sh.X[64 * b + 4 * g + j][c];
+      uint64_t cur = 0ull;
+      for (int j = 0; j < 16; ++j) {
+        sh.T[g][j ^ (j >> 1)][c] = cur;
+        if (j < 15) cur ^= v[__builtin_ctz(j + 1)];
+      }
+    }
+    __syncthreads();
+  };
+  for (int b = 0; b < s_eff; ++b) {
+    const int rb = sh.Sb[b].r;
+    if (rb == 0) continue;
+    tables(b);
+    {
+      const int t = 4 * wv + h;  // 16 waves x 4 groups = 64 rows
+      if (t < rb) {
+        const uint64_t l = sh.Li[b][t];
+        uint64_t v = 0ull;
+#pragma unroll
+        for (int g = 0; g < 16; ++g) v ^= sh.T[g][(l >> (4 * g)) & 15u][wl];
+        sh.X[64 * b + t][wl] = v;
+      }
+    }
+    __syncthreads();
+    if (b == s_eff - 1) break;
+    tables(b);
+    // multipliers have no bits at or beyond rb, so unused tables contribute entry 0 = 0
+    for (int ri = 64 * (b + 1) + 4 * wv + h; ri < 64 * s_eff; ri += kPostThreads / 16) {
+      const int c = ri >> 6, t = ri & 63;
+      if (t < sh.Sb[c].r) {
+        const uint64_t l = sh.Cf[ri][b];
+        uint64_t v = 0ull;
+#pragma unroll
+        for (int g = 0; g < 16; ++g) v ^= sh.T[g][(l >> (4 * g)) & 15u][wl];
+        sh.X[ri][wl] ^= v;
+      }
+    }
+    __syncthreads();
+  }
+  for (int ri = tid >> 4; ri < 64 * s_eff; ri += kPostThreads / 16) {
+    const int b = ri >> 6, t = ri & 63;
+    if (qok && t < sh.Sb[b].r) W[widx(ldw, sh.Sb[b].R + t, qw)] = sh.X[ri][wl];
+  }
+}
+
+__device__ void post_rows(const DecWork &w, int q0, int s_eff, int64_t blk0, RowsShared &sh) {
   const SubInfo last = w.sub[q0 + s_eff - 1];
   const int64_t rowbeg = last.R + last.r;
-  const int64_t blk0 = (int64_t)blockIdx.x * kRowsThreads * kRowsPerThread;
-  if (blk0 + kRowsThreads * kRowsPerThread <= rowbeg || blk0 >= w.n) return;
-  build_panel_tables(pt, src, w, q0, s_eff, s_eff, threadIdx.x, kRowsThreads);
-  for (int u = 0; u < kRowsPerThread; ++u) {
-    const int64_t i = blk0 + (int64_t)u * kRowsThreads + threadIdx.x;
+  if (blk0 + kRowsPerWG <= rowbeg || blk0 >= w.n) return;
+  build_panel_tables(sh.pt, sh.src, w, q0, s_eff, s_eff, threadIdx.x, kPostThreads);
+  for (int u = 0; u < kRowsPerWG / kPostThreads; ++u) {
+    const int64_t i = blk0 + (int64_t)u * kPostThreads + threadIdx.x;
     if (i < rowbeg || i >= w.n) continue;
     const int L = row_level(w, i, q0);
+    if (L >= s_eff) continue;  // already at the panel's last level (held by the chain kernel)
     uint64_t x[kMaxPanelWords];
 #pragma unroll
     for (int j = 0; j < kMaxPanelWords; ++j) x[j] = j < s_eff ? w.W[widx(w.ldw, i, q0 + j)] : 0ull;
-    panel_update(x, L, s_eff, s_eff - 1, pt);
+    panel_update(x, L, s_eff, s_eff - 1, sh.pt);
 #pragma unroll
     for (int j = 0; j < kMaxPanelWords; ++j)
       if (j >= L && j < s_eff) w.W[widx(w.ldw, i, q0 + j)] = x[j];
   }
 }
 
-hipError_t launch_rows_panel(const DecWork &w, int q0, int s_eff, hipStream_t s) {
-  const int64_t per = (int64_t)kRowsThreads * kRowsPerThread;
-  const int64_t blocks = (w.n + per - 1) / per;
-  if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rows_panel, dim3((unsigned)blocks), dim3(kRowsThreads), 0, s, w, q0, s_eff);
-  return hipGetLastError();
-}
-
-// Net row permutation of the panel on all words outside the panel: the row now
-// at listed position p comes from position bp_src[p] at the panel start.
-__global__ __launch_bounds__(1024) void k_swap(DecWork w, int q0, int s_eff) {
-  const int cnt = w.st->bp_count;
-  if (cnt == 0) return;
-  const int tid = threadIdx.x, wl = tid & 15, e0 = tid >> 4;
-  const int64_t qw = (int64_t)blockIdx.x * TW + wl;
-  const bool act = qw < w.Mw && !(qw >= q0 && qw < q0 + s_eff);
-  constexpr int PER = (kMaxPanelWords * 64 * 2) / 64;
-  uint64_t vals[PER];
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = e0 + 64 * u;
-    vals[u] = (act && e < cnt) ? w.W[widx(w.ldw, w.bp_src[w.bp_list[e]], qw)] : 0ull;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = e0 + 64 * u;
-    if (act && e < cnt) w.W[widx(w.ldw, w.bp_list[e], qw)] = vals[u];
+__global__ __launch_bounds__(kPostThreads) void k_post(DecWork w, int q0, int s_eff) {
+  __shared__ PostShared sh;
+  const int nb = w.NB;
+  if ((int)blockIdx.x < nb) {
+    const int blk = blockIdx.x;
+    post_swap(w, q0, s_eff, blk);
+    const int qc0 = q0 + s_eff;
+    if (qc0 < w.Mw && blk >= (qc0 >> 4)) post_trsm(w, q0, s_eff, blk, sh.t);
+  } else {
+    post_rows(w, q0, s_eff, (int64_t)(blockIdx.x - nb) * kRowsPerWG, sh.r);
   }
 }
 
-hipError_t launch_swap(const DecWork &w, int q0, int s_eff, hipStream_t s) {
-  hipLaunchKernelGGL(k_swap, dim3((unsigned)w.NB), dim3(1024), 0, s, w, q0, s_eff);
-  return hipGetLastError();
-}
-
-// Pivot rows of the panel, words right of the panel:
-//   E_b = Linv_b * X_b, then X_c ^= L_cb * E_b for later sub-panels c,
-// with L_cb = word q0+b of the pivot rows of sub-panel c (their multipliers for
-// the pivots of sub-panel b).  16-lane groups over a 16-word block, 4-bit tables.
-constexpr int kTrsmThreads = 1024;
-__global__ __launch_bounds__(kTrsmThreads) void k_trsm(DecWork w, int q0, int s_eff) {
-  __shared__ uint64_t X[kMaxPanelWords * 64][TW];           // 64 KB: pivot rows, this block
-  __shared__ uint64_t T[16][16][TW];                        // 32 KB: 4-bit tables
-  __shared__ uint64_t Cf[kMaxPanelWords * 64][kMaxPanelWords];  // 32 KB: multipliers L_cb
-  __shared__ uint64_t Li[kMaxPanelWords][64];               // 4 KB: Linv_b
-  __shared__ SubInfo Sb[kMaxPanelWords];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, h = lane >> 4, wl = lane & 15;
-  const int qc0 = q0 + s_eff;
-  const int blk = blockIdx.x + (qc0 >> 4);
-  const int64_t qw = (int64_t)blk * TW + wl;
-  const bool qok = qw >= qc0 && qw < w.Mw;
-  const int64_t ldw = w.ldw;
-  uint64_t *W = w.W;
-  if (tid < s_eff) Sb[tid] = w.sub[q0 + tid];
-  __syncthreads();
-  int rtot = 0;
-  for (int b = 0; b < s_eff; ++b) rtot += Sb[b].r;
-  if (rtot == 0) return;
-  for (int ri = tid >> 4; ri < 64 * s_eff; ri += kTrsmThreads / 16) {
-    const int b = ri >> 6, t = ri & 63;
-    X[ri][wl] = (qok && t < Sb[b].r) ? W[widx(ldw, Sb[b].R + t, qw)] : 0ull;
-  }
-  for (int e = tid; e < 64 * s_eff * s_eff; e += kTrsmThreads) {
-    const int ri = e / s_eff, b = e - ri * s_eff;
-    const int c = ri >> 6, t = ri & 63;
-    Cf[ri][b] = (b < c && t < Sb[c].r) ? W[widx(ldw, Sb[c].R + t, q0 + b)] : 0ull;
-  }
-  for (int e = tid; e < 64 * s_eff; e += kTrsmThreads) Li[e >> 6][e & 63] = w.Linv[(size_t)(q0 + (e >> 6)) * 64 + (e & 63)];
-  __syncthreads();
-  for (int b = 0; b < s_eff; ++b) {
-    const int rb = Sb[b].r;
-    if (rb == 0) continue;
-    // tables over the rows of X_b
-    if (tid < 256) {
-      const int g = tid >> 4, c = tid & 15;
-      uint64_t v[4];
-      for (int j = 0; j < 4; ++j) v[j] = X[64 * b + 4 * g + j][c];
-      uint64_t cur = 0ull;
-      for (int j = 0; j < 16; ++j) {
-        T[g][j ^ (j >> 1)][c] = cur;
-        if (j < 15) cur ^= v[__builtin_ctz(j + 1)];
-      }
-    }
-    __syncthreads();
-    {
-      const int t = 4 * wv + h;  // 16 waves x 4 groups = 64 rows
-      if (t < rb) {
-        const uint64_t l = Li[b][t];
-        uint64_t v = 0ull;
-#pragma unroll
-        for (int g = 0; g < 16; ++g) v ^= T[g][(l >> (4 * g)) & 15u][wl];
-        X[64 * b + t][wl] = v;
-      }
-    }
-    __syncthreads();
-    if (b == s_eff - 1) break;
-    if (tid < 256) {
-      const int g = tid >> 4, c = tid & 15;
-      uint64_t v[4];
-      for (int j = 0; j < 4; ++j) v[j] = X[64 * b + 4 * g + j][c];
-      uint64_t cur = 0ull;
-      for (int j = 0; j < 16; ++j) {
-        T[g][j ^ (j >> 1)][c] = cur;
-        if (j < 15) cur ^= v[__builtin_ctz(j + 1)];
-      }
-    }
-    __syncthreads();
-    // multipliers have no bits at or beyond rb, so unused tables contribute entry 0 = 0
-    for (int ri = 64 * (b + 1) + 4 * wv + h; ri < 64 * s_eff; ri += kTrsmThreads / 16) {
-      const int c = ri >> 6, t = ri & 63;
-      if (t < Sb[c].r) {
-        const uint64_t l = Cf[ri][b];
-        uint64_t v = 0ull;
-#pragma unroll
-        for (int g = 0; g < 16; ++g) v ^= T[g][(l >> (4 * g)) & 15u][wl];
-        X[ri][wl] ^= v;
-      }
-    }
-    __syncthreads();
-  }
-  for (int ri = tid >> 4; ri < 64 * s_eff; ri += kTrsmThreads / 16) {
-    const int b = ri >> 6, t = ri & 63;
-    if (qok && t < Sb[b].r) W[widx(ldw, Sb[b].R + t, qw)] = X[ri][wl];
-  }
-}
-
-hipError_t launch_trsm(const DecWork &w, int q0, int s_eff, hipStream_t s) {
-  const int qc0 = q0 + s_eff;
-  if (qc0 >= w.Mw) return hipSuccess;
-  const int blocks = ((w.Mw - 1) >> 4) - (qc0 >> 4) + 1;
-  hipLaunchKernelGGL(k_trsm, dim3((unsigned)blocks), dim3(kTrsmThreads), 0, s, w, q0, s_eff);
+hipError_t launch_post(const DecWork &w, int q0, int s_eff, hipStream_t s) {
+  const int64_t rows_wg = (w.n + kRowsPerWG - 1) / kRowsPerWG;
+  const int64_t blocks = (int64_t)w.NB + rows_wg;
+  hipLaunchKernelGGL(k_post, dim3((unsigned)blocks), dim3(kPostThreads), 0, s, w, q0, s_eff);
   return hipGetLastError();
 }
 
