@@ -109,6 +109,9 @@ int gf2_solve(const gf2_mat *A, const gf2_mat *B, const gf2_mat *X, uint64_t *co
  *   "panel_gemm_variant" : product-kernel variant for the trailing update (-1 = automatic)
  *   "chain_cus"          : CUs reserved for the pivot chain through CU-masked
  *                          streams (0 = two unmasked streams, the default)
+ *   "overlap_lookups"    : size of a panel's bulk update (table lookups) from
+ *                          which the next panel's columns are updated concurrently
+ *                          with it rather than before it
  * Returns 0, or GF2_EINVAL for an unknown name or out-of-range value.
  */
 int gf2_set_param(const char *name, int64_t value);

@@ -35,6 +35,9 @@ int g_panel_gemm_variant = -1;  // product-kernel variant for the trailing updat
 // plain streams (the default: measured faster, since a masked product launch
 // leaves the CUs of the reserved range idle and unbalances its XCD)
 int g_chain_cus = 0;
+// bulk-update size (table lookups) above which the next panel's columns are
+// updated concurrently with the bulk update instead of before it
+double g_overlap_lookups = 1.2e9;
 
 // Per device: the two internal streams of the look-ahead pipeline.  The pivot
 // chain of panel J+1 (panel and row kernels) runs on `chain`, restricted to a
@@ -293,9 +296,38 @@ int factor(const gf2_mat *A, DecWork &w, hipStream_t user) {
   HIPCHK(launch_init_state(w, G));
   HIPCHK(launch_pack(*A, w.W, w.ldw, w.n, w.m, w.NB, G));
   const int S = g_panel_words;
+  int prev = -1;
+  if (g_chain_cus == 0) {
+    // Main stream G: post(J), next panel's columns, chain(J+1), in order (no
+    // stream hop before the chain).  Bulk stream Cs: the rest of panel J's
+    // update, started after post(J) when it clearly outlasts the chain (it then
+    // runs beside the next panel's columns and the chain), else after the next
+    // panel's columns.  post(J+1) waits for it.
+    if ((rc = chain(w, 0, w.Mw < S ? w.Mw : S, -1, G))) return rc;
+    for (int q0 = 0; q0 < w.Mw; q0 += S) {
+      const int s_eff = (w.Mw - q0) < S ? (w.Mw - q0) : S;
+      HIPCHK(launch_post(w, q0, s_eff, G));  // row exchanges, multipliers, pivot rows in echelon form
+      const int nq0 = q0 + s_eff;
+      if (nq0 < w.Mw) {
+        const int ns = (w.Mw - nq0) < S ? (w.Mw - nq0) : S;
+        // lookups of the bulk update (rows left >= n - 64 * sub-panels done)
+        const int64_t rows_left = w.n - 64ll * nq0;
+        const double bulk = (double)(rows_left > 0 ? rows_left : 0) * (double)(w.Mw - nq0 - ns) * 8.0 * s_eff;
+        const bool early = bulk >= g_overlap_lookups;
+        if (early && (rc = link(P, G, Cs))) return rc;
+        if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0, nq0 + ns, G))) return rc;  // next panel's columns
+        if (!early && (rc = link(P, G, Cs))) return rc;
+        if ((rc = chain(w, nq0, ns, prev, G))) return rc;                           // look-ahead
+        if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0 + ns, w.Mw, Cs))) return rc; // the rest
+        if ((rc = link(P, Cs, G))) return rc;
+      }
+      prev = q0;
+    }
+    return link(P, G, user);
+  }
+  // CU-masked pair: the chain runs on its reserved CUs (stream Cs).
   if ((rc = link(P, G, Cs))) return rc;
   if ((rc = chain(w, 0, w.Mw < S ? w.Mw : S, -1, Cs))) return rc;
-  int prev = -1;
   for (int q0 = 0; q0 < w.Mw; q0 += S) {
     const int s_eff = (w.Mw - q0) < S ? (w.Mw - q0) : S;
     if ((rc = link(P, Cs, G))) return rc;  // panel J's chain is done
@@ -303,10 +335,10 @@ int factor(const gf2_mat *A, DecWork &w, hipStream_t user) {
     const int nq0 = q0 + s_eff;
     if (nq0 < w.Mw) {
       const int ns = (w.Mw - nq0) < S ? (w.Mw - nq0) : S;
-      if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0, nq0 + ns, G))) return rc;  // next panel's columns
+      if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0, nq0 + ns, G))) return rc;   // next panel's columns
       if ((rc = link(P, G, Cs))) return rc;
-      if ((rc = chain(w, nq0, ns, prev, Cs))) return rc;                          // look-ahead
-      if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0 + ns, w.Mw, G))) return rc; // the rest
+      if ((rc = chain(w, nq0, ns, prev, Cs))) return rc;                           // look-ahead
+      if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0 + ns, w.Mw, G))) return rc;  // the rest
     }
     prev = q0;
   }
@@ -357,6 +389,11 @@ int gf2_set_param(const char *name, int64_t value) {
   if (!strcmp(name, "panel_gemm_variant")) {
     if (value < -1 || value >= kGemmVariants) return fail(GF2_EINVAL, "panel_gemm_variant out of range");
     g_panel_gemm_variant = (int)value;
+    return GF2_OK;
+  }
+  if (!strcmp(name, "overlap_lookups")) {
+    if (value < 0) return fail(GF2_EINVAL, "overlap_lookups must be >= 0");
+    g_overlap_lookups = (double)value;
     return GF2_OK;
   }
   if (!strcmp(name, "chain_cus")) {
