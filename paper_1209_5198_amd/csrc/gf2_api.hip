@@ -199,10 +199,7 @@ int device_cus() {
 
 // active_rows: rows expected to do work (used only to pick a tile size)
 int run_gemm(GemmArgs &a, int64_t nrows_max, int variant, int64_t active_rows, hipStream_t s) {
-  if (variant < 0) {
-    const int blocks_y = ((a.qc1 - 1) >> 4) - (a.qc0 >> 4) + 1;
-    variant = gemm_auto_variant(active_rows, blocks_y, device_cus());
-  }
+  if (variant < 0) variant = gemm_auto_variant(active_rows, a.qc0, a.qc1, device_cus());
   hipEvent_t e0 = nullptr;
   int rc = profile_begin(s, &e0);
   if (rc) return rc;

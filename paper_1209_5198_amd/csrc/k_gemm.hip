@@ -616,6 +616,164 @@ __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
 }
 
 
+// Narrow product for an 8-word column range [qc0, qc0+8) (qc0 % 8 == 0): the
+// update of the next panel's columns.  Entries are 64 bytes (8 words) and a
+// step takes a whole 64-bit A word: eight tables of 256 entries (128 KB),
+// tables g = 4p + s at byte p*65536 + idx*256 + s*64 + word*8.  A wave is 16
+// groups of 4 lanes; lane w4 owns words 2*w4, 2*w4+1 and a 16-byte read
+// fetches them.  In read i of a row, group G uses table (i + G) mod 4 of half
+// p = i / 4, so the four groups of every 16 lanes cover 256 distinct bytes.
+template <int NT, int TM>
+__global__ __launch_bounds__(NT) void k_gemm_narrow(GemmArgs a) {
+  constexpr int NW = NT / 64;          // waves
+  constexpr int RPL = TM / (16 * NW);  // rows per lane
+  constexpr int JOBS = NT / 4;         // table-build jobs (4 threads each, one word pair per thread)
+  constexpr int EPJ = 8 * 256 / JOBS;  // entries per job
+  constexpr int LOGE = EPJ == 8 ? 3 : (EPJ == 16 ? 4 : (EPJ == 32 ? 5 : 6));
+  static_assert(RPL * 16 * NW == TM && RPL >= 1, "tile");
+  static_assert(EPJ == 8 || EPJ == 16 || EPJ == 32 || EPJ == 64, "build split");
+  static_assert(TM % NT == 0, "A staging");
+  __shared__ uint64_t T[2][256][4][8];
+  __shared__ uint64_t As[TM];          // the tile's A word for the current 64 inner bits
+
+  if (a.skip_flag && *a.skip_flag == 0u) return;  // the Schur complement is already zero
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, G = lane >> 2, w4 = lane & 3;
+  const int64_t q8 = a.qc0;  // first word of the range
+  const int64_t qw = q8 + 2 * w4;
+  const bool ok0 = qw < a.qc1, ok1 = qw + 1 < a.qc1;
+
+  const int64_t tile0 = a.row_tile0 + (int64_t)blockIdx.x * TM;
+  int64_t rb = tile0;
+  if (a.bsub) {
+    const int64_t d = a.bsub[a.kwords - 1].R + a.bsub[a.kwords - 1].r;
+    if (d > rb) rb = d;
+  }
+  int64_t re = tile0 + TM < a.row_end ? tile0 + TM : a.row_end;
+  if (rb >= re) return;
+
+  // rows of this lane: tile0 + 16*wv + G + 16*NW*u
+  int ulo, uhi;
+  lane_rows<RPL, 16 * NW>(tile0, 16 * wv + G, rb, re, ulo, uhi);
+  const size_t cbase = widx(a.ldC, tile0 + 16 * wv + G, q8) + 2 * w4;  // (q8 % 16) + 2*w4 stays in the block
+  uint64_t acc[RPL][2];
+  {
+    uint64_t *C = a.C;
+    asm volatile("" : "+s"(C));
+    load_acc2<RPL, 16 * NW>(acc, C + cbase, a.accumulate && ok0, a.accumulate && ok1, ulo, uhi);
+  }
+
+  const int bw4 = tid & 3;
+  const int job = tid >> 2;
+  const int gb = job / (256 / EPJ), uu = job % (256 / EPJ);  // table 0..7, entry block
+  const int64_t bq = q8 + 2 * bw4;
+  const bool bok0 = bq < a.qc1, bok1 = bq + 1 < a.qc1;
+
+  // B rows of table gb of inner word kw (bits [64 kw + 8 gb, +8))
+  auto load_b = [&](int kw, uint64_t (&bv)[8][2]) {
+    int64_t browR = 64ll * kw;
+    int blim;
+    if (a.bsub) {
+      browR = a.bsub[kw].R;
+      blim = a.bsub[kw].r;
+    } else {
+      const int64_t left = a.b_rows - 64ll * kw;
+      blim = left >= 64 ? 64 : (left > 0 ? (int)left : 0);
+    }
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int t = 8 * gb + b;
+      const uint64_t *p = a.B + widx(a.ldB, browR + t, bq);
+      bv[b][0] = (bok0 && t < blim) ? p[0] : 0ull;
+      bv[b][1] = (bok1 && t < blim) ? p[1] : 0ull;
+    }
+  };
+  constexpr int APT = TM / NT;
+  auto load_a = [&](int kw, uint64_t (&av)[APT]) {
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+      const int64_t i = tile0 + tid + (int64_t)j * NT;
+      av[j] = (i >= rb && i < re) ? a.A[widx(a.ldA, i, a.a_word0 + kw)] : 0ull;
+    }
+  };
+
+  uint64_t bv[8][2], av[APT];
+  load_b(0, bv);
+  load_a(0, av);
+  const char *Tb = (const char *)&T[0][0][0][0];
+  uint32_t lbase[4], sel[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int s = (i + G) & 3;
+    lbase[i] = ((uint32_t)s << 6) | ((uint32_t)w4 << 4);
+    sel[i] = 0x0C0C0000u | ((4u + (uint32_t)s) << 8);  // [lane base | byte s of the A half | 0 | 0]
+  }
+  for (int kw = 0; kw < a.kwords; ++kw) {
+    __syncthreads();  // previous lookups finished: T and As are free
+#pragma unroll
+    for (int j = 0; j < APT; ++j) As[tid + j * NT] = av[j];
+    {
+      uint64_t c0 = 0ull, c1 = 0ull;
+#pragma unroll
+      for (int b = LOGE; b < 8; ++b)
+        if ((uu >> (b - LOGE)) & 1) {
+          c0 ^= bv[b][0];
+          c1 ^= bv[b][1];
+        }
+#pragma unroll
+      for (int j = 0; j < EPJ; ++j) {
+        const int gj = j ^ (j >> 1);
+        *(ulonglong2 *)&T[gb >> 2][EPJ * uu + gj][gb & 3][2 * bw4] = make_ulonglong2(c0, c1);
+        if (j < EPJ - 1) {
+          c0 ^= bv[__builtin_ctz(j + 1)][0];
+          c1 ^= bv[__builtin_ctz(j + 1)][1];
+        }
+      }
+    }
+    if (kw + 1 < a.kwords) {  // in flight during the lookups
+      load_b(kw + 1, bv);
+      load_a(kw + 1, av);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      const uint64_t aw = As[16 * (wv + NW * u) + G];
+      const uint32_t alo = (uint32_t)aw, ahi = (uint32_t)(aw >> 32);
+      uint4 t[8];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        t[i] = *(const uint4 *)(Tb + __builtin_amdgcn_perm(alo, lbase[i], sel[i]));
+        t[4 + i] = *(const uint4 *)(Tb + (__builtin_amdgcn_perm(ahi, lbase[i], sel[i]) | 0x10000u));
+      }
+      uint32_t x0 = (uint32_t)acc[u][0], x1 = (uint32_t)(acc[u][0] >> 32);
+      uint32_t x2 = (uint32_t)acc[u][1], x3 = (uint32_t)(acc[u][1] >> 32);
+#pragma unroll
+      for (int i = 0; i < 8; i += 2) {
+        x0 = __builtin_amdgcn_bitop3_b32(x0, t[i].x, t[i + 1].x, 0x96);
+        x1 = __builtin_amdgcn_bitop3_b32(x1, t[i].y, t[i + 1].y, 0x96);
+        x2 = __builtin_amdgcn_bitop3_b32(x2, t[i].z, t[i + 1].z, 0x96);
+        x3 = __builtin_amdgcn_bitop3_b32(x3, t[i].w, t[i + 1].w, 0x96);
+      }
+      acc[u][0] = ((uint64_t)x1 << 32) | x0;
+      acc[u][1] = ((uint64_t)x3 << 32) | x2;
+    }
+  }
+
+  uint64_t any;
+  {
+    uint64_t *C = a.C;
+    asm volatile("" : "+s"(C));
+    any = store_acc2<RPL, 16 * NW>(acc, C + cbase, ok0, ok1, ulo, uhi);
+  }
+  if (a.nzflag) {
+    if (__ballot(any != 0ull) != 0ull && lane == 0) atomicOr(a.nzflag, 1u);
+  }
+  if (a.work && tid == 0) {
+    const unsigned long long words = (unsigned long long)(a.qc1 - a.qc0);
+    atomicAdd(a.work, (unsigned long long)(re - rb) * words * (unsigned long long)a.kwords * 8ull);
+  }
+}
+
 // Product-kernel variants (same results; chosen per call by a tuning knob, or
 // automatically when the knob is -1):
 //   0: four tables / 32 inner bits, 1024 threads, 1024-row tiles
@@ -629,19 +787,27 @@ __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
 //   8: four tables with 16-byte lookups, 512 threads, 1024-row tiles
 //   9: four tables with 16-byte lookups, 256 threads, 256-row tiles
 //  10: four tables with 16-byte lookups, 256 threads, 512-row tiles
+//  11: eight 64-byte-entry tables, 256 threads, 256-row tiles (8-word ranges only)
+//  12: eight 64-byte-entry tables, 256 threads, 512-row tiles (8-word ranges only)
 // Automatic choice: the largest tile that still gives at least one workgroup
 // per CU for the rows expected to be active; small launches get small tiles.
 int gemm_tile_rows(int v) {
   switch (v) {
     case 2: case 4: case 7: return 2048;
-    case 5: case 10: return 512;
-    case 6: case 9: return 256;
+    case 5: case 10: case 12: return 512;
+    case 6: case 9: case 11: return 256;
     default: return 1024;
   }
 }
 
-int gemm_auto_variant(int64_t active_rows, int blocks_y, int ncu) {
+// An 8-word column range starting at a multiple of 8 (the next panel's
+// columns) fits the narrow kernel.
+bool gemm_narrow_ok(int qc0, int qc1) { return qc0 % 8 == 0 && qc1 > qc0 && qc1 - qc0 <= 8; }
+
+int gemm_auto_variant(int64_t active_rows, int qc0, int qc1, int ncu) {
   const int64_t want = ncu;
+  if (gemm_narrow_ok(qc0, qc1)) return (active_rows + 511) / 512 >= want ? 12 : 11;
+  const int blocks_y = ((qc1 - 1) >> 4) - (qc0 >> 4) + 1;
   const int order[4] = {7, 8, 10, 9};
   for (int i = 0; i < 4; ++i) {
     const int tm = gemm_tile_rows(order[i]);
@@ -652,6 +818,7 @@ int gemm_auto_variant(int64_t active_rows, int blocks_y, int ncu) {
 
 hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t s) {
   if (nrows_max <= 0 || a.qc1 <= a.qc0) return hipSuccess;
+  if ((v == 11 || v == 12) && !gemm_narrow_ok(a.qc0, a.qc1)) v = 9;  // narrow kernels need an 8-word range
   const int TM = gemm_tile_rows(v);
   const int64_t tiles = (nrows_max + TM - 1) / TM;
   const int blocks_y = ((a.qc1 - 1) >> 4) - (a.qc0 >> 4) + 1;
@@ -667,6 +834,8 @@ hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t 
     case 8: hipLaunchKernelGGL((k_gemm_wide<512, 1024>), grid, dim3(512), 0, s, a); break;
     case 9: hipLaunchKernelGGL((k_gemm_wide<256, 256>), grid, dim3(256), 0, s, a); break;
     case 10: hipLaunchKernelGGL((k_gemm_wide<256, 512>), grid, dim3(256), 0, s, a); break;
+    case 11: hipLaunchKernelGGL((k_gemm_narrow<256, 256>), dim3((unsigned)tiles), dim3(256), 0, s, a); break;
+    case 12: hipLaunchKernelGGL((k_gemm_narrow<256, 512>), dim3((unsigned)tiles), dim3(256), 0, s, a); break;
     default: hipLaunchKernelGGL((k_gemm_quad<1024, 1024>), grid, dim3(1024), 0, s, a); break;
   }
   return hipGetLastError();

@@ -134,7 +134,8 @@ def test_decompose_panel_width_invariant(g, orc, panel_words):
                                         ("panel_gemm_variant", 4), ("panel_gemm_variant", 5),
                                         ("panel_gemm_variant", 6), ("panel_gemm_variant", 7),
                                         ("panel_gemm_variant", 8), ("panel_gemm_variant", 9),
-                                        ("panel_gemm_variant", 10), ("overlap_lookups", 0),
+                                        ("panel_gemm_variant", 10), ("panel_gemm_variant", 11),
+                                        ("panel_gemm_variant", 12), ("overlap_lookups", 0),
                                         ("overlap_lookups", 10 ** 15)])
 def test_decompose_tuning_invariant(g, orc, knob, value):
     """Look-ahead split and product-kernel variant do not change any result."""
@@ -151,7 +152,7 @@ def test_decompose_tuning_invariant(g, orc, knob, value):
     assert_same_ple(got, ref, (knob, value))
 
 
-@pytest.mark.parametrize("variant", list(range(11)))
+@pytest.mark.parametrize("variant", list(range(13)))
 def test_matmul_variants(g, orc, variant):
     n, k, m = 2100, 1300, 2500
     say("matmul variant", variant)
@@ -164,6 +165,24 @@ def test_matmul_variants(g, orc, variant):
     finally:
         g.gf2_set_param("gemm_variant", -1)
     assert np.array_equal(C.to_rowmajor(), ref)
+
+
+@pytest.mark.parametrize("variant", [-1, 11, 12])
+@pytest.mark.parametrize("n,k,m", [(3000, 1300, 512), (2500, 700, 300), (1030, 64, 64), (700, 2049, 100)])
+def test_matmul_narrow(g, orc, variant, n, k, m):
+    """Products at most 8 words wide (the next-panel update shape), narrow kernels."""
+    say("matmul narrow", variant, n, k, m)
+    A = synth.dense(24, 1, n, k)
+    B = synth.dense(24, 2, k, m)
+    C0 = synth.dense(24, 3, n, m)
+    ref = orc.matmul(A, B, n, k, m, C=C0)
+    Cg = g.Mat.from_rowmajor(C0, n, m)
+    g.gf2_set_param("gemm_variant", variant)
+    try:
+        g.gf2_matmul(Cg, g.Mat.from_rowmajor(A, n, k), g.Mat.from_rowmajor(B, k, m), accumulate=True)
+    finally:
+        g.gf2_set_param("gemm_variant", -1)
+    assert np.array_equal(Cg.to_rowmajor(), ref)
 
 
 def test_decompose_special(g, orc):
