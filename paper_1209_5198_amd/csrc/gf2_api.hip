@@ -149,6 +149,7 @@ size_t decomp_bytes(int64_t n, int64_t m, int64_t ldw, int64_t Mw, int64_t NB) {
   b += align256((size_t)kMaxPanelWords * 64 * 2 * 4);
   b += align256((size_t)Mw * 4);
   b += align256((size_t)n * 4);
+  b += align256((size_t)kPanelTabWords * 8);
   (void)m;
   return b;
 }
@@ -166,6 +167,7 @@ void carve_decomp(Carver &c, DecWork &w) {
   w.bp_list = c.take<int32_t>((size_t)kMaxPanelWords * 64 * 2);
   w.nzflag = c.take<uint32_t>(w.Mw);
   w.lvl = c.take<int32_t>(w.n);
+  w.ptab = c.take<uint64_t>(kPanelTabWords);
 }
 
 int profile_begin(hipStream_t s, hipEvent_t *a) {

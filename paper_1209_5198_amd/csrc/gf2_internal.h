@@ -68,17 +68,22 @@ struct DecWork {
   int32_t *bp_list;  // [kMaxPanelWords * 64 * 2]
   uint32_t *nzflag;  // [Mw]  trailing-update nonzero flag per panel
   int32_t *lvl;      // [n]   16*q0 + L: sub-panels 0..L-1 of the panel at q0 applied to row p
+  uint64_t *ptab;    // [kPanelTabWords] 4-bit tables of the current panel (written by its chain)
 };
 
 constexpr int kMaxPanelWords = 8;       // s <= 8 sub-panels per trailing-update panel
 constexpr int kWin = 128;               // window rows examined per sub-panel
+// words of one panel's 4-bit tables: Tz (y = x * Zc_c) for 8 sub-panels and Te
+// (y * E_c[w]) for the 28 sub-panel / later-word pairs, 16 x 16 entries each
+constexpr int kPanelTabWords = (kMaxPanelWords + kMaxPanelWords * (kMaxPanelWords - 1) / 2) * 256;
 
 // ---------------------------------------------------------------- product arguments
 struct GemmArgs {
   const uint64_t *A; int64_t ldA; int32_t a_word0;   // A words [a_word0, a_word0 + kwords)
   const uint64_t *B; int64_t ldB; int64_t b_rows;    // plain B: row k for k < b_rows
   const SubInfo *bsub;                               // mapped B: row (kw, t) -> bsub[kw].R + t, t < bsub[kw].r;
-                                                     // then also rows >= bsub[kwords-1].R + bsub[kwords-1].r
+                                                     // then also rows >= bsub[kwords-1].R + bsub[kwords-1].r;
+                                                     // with bsub, kwords <= kMaxPanelWords
   uint64_t *C; int64_t ldC;
   int64_t row_tile0;                                 // first row of tile 0
   int64_t row_end;                                   // rows < row_end

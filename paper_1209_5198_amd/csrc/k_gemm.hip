@@ -408,18 +408,21 @@ __device__ inline uint64_t store_acc2(const uint64_t (&acc)[RPL][2], uint64_t *C
 
 template <int NT, int TM>
 __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
+  constexpr int UB = 2;                // rows per lane looked up together
   constexpr int NW = NT / 64;          // waves
   constexpr int RPL = TM / (8 * NW);   // rows per lane
   constexpr int JOBS = NT / 8;         // table-build jobs (8 threads each, one word pair per thread)
   constexpr int EPJ = 4 * 256 / JOBS;  // entries per job
   constexpr int LOGE = EPJ == 8 ? 3 : (EPJ == 16 ? 4 : (EPJ == 32 ? 5 : 6));
-  static_assert(RPL * 8 * NW == TM && RPL % 2 == 0, "tile");
+  static_assert(RPL * 8 * NW == TM && RPL % UB == 0, "tile");
   static_assert(EPJ == 8 || EPJ == 16 || EPJ == 32 || EPJ == 64, "build split");
   static_assert(TM % NT == 0, "A staging");
   // Tables g = 2p + s stored as T[p][idx][s][word]: entry idx of table g, word w
   // at byte p*65536 + idx*256 + s*128 + w*8.
   __shared__ uint64_t T[2][256][2][TW];
   __shared__ uint32_t As[2 * TM];      // the tile's A word for the current 64 inner bits
+  __shared__ int64_t sR[kMaxPanelWords];  // pivot-row ranges of a mapped B (at most one panel)
+  __shared__ int sr[kMaxPanelWords];
 
   if (a.skip_flag && *a.skip_flag == 0u) return;  // the Schur complement is already zero
   const int tid = threadIdx.x;
@@ -440,44 +443,13 @@ __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
   // rows of this lane: tile0 + 8*wv + G + 8*NW*u
   int ulo, uhi;
   lane_rows<RPL, 8 * NW>(tile0, 8 * wv + G, rb, re, ulo, uhi);
-  // With accumulation, C arrives in chunks of CH rows per lane, one chunk per
-  // step, so its HBM latency hides behind the lookups instead of stalling the
-  // prologue (one workgroup per CU leaves nothing else to overlap it with).
-  constexpr int CH = 2, NCH = RPL / CH;
-  const int nh = 2 * a.kwords;
-  const bool cstream = a.accumulate && nh >= NCH;
   uint64_t acc[RPL][2];
   {
     uint64_t *C = a.C;
     asm volatile("" : "+s"(C));
     const uint64_t *Cl = C + (((int64_t)blk * a.ldC + tile0 + 8 * wv + G) * TW + 2 * w2);
-    const bool pro = a.accumulate && !cstream;
-    load_acc2<RPL, 8 * NW>(acc, Cl, pro && ok0, pro && ok1, ulo, uhi);
+    load_acc2<RPL, 8 * NW>(acc, Cl, a.accumulate && ok0, a.accumulate && ok1, ulo, uhi);
   }
-  uint64_t cb[CH][2];
-  auto load_chunk = [&](int c) {
-    uint64_t *C = a.C;
-    asm volatile("" : "+s"(C));
-    const uint64_t *Cl = C + (((int64_t)blk * a.ldC + tile0 + 8 * wv + G) * TW + 2 * w2);
-#pragma unroll
-    for (int i = 0; i < CH; ++i) {
-      const int u = c * CH + i;
-      cb[i][0] = 0ull;
-      cb[i][1] = 0ull;
-      if (u >= ulo && u < uhi) {
-        const uint64_t *p = Cl + (int64_t)u * (8 * NW) * TW;
-        if (ok0 && ok1) {
-          const ulonglong2 v = *(const ulonglong2 *)p;
-          cb[i][0] = v.x;
-          cb[i][1] = v.y;
-        } else {
-          if (ok0) cb[i][0] = p[0];
-          if (ok1) cb[i][1] = p[1];
-        }
-      }
-    }
-  };
-  if (cstream) load_chunk(0);
 
   const int bw2 = tid & 7;
   const int job = tid >> 3;
@@ -485,23 +457,31 @@ __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
   const int64_t bq = (int64_t)blk * TW + 2 * bw2;
   const bool bok0 = bq >= a.qc0 && bq < a.qc1, bok1 = bq + 1 >= a.qc0 && bq + 1 < a.qc1;
 
+  // B rows of table g_b for step hh (inner bits [32 hh + 8 g_b, +8)): raw
+  // 16-byte loads from a clamped (always valid) row; rows past the operand are
+  // masked when the table is built, a full step later, so the loads stay in
+  // flight during the lookups.
+  int bl_lim = 0, bl_half = 0;  // row limit and half of the loaded step
   auto load_b = [&](int hh, uint64_t (&bv)[8][2]) {
-    const int kw = hh >> 1, half = hh & 1;
+    const int kw = hh >> 1;
     int64_t browR = 64ll * kw;
     int blim;
     if (a.bsub) {
-      browR = a.bsub[kw].R;
-      blim = a.bsub[kw].r;
+      browR = sR[kw];
+      blim = sr[kw];
     } else {
       const int64_t left = a.b_rows - 64ll * kw;
       blim = left >= 64 ? 64 : (left > 0 ? (int)left : 0);
     }
+    bl_lim = blim;
+    bl_half = hh & 1;
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const int t = 32 * half + 8 * g_b + b;
-      const uint64_t *p = a.B + widx(a.ldB, browR + t, bq);
-      bv[b][0] = (bok0 && t < blim) ? p[0] : 0ull;
-      bv[b][1] = (bok1 && t < blim) ? p[1] : 0ull;
+      int64_t row = browR + 32 * (hh & 1) + 8 * g_b + b;
+      row = row < a.ldB ? row : a.ldB - 1;
+      const ulonglong2 v = *(const ulonglong2 *)(a.B + widx(a.ldB, row, bq));
+      bv[b][0] = v.x;
+      bv[b][1] = v.y;
     }
   };
   constexpr int APT = TM / NT;
@@ -509,10 +489,17 @@ __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
 #pragma unroll
     for (int j = 0; j < APT; ++j) {
       const int64_t i = tile0 + tid + (int64_t)j * NT;
-      av[j] = (i >= rb && i < re) ? a.A[widx(a.ldA, i, a.a_word0 + kw)] : 0ull;
+      av[j] = a.A[widx(a.ldA, i < a.ldA ? i : a.ldA - 1, a.a_word0 + kw)];  // masked when staged
     }
   };
 
+  if (a.bsub) {
+    if (tid < a.kwords) {
+      sR[tid] = a.bsub[tid].R;
+      sr[tid] = a.bsub[tid].r;
+    }
+    __syncthreads();
+  }
   uint64_t bv[8][2], av[APT];
   load_b(0, bv);
   load_a(0, av);
@@ -525,29 +512,26 @@ __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
     lbase[g] = ((uint32_t)(gg >> 1) << 16) | ((uint32_t)(gg & 1) << 7) | ((uint32_t)w2 << 4);
     sel[g] = 0x0C020000u | ((4u + (uint32_t)gg) << 8);  // [lane base | byte gg of A | pair | 0]
   }
+  const int nh = 2 * a.kwords;
   for (int hh = 0; hh < nh; ++hh) {
     const int half = hh & 1;
-    if (cstream && hh < NCH) {  // chunk hh (requested one step earlier) joins its accumulators
-#pragma unroll
-      for (int c = 0; c < NCH; ++c)
-        if (c == hh) {
-#pragma unroll
-          for (int i = 0; i < CH; ++i) {
-            acc[c * CH + i][0] ^= cb[i][0];
-            acc[c * CH + i][1] ^= cb[i][1];
-          }
-        }
-      if (hh + 1 < NCH) load_chunk(hh + 1);
-    }
     __syncthreads();  // previous lookups finished: T and As are free
     if (half == 0) {
 #pragma unroll
       for (int j = 0; j < APT; ++j) {
-        As[2 * (tid + j * NT)] = (uint32_t)av[j];
-        As[2 * (tid + j * NT) + 1] = (uint32_t)(av[j] >> 32);
+        const int64_t i = tile0 + tid + (int64_t)j * NT;
+        const uint64_t v = (i >= rb && i < re) ? av[j] : 0ull;
+        As[2 * (tid + j * NT)] = (uint32_t)v;
+        As[2 * (tid + j * NT) + 1] = (uint32_t)(v >> 32);
       }
     }
     {
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {  // rows past the operand, words outside [qc0, qc1): zero
+        const bool ok = 32 * bl_half + 8 * g_b + b < bl_lim;
+        bv[b][0] = (ok && bok0) ? bv[b][0] : 0ull;
+        bv[b][1] = (ok && bok1) ? bv[b][1] : 0ull;
+      }
       uint64_t c0 = 0ull, c1 = 0ull;
 #pragma unroll
       for (int b = LOGE; b < 8; ++b)
@@ -569,17 +553,17 @@ __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
     if (half == 0 && (hh >> 1) + 1 < a.kwords) load_a((hh >> 1) + 1, av);
     __syncthreads();
 #pragma unroll
-    for (int u0 = 0; u0 < RPL; u0 += 2) {
-      uint32_t a32[2];
+    for (int u0 = 0; u0 < RPL; u0 += UB) {
+      uint32_t a32[UB];
 #pragma unroll
-      for (int v = 0; v < 2; ++v) a32[v] = As[2 * (8 * (wv + NW * (u0 + v)) + G) + half];
-      uint4 t[2][4];
+      for (int v = 0; v < UB; ++v) a32[v] = As[2 * (8 * (wv + NW * (u0 + v)) + G) + half];
+      uint4 t[UB][4];
 #pragma unroll
-      for (int v = 0; v < 2; ++v)
+      for (int v = 0; v < UB; ++v)
 #pragma unroll
         for (int g = 0; g < 4; ++g) t[v][g] = *(const uint4 *)(Tb + __builtin_amdgcn_perm(a32[v], lbase[g], sel[g]));
 #pragma unroll
-      for (int v = 0; v < 2; ++v) {
+      for (int v = 0; v < UB; ++v) {
         uint32_t x0 = (uint32_t)acc[u0 + v][0], x1 = (uint32_t)(acc[u0 + v][0] >> 32);
         uint32_t x2 = (uint32_t)acc[u0 + v][1], x3 = (uint32_t)(acc[u0 + v][1] >> 32);
         x0 = __builtin_amdgcn_bitop3_b32(x0, t[v][0].x, t[v][1].x, 0x96);
@@ -616,32 +600,34 @@ __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
 }
 
 
-// Narrow product for an 8-word column range [qc0, qc0+8) (qc0 % 8 == 0): the
-// update of the next panel's columns.  Entries are 64 bytes (8 words) and a
-// step takes a whole 64-bit A word: eight tables of 256 entries (128 KB),
-// tables g = 4p + s at byte p*65536 + idx*256 + s*64 + word*8.  A wave is 16
-// groups of 4 lanes; lane w4 owns words 2*w4, 2*w4+1 and a 16-byte read
-// fetches them.  In read i of a row, group G uses table (i + G) mod 4 of half
-// p = i / 4, so the four groups of every 16 lanes cover 256 distinct bytes.
+// Narrow product (the next panel's columns): column tiles of 8 words (chunk
+// blockIdx.y of the 8-aligned chunks covering [qc0, qc1)), 64-byte entries
+// (8 words), and a step takes a whole 64-bit A word: eight tables of 256
+// entries (128 KB), so K = 512 takes 8 barrier-separated steps instead of 16.
+// Tables g = 4p + s at byte p*65536 + idx*256 + s*64 + word*8.
+// A wave is 16 groups of 4 lanes; lane w4 owns words 2*w4, 2*w4+1 and a 16-byte
+// read fetches them.  In read i of a row, group G uses table (i + G) mod 4 of
+// half p, so the four groups of every 16 lanes cover 256 distinct bytes.
 template <int NT, int TM>
 __global__ __launch_bounds__(NT) void k_gemm_narrow(GemmArgs a) {
-  constexpr int NW = NT / 64;          // waves
-  constexpr int RPL = TM / (16 * NW);  // rows per lane
-  constexpr int JOBS = NT / 4;         // table-build jobs (4 threads each, one word pair per thread)
-  constexpr int EPJ = 8 * 256 / JOBS;  // entries per job
-  constexpr int LOGE = EPJ == 8 ? 3 : (EPJ == 16 ? 4 : (EPJ == 32 ? 5 : 6));
+  constexpr int TPS = 8;                 // tables per step
+  constexpr int NW = NT / 64;            // waves
+  constexpr int RPL = TM / (16 * NW);    // rows per lane
+  constexpr int JOBS = NT / 4;           // table-build jobs (4 threads each, one word pair per thread)
+  constexpr int EPJ = TPS * 256 / JOBS;  // entries per job
+  constexpr int LOGE = EPJ == 4 ? 2 : (EPJ == 8 ? 3 : (EPJ == 16 ? 4 : (EPJ == 32 ? 5 : 6)));
   static_assert(RPL * 16 * NW == TM && RPL >= 1, "tile");
-  static_assert(EPJ == 8 || EPJ == 16 || EPJ == 32 || EPJ == 64, "build split");
+  static_assert(EPJ == 4 || EPJ == 8 || EPJ == 16 || EPJ == 32 || EPJ == 64, "build split");
   static_assert(TM % NT == 0, "A staging");
   __shared__ uint64_t T[2][256][4][8];
-  __shared__ uint64_t As[TM];          // the tile's A word for the current 64 inner bits
+  __shared__ uint64_t As[TM];            // the tile's A word for the current 64 inner bits
 
   if (a.skip_flag && *a.skip_flag == 0u) return;  // the Schur complement is already zero
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6, G = lane >> 2, w4 = lane & 3;
-  const int64_t q8 = a.qc0;  // first word of the range
+  const int64_t q8 = (int64_t)(a.qc0 & ~7) + 8ll * blockIdx.y;  // first word of this chunk
   const int64_t qw = q8 + 2 * w4;
-  const bool ok0 = qw < a.qc1, ok1 = qw + 1 < a.qc1;
+  const bool ok0 = qw >= a.qc0 && qw < a.qc1, ok1 = qw + 1 >= a.qc0 && qw + 1 < a.qc1;
 
   const int64_t tile0 = a.row_tile0 + (int64_t)blockIdx.x * TM;
   int64_t rb = tile0;
@@ -665,9 +651,9 @@ __global__ __launch_bounds__(NT) void k_gemm_narrow(GemmArgs a) {
 
   const int bw4 = tid & 3;
   const int job = tid >> 2;
-  const int gb = job / (256 / EPJ), uu = job % (256 / EPJ);  // table 0..7, entry block
+  const int gb = job / (256 / EPJ), uu = job % (256 / EPJ);  // table of the step, entry block
   const int64_t bq = q8 + 2 * bw4;
-  const bool bok0 = bq < a.qc1, bok1 = bq + 1 < a.qc1;
+  const bool bok0 = bq >= a.qc0 && bq < a.qc1, bok1 = bq + 1 >= a.qc0 && bq + 1 < a.qc1;
 
   // B rows of table gb of inner word kw (bits [64 kw + 8 gb, +8))
   auto load_b = [&](int kw, uint64_t (&bv)[8][2]) {
@@ -739,7 +725,7 @@ __global__ __launch_bounds__(NT) void k_gemm_narrow(GemmArgs a) {
     for (int u = 0; u < RPL; ++u) {
       const uint64_t aw = As[16 * (wv + NW * u) + G];
       const uint32_t alo = (uint32_t)aw, ahi = (uint32_t)(aw >> 32);
-      uint4 t[8];
+      uint4 t[TPS];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         t[i] = *(const uint4 *)(Tb + __builtin_amdgcn_perm(alo, lbase[i], sel[i]));
@@ -748,7 +734,7 @@ __global__ __launch_bounds__(NT) void k_gemm_narrow(GemmArgs a) {
       uint32_t x0 = (uint32_t)acc[u][0], x1 = (uint32_t)(acc[u][0] >> 32);
       uint32_t x2 = (uint32_t)acc[u][1], x3 = (uint32_t)(acc[u][1] >> 32);
 #pragma unroll
-      for (int i = 0; i < 8; i += 2) {
+      for (int i = 0; i < TPS; i += 2) {
         x0 = __builtin_amdgcn_bitop3_b32(x0, t[i].x, t[i + 1].x, 0x96);
         x1 = __builtin_amdgcn_bitop3_b32(x1, t[i].y, t[i + 1].y, 0x96);
         x2 = __builtin_amdgcn_bitop3_b32(x2, t[i].z, t[i + 1].z, 0x96);
@@ -769,7 +755,10 @@ __global__ __launch_bounds__(NT) void k_gemm_narrow(GemmArgs a) {
     if (__ballot(any != 0ull) != 0ull && lane == 0) atomicOr(a.nzflag, 1u);
   }
   if (a.work && tid == 0) {
-    const unsigned long long words = (unsigned long long)(a.qc1 - a.qc0);
+    int64_t lo = q8, hi = q8 + 8;
+    if (lo < a.qc0) lo = a.qc0;
+    if (hi > a.qc1) hi = a.qc1;
+    const unsigned long long words = hi > lo ? (unsigned long long)(hi - lo) : 0ull;
     atomicAdd(a.work, (unsigned long long)(re - rb) * words * (unsigned long long)a.kwords * 8ull);
   }
 }
@@ -787,8 +776,8 @@ __global__ __launch_bounds__(NT) void k_gemm_narrow(GemmArgs a) {
 //   8: four tables with 16-byte lookups, 512 threads, 1024-row tiles
 //   9: four tables with 16-byte lookups, 256 threads, 256-row tiles
 //  10: four tables with 16-byte lookups, 256 threads, 512-row tiles
-//  11: eight 64-byte-entry tables, 256 threads, 256-row tiles (8-word ranges only)
-//  12: eight 64-byte-entry tables, 256 threads, 512-row tiles (8-word ranges only)
+//  11: eight 64-byte-entry tables per step, 256 threads, 256 rows x 8 words
+//  12: eight 64-byte-entry tables per step, 256 threads, 512 rows x 8 words
 // Automatic choice: the largest tile that still gives at least one workgroup
 // per CU for the rows expected to be active; small launches get small tiles.
 int gemm_tile_rows(int v) {
@@ -818,11 +807,13 @@ int gemm_auto_variant(int64_t active_rows, int qc0, int qc1, int ncu) {
 
 hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t s) {
   if (nrows_max <= 0 || a.qc1 <= a.qc0) return hipSuccess;
-  if ((v == 11 || v == 12) && !gemm_narrow_ok(a.qc0, a.qc1)) v = 9;  // narrow kernels need an 8-word range
+
   const int TM = gemm_tile_rows(v);
   const int64_t tiles = (nrows_max + TM - 1) / TM;
   const int blocks_y = ((a.qc1 - 1) >> 4) - (a.qc0 >> 4) + 1;
   const dim3 grid((unsigned)tiles, (unsigned)blocks_y);
+  const int chunks = ((a.qc1 - 1) >> 3) - (a.qc0 >> 3) + 1;  // 8-word chunks (narrow kernels)
+  const dim3 gridn((unsigned)tiles, (unsigned)chunks);
   switch (v) {
     case 1: hipLaunchKernelGGL((k_gemm_quad<512, 1024>), grid, dim3(512), 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_gemm_quad<512, 2048>), grid, dim3(512), 0, s, a); break;
@@ -834,8 +825,8 @@ hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t 
     case 8: hipLaunchKernelGGL((k_gemm_wide<512, 1024>), grid, dim3(512), 0, s, a); break;
     case 9: hipLaunchKernelGGL((k_gemm_wide<256, 256>), grid, dim3(256), 0, s, a); break;
     case 10: hipLaunchKernelGGL((k_gemm_wide<256, 512>), grid, dim3(256), 0, s, a); break;
-    case 11: hipLaunchKernelGGL((k_gemm_narrow<256, 256>), dim3((unsigned)tiles), dim3(256), 0, s, a); break;
-    case 12: hipLaunchKernelGGL((k_gemm_narrow<256, 512>), dim3((unsigned)tiles), dim3(256), 0, s, a); break;
+    case 11: hipLaunchKernelGGL((k_gemm_narrow<256, 256>), gridn, dim3(256), 0, s, a); break;
+    case 12: hipLaunchKernelGGL((k_gemm_narrow<256, 512>), gridn, dim3(256), 0, s, a); break;
     default: hipLaunchKernelGGL((k_gemm_quad<1024, 1024>), grid, dim3(1024), 0, s, a); break;
   }
   return hipGetLastError();

@@ -66,47 +66,7 @@ struct PanelTables {
   uint64_t Tz[kMaxPanelWords][16][16];  // y = x * Zc_c
   uint64_t Te[kPairs][16][16];          // y * E_c[w]
 };
-typedef uint64_t TableSrc[kPairs + kMaxPanelWords][64];  // staged Zc_c rows and E_c[w] words
-
-// Tables of sub-panels c in [0, cend) of the panel starting at q0 (all threads).
-__device__ void build_panel_tables(PanelTables &pt, TableSrc &Src, const DecWork &w, int q0, int s_eff,
-                                   int cend, int tid, int nthr) {
-  // stage: slot c*64+t of Src for Zc_c; slot (kMaxPanelWords + pidx)*64 + t for E_c[w]
-  for (int e = tid; e < cend * 64; e += nthr) {
-    const int c = e >> 6, t = e & 63;
-    Src[c][t] = w.Zc[(size_t)(q0 + c) * 64 + t];
-  }
-  for (int c = 0; c < cend; ++c) {
-    const SubInfo sc = w.sub[q0 + c];
-    const int nwd = s_eff - 1 - c;
-    for (int e = tid; e < nwd * 64; e += nthr) {
-      const int wd = c + 1 + (e >> 6), t = e & 63;
-      Src[kMaxPanelWords + pidx(c, wd)][t] = t < sc.r ? w.W[widx(w.ldw, sc.R + t, q0 + wd)] : 0ull;
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < cend * 256; e += nthr) {
-    const int c = e >> 8, g = (e >> 4) & 15, v = e & 15;
-    uint64_t acc = 0ull;
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-      if (v & (1 << b)) acc ^= Src[c][4 * g + b];
-    pt.Tz[c][g][v] = acc;
-  }
-  for (int c = 0; c < cend; ++c) {
-    const int nwd = s_eff - 1 - c;
-    for (int e = tid; e < nwd * 256; e += nthr) {
-      const int wd = c + 1 + (e >> 8), g = (e >> 4) & 15, v = e & 15;
-      const int pi = pidx(c, wd);
-      uint64_t acc = 0ull;
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        if (v & (1 << b)) acc ^= Src[kMaxPanelWords + pi][4 * g + b];
-      pt.Te[pi][g][v] = acc;
-    }
-  }
-  __syncthreads();
-}
+static_assert(sizeof(PanelTables) == (size_t)kPanelTabWords * 8, "table buffer size");
 
 // Apply sub-panels [from, to) to the panel words x[], touching words <= wmax.
 __device__ inline void panel_update(uint64_t (&x)[kMaxPanelWords], int from, int to, int wmax,
@@ -608,6 +568,13 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
     }
   }
   for (int i = tid; i < nblk; i += NT) w.lvl[R0 + i] = i < wb ? (q0 << 4) | 15 : (q0 << 4) | s_eff;
+  // ---- the panel's tables for the row update after the chain (before the
+  // staging below reuses their LDS); sub-panels never reached stay zero there
+  {
+    const uint64_t *src = &sh.pt.Tz[0][0][0];
+    for (int e = tid; e < kPanelTabWords; e += NT) w.ptab[e] = src[e];
+  }
+  __syncthreads();
   // ---- permutation bookkeeping of every position whose row changed
   ChainMoved &mv = *reinterpret_cast<ChainMoved *>(&sh.pt);
   if (tid == 0) sh.nmv = 0;
@@ -655,11 +622,11 @@ hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, hipStr
 //     for trailing words, the pivot rows in echelon form E = L_pp^{-1} * rows
 //     (block forward substitution over the sub-panels).  Both touch only the
 //     block's own words, so the permutation finishes before the solve reads.
-//   * one per 2048 rows: every row below the pivots gets the sub-panels it still
+//   * one per 512 rows: every row below the pivots gets the sub-panels it still
 //     lacks, so its panel words hold its multipliers y_c (the Y of D*Z = Y,
 //     eq. (Aj) restricted to the panel).  These touch only panel words.
 constexpr int kPostThreads = 1024;
-constexpr int kRowsPerWG = 2 * kPostThreads;
+constexpr int kRowsPerWG = kPostThreads / 2;
 
 struct TrsmShared {
   uint64_t X[kMaxPanelWords * 64][TW];              // 64 KB: pivot rows, this block
@@ -668,13 +635,9 @@ struct TrsmShared {
   uint64_t Li[kMaxPanelWords][64];                  // 4 KB: Linv_b
   SubInfo Sb[kMaxPanelWords];
 };
-struct RowsShared {
-  PanelTables pt;
-  TableSrc src;
-};
 union PostShared {
   TrsmShared t;
-  RowsShared r;
+  PanelTables pt;
 };
 
 // the row now at listed position p comes from position bp_src[p] at the panel start
@@ -777,24 +740,30 @@ __device__ void post_trsm(const DecWork &w, int q0, int s_eff, int blk, TrsmShar
   }
 }
 
-__device__ void post_rows(const DecWork &w, int q0, int s_eff, int64_t blk0, RowsShared &sh) {
+__device__ void post_rows(const DecWork &w, int q0, int s_eff, int64_t blk0, PanelTables &pt) {
+  int rtot = 0;
+  for (int b = 0; b < s_eff; ++b) rtot += w.sub[q0 + b].r;
+  if (rtot == 0) return;  // no pivots: the rows below are zero in the panel (and stay so)
   const SubInfo last = w.sub[q0 + s_eff - 1];
   const int64_t rowbeg = last.R + last.r;
   if (blk0 + kRowsPerWG <= rowbeg || blk0 >= w.n) return;
-  build_panel_tables(sh.pt, sh.src, w, q0, s_eff, s_eff, threadIdx.x, kPostThreads);
-  for (int u = 0; u < kRowsPerWG / kPostThreads; ++u) {
-    const int64_t i = blk0 + (int64_t)u * kPostThreads + threadIdx.x;
-    if (i < rowbeg || i >= w.n) continue;
-    const int L = row_level(w, i, q0);
-    if (L >= s_eff) continue;  // already at the panel's last level (held by the chain kernel)
-    uint64_t x[kMaxPanelWords];
-#pragma unroll
-    for (int j = 0; j < kMaxPanelWords; ++j) x[j] = j < s_eff ? w.W[widx(w.ldw, i, q0 + j)] : 0ull;
-    panel_update(x, L, s_eff, s_eff - 1, sh.pt);
-#pragma unroll
-    for (int j = 0; j < kMaxPanelWords; ++j)
-      if (j >= L && j < s_eff) w.W[widx(w.ldw, i, q0 + j)] = x[j];
+  // the chain kernel left the panel's tables in w.ptab
+  {
+    uint64_t *dst = &pt.Tz[0][0][0];
+    for (int e = threadIdx.x; e < kPanelTabWords; e += kPostThreads) dst[e] = w.ptab[e];
   }
+  __syncthreads();
+  const int64_t i = blk0 + threadIdx.x;
+  if (threadIdx.x >= kRowsPerWG || i < rowbeg || i >= w.n) return;
+  const int L = row_level(w, i, q0);
+  if (L >= s_eff) return;  // already at the panel's last level (held by the chain kernel)
+  uint64_t x[kMaxPanelWords];
+#pragma unroll
+  for (int j = 0; j < kMaxPanelWords; ++j) x[j] = j < s_eff ? w.W[widx(w.ldw, i, q0 + j)] : 0ull;
+  panel_update(x, L, s_eff, s_eff - 1, pt);
+#pragma unroll
+  for (int j = 0; j < kMaxPanelWords; ++j)
+    if (j >= L && j < s_eff) w.W[widx(w.ldw, i, q0 + j)] = x[j];
 }
 
 __global__ __launch_bounds__(kPostThreads) void k_post(DecWork w, int q0, int s_eff) {
@@ -806,7 +775,7 @@ __global__ __launch_bounds__(kPostThreads) void k_post(DecWork w, int q0, int s_
     const int qc0 = q0 + s_eff;
     if (qc0 < w.Mw && blk >= (qc0 >> 4)) post_trsm(w, q0, s_eff, blk, sh.t);
   } else {
-    post_rows(w, q0, s_eff, (int64_t)(blockIdx.x - nb) * kRowsPerWG, sh.r);
+    post_rows(w, q0, s_eff, (int64_t)(blockIdx.x - nb) * kRowsPerWG, sh.pt);
   }
 }
 
