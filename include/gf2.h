@@ -103,8 +103,9 @@ int gf2_solve(const gf2_mat *A, const gf2_mat *B, const gf2_mat *X, uint64_t *co
 /*
  * Tuning knobs, process-wide (no knob changes any result):
  *   "panel_words"        : s, sub-panels of 64 columns per trailing-update panel (1..8)
- *   "strassen_cutoff"    : smallest dimension (bits) at which gf2_matmul recurses
- *                          with Strassen-Winograd instead of a single product
+ *   "strassen_cutoff"    : gf2_matmul recurses with Strassen-Winograd (one level
+ *                          per halving) while every dimension of the current
+ *                          product is at least this many bits (default 65536; 0 = never)
  *   "gemm_variant"       : product-kernel variant for gf2_matmul (-1 = automatic)
  *   "panel_gemm_variant" : product-kernel variant for the trailing update (-1 = automatic)
  *   "chain_cus"          : CUs reserved for the pivot chain through CU-masked

@@ -15,6 +15,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -28,7 +29,10 @@ namespace {
 
 thread_local std::string g_err;
 int g_panel_words = 8;
-int64_t g_strassen_cutoff = 0;  // 0: never recurse
+// Strassen-Winograd recursion while every dimension of the current product is
+// at least this many bits (0: never).  Measured on MI355X: one level pays at
+// 65536^3 (56 ms against 62 ms), none at 32768^3 (10.3 ms against 8 ms).
+int64_t g_strassen_cutoff = 65536;
 int g_gemm_variant = -1;        // product-kernel variant for gf2_matmul (-1: automatic)
 int g_panel_gemm_variant = -1;  // product-kernel variant for the trailing update (-1: automatic)
 // CUs reserved for the pivot chain through a CU-masked stream pair; 0 = two
@@ -455,6 +459,105 @@ int gf2_release(void) {
   return GF2_OK;
 }
 
+namespace {
+
+// ---------------------------------------------------------------- Strassen-Winograd
+// One level on quadrant views (Winograd's form: 7 products, 15 additions;
+// over GF(2) every addition and subtraction is an exclusive or):
+//   S1 = A21+A22, S2 = S1+A11, S3 = A11+A21, S4 = A12+S2
+//   T1 = B12+B11, T2 = B22+T1, T3 = B22+B12, T4 = T2+B21
+//   P1 = A11 B11, P2 = A12 B21, P3 = S4 B22, P4 = A22 T4, P5 = S1 T1, P6 = S2 T2, P7 = S3 T3
+//   C11 = P1+P2, U2 = P1+P6, U3 = U2+P7, C12 = U2+P5+P3, C21 = U3+P4, C22 = U3+P5
+// Products recurse while levels remain; leaves are single Four-Russians launches.
+// Temporaries come from a stack (`top`) that a level releases when it returns:
+// all launches go to one stream, so later work reuses the memory only after the
+// earlier kernels that read it.
+struct Stack {
+  char *base;
+  size_t top, cap;
+};
+
+BView quad(const BView &v, int i, int j) {
+  BView q;
+  q.ld = v.ld;
+  q.rows = v.rows / 2;
+  q.words = v.words / 2;
+  q.p = v.p + ((int64_t)j * (q.words / TW) * v.ld + (int64_t)i * q.rows) * TW;
+  return q;
+}
+
+BView temp(Stack &st, int64_t rows, int64_t words) {
+  BView t;
+  t.ld = rows;
+  t.rows = rows;
+  t.words = words;
+  t.p = (uint64_t *)(st.base + st.top);
+  st.top += align256((size_t)(words / TW) * rows * TW * 8);
+  return t;
+}
+
+size_t strassen_bytes(int64_t n, int64_t kw, int64_t mw, int depth) {
+  size_t b = 0;
+  for (int d = 0; d < depth; ++d) {
+    n /= 2;
+    kw /= 2;
+    mw /= 2;
+    const int64_t kr = kw * 64;
+    b += 4 * align256((size_t)(kw / TW) * n * TW * 8) + 4 * align256((size_t)(mw / TW) * kr * TW * 8) +
+         7 * align256((size_t)(mw / TW) * n * TW * 8);
+  }
+  return b;
+}
+
+int gemm_view(const BView &C, const BView &A, const BView &B, int acc, hipStream_t s) {
+  GemmArgs a;
+  memset(&a, 0, sizeof(a));
+  a.A = A.p; a.ldA = A.ld; a.a_word0 = 0;
+  a.B = B.p; a.ldB = B.ld; a.b_rows = B.rows; a.bsub = nullptr;
+  a.C = C.p; a.ldC = C.ld;
+  a.row_tile0 = 0; a.row_end = C.rows;
+  a.kwords = (int32_t)A.words;
+  a.qc0 = 0; a.qc1 = (int32_t)C.words;
+  a.accumulate = acc;
+  return run_gemm(a, C.rows, g_gemm_variant, C.rows, s);
+}
+
+int strassen(const BView &C, const BView &A, const BView &B, int depth, int acc, Stack &st, hipStream_t s) {
+  if (depth == 0) return gemm_view(C, A, B, acc, s);
+  const size_t mark = st.top;
+  const BView A11 = quad(A, 0, 0), A12 = quad(A, 0, 1), A21 = quad(A, 1, 0), A22 = quad(A, 1, 1);
+  const BView B11 = quad(B, 0, 0), B12 = quad(B, 0, 1), B21 = quad(B, 1, 0), B22 = quad(B, 1, 1);
+  const BView C11 = quad(C, 0, 0), C12 = quad(C, 0, 1), C21 = quad(C, 1, 0), C22 = quad(C, 1, 1);
+  BView S[4], T[4], P[7];
+  for (auto &x : S) x = temp(st, A11.rows, A11.words);
+  for (auto &x : T) x = temp(st, B11.rows, B11.words);
+  for (auto &x : P) x = temp(st, C11.rows, C11.words);
+  HIPCHK(launch_xor_view(S[0], A21, A22, nullptr, 0, s));
+  HIPCHK(launch_xor_view(S[1], S[0], A11, nullptr, 0, s));
+  HIPCHK(launch_xor_view(S[2], A11, A21, nullptr, 0, s));
+  HIPCHK(launch_xor_view(S[3], A12, S[1], nullptr, 0, s));
+  HIPCHK(launch_xor_view(T[0], B12, B11, nullptr, 0, s));
+  HIPCHK(launch_xor_view(T[1], B22, T[0], nullptr, 0, s));
+  HIPCHK(launch_xor_view(T[2], B22, B12, nullptr, 0, s));
+  HIPCHK(launch_xor_view(T[3], T[1], B21, nullptr, 0, s));
+  int rc;
+  if ((rc = strassen(P[0], A11, B11, depth - 1, 0, st, s)) || (rc = strassen(P[1], A12, B21, depth - 1, 0, st, s)) ||
+      (rc = strassen(P[2], S[3], B22, depth - 1, 0, st, s)) || (rc = strassen(P[3], A22, T[3], depth - 1, 0, st, s)) ||
+      (rc = strassen(P[4], S[0], T[0], depth - 1, 0, st, s)) || (rc = strassen(P[5], S[1], T[1], depth - 1, 0, st, s)) ||
+      (rc = strassen(P[6], S[2], T[2], depth - 1, 0, st, s)))
+    return rc;
+  HIPCHK(launch_xor_view(C11, P[0], P[1], nullptr, acc, s));
+  HIPCHK(launch_xor_view(P[5], P[0], P[5], nullptr, 0, s));  // U2
+  HIPCHK(launch_xor_view(P[6], P[5], P[6], nullptr, 0, s));  // U3
+  HIPCHK(launch_xor_view(C12, P[5], P[4], &P[2], acc, s));
+  HIPCHK(launch_xor_view(C21, P[6], P[3], nullptr, acc, s));
+  HIPCHK(launch_xor_view(C22, P[6], P[4], nullptr, acc, s));
+  st.top = mark;
+  return GF2_OK;
+}
+
+}  // namespace
+
 int gf2_matmul(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B, int accumulate, void *stream) {
   int rc;
   if ((rc = check_mat(C, "C")) || (rc = check_mat(A, "A")) || (rc = check_mat(B, "B"))) return rc;
@@ -463,18 +566,33 @@ int gf2_matmul(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B, int accumul
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = A->rows, k = A->cols, m = B->cols;
   if (n == 0 || m == 0) return GF2_OK;
-  const int64_t Kw = ceil_div(k, 64), Mw = ceil_div(m, 64);
+  // Strassen-Winograd levels: while every dimension of the (halved) problem is
+  // at least the cutoff (Section 6: the recursion pays only for large products)
+  int depth = 0;
+  if (g_strassen_cutoff > 0)
+    while (depth < 4 && std::min(n, std::min(k, m)) >> depth >= g_strassen_cutoff) ++depth;
+  // padded shape: rows a multiple of 256 * 2^depth, inner and output columns of
+  // 1024 * 2^depth bits (so every quadrant is a whole number of 16-word blocks)
+  const int64_t rq = (int64_t)256 << depth, cq = (int64_t)1024 << depth;
+  const int64_t np = ceil_div(n, rq) * rq;
+  const int64_t kp = depth ? ceil_div(k, cq) * cq : k, mp = depth ? ceil_div(m, cq) * cq : m;
+  const int64_t Kw = ceil_div(kp, 64), Mw = ceil_div(mp, 64);
   const int64_t NBa = ceil_div(Kw > 0 ? Kw : 1, TW), NBb = ceil_div(Mw, TW);
-  const int64_t lda = ceil_div(n, 256) * 256, ldb = ceil_div(k > 0 ? k : 1, 256) * 256;
+  const int64_t lda = np, ldb = ceil_div(kp > 0 ? kp : 1, 256) * 256;
   const size_t ba = align256((size_t)NBa * lda * TW * 8), bb = align256((size_t)NBb * ldb * TW * 8),
                bc = align256((size_t)NBb * lda * TW * 8);
+  const size_t bs = depth ? strassen_bytes(np, NBa * TW, NBb * TW, depth) : 0;
   void *ws = nullptr;
-  if ((rc = get_workspace(s, ba + bb + bc, &ws))) return rc;
+  if ((rc = get_workspace(s, ba + bb + bc + bs, &ws))) return rc;
   uint64_t *Aw = (uint64_t *)ws, *Bw = (uint64_t *)((char *)ws + ba), *Cw = (uint64_t *)((char *)ws + ba + bb);
   HIPCHK(launch_pack(*A, Aw, lda, n, k, (int32_t)NBa, s));
   HIPCHK(launch_pack(*B, Bw, ldb, k, m, (int32_t)NBb, s));
   if (accumulate) HIPCHK(launch_pack(*C, Cw, lda, n, m, (int32_t)NBb, s));
-  if (k > 0 || accumulate) {
+  if (depth > 0) {
+    Stack st{(char *)ws + ba + bb + bc, 0, bs};
+    const BView Cv{Cw, lda, np, NBb * TW}, Av{Aw, lda, np, NBa * TW}, Bv{Bw, ldb, NBa * TW * 64, NBb * TW};
+    if ((rc = strassen(Cv, Av, Bv, depth, accumulate ? 1 : 0, st, s))) return rc;
+  } else if (k > 0 || accumulate) {
     GemmArgs a;
     memset(&a, 0, sizeof(a));
     a.A = Aw; a.ldA = lda; a.a_word0 = 0;

@@ -114,6 +114,19 @@ hipError_t launch_post(const DecWork &w, int q0, int s_eff, hipStream_t s);
 hipError_t launch_xor(uint64_t *dst, const uint64_t *a, const uint64_t *b, size_t nwords,
                       hipStream_t s);
 
+// A rows x (words) region of a working-layout matrix: word (i, q) at
+// p[((q / 16) * ld + i) * 16 + q % 16].  A quadrant of a view whose words are
+// a multiple of 32 is again a view (a pointer offset with the same ld).
+struct BView {
+  uint64_t *p;
+  int64_t ld;
+  int64_t rows;
+  int64_t words;
+};
+// dst = (acc ? dst : 0) ^ a ^ b ^ (c ? c : 0), all of dst's shape; views may coincide with dst
+hipError_t launch_xor_view(const BView &dst, const BView &a, const BView &b, const BView *c, int acc,
+                           hipStream_t s);
+
 struct SolveWork {
   uint64_t *Y;       // n x kw words, row-major (right-hand sides after P, then Y)
   int64_t kw;        // words per RHS row

@@ -215,4 +215,30 @@ hipError_t launch_xor(uint64_t *dst, const uint64_t *a, const uint64_t *b, size_
   return hipGetLastError();
 }
 
+__global__ void k_xor_view(BView d, BView a, BView b, BView c, int has_c, int acc) {
+  const int64_t nblk = (d.words + TW - 1) / TW;
+  const int64_t total = nblk * d.rows * TW;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t w = e % TW;
+    const int64_t r = (e / TW) % d.rows;
+    const int64_t blk = e / (TW * d.rows);
+    if (blk * TW + w >= d.words) continue;
+    uint64_t v = a.p[(blk * a.ld + r) * TW + w] ^ b.p[(blk * b.ld + r) * TW + w];
+    if (has_c) v ^= c.p[(blk * c.ld + r) * TW + w];
+    uint64_t *q = d.p + (blk * d.ld + r) * TW + w;
+    *q = acc ? (*q ^ v) : v;
+  }
+}
+
+hipError_t launch_xor_view(const BView &dst, const BView &a, const BView &b, const BView *c, int acc,
+                           hipStream_t s) {
+  if (dst.rows <= 0 || dst.words <= 0) return hipSuccess;
+  const int64_t total = (dst.words + TW - 1) / TW * dst.rows * TW;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_xor_view, dim3((unsigned)blocks), dim3(256), 0, s, dst, a, b, c ? *c : a, c ? 1 : 0, acc);
+  return hipGetLastError();
+}
+
 }  // namespace gf2

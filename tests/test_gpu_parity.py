@@ -185,6 +185,24 @@ def test_matmul_narrow(g, orc, variant, n, k, m):
     assert np.array_equal(Cg.to_rowmajor(), ref)
 
 
+@pytest.mark.parametrize("cutoff", [256, 700, 1024])
+@pytest.mark.parametrize("n,k,m,acc", [(2100, 1500, 2500, False), (1030, 2049, 1100, True), (3000, 1024, 1024, True)])
+def test_matmul_strassen(g, orc, cutoff, n, k, m, acc):
+    """Strassen-Winograd recursion (Section 6) at 1 to 3 levels, ragged shapes, accumulate."""
+    say("matmul strassen", cutoff, n, k, m, acc)
+    A = synth.dense(25, 1, n, k)
+    B = synth.dense(25, 2, k, m)
+    C0 = synth.dense(25, 3, n, m)
+    ref = orc.matmul(A, B, n, k, m, C=C0 if acc else None)
+    Cg = g.Mat.from_rowmajor(C0, n, m)
+    g.gf2_set_param("strassen_cutoff", cutoff)
+    try:
+        g.gf2_matmul(Cg, g.Mat.from_rowmajor(A, n, k), g.Mat.from_rowmajor(B, k, m), accumulate=acc)
+    finally:
+        g.gf2_set_param("strassen_cutoff", 65536)
+    assert np.array_equal(Cg.to_rowmajor(), ref)
+
+
 def test_decompose_special(g, orc):
     for n, m in [(1, 1), (5, 9), (64, 64), (130, 70), (700, 1300)]:
         say("special", n, m)
