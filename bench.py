@@ -10,11 +10,12 @@ Roofline of the dominant kernel (the trailing-update Four-Russians product):
 its launches are bracketed by HIP events inside the library on the launch
 stream during the timed steps; its algorithmic work is one 8-byte LDS table
 read and one 64-bit XOR per table lookup (one lookup per output word per 8
-inner bits); the bound is the on-chip table-read rate (LDS: 128 B/clk/CU x 256
-CUs x 2.4 GHz).
+inner bits); the bound is the on-chip table-read rate: LDS reads of 256 B/clk
+per CU (gfx950) x 256 CUs x 2.4 GHz = 157.3 TB/s.
 
 cpu_baseline: the CPU oracle (plain elimination, OpenMP) timed on a bounded
-sample of the same workload (a smaller dense matrix of the same distribution),
+sample of the same workload (the largest dense matrix of the same distribution
+that fits the time budget, the 65536^2 matrix itself on a 16-thread host),
 expressed in the same unit.
 
 HBM traffic of that kernel is read from rocprofv3 counters (FETCH_SIZE and
@@ -27,6 +28,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--copy-calib
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -39,7 +41,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "effective GF(2) bit-ops/s for 65536² decompose; batched solves/s + p99 latency"
 PAPER_BITOPS_PER_S = 1.876e14 / 86.156   # paper's best 65536^2 time (Table 4, b = 128, recursive), context
-LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12   # 78.6 TB/s
+LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12   # 157.3 TB/s: 256 CUs x 256 B/clk x 2.4 GHz
+# HBM bytes per product launch in this decomposition, from rocprofv3 counters:
+# FETCH_SIZE (KiB per dispatch, x2: a plain 1 GiB copy reads 524305 KiB) and
+# WRITE_SIZE (KiB, x1: the copy reads 1048576 KiB), averaged over the 253
+# product launches of one 65536^2 decomposition.  Valid only for the product
+# kernel source they were measured on.
+TRAFFIC = {"kernel_source_sha256": "763d5a591f6203f0e31a3b40564d2f47dfe68f327799030b82e4870e243b17ad",
+           "fetch_bytes": 55133.5 * 2 * 1024, "write_bytes": 87514.3 * 1024}
 SEED = 65536
 
 
@@ -49,8 +58,9 @@ def eff_bitops(n: int, m: int, pivcols: np.ndarray) -> float:
     return float(2.0 * np.sum((n - 1 - t) * (m - 1 - p)))
 
 
-def cpu_baseline(budget_s: float = 12.0):
-    """Time the oracle on a dense sample sized to roughly budget_s seconds."""
+def cpu_baseline(budget_s: float = 24.0):
+    """Time the oracle on a dense sample: sizes double from 2048 while the next
+    one (8x the work) is predicted to fit budget_s, up to the full 65536^2."""
     import oracle
     from paper_1209_5198_amd import synth
 
@@ -63,7 +73,7 @@ def cpu_baseline(budget_s: float = 12.0):
         res = oracle.ple(A, n, n, want_le=False)
         dt = time.perf_counter() - t0
         last = (n, dt, res)
-        if dt * 8 > budget_s or n >= 32768:
+        if dt * 8 > budget_s or n >= 65536:
             break
         n *= 2
     n, dt, res = last
@@ -147,8 +157,14 @@ def main():
     per_launch_ms = kms / max(klaunch, 1)
     lookups_per_launch = lookups / max(klaunch, 1)
     achieved_tbs = (8.0 * lookups_per_launch) / (per_launch_ms / 1e3) / 1e12 if per_launch_ms > 0 else 0.0
+    traffic = None
+    src = os.path.join(ROOT, "paper_1209_5198_amd", "csrc", "k_gemm.hip")
+    if n == 65536 and os.path.exists(src):
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() == TRAFFIC["kernel_source_sha256"]:
+                traffic = TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
     roof = {"bound": "alu", "achieved": achieved_tbs, "peak": LDS_PEAK_TBS, "unit": "TB/s",
-            "frac": achieved_tbs / LDS_PEAK_TBS, "traffic": None,
+            "frac": achieved_tbs / LDS_PEAK_TBS, "traffic": traffic,
             "kernel": "k_gemm_m4rm (trailing-update Four-Russians product)",
             "work_per_launch": {"lookups": lookups_per_launch, "lds_bytes": 8.0 * lookups_per_launch},
             "avg_launch_ms": per_launch_ms, "launches": klaunch,

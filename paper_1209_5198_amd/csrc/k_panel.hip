@@ -2,24 +2,23 @@
 //
 // A trailing-update panel is s <= 8 consecutive 64-column sub-panels (words
 // q0 .. q0+s-1):
-//   k_chain        one workgroup per panel: for each sub-panel q in order it
-//                  selects the pivots of the 64 columns of word q (procedure
-//                  buildZ, Sections 4.2-4.4): for each bit k in order, the first
-//                  row at or below the next free position whose reduced bit k is
-//                  1 becomes the pivot and is exchanged with that position (a
-//                  transposition).  It produces the pivot columns, the
-//                  coefficient map Zc (row j of Zc gives the multipliers of bit
-//                  j, so y = x * Zc are a row's multipliers -- the role of Z in
-//                  D*Z = Y, Section 4.1), the inverse of the sub-panel's unit
-//                  lower block and the pivot rows in final form, and applies the
-//                  sub-panel to the rows it holds in LDS.
-//   k_rows_panel   once per panel: every row below the pivots gets the
-//                  sub-panels it still lacks, so its panel words hold its
-//                  multipliers (eq. (Aj) restricted to the panel).
-//   k_swap         applies the panel's net row permutation to all words
-//                  outside the panel (P^(j) applied to all columns).
-//   k_trsm         pivot rows right of the panel: E = L_pp^{-1} * rows
-//                  (block forward substitution over the sub-panels).
+//   k_chain   one workgroup per panel: for each sub-panel q in order it selects
+//             the pivots of the 64 columns of word q (procedure buildZ,
+//             Sections 4.2-4.4): for each bit k in order, the first row at or
+//             below the next free position whose reduced bit k is 1 becomes the
+//             pivot and is exchanged with that position (a transposition).  It
+//             produces the pivot columns, the coefficient map Zc (row j of Zc
+//             gives the multipliers of bit j, so y = x * Zc are a row's
+//             multipliers -- the role of Z in D*Z = Y, Section 4.1), the
+//             inverse of the sub-panel's unit lower block and the pivot rows in
+//             final form, and applies the sub-panel to the rows it holds in LDS.
+//   k_post    one launch per panel after its chain: the panel's net row
+//             permutation on all words outside the panel (P^(j) applied to all
+//             columns), the pivot rows right of the panel in echelon form
+//             (E = L_pp^{-1} * rows, block forward substitution over the
+//             sub-panels), and every row below the pivots brought to the
+//             panel's last sub-panel so its panel words hold its multipliers
+//             (eq. (Aj) restricted to the panel).
 // The trailing product (Schur complement, eq. (Aj)) is k_gemm.
 //
 // Reduced bit of a row.  The chain kernel keeps, for every pivot found so
@@ -104,21 +103,23 @@ __device__ inline int row_level(const DecWork &w, int64_t p, int q0) {
 }
 
 // ---------------------------------------------------------------- pivot selection
-// One workgroup of 4 waves factors a whole panel (s <= 8 sub-panels).  The rows
+// One workgroup of 8 waves factors a whole panel (s <= 8 sub-panels).  The rows
 // at positions [R0, R0 + 64 s + kWin) -- every position a window of this panel
 // can reach -- are held in LDS ("block") with their panel words, and are
-// brought up to date right-looking after each sub-panel (eq. (Aj) restricted
-// to the panel).  Rows further down stay in HBM at their level and are only
-// read by the rare scan below the window.
+// brought up to date right-looking after each sub-panel by all waves (eq. (Aj)
+// restricted to the panel).  Rows further down stay in HBM at their level and
+// are only read by the rare scan below the window.
 //
 // Per sub-panel b (word q = q0 + b, rank Rb before it): the window is the kWin
-// positions from Rb; all four waves hold the same reduced words of word q of
-// the window (slot 64g + lane) and take the same decisions.  For each bit k the
-// candidates are one ballot per half ANDed with the scalar mask of free slots;
-// the first candidate becomes the pivot of position Rb + ib (a transposition),
-// and every other candidate is reduced by it.  The fully reduced pivot rows M_j
-// (lane j) and their coefficient map Zc are updated in the same step.  When no
-// window row has bit k, all threads scan the rows below the window with
+// positions from Rb, slot s = position Rb + s.  Wave 0 alone takes the pivot
+// decisions with lane-indexed registers: the first 64 slots are kept reduced by
+// every pivot; the second 64 are reduced on demand (Proj, 4-bit tables) only
+// when the first half has no candidate.  For each bit k the candidates are one
+// ballot ANDed with the scalar mask of free slots; the first candidate becomes
+// the pivot of position Rb + ib (a transposition of slots), and every other
+// candidate is reduced by it.  The fully reduced pivot rows M_j (lane j) and
+// their coefficient map Zc are updated in the same step.  When no window row
+// has bit k, all threads scan the rows below the window with
 // Proj(x) = x xor sum_j x_j M_j and keep an over-approximation F of the bits
 // such rows can still have, so a zero tail costs one scan per sub-panel.
 constexpr int kBlkMax = 64 * kMaxPanelWords + kWin;  // block rows
