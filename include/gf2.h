@@ -101,6 +101,59 @@ int gf2_solve(const gf2_mat *A, const gf2_mat *B, const gf2_mat *X, uint64_t *co
               int64_t *rank, void *stream);
 
 /*
+ * ---------------------------------------------------------------- batches
+ * Many independent matrices of at most GF2_BATCH_MAX_DIM rows and columns,
+ * each of its own shape, factored (and solved) in one launch.  The matrices
+ * and results live in caller-owned device pools; item i of the host array
+ * `items` gives matrix i's shape and the offsets of its pieces.  Every piece is
+ * plain row-major: a row of c columns is ceil(c/64) words, element j of a row
+ * is bit j % 64 of word j / 64 (Section 3's bit order), padding bits are
+ * ignored on input and written as zero.  With kmin_i = min(rows, cols):
+ */
+#define GF2_BATCH_MAX_DIM 2048
+
+typedef struct gf2_batch_item {
+  int64_t rows; /* n_i, 0 <= n_i <= GF2_BATCH_MAX_DIM                          */
+  int64_t cols; /* m_i, 0 <= m_i <= GF2_BATCH_MAX_DIM                          */
+  int64_t a;    /* A_i at A + a: n_i rows of ceil(m_i/64) words                 */
+  int64_t l;    /* L_i at L + l: n_i rows of ceil(kmin_i/64) words              */
+  int64_t e;    /* E_i at E + e: kmin_i rows of ceil(m_i/64) words              */
+  int64_t p;    /* perm_i at perm + p: n_i int64                               */
+  int64_t c;    /* pivcols_i at pivcols + c: kmin_i int64                      */
+  int64_t b;    /* b_i at B + b: ceil(n_i/64) words, bit i of the vector is     */
+                /* bit i % 64 of word i / 64 (gf2_solve_batched only)           */
+  int64_t x;    /* x_i at X + x: ceil(m_i/64) words (gf2_solve_batched only)    */
+} gf2_batch_item;
+
+/*
+ * P_i*A_i = L_i*E_i for every item, with the meaning of gf2_decompose (same
+ * pivots, same L, E, perm, pivcols).  rank[i] (int64, caller order) receives
+ * the rank of item i.  L, E, perm and pivcols may each be NULL (not written);
+ * A and rank are required.  The items are taken largest first by one
+ * persistent launch in which each workgroup factors whole matrices (Section 4
+ * with 64-column panels, 4-bit Four-Russians trailing updates of Section 6).
+ * Errors: GF2_EINVAL for count < 0, a null required pointer, a shape outside
+ * [0, GF2_BATCH_MAX_DIM] or a negative offset (checked on the host before any
+ * launch; pools are not bounds-checked against the offsets).
+ */
+int gf2_decompose_batched(const gf2_batch_item *items, int64_t count, const uint64_t *A,
+                          uint64_t *L, uint64_t *E, int64_t *perm, int64_t *pivcols,
+                          int64_t *rank, void *stream);
+
+/*
+ * Solve A_i x = b_i for every item from the outputs of gf2_decompose_batched
+ * (L, E, perm, pivcols, rank for the same items and pools): y = L_top^{-1}
+ * (P b)_top, consistent iff L_bot y = (P b)_bot, then x by back-substitution
+ * with E, free (non-pivot) variables zero (the uses of the decomposition in
+ * Section 1).  consistent[i] (int32, caller order) is 1 or 0; x_i is zero when
+ * system i is inconsistent.  All pointers are required; errors as above.
+ */
+int gf2_solve_batched(const gf2_batch_item *items, int64_t count, const uint64_t *L,
+                      const uint64_t *E, const int64_t *perm, const int64_t *pivcols,
+                      const int64_t *rank, const uint64_t *B, uint64_t *X, int32_t *consistent,
+                      void *stream);
+
+/*
  * Tuning knobs, process-wide (no knob changes any result):
  *   "panel_words"        : s, sub-panels of 64 columns per trailing-update panel (1..8)
  *   "strassen_cutoff"    : gf2_matmul recurses with Strassen-Winograd (one level

@@ -15,6 +15,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <limits.h>
+
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -68,6 +70,17 @@ struct ProfState {
   unsigned long long *work_dev = nullptr;
   int64_t launches = 0;
 } g_prof;
+
+// Descriptors of a batch travel through one pinned host buffer; a copy is
+// complete (event) before the buffer is refilled by the next batched call.
+struct Staging {
+  void *host = nullptr;
+  size_t bytes = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+};
+Staging g_stage;
+std::mutex g_stage_mu;
 
 int fail(int code, const std::string &msg) {
   g_err = msg;
@@ -456,10 +469,93 @@ int gf2_release(void) {
   }
   g_ws.clear();
   HIPCHK(hipSetDevice(cur));
+  {
+    std::lock_guard<std::mutex> ls(g_stage_mu);
+    if (g_stage.ev) {
+      HIPCHK(hipEventSynchronize(g_stage.ev));
+      HIPCHK(hipEventDestroy(g_stage.ev));
+    }
+    if (g_stage.host) HIPCHK(hipHostFree(g_stage.host));
+    g_stage = Staging();
+  }
   return GF2_OK;
 }
 
 namespace {
+
+// ---------------------------------------------------------------- batches
+int stage_descs(const std::vector<BatchDesc> &v, BatchDesc *dev, hipStream_t s) {
+  const size_t bytes = v.size() * sizeof(BatchDesc);
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  if (g_stage.pending) {
+    HIPCHK(hipEventSynchronize(g_stage.ev));
+    g_stage.pending = false;
+  }
+  if (g_stage.bytes < bytes) {
+    if (g_stage.host) HIPCHK(hipHostFree(g_stage.host));
+    g_stage.host = nullptr;
+    g_stage.bytes = 0;
+    HIPCHK(hipHostMalloc(&g_stage.host, bytes));
+    g_stage.bytes = bytes;
+  }
+  if (!g_stage.ev) HIPCHK(hipEventCreateWithFlags(&g_stage.ev, hipEventDisableTiming));
+  memcpy(g_stage.host, v.data(), bytes);
+  HIPCHK(hipMemcpyAsync(dev, g_stage.host, bytes, hipMemcpyHostToDevice, s));
+  HIPCHK(hipEventRecord(g_stage.ev, s));
+  g_stage.pending = true;
+  return GF2_OK;
+}
+
+// Validate the items and order them by decreasing work (n * m * min(n, m)),
+// so that a persistent launch starts the largest matrices first.
+int batch_descs(const gf2_batch_item *items, int64_t count, bool solve, std::vector<BatchDesc> &out,
+                int64_t *max_words) {
+  if (count < 0 || count > (int64_t)INT32_MAX) return fail(GF2_EINVAL, "batch: count out of range");
+  if (count > 0 && !items) return fail(GF2_EINVAL, "batch: null items");
+  std::vector<std::pair<double, int32_t>> key((size_t)count);
+  int64_t mw = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const gf2_batch_item &it = items[i];
+    if (it.rows < 0 || it.rows > GF2_BATCH_MAX_DIM || it.cols < 0 || it.cols > GF2_BATCH_MAX_DIM)
+      return fail(GF2_EINVAL, "batch item " + std::to_string(i) + ": rows and cols must be in [0, " +
+                                  std::to_string(GF2_BATCH_MAX_DIM) + "]");
+    if (it.a < 0 || it.l < 0 || it.e < 0 || it.p < 0 || it.c < 0 || (solve && (it.b < 0 || it.x < 0)))
+      return fail(GF2_EINVAL, "batch item " + std::to_string(i) + ": negative offset");
+    const double n = (double)it.rows, m = (double)it.cols;
+    key[(size_t)i] = std::make_pair(n * m * (n < m ? n : m) + n + m, (int32_t)i);
+    mw = std::max(mw, it.rows * ceil_div(it.cols, 64));
+  }
+  std::stable_sort(key.begin(), key.end(),
+                   [](const std::pair<double, int32_t> &x, const std::pair<double, int32_t> &y) {
+                     return x.first > y.first;
+                   });
+  out.resize((size_t)count);
+  for (int64_t j = 0; j < count; ++j) {
+    const gf2_batch_item &it = items[key[(size_t)j].second];
+    BatchDesc &d = out[(size_t)j];
+    d.n = (int32_t)it.rows;
+    d.m = (int32_t)it.cols;
+    d.idx = key[(size_t)j].second;
+    d.pad = 0;
+    d.a = it.a;
+    d.l = it.l;
+    d.e = it.e;
+    d.p = it.p;
+    d.c = it.c;
+    d.b = solve ? it.b : 0;
+    d.x = solve ? it.x : 0;
+  }
+  *max_words = mw;
+  return GF2_OK;
+}
+
+int device_cus(int *ncu) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  if (*ncu < 1) *ncu = 1;
+  return GF2_OK;
+}
 
 // ---------------------------------------------------------------- Strassen-Winograd
 // One level on quadrant views (Winograd's form: 7 products, 15 additions;
@@ -684,6 +780,77 @@ int gf2_solve(const gf2_mat *A, const gf2_mat *B, const gf2_mat *X, uint64_t *co
   sw.bad = (uint64_t *)((char *)extra + align256((size_t)n * kw * 8));
   HIPCHK(launch_solve(w, *B, *X, sw, consistent, s));
   HIPCHK(launch_finish(w, nullptr, nullptr, rank, s));
+  return GF2_OK;
+}
+
+int gf2_decompose_batched(const gf2_batch_item *items, int64_t count, const uint64_t *A,
+                          uint64_t *L, uint64_t *E, int64_t *perm, int64_t *pivcols,
+                          int64_t *rank, void *stream) {
+  std::vector<BatchDesc> descs;
+  int64_t maxw = 0;
+  int rc = batch_descs(items, count, false, descs, &maxw);
+  if (rc) return rc;
+  if (count == 0) return GF2_OK;
+  if (!rank) return fail(GF2_EINVAL, "gf2_decompose_batched: null rank");
+  if (maxw > 0 && !A) return fail(GF2_EINVAL, "gf2_decompose_batched: null A");
+  hipStream_t s = (hipStream_t)stream;
+  int ncu = 1;
+  if ((rc = device_cus(&ncu))) return rc;
+  const int workers = (int)std::min<int64_t>(count, batch_workers(ncu));
+  const int64_t wslot = (std::max<int64_t>(maxw, 1) + 31) / 32 * 32;
+  const size_t need = align256((size_t)count * sizeof(BatchDesc)) + 256 +
+                      align256((size_t)workers * (size_t)wslot * 8);
+  void *ws = nullptr;
+  if ((rc = get_workspace(s, need, &ws))) return rc;
+  Carver c(ws);
+  BatchDesc *dd = c.take<BatchDesc>((size_t)count);
+  uint32_t *ctr = c.take<uint32_t>(64);
+  uint64_t *W = c.take<uint64_t>((size_t)workers * (size_t)wslot);
+  if ((rc = stage_descs(descs, dd, s))) return rc;
+  BatchArgs a;
+  a.d = dd;
+  a.count = (int32_t)count;
+  a.counter = ctr;
+  a.A = A;
+  a.L = L;
+  a.E = E;
+  a.perm = perm;
+  a.pivcols = pivcols;
+  a.rank = rank;
+  a.W = W;
+  a.wslot = wslot;
+  HIPCHK(launch_batch_dec(a, workers, s));
+  return GF2_OK;
+}
+
+int gf2_solve_batched(const gf2_batch_item *items, int64_t count, const uint64_t *L,
+                      const uint64_t *E, const int64_t *perm, const int64_t *pivcols,
+                      const int64_t *rank, const uint64_t *B, uint64_t *X, int32_t *consistent,
+                      void *stream) {
+  std::vector<BatchDesc> descs;
+  int64_t maxw = 0;
+  int rc = batch_descs(items, count, true, descs, &maxw);
+  if (rc) return rc;
+  if (count == 0) return GF2_OK;
+  if (!L || !E || !perm || !pivcols || !rank || !B || !X || !consistent)
+    return fail(GF2_EINVAL, "gf2_solve_batched: null pointer argument");
+  hipStream_t s = (hipStream_t)stream;
+  void *ws = nullptr;
+  if ((rc = get_workspace(s, align256((size_t)count * sizeof(BatchDesc)), &ws))) return rc;
+  BatchDesc *dd = (BatchDesc *)ws;
+  if ((rc = stage_descs(descs, dd, s))) return rc;
+  BatchSolveArgs a;
+  a.d = dd;
+  a.count = (int32_t)count;
+  a.L = L;
+  a.E = E;
+  a.perm = perm;
+  a.pivcols = pivcols;
+  a.rank = rank;
+  a.B = B;
+  a.X = X;
+  a.consistent = consistent;
+  HIPCHK(launch_batch_solve(a, s));
   return GF2_OK;
 }
 

@@ -136,4 +136,47 @@ struct SolveWork {
 hipError_t launch_solve(const DecWork &w, const gf2_mat &B, const gf2_mat &X,
                         const SolveWork &sw, uint64_t *consistent, hipStream_t s);
 
+// ---------------------------------------------------------------- batches
+// Many independent matrices of at most kBatchMaxDim rows and columns, each
+// factored from start to finish by one workgroup of a persistent launch.
+constexpr int kBatchMaxDim = GF2_BATCH_MAX_DIM;
+constexpr int kBatchMaxPanels = kBatchMaxDim / 64;
+constexpr int kBatchThreads = 256;   // threads per workgroup
+constexpr int kBatchWGPerCU = 3;     // resident workgroups per CU (LDS-limited)
+
+// One matrix of a batch, in the order the workers take them (offsets as in
+// gf2_batch_item; idx = the item's index in the caller's array).
+struct BatchDesc {
+  int32_t n, m;
+  int32_t idx;
+  int32_t pad;
+  int64_t a, l, e, p, c, b, x;
+};
+
+struct BatchArgs {
+  const BatchDesc *d;
+  int32_t count;
+  uint32_t *counter;     // queue head, zeroed by the launcher
+  const uint64_t *A;
+  uint64_t *L, *E;       // may be null
+  int64_t *perm, *pivcols;  // may be null
+  int64_t *rank;
+  uint64_t *W;           // worker slots, wslot words each
+  int64_t wslot;
+};
+
+struct BatchSolveArgs {
+  const BatchDesc *d;
+  int32_t count;
+  const uint64_t *L, *E;
+  const int64_t *perm, *pivcols, *rank;
+  const uint64_t *B;
+  uint64_t *X;
+  int32_t *consistent;
+};
+
+int batch_workers(int ncu);  // workgroups of one batched launch on a device of ncu CUs
+hipError_t launch_batch_dec(const BatchArgs &a, int workers, hipStream_t s);
+hipError_t launch_batch_solve(const BatchSolveArgs &a, hipStream_t s);
+
 }  // namespace gf2

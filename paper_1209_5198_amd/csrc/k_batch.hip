@@ -1,0 +1,507 @@
+// k_batch.hip -- many independent decompositions (and solves) in one launch.
+//
+// A batch holds up to thousands of matrices of at most kBatchMaxDim rows and
+// columns, each of its own shape.  One persistent launch factors all of them:
+// every workgroup takes the next matrix from a queue (the host orders the queue
+// by decreasing work, so the largest matrices start first and the small ones
+// fill the tail) and runs the whole decomposition of Section 4 on it, with the
+// matrix's working copy in a slot of its own (L2-resident for the sizes here).
+//
+// Per 64-column panel (word q of every row; the b = 64 panel of Section 4):
+//   * pivot search, procedure buildZ (Sections 4.2-4.4) in its b = 1 reading:
+//     for each bit k, the first position at or below the next free one whose
+//     reduced bit k is 1 is exchanged with it (a transposition of the
+//     position -> row map; rows never move in memory).  The panel words of the
+//     rows at or below R live in registers (8 per thread) while the search
+//     runs; every later row with bit k set is reduced in the bits above k and
+//     keeps its bit k as the multiplier (the compressed L of Fig. 1).
+//   * canonical multipliers: with T the unit lower matrix of the pivot rows'
+//     multipliers (U = T * E for the panel's pivot rows U and echelon rows E),
+//     every row at or below R gets c = y * T^-1 (its multipliers y applied to
+//     the unreduced pivot rows), and pivot row t gets row t of T^-1 without its
+//     diagonal.  Everything is indexed by bit position inside word q.
+//   * trailing update (the Schur complement, eq. (Aj)): for each chunk of 8
+//     later words, sixteen 4-bit Four-Russians tables (Section 6, c = 4) of
+//     the pivot rows' chunk words are built in LDS, and each row XORs in
+//     sixteen 64-byte table entries selected by the nibbles of its c; rows of
+//     the panel's pivots get their echelon form by the same product.
+// At the end L, E, the permutation, the pivot columns and the rank are written
+// in the caller's row-major formats.
+#include <limits.h>
+
+#include "gf2_internal.h"
+
+namespace gf2 {
+namespace {
+
+constexpr int NT = kBatchThreads;          // threads per workgroup
+constexpr int RPT = kBatchMaxDim / NT;     // panel positions per thread in the pivot search
+constexpr int NW = NT / 64;                // waves per workgroup
+constexpr int kChunk = 8;                  // later words per table build
+static_assert(RPT * NT == kBatchMaxDim, "positions per thread");
+
+__device__ inline uint64_t rdl64b(uint64_t v, int l) {
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Register array element at a run-time index, written with masks so that the
+// compiler keeps the array in registers instead of indexing local memory.
+__device__ inline uint64_t pick(const uint64_t (&x)[RPT], int u) {
+  uint64_t v = 0ull;
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) v |= x[j] & (0ull - (uint64_t)(u == j));
+  return v;
+}
+__device__ inline void put(uint64_t (&x)[RPT], int u, uint64_t v) {
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) x[j] ^= (x[j] ^ v) & (0ull - (uint64_t)(u == j));
+}
+
+// Bit compression (gather the bits of x selected by mask into the low bits, in
+// order): the parallel-suffix method of H. S. Warren, "Hacker's Delight",
+// Section 7-4.  The six move masks depend on the mask only and are computed
+// once per panel; compressing a word then costs six and/xor/shift/or steps.
+__device__ inline void compress_masks(uint64_t m, uint64_t (&mv)[6]) {
+  uint64_t mk = ~m << 1;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    uint64_t mp = mk ^ (mk << 1);
+    mp ^= mp << 2;
+    mp ^= mp << 4;
+    mp ^= mp << 8;
+    mp ^= mp << 16;
+    mp ^= mp << 32;
+    const uint64_t v = mp & m;
+    mv[i] = v;
+    m = (m ^ v) | (v >> (1 << i));
+    mk &= ~mp;
+  }
+}
+__device__ inline uint64_t compress(uint64_t x, uint64_t m, const uint64_t *mv) {
+  x &= m;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const uint64_t t = x & mv[i];
+    x = (x ^ t) | (t >> (1 << i));
+  }
+  return x;
+}
+
+struct BatchShared {
+  int32_t map[kBatchMaxDim];          // position -> row of the working copy
+  uint64_t cvec[kBatchMaxDim];        // canonical multipliers of positions R.. (then pivot columns)
+  uint64_t T[16][16][kChunk];         // 4-bit tables of the current chunk
+  uint64_t U[64][kChunk];             // pivot rows' chunk words, by pivot bit position
+  uint64_t Tt[16][16];                // 4-bit tables of the rows of T^-1
+  uint64_t tinv[64];                  // row k of T^-1 (bit-position space)
+  uint64_t pivw[64];                  // panel words of the panel's pivot rows
+  uint64_t pK[kBatchMaxPanels];       // pivot mask of each panel
+  uint64_t pmv[kBatchMaxPanels][6];   // compress masks of each panel's pivot mask
+  int32_t pR[kBatchMaxPanels];        // rank before each panel
+  int32_t pr[kBatchMaxPanels];        // pivots of each panel
+  int32_t prow[64];                   // pivot t of the current panel -> bit position
+  int32_t wc[2][NW];                  // per-wave first candidate (double-buffered by bit)
+  uint64_t pw, sw;                    // pivot word, word of the exchanged position
+  int32_t job;
+};
+
+__global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
+  __shared__ BatchShared sh;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  uint64_t *W = a.W + (size_t)blockIdx.x * (size_t)a.wslot;
+
+  for (;;) {
+    __syncthreads();  // the previous matrix is finished with the shared state
+    if (tid == 0) sh.job = (int)atomicAdd(a.counter, 1u);
+    __syncthreads();
+    const int job = sh.job;
+    if (job >= a.count) return;
+    const BatchDesc d = a.d[job];
+    const int n = d.n, m = d.m, Mw = (m + 63) >> 6, kmin = n < m ? n : m;
+
+    // ---- working copy (padding bits cleared) and identity map
+    {
+      const uint64_t *A = a.A + d.a;
+      const int nwords = n * Mw;
+      for (int e = tid; e < nwords; e += NT) W[e] = A[e] & pad_mask(m, e % Mw);
+      for (int i = tid; i < n; i += NT) sh.map[i] = i;
+    }
+    __syncthreads();
+
+    int R = 0, nq = 0;
+    for (int q = 0; q < Mw && R < n; ++q) {
+      nq = q + 1;
+      const int nbits = (m - 64 * q) < 64 ? (m - 64 * q) : 64;
+      const int base = R + RPT * tid;
+      uint64_t x[RPT];
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) x[u] = (base + u < n) ? W[(size_t)sh.map[base + u] * Mw + q] : 0ull;
+
+      // ---- pivot search over the bits of word q
+      int t = 0;
+      uint64_t K = 0ull;
+      for (int k = 0; k < nbits; ++k) {
+        const int pos = R + t;
+        if (pos >= n) break;
+        int fu = RPT;
+#pragma unroll
+        for (int u = RPT - 1; u >= 0; --u)
+          if (base + u >= pos && base + u < n && ((x[u] >> k) & 1ull)) fu = u;
+        const uint64_t bal = __ballot(fu < RPT);
+        int cand = INT_MAX;
+        if (bal) {
+          const int fl = (int)__builtin_ctzll(bal);
+          cand = R + RPT * (64 * wv + fl) + __builtin_amdgcn_readlane(fu, fl);
+        }
+        if (lane == 0) sh.wc[k & 1][wv] = cand;
+        __syncthreads();
+        int p = sh.wc[k & 1][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) p = min(p, sh.wc[k & 1][w]);
+        if (p == INT_MAX) continue;  // no row has bit k: not a pivot column
+        const int tp = (p - R) / RPT, up = (p - R) % RPT;
+        const int tq = (pos - R) / RPT, uq = (pos - R) % RPT;
+        if (tid == tp) sh.pw = pick(x, up);
+        if (tid == tq) sh.sw = pick(x, uq);
+        __syncthreads();
+        const uint64_t pw = sh.pw, sw = sh.sw;
+        if (tid == tp) put(x, up, sw);
+        if (tid == tq) put(x, uq, pw);
+        if (tid == 0) {
+          const int tmp = sh.map[pos];
+          sh.map[pos] = sh.map[p];
+          sh.map[p] = tmp;
+          sh.prow[t] = k;
+        }
+        const uint64_t hi = (k == 63) ? 0ull : (~0ull << (k + 1));
+#pragma unroll
+        for (int u = 0; u < RPT; ++u)
+          if (base + u > pos && base + u < n && ((x[u] >> k) & 1ull)) x[u] ^= pw & hi;
+        K |= 1ull << k;
+        ++t;
+      }
+      const int r = t;
+      __syncthreads();  // map exchanges by thread 0 are visible
+
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+        const int pos = base + u;
+        if (pos < n) W[(size_t)sh.map[pos] * Mw + q] = x[u];
+        if (pos < R + r) sh.pivw[pos - R] = x[u];
+      }
+      if (tid == 0) {
+        sh.pK[q] = K;
+        sh.pR[q] = R;
+        sh.pr[q] = r;
+      }
+      if (tid == 64) {
+        uint64_t mv[6];
+        compress_masks(K, mv);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) sh.pmv[q][i] = mv[i];
+      }
+      __syncthreads();
+      if (r == 0) continue;
+
+      // ---- T^-1 in bit-position space (wave 0, lane = bit position)
+      if (wv == 0) {
+        uint64_t trow = 0ull, tv = 0ull;
+        const uint64_t below = (1ull << lane) - 1ull;
+        if ((K >> lane) & 1ull) {
+          trow = sh.pivw[__popcll(K & below)] & K & below;
+          tv = 1ull << lane;
+        }
+        uint64_t Kr = K;
+        while (Kr) {
+          const int k = (int)__builtin_ctzll(Kr);
+          Kr &= Kr - 1ull;
+          const uint64_t v = rdl64b(tv, k);
+          if ((trow >> k) & 1ull) tv ^= v;
+        }
+        sh.tinv[lane] = tv;
+      }
+      __syncthreads();
+      {
+        const int g = tid >> 4, v = tid & 15;
+        uint64_t acc = 0ull;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if ((v >> b) & 1) acc ^= sh.tinv[4 * g + b];
+        sh.Tt[g][v] = acc;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+        const int pos = base + u;
+        if (pos < n) {
+          uint64_t c;
+          if (pos < R + r) {
+            const int k = sh.prow[pos - R];
+            c = sh.tinv[k] & ~(1ull << k);
+          } else {
+            const uint64_t xx = x[u] & K;
+            c = 0ull;
+#pragma unroll
+            for (int g = 0; g < 16; ++g) c ^= sh.Tt[g][(xx >> (4 * g)) & 15u];
+          }
+          sh.cvec[pos - R] = c;
+        }
+      }
+
+      // ---- trailing update, chunks of kChunk later words
+      for (int c0 = q + 1; c0 < Mw; c0 += kChunk) {
+        const int nw = (Mw - c0) < kChunk ? (Mw - c0) : kChunk;
+        __syncthreads();  // multipliers written; the previous chunk's tables are no longer read
+        for (int e = tid; e < 64 * kChunk; e += NT) {
+          const int k = e / kChunk, w = e % kChunk;
+          uint64_t v = 0ull;
+          if (((K >> k) & 1ull) && w < nw) {
+            const int s = __popcll(K & ((1ull << k) - 1ull));
+            v = W[(size_t)sh.map[R + s] * Mw + c0 + w];
+          }
+          sh.U[k][w] = v;
+        }
+        __syncthreads();
+        for (int e = tid; e < 16 * 16 * kChunk; e += NT) {
+          const int g = e / (16 * kChunk), v = (e / kChunk) & 15, w = e % kChunk;
+          uint64_t acc = 0ull;
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if ((v >> b) & 1) acc ^= sh.U[4 * g + b][w];
+          sh.T[g][v][w] = acc;
+        }
+        __syncthreads();
+        const int grp = tid / kChunk, w = tid % kChunk;
+        constexpr int G = NT / kChunk;  // row groups
+        if (w < nw) {
+          for (int i0 = R + grp; i0 < n; i0 += 4 * G) {
+            size_t off[4];
+            uint64_t old[4], cc[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int i = i0 + j * G;
+              off[j] = 0;
+              old[j] = 0ull;
+              cc[j] = 0ull;
+              if (i < n) {
+                off[j] = (size_t)sh.map[i] * Mw + c0 + w;
+                old[j] = W[off[j]];
+                cc[j] = sh.cvec[i - R];
+              }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              uint64_t acc = 0ull;
+#pragma unroll
+              for (int g = 0; g < 16; ++g) acc ^= sh.T[g][(cc[j] >> (4 * g)) & 15u][w];
+              if (i0 + j * G < n) W[off[j]] = old[j] ^ acc;
+            }
+          }
+        }
+      }
+      R += r;
+      __syncthreads();  // the next panel reads words written above
+    }
+
+    // ---- outputs
+    const int rank = R;
+    int32_t *pcol = (int32_t *)sh.cvec;  // pivot column of pivot t
+    for (int t = tid; t < rank; t += NT) {
+      int j = 0;
+      for (int jj = 0; jj < nq; ++jj)
+        if (t >= sh.pR[jj] && t < sh.pR[jj] + sh.pr[jj]) j = jj;
+      uint64_t Kj = sh.pK[j];
+      for (int s = t - sh.pR[j]; s > 0; --s) Kj &= Kj - 1ull;
+      pcol[t] = 64 * j + (int)__builtin_ctzll(Kj);
+    }
+    __syncthreads();
+    if (tid == 0) a.rank[d.idx] = rank;
+    if (a.pivcols)
+      for (int t = tid; t < kmin; t += NT) a.pivcols[d.c + t] = t < rank ? pcol[t] : -1;
+    if (a.perm)
+      for (int i = tid; i < n; i += NT) a.perm[d.p + i] = sh.map[i];
+    if (a.E) {
+      uint64_t *E = a.E + d.e;
+      for (int e = tid; e < kmin * Mw; e += NT) {
+        const int t = e / Mw, w = e - t * Mw;
+        uint64_t v = 0ull;
+        if (t < rank) {
+          const int pc = pcol[t], qt = pc >> 6;
+          if (w >= qt) {
+            v = W[(size_t)sh.map[t] * Mw + w];
+            if (w == qt) v &= ~0ull << (pc & 63);
+          }
+        }
+        E[e] = v;
+      }
+    }
+    if (a.L) {
+      uint64_t *L = a.L + d.l;
+      const int Lw = (kmin + 63) >> 6;
+      for (int e = tid; e < n * Lw; e += NT) {
+        const int i = e / Lw, lw = e - i * Lw;
+        const int c_lo = 64 * lw;
+        uint64_t v = 0ull;
+        for (int j = 0; j < nq; ++j) {
+          const int Rj = sh.pR[j], rj = sh.pr[j];
+          if (rj == 0 || i < Rj || Rj >= c_lo + 64 || Rj + rj <= c_lo) continue;
+          const uint64_t xw = W[(size_t)sh.map[i] * Mw + j];
+          uint64_t bits;
+          if (i < Rj + rj) {
+            const int s = i - Rj, kk = pcol[i] & 63;
+            bits = compress(xw & ((1ull << kk) - 1ull), sh.pK[j], sh.pmv[j]) | (1ull << s);
+          } else {
+            bits = compress(xw, sh.pK[j], sh.pmv[j]);
+          }
+          const int shf = Rj - c_lo;
+          v |= shf >= 0 ? (bits << shf) : (bits >> (-shf));
+        }
+        L[e] = v;
+      }
+    }
+  }
+}
+
+__global__ void k_batch_reset(uint32_t *counter) {
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+// ---------------------------------------------------------------- solve
+// One wave per system A x = b from the factors P*A = L*E (the use of the
+// decomposition named in Section 1): y = L_top^-1 (P b)_top by blocks of 64
+// pivots, consistency L_bot y = (P b)_bot, then x from E by back-substitution
+// with the free (non-pivot) variables zero.  Within a block of 64 the
+// triangular recurrences run on lane-indexed registers; across blocks they are
+// parities of staged rows against the finished part.
+constexpr int kSolveNT = 64;
+
+__global__ __launch_bounds__(kSolveNT) void k_batch_solve(BatchSolveArgs a) {
+  __shared__ uint64_t pb[kBatchMaxDim / 64], y[kBatchMaxDim / 64], xs[kBatchMaxDim / 64];
+  __shared__ uint64_t blk[64][kBatchMaxDim / 64 + 1];
+  const int lane = threadIdx.x;
+  const BatchDesc d = a.d[blockIdx.x];
+  const int n = d.n, m = d.m, kmin = n < m ? n : m;
+  const int Mw = (m + 63) >> 6, Lw = (kmin + 63) >> 6, nbw = (n + 63) >> 6;
+  int64_t rr = a.rank[d.idx];
+  const int r = rr < 0 ? 0 : (rr > kmin ? kmin : (int)rr);
+  const uint64_t *L = a.L + d.l, *E = a.E + d.e, *B = a.B + d.b;
+  const int64_t *perm = a.perm + d.p, *pivcols = a.pivcols + d.c;
+
+  if (lane < kBatchMaxDim / 64) {
+    y[lane] = 0ull;
+    xs[lane] = 0ull;
+    pb[lane] = 0ull;
+  }
+  __syncthreads();
+  for (int c = 0; c < nbw; ++c) {
+    const int i = 64 * c + lane;
+    uint32_t bit = 0u;
+    if (i < n) {
+      int64_t pi = perm[i];
+      pi = pi < 0 ? 0 : (pi >= n ? n - 1 : pi);
+      bit = (uint32_t)((B[pi >> 6] >> (pi & 63)) & 1ull);
+    }
+    const uint64_t wbits = __ballot(bit);
+    if (lane == 0) pb[c] = wbits;
+  }
+  __syncthreads();
+
+  // ---- forward substitution with L's unit lower r x r block
+  const int nblk = (r + 63) >> 6;
+  for (int b = 0; b < nblk; ++b) {
+    const int t0 = 64 * b, nb = (r - t0) < 64 ? (r - t0) : 64;
+    for (int e = lane; e < 64 * (b + 1); e += kSolveNT) {
+      const int row = e / (b + 1), w = e - row * (b + 1);
+      blk[row][w] = row < nb ? L[(size_t)(t0 + row) * Lw + w] : 0ull;
+    }
+    __syncthreads();
+    uint32_t acc = (uint32_t)((pb[b] >> lane) & 1ull);
+    for (int w = 0; w < b; ++w) acc ^= (uint32_t)__popcll(blk[lane][w] & y[w]) & 1u;
+    const uint64_t dw = blk[lane][b] & ((1ull << lane) - 1ull);
+    uint64_t yb = 0ull;
+    for (int s = 0; s < nb; ++s) {
+      const uint64_t ds = rdl64b(dw, s);
+      const uint32_t as = __builtin_amdgcn_readlane(acc, s);
+      yb |= (uint64_t)((as ^ (uint32_t)__popcll(ds & yb)) & 1u) << s;
+    }
+    __syncthreads();
+    if (lane == 0) y[b] = yb;
+    __syncthreads();
+  }
+
+  // ---- consistency of the rows below the pivots
+  uint64_t bad = 0ull;
+  for (int i0 = r; i0 < n; i0 += 64) {
+    const int i = i0 + lane;
+    uint32_t v = 0u;
+    if (i < n) {
+      v = (uint32_t)((pb[i >> 6] >> (i & 63)) & 1ull);
+      for (int w = 0; w < nblk; ++w) v ^= (uint32_t)__popcll(L[(size_t)i * Lw + w] & y[w]) & 1u;
+    }
+    bad |= __ballot(v);
+  }
+  const bool ok = bad == 0ull;
+
+  // ---- back-substitution with E, free variables zero
+  if (ok) {
+    for (int b = nblk - 1; b >= 0; --b) {
+      const int t0 = 64 * b, nb = (r - t0) < 64 ? (r - t0) : 64;
+      __syncthreads();
+      for (int e = lane; e < 64 * Mw; e += kSolveNT) {
+        const int row = e / Mw, w = e - row * Mw;
+        blk[row][w] = row < nb ? E[(size_t)(t0 + row) * Mw + w] : 0ull;
+      }
+      __syncthreads();
+      const bool valid = lane < nb;
+      int pc = 0;
+      if (valid) {
+        const int64_t v = pivcols[t0 + lane];
+        pc = v < 0 ? 0 : (v >= m ? m - 1 : (int)v);
+      }
+      uint32_t acc = valid ? (uint32_t)((y[b] >> lane) & 1ull) : 0u;
+      for (int w = 0; w < Mw; ++w) acc ^= (uint32_t)__popcll(blk[lane][w] & xs[w]) & 1u;
+      uint64_t dm = 0ull;
+      for (int u = 0; u < nb; ++u) {
+        const int pu = __builtin_amdgcn_readlane(pc, u);
+        dm |= ((blk[lane][pu >> 6] >> (pu & 63)) & 1ull) << u;
+      }
+      dm &= lane >= 63 ? 0ull : (~0ull << (lane + 1));
+      uint64_t xb = 0ull;
+      for (int u = nb - 1; u >= 0; --u) {
+        const uint64_t du = rdl64b(dm, u);
+        const uint32_t au = __builtin_amdgcn_readlane(acc, u);
+        xb |= (uint64_t)((au ^ (uint32_t)__popcll(du & xb)) & 1u) << u;
+      }
+      __syncthreads();
+      if (valid && ((xb >> lane) & 1ull)) atomicOr((unsigned long long *)&xs[pc >> 6], 1ull << (pc & 63));
+    }
+  }
+  __syncthreads();
+  uint64_t *X = a.X + d.x;
+  for (int w = lane; w < Mw; w += kSolveNT) X[w] = ok ? xs[w] : 0ull;
+  if (lane == 0) a.consistent[d.idx] = ok ? 1 : 0;
+}
+
+}  // namespace
+
+int batch_workers(int ncu) { return kBatchWGPerCU * ncu; }
+
+hipError_t launch_batch_dec(const BatchArgs &a, int workers, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, a.counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_dec, dim3(workers), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_solve(const BatchSolveArgs &a, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_solve, dim3(a.count), dim3(kSolveNT), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace gf2

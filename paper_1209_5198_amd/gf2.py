@@ -26,8 +26,10 @@ GF2_EINVAL = -1
 GF2_ENOMEM = -2
 GF2_EHIP = -3
 
-EXPORTED = ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_set_param",
-            "gf2_profile", "gf2_profile_read", "gf2_release", "gf2_last_error", "gf2_version")
+EXPORTED = ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_decompose_batched",
+            "gf2_solve_batched", "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_release",
+            "gf2_last_error", "gf2_version")
+BATCH_MAX_DIM = 2048
 
 
 class Gf2Error(RuntimeError):
@@ -39,6 +41,11 @@ class Gf2Error(RuntimeError):
 class _Mat(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
                 ("w", ctypes.c_int64), ("ld", ctypes.c_int64)]
+
+
+class BatchItem(ctypes.Structure):
+    """gf2_batch_item: shape of one batch matrix and the offsets of its pieces."""
+    _fields_ = [(f, ctypes.c_int64) for f in ("rows", "cols", "a", "l", "e", "p", "c", "b", "x")]
 
 
 _lib = None
@@ -58,6 +65,9 @@ def load():
         lib.gf2_decompose.argtypes = [P, P, P, vp, vp, vp, vp]
         lib.gf2_rank.argtypes = [P, vp, vp]
         lib.gf2_solve.argtypes = [P, P, P, vp, vp, vp]
+        PB = ctypes.POINTER(BatchItem)
+        lib.gf2_decompose_batched.argtypes = [PB, i64, vp, vp, vp, vp, vp, vp, vp]
+        lib.gf2_solve_batched.argtypes = [PB, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.gf2_set_param.argtypes = [ctypes.c_char_p, i64]
         lib.gf2_profile.argtypes = [ctypes.c_int]
         lib.gf2_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
@@ -65,8 +75,9 @@ def load():
         lib.gf2_release.argtypes = []
         lib.gf2_last_error.restype = ctypes.c_char_p
         lib.gf2_version.restype = ctypes.c_char_p
-        for name in ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_set_param",
-                     "gf2_profile", "gf2_profile_read", "gf2_release"):
+        for name in ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_decompose_batched",
+                     "gf2_solve_batched", "gf2_set_param", "gf2_profile", "gf2_profile_read",
+                     "gf2_release"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -175,6 +186,17 @@ def gf2_solve(A: Mat, B: Mat, X: Mat, consistent, rank=None, stream=None) -> Non
                             _ptr(consistent), _ptr(rank), _stream(stream)))
 
 
+def gf2_decompose_batched(items, A, L, E, perm, pivcols, rank, stream=None) -> None:
+    """items: a ctypes array of BatchItem (host); the pools are device tensors (or None)."""
+    _check(load().gf2_decompose_batched(items, len(items), _ptr(A), _ptr(L), _ptr(E), _ptr(perm),
+                                        _ptr(pivcols), _ptr(rank), _stream(stream)))
+
+
+def gf2_solve_batched(items, L, E, perm, pivcols, rank, B, X, consistent, stream=None) -> None:
+    _check(load().gf2_solve_batched(items, len(items), _ptr(L), _ptr(E), _ptr(perm), _ptr(pivcols),
+                                    _ptr(rank), _ptr(B), _ptr(X), _ptr(consistent), _stream(stream)))
+
+
 def gf2_set_param(name: str, value: int) -> None:
     _check(load().gf2_set_param(name.encode(), int(value)))
 
@@ -235,3 +257,101 @@ def solve(A: Mat, B: Mat, stream=None):
     rank = torch.empty(1, dtype=torch.int64, device=A.t.device)
     gf2_solve(A, B, X, cons, rank, stream)
     return dict(X=X, consistent=cons, rank=rank)
+
+
+class Batch:
+    """Device pools of a batch of row-major bit matrices (the gf2_batch_item layout).
+
+    ``shapes`` is a list of (rows, cols).  Offsets are assigned in order; every
+    pool is an int64 torch tensor of raw words.  ``set_matrices`` / ``set_rhs``
+    upload numpy word arrays, ``decompose`` / ``solve`` call the ABI, and
+    ``fetch`` copies every pool back once so that ``result(i)`` can slice it.
+    """
+
+    def __init__(self, shapes, device="cuda"):
+        import torch
+
+        self.shapes = [(int(n), int(m)) for n, m in shapes]
+        cnt = len(self.shapes)
+        self.items = (BatchItem * cnt)()
+        offs = dict(a=0, l=0, e=0, p=0, c=0, b=0, x=0)
+        self.off = []
+        for i, (n, m) in enumerate(self.shapes):
+            k = min(n, m)
+            o = dict(offs)
+            self.off.append(o)
+            it = self.items[i]
+            it.rows, it.cols = n, m
+            it.a, it.l, it.e, it.p, it.c, it.b, it.x = o["a"], o["l"], o["e"], o["p"], o["c"], o["b"], o["x"]
+            offs["a"] += n * wpr(m)
+            offs["l"] += n * wpr(k)
+            offs["e"] += k * wpr(m)
+            offs["p"] += n
+            offs["c"] += k
+            offs["b"] += wpr(n)
+            offs["x"] += wpr(m)
+        self.size = offs
+
+        def pool(words, dtype=torch.int64):
+            return torch.zeros(max(words, 1), dtype=dtype, device=device)
+
+        self.A, self.L, self.E = pool(offs["a"]), pool(offs["l"]), pool(offs["e"])
+        self.perm, self.pivcols = pool(offs["p"]), pool(offs["c"])
+        self.B, self.X = pool(offs["b"]), pool(offs["x"])
+        self.rank = pool(cnt)
+        self.consistent = pool(cnt, torch.int32)
+        self.host = None
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def _upload(self, dst, arrays, key, rows_of):
+        import torch
+
+        flat = np.zeros(max(self.size[key], 1), dtype=np.uint64)
+        for i, a in enumerate(arrays):
+            o = self.off[i][key]
+            a = np.ascontiguousarray(a, dtype=np.uint64).reshape(-1)
+            assert a.size == rows_of(i), (i, a.size, rows_of(i))
+            flat[o:o + a.size] = a
+        dst.copy_(torch.from_numpy(flat.view(np.int64)))
+
+    def set_matrices(self, mats):
+        """mats[i]: numpy uint64 array of rows x ceil(cols/64) words."""
+        self._upload(self.A, mats, "a", lambda i: self.shapes[i][0] * wpr(self.shapes[i][1]))
+
+    def set_rhs(self, rhs):
+        """rhs[i]: numpy uint64 array of ceil(rows/64) words (bit j = entry j)."""
+        self._upload(self.B, rhs, "b", lambda i: wpr(self.shapes[i][0]))
+
+    def mat_view(self, i) -> "Mat":
+        """Matrix i of the A pool as a row-major Mat (a view; for gf2_matmul)."""
+        n, m = self.shapes[i]
+        o = self.off[i]["a"]
+        return Mat(self.A[o:o + max(n * wpr(m), 1)], n, m, max(wpr(m), 1), max(n, 1))
+
+    def decompose(self, want_le=True, stream=None):
+        gf2_decompose_batched(self.items, self.A, self.L if want_le else None, self.E if want_le else None,
+                              self.perm, self.pivcols, self.rank, stream)
+
+    def solve(self, stream=None):
+        gf2_solve_batched(self.items, self.L, self.E, self.perm, self.pivcols, self.rank, self.B, self.X,
+                          self.consistent, stream)
+
+    def fetch(self):
+        self.host = {k: getattr(self, k).cpu().numpy() for k in
+                     ("L", "E", "perm", "pivcols", "rank", "X", "consistent")}
+        return self.host
+
+    def result(self, i):
+        h = self.host if self.host is not None else self.fetch()
+        n, m = self.shapes[i]
+        k = min(n, m)
+        o = self.off[i]
+        return dict(rank=int(h["rank"][i]),
+                    perm=h["perm"][o["p"]:o["p"] + n],
+                    pivcols=h["pivcols"][o["c"]:o["c"] + k],
+                    L=h["L"][o["l"]:o["l"] + n * wpr(k)].view(np.uint64).reshape(n, wpr(k)),
+                    E=h["E"][o["e"]:o["e"] + k * wpr(m)].view(np.uint64).reshape(k, wpr(m)),
+                    x=h["X"][o["x"]:o["x"] + wpr(m)].view(np.uint64),
+                    consistent=int(h["consistent"][i]))

@@ -24,6 +24,10 @@ Workloads (shapes, value distributions and structure of the paper's tests):
   * ``sparse_rows`` exactly ``k`` ones per row at distinct uniform positions
                    (the shape of the low-rank sample S_n of Section 7).
   * ``planted``    factors X (n x r), Y (r x m) of a rank-<=r product X*Y.
+  * ``batch_specs`` shapes and kinds of a batch of independent matrices (sides
+                   uniform in [lo, hi], density 1/2 or 1/10, half of them with
+                   a planted rank), ``batch_matrix`` / ``batch_rhs`` their
+                   entries and right-hand sides.
 """
 from __future__ import annotations
 
@@ -117,3 +121,54 @@ def planted(seed: int, stream: int, rows: int, cols: int, r: int, p: float = 0.5
     X = bernoulli(seed, 2 * stream, rows, r, p)
     Y = bernoulli(seed, 2 * stream + 1, r, cols, p)
     return X, Y
+
+
+# ---------------------------------------------------------------- batches
+BATCH_SPEC_STREAM = 0x6261  # draws of the batch shapes
+BATCH_MAT_STREAM = 1_000_000  # + i: entries of matrix i (planted: 2 * (this + i) and + 1)
+BATCH_RHS_STREAM = 5_000_000  # + i: right-hand side of matrix i
+
+
+def batch_specs(seed: int, count: int, lo: int = 64, hi: int = 2048, densities=(0.5, 0.1)):
+    """Per-matrix workload parameters of a batch.
+
+    Matrix i uses draws 4i..4i+3 of stream BATCH_SPEC_STREAM: n = lo + d0 mod
+    (hi-lo+1), m likewise from d1 (independent sides), density densities[d2 & 1],
+    planted iff bit 1 of d2 (probability 1/2), with planted rank
+    r = r_lo + d3 mod (kmin - r_lo + 1), r_lo = min(ceil(m/4), kmin); r = 0 means
+    an iid matrix.
+    """
+    d = words(seed, BATCH_SPEC_STREAM, 0, 4 * count).reshape(count, 4) if count else np.zeros((0, 4), np.uint64)
+    span = hi - lo + 1
+    out = []
+    for i in range(count):
+        n = lo + int(d[i, 0] % np.uint64(span))
+        m = lo + int(d[i, 1] % np.uint64(span))
+        p = densities[int(d[i, 2] & np.uint64(1))]
+        r = 0
+        if int(d[i, 2] >> np.uint64(1)) & 1:
+            kmin = min(n, m)
+            r_lo = min((m + 3) // 4, kmin)
+            r = r_lo + int(d[i, 3] % np.uint64(kmin - r_lo + 1))
+        out.append(dict(i=i, n=n, m=m, p=p, r=r))
+    return out
+
+
+def batch_matrix(seed: int, spec):
+    """Entries of a batch matrix: ('iid', A) or ('planted', X, Y) with X n x r and Y r x m
+    of the matrix's density (each side forms the product with its own code)."""
+    i, n, m, p, r = spec["i"], spec["n"], spec["m"], spec["p"], spec["r"]
+    if r:
+        X, Y = planted(seed, BATCH_MAT_STREAM + i, n, m, r, p)
+        return ("planted", X, Y)
+    return ("iid", bernoulli(seed, BATCH_MAT_STREAM + i, n, m, p))
+
+
+def batch_rhs(seed: int, spec) -> np.ndarray:
+    """Right-hand side of batch matrix i: n Bernoulli(1/2) bits, bit j of the vector
+    is bit j % 64 of word j // 64."""
+    n = spec["n"]
+    out = words(seed, BATCH_RHS_STREAM + spec["i"], 0, wpr(n))
+    if out.size:
+        out[-1] &= pad_mask(n)
+    return out

@@ -86,3 +86,54 @@ def test_blocked_layout_roundtrip():
         for i in range(rows):
             for q in range(nw):
                 assert flat[(q // w) * ld * w + i * w + q % w] == words[i, q]
+
+
+def test_batched_validation_without_gpu():
+    """Host-side checks of the batched entry points reject bad items before any launch."""
+    import ctypes
+
+    from paper_1209_5198_amd import gf2
+
+    lib = gf2.load()
+    items = (gf2.BatchItem * 2)()
+    items[0].rows, items[0].cols = 10, 10
+    items[1].rows, items[1].cols = gf2.BATCH_MAX_DIM + 1, 5
+    dummy = ctypes.c_void_p(16)
+    rc = lib.gf2_decompose_batched(items, 2, dummy, None, None, None, None, dummy, None)
+    assert rc == gf2.GF2_EINVAL and b"rows and cols" in lib.gf2_last_error()
+    items[1].rows = 5
+    items[1].e = -1
+    assert lib.gf2_decompose_batched(items, 2, dummy, None, None, None, None, dummy, None) == gf2.GF2_EINVAL
+    assert b"negative offset" in lib.gf2_last_error()
+    items[1].e = 0
+    assert lib.gf2_decompose_batched(items, -1, dummy, None, None, None, None, dummy, None) == gf2.GF2_EINVAL
+    assert lib.gf2_decompose_batched(None, 3, dummy, None, None, None, None, dummy, None) == gf2.GF2_EINVAL
+    assert lib.gf2_decompose_batched(items, 2, dummy, None, None, None, None, None, None) == gf2.GF2_EINVAL
+    assert b"null rank" in lib.gf2_last_error()
+    assert lib.gf2_solve_batched(items, 2, dummy, dummy, dummy, dummy, dummy, None, dummy, dummy,
+                                 None) == gf2.GF2_EINVAL
+    # an empty batch is a valid no-op
+    assert lib.gf2_decompose_batched(items, 0, None, None, None, None, None, None, None) == gf2.GF2_OK
+
+
+def test_batch_offsets_pack_the_pools():
+    """The binding's Batch offsets follow the gf2_batch_item layout (no GPU: offsets only)."""
+    from paper_1209_5198_amd import gf2
+
+    shapes = [(3, 70), (0, 5), (130, 64), (64, 1)]
+    off = dict(a=0, l=0, e=0, p=0, c=0, b=0, x=0)
+    want = []
+    for n, m in shapes:
+        k = min(n, m)
+        want.append(dict(off))
+        off["a"] += n * gf2.wpr(m)
+        off["l"] += n * gf2.wpr(k)
+        off["e"] += k * gf2.wpr(m)
+        off["p"] += n
+        off["c"] += k
+        off["b"] += gf2.wpr(n)
+        off["x"] += gf2.wpr(m)
+    b = gf2.Batch(shapes, device="cpu")
+    assert b.off == want and b.size == off
+    assert [(it.rows, it.cols, it.a, it.l, it.e) for it in b.items] == [
+        (n, m, w["a"], w["l"], w["e"]) for (n, m), w in zip(shapes, want)]

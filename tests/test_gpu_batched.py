@@ -1,0 +1,240 @@
+"""GPU parity of the batched entry points (gf2_decompose_batched, gf2_solve_batched).
+
+Every matrix of a batch is compared with the CPU oracle bit for bit: rank,
+perm, pivcols, L, E from the oracle's decomposition and x, consistent from the
+oracle's solve of A x = b.  Inputs come from the shared seeded generator;
+planted products are formed by gf2_matmul on the GPU side and by the oracle's
+product on the oracle side (their equality is checked too).  Cases: the
+degenerate shapes (0 rows or columns, 1 x 1, one row or column of the maximum
+length, zero, identity, all ones, duplicate rows), ragged random mixes, the
+full 4096-matrix workload (sides uniform in [64, 2048], density 1/2 or 1/10,
+half planted), rank-only calls, and the same matrices alone and in a mix.
+"""
+import concurrent.futures
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1209_5198_amd import synth
+
+pytestmark = pytest.mark.gpu
+wpr = synth.wpr
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1209_5198_amd import gf2
+
+    gf2.load()
+    return gf2
+
+
+def bits_to_col(v, n):
+    """Bit vector (wpr(n) words) -> n x 1 matrix (one word per row, bit 0)."""
+    out = np.zeros((n, 1), dtype=np.uint64)
+    for j in range(n):
+        out[j, 0] = (int(v[j >> 6]) >> (j & 63)) & 1
+    return out
+
+
+def col_to_bits(X, m):
+    out = np.zeros(wpr(m), dtype=np.uint64)
+    for j in range(m):
+        if int(X[j, 0]) & 1:
+            out[j >> 6] |= np.uint64(1) << np.uint64(j & 63)
+    return out
+
+
+def oracle_one(orc, A, n, m, b):
+    orc.set_threads(1)  # per OS thread: the pool supplies the parallelism
+    ple = orc.ple(A, n, m)
+    sol = orc.solve(A, bits_to_col(b, n), n, m, 1)
+    ple["x"] = col_to_bits(sol["X"], m)
+    ple["consistent"] = int(sol["consistent"][0]) & 1
+    return ple
+
+
+def oracle_all(orc, mats, shapes, rhs):
+    with concurrent.futures.ThreadPoolExecutor(16) as ex:
+        return list(ex.map(lambda i: oracle_one(orc, mats[i], shapes[i][0], shapes[i][1], rhs[i]),
+                           range(len(shapes))))
+
+
+def run_batch(g, shapes, mats, rhs, planted=None, want_le=True, solve=True):
+    """Upload, form planted products on the GPU, decompose (and solve); returns the Batch."""
+    import torch
+
+    b = g.Batch(shapes)
+    b.set_matrices(mats)
+    for i, (X, Y, r) in (planted or {}).items():
+        n, m = shapes[i]
+        C = b.mat_view(i)
+        g.gf2_matmul(C, g.Mat.from_rowmajor(X, n, r), g.Mat.from_rowmajor(Y, r, m))
+    b.set_rhs(rhs)
+    b.decompose(want_le=want_le)
+    if solve:
+        b.solve()
+    torch.cuda.synchronize()
+    b.fetch()
+    return b
+
+
+def compare(b, refs, want_le=True, solve=True, tag=""):
+    bad = []
+    for i, ref in enumerate(refs):
+        got = b.result(i)
+        ok = got["rank"] == ref["rank"] and np.array_equal(got["perm"], ref["perm"]) and np.array_equal(
+            got["pivcols"], ref["pivcols"])
+        if want_le:
+            # the oracle returns L with max(1, wpr(kmin)) word columns; compare wpr(kmin)
+            Lref = ref["L"][:, :wpr(min(b.shapes[i]))]
+            ok = ok and np.array_equal(got["E"], ref["E"]) and np.array_equal(got["L"], Lref)
+        if solve:
+            ok = ok and got["consistent"] == ref["consistent"] and np.array_equal(got["x"], ref["x"])
+        if not ok:
+            bad.append((i, b.shapes[i], got["rank"], ref["rank"]))
+    assert not bad, (tag, len(bad), bad[:8])
+
+
+def spec_inputs(orc, seed, specs):
+    """Shapes, GPU upload arrays (planted slots zero), planted factors, oracle matrices, rhs."""
+    def one(s):
+        n, m = s["n"], s["m"]
+        kind = synth.batch_matrix(seed, s)
+        if kind[0] == "iid":
+            return kind[1], None, kind[1]
+        X, Y = kind[1], kind[2]
+        orc.set_threads(1)
+        return np.zeros((n, wpr(m)), dtype=np.uint64), (X, Y, s["r"]), orc.matmul(X, Y, n, s["r"], m)
+
+    with concurrent.futures.ThreadPoolExecutor(16) as ex:
+        got = list(ex.map(one, specs))
+    shapes = [(s["n"], s["m"]) for s in specs]
+    mats = [x[0] for x in got]
+    planted = {s["i"]: x[1] for s, x in zip(specs, got) if x[1] is not None}
+    omats = [x[2] for x in got]
+    rhs = [synth.batch_rhs(seed, s) for s in specs]
+    return shapes, mats, planted, omats, rhs
+
+
+def column_bits(A, n, j):
+    """Column j of a row-major word matrix as a bit vector (data movement only)."""
+    out = np.zeros(wpr(n), dtype=np.uint64)
+    for i in range(n):
+        if (int(A[i, j >> 6]) >> (j & 63)) & 1:
+            out[i >> 6] |= np.uint64(1) << np.uint64(i & 63)
+    return out
+
+
+def edge_inputs(orc):
+    """Degenerate and boundary shapes.  Odd cases get a right-hand side equal to
+    a column of A (always consistent), even ones a random one."""
+    cases = []
+
+    def add(A, n, m):
+        cases.append((np.ascontiguousarray(A, dtype=np.uint64).reshape(n, wpr(m)), n, m))
+
+    add(np.zeros((0, 0)), 0, 0)
+    add(np.zeros((0, 1)), 0, 7)
+    add(np.zeros((7, 0)), 7, 0)
+    add(np.ones((1, 1)), 1, 1)
+    add(np.zeros((1, 1)), 1, 1)
+    ident = np.zeros((64, 1), dtype=np.uint64)
+    for i in range(64):
+        ident[i, 0] = np.uint64(1) << np.uint64(i)
+    add(ident, 64, 64)
+    add(np.full((65, 3), np.uint64(0xFFFFFFFFFFFFFFFF)) & synth.pad_mask(130), 65, 130)  # all ones, rank 1
+    add(synth.dense(3, 1, 2048, 1), 2048, 1)
+    add(synth.dense(3, 2, 1, 2048), 1, 2048)
+    dup = synth.dense(3, 3, 65, 70)
+    add(np.concatenate([dup, dup]), 130, 70)
+    add(synth.dense(3, 4, 2048, 2048), 2048, 2048)
+    add(synth.bernoulli(3, 5, 200, 2048, 0.02), 200, 2048)
+    add(synth.dense(3, 6, 2048, 200), 2048, 200)
+    add(np.zeros((100, 2)), 100, 100)
+    add(synth.dense(3, 7, 63, 65), 63, 65)
+    add(synth.dense(3, 8, 129, 64), 129, 64)
+    shapes = [(n, m) for _, n, m in cases]
+    mats = [A for A, _, _ in cases]
+    omats = list(mats)
+    # planted rank 37: the GPU forms X*Y with gf2_matmul, the oracle with its product
+    n, m, r = 1500, 1700, 37
+    X, Y = synth.planted(3, 9, n, m, r, 0.5)
+    planted = {len(shapes): (X, Y, r)}
+    shapes.append((n, m))
+    mats.append(np.zeros((n, wpr(m)), dtype=np.uint64))
+    omats.append(orc.matmul(X, Y, n, r, m))
+    rhs = []
+    for i, (n, m) in enumerate(shapes):
+        if i % 2 and m > 0 and n > 0:
+            rhs.append(column_bits(omats[i], n, (7 * i) % m))
+        else:
+            rhs.append(synth.dense(3, 200 + i, 1, n)[0] if n else np.zeros(0, dtype=np.uint64))
+    return shapes, mats, planted, omats, rhs
+
+
+def test_batched_edge_cases(g, orc):
+    shapes, mats, planted, omats, rhs = edge_inputs(orc)
+    say("batched edge cases", len(shapes))
+    refs = oracle_all(orc, omats, shapes, rhs)
+    b = run_batch(g, shapes, mats, rhs, planted)
+    compare(b, refs, tag="edge")
+    assert any(r["consistent"] for r in refs) and not all(r["consistent"] for r in refs)
+
+
+def test_batched_random_mix(g, orc):
+    specs = synth.batch_specs(11, 300, lo=1, hi=700)
+    shapes, mats, planted, omats, rhs = spec_inputs(orc, 11, specs)
+    say("batched random mix", len(specs), "planted", len(planted))
+    refs = oracle_all(orc, omats, shapes, rhs)
+    b = run_batch(g, shapes, mats, rhs, planted)
+    compare(b, refs, tag="mix")
+
+
+def test_batched_rank_only_and_alone_vs_mix(g, orc):
+    specs = synth.batch_specs(12, 40, lo=1, hi=1200)
+    shapes, mats, planted, omats, rhs = spec_inputs(orc, 12, specs)
+    say("batched rank-only / alone vs mix", len(specs))
+    refs = oracle_all(orc, omats, shapes, rhs)
+    mix = run_batch(g, shapes, mats, rhs, planted)
+    compare(mix, refs, tag="mix40")
+    ro = run_batch(g, shapes, mats, rhs, planted, want_le=False, solve=False)
+    compare(ro, refs, want_le=False, solve=False, tag="rank-only")
+    for i in (0, 7, 19, 39):
+        one_planted = {0: planted[i]} if i in planted else None
+        alone = run_batch(g, [shapes[i]], [mats[i]], [rhs[i]], one_planted)
+        a, b = alone.result(0), mix.result(i)
+        for k in ("rank", "consistent"):
+            assert a[k] == b[k], (i, k)
+        for k in ("perm", "pivcols", "L", "E", "x"):
+            assert np.array_equal(a[k], b[k]), (i, k)
+
+
+def test_batched_full_workload(g, orc):
+    """The 4096-matrix workload: sides uniform in [64, 2048], density 1/2 or 1/10, half planted."""
+    import torch
+
+    specs = synth.batch_specs(4096, 4096)
+    shapes, mats, planted, omats, rhs = spec_inputs(orc, 4096, specs)
+    say("batched full workload", len(specs), "planted", len(planted))
+    b = run_batch(g, shapes, mats, rhs, planted)
+    # the planted products formed on the GPU equal the oracle's
+    Ah = b.A.cpu().numpy().view(np.uint64)
+    for i in planted:
+        n, m = shapes[i]
+        o = b.off[i]["a"]
+        assert np.array_equal(Ah[o:o + n * wpr(m)].reshape(n, wpr(m)), omats[i]), ("planted product", i)
+    del Ah
+    torch.cuda.synchronize()
+    refs = oracle_all(orc, omats, shapes, rhs)
+    compare(b, refs, tag="full")
