@@ -18,6 +18,13 @@ sample of the same workload (the largest dense matrix of the same distribution
 that fits the time budget, the 65536^2 matrix itself on a 16-thread host),
 expressed in the same unit.
 
+batched: the 4096-matrix workload (sides uniform in [64, 2048], density 1/2 or
+1/10, half with a planted rank, one random right-hand side each) factored by
+gf2_decompose_batched and solved by gf2_solve_batched, timed with HIP events
+over `--batch-steps` passes with the inputs resident; reported as matrices/s,
+solves/s (decomposition + solve per system) and effective bit-ops/s, beside one
+gf2_decompose call per matrix on the same GPU (same outputs, checked equal).
+
 HBM traffic of that kernel is read from rocprofv3 counters (FETCH_SIZE and
 WRITE_SIZE, separate runs); --copy-calibration runs only a plain 1 GiB device
 copy, whose counter readings give the scale factor between counter units and
@@ -83,6 +90,89 @@ def cpu_baseline(budget_s: float = 24.0):
                       f"{dt:.2f} s, rank {res['rank']}"}
 
 
+BATCH_SEED, BATCH_COUNT = 4096, 4096
+
+
+def batched_section(gf2, synth, steps: int, per_matrix: bool = True):
+    """The batched workload: device-resident batch, decomposition + solve per pass."""
+    import concurrent.futures
+
+    import torch
+
+    wpr = synth.wpr
+    t0 = time.perf_counter()
+    specs = synth.batch_specs(BATCH_SEED, BATCH_COUNT)
+    with concurrent.futures.ThreadPoolExecutor(16) as ex:
+        kinds = list(ex.map(lambda s: synth.batch_matrix(BATCH_SEED, s), specs))
+    shapes = [(s["n"], s["m"]) for s in specs]
+    b = gf2.Batch(shapes)
+    b.set_matrices([k[1] if k[0] == "iid" else np.zeros((s["n"], wpr(s["m"])), np.uint64)
+                    for k, s in zip(kinds, specs)])
+    for k, s in zip(kinds, specs):  # planted products X*Y formed on the GPU
+        if k[0] == "planted":
+            n, m, r = s["n"], s["m"], s["r"]
+            gf2.gf2_matmul(b.mat_view(s["i"]), gf2.Mat.from_rowmajor(k[1], n, r), gf2.Mat.from_rowmajor(k[2], r, m))
+    b.set_rhs([synth.batch_rhs(BATCH_SEED, s) for s in specs])
+    del kinds
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_dec = timed(lambda: b.decompose(stream=stream), steps)
+    ms_solve = timed(lambda: b.solve(stream=stream), steps)
+    ms_rank = timed(lambda: b.decompose(want_le=False, stream=stream), steps)
+    b.decompose(stream=stream)
+    b.solve(stream=stream)
+    torch.cuda.synchronize()
+    h = b.fetch()
+    ops = 0.0
+    for i, (n, m) in enumerate(shapes):
+        o = b.off[i]["c"]
+        ops += eff_bitops(n, m, h["pivcols"][o:o + min(n, m)])
+    out = {"workload": f"{BATCH_COUNT} matrices, n and m uniform in [64, 2048], Bernoulli(1/2 or 1/10), "
+                       "half planted rank, one rhs each; seed %d" % BATCH_SEED,
+           "steps": steps, "ms_decompose": ms_dec, "ms_solve": ms_solve, "ms_rank_only": ms_rank,
+           "matrices_per_s": BATCH_COUNT / (ms_dec / 1e3),
+           "solves_per_s": BATCH_COUNT / ((ms_dec + ms_solve) / 1e3),
+           "eff_bitops_per_s": ops / (ms_dec / 1e3), "eff_bitops_per_pass": ops,
+           "consistent_systems": int(h["consistent"][:BATCH_COUNT].sum()), "setup_s": round(setup_s, 1)}
+    if per_matrix:
+        keep = {k: h[k].copy() for k in ("L", "E", "perm", "pivcols", "rank")}
+
+        def one_by_one():
+            for i, (n, m) in enumerate(shapes):
+                k = min(n, m)
+                o = b.off[i]
+                L = gf2.Mat(b.L[o["l"]:o["l"] + max(n * wpr(k), 1)], n, k, max(wpr(k), 1), max(n, 1))
+                E = gf2.Mat(b.E[o["e"]:o["e"] + max(k * wpr(m), 1)], k, m, max(wpr(m), 1), max(k, 1))
+                gf2.gf2_decompose(b.mat_view(i), L, E, b.perm[o["p"]:], b.pivcols[o["c"]:], b.rank[i:i + 1],
+                                  stream)
+
+        one_by_one()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        one_by_one()
+        torch.cuda.synchronize()
+        ms_pm = (time.perf_counter() - t1) * 1e3
+        h2 = b.fetch()
+        out["one_launch_per_matrix"] = {"ms_decompose": ms_pm, "matrices_per_s": BATCH_COUNT / (ms_pm / 1e3),
+                                        "batched_speedup": ms_pm / ms_dec,
+                                        "outputs_identical": all(np.array_equal(keep[k], h2[k]) for k in keep)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +180,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
+    ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -178,6 +270,11 @@ def main():
                       "n": n, "m": m, "seed": SEED, "rank": r, "eff_bitops_per_step": ops,
                       "panel_words": 8},
            "roofline": roof}
+    if not args.no_batched:
+        print("# batched workload", file=sys.stderr, flush=True)
+        del A, L, E
+        torch.cuda.empty_cache()
+        out["batched"] = batched_section(gf2, synth, args.batch_steps)
     if not args.no_cpu:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

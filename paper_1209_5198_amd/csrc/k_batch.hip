@@ -46,19 +46,6 @@ __device__ inline uint64_t rdl64b(uint64_t v, int l) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Register array element at a run-time index, written with masks so that the
-// compiler keeps the array in registers instead of indexing local memory.
-__device__ inline uint64_t pick(const uint64_t (&x)[RPT], int u) {
-  uint64_t v = 0ull;
-#pragma unroll
-  for (int j = 0; j < RPT; ++j) v |= x[j] & (0ull - (uint64_t)(u == j));
-  return v;
-}
-__device__ inline void put(uint64_t (&x)[RPT], int u, uint64_t v) {
-#pragma unroll
-  for (int j = 0; j < RPT; ++j) x[j] ^= (x[j] ^ v) & (0ull - (uint64_t)(u == j));
-}
-
 // Bit compression (gather the bits of x selected by mask into the low bits, in
 // order): the parallel-suffix method of H. S. Warren, "Hacker's Delight",
 // Section 7-4.  The six move masks depend on the mask only and are computed
@@ -102,8 +89,12 @@ struct BatchShared {
   int32_t pR[kBatchMaxPanels];        // rank before each panel
   int32_t pr[kBatchMaxPanels];        // pivots of each panel
   int32_t prow[64];                   // pivot t of the current panel -> bit position
-  int32_t wc[2][NW];                  // per-wave first candidate (double-buffered by bit)
-  uint64_t pw, sw;                    // pivot word, word of the exchanged position
+  int32_t wc[2][NW];                  // per-wave first candidate position (double-buffered by bit)
+  uint64_t ww[2][NW];                 // ... its word
+  int32_t wo[2][NW];                  // ... its row
+  uint64_t sw[2];                     // word at the next free position
+  int32_t so[2];                      // ... its row
+  int32_t lj0[kBatchMaxPanels];       // first panel whose pivots reach L word lw
   int32_t job;
 };
 
@@ -135,63 +126,111 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
     for (int q = 0; q < Mw && R < n; ++q) {
       nq = q + 1;
       const int nbits = (m - 64 * q) < 64 ? (m - 64 * q) : 64;
-      const int base = R + RPT * tid;
+      // Position R + NT*u + tid is slot u of thread tid; slots at or beyond
+      // nsl hold no row for any thread and are skipped with uniform branches.
+      const int nsl = (n - R + NT - 1) / NT;
       uint64_t x[RPT];
+      int org[RPT];
 #pragma unroll
-      for (int u = 0; u < RPT; ++u) x[u] = (base + u < n) ? W[(size_t)sh.map[base + u] * Mw + q] : 0ull;
+      for (int u = 0; u < RPT; ++u) {
+        x[u] = 0ull;
+        org[u] = 0;
+        const int pos = R + NT * u + tid;
+        if (u < nsl && pos < n) {
+          org[u] = sh.map[pos];
+          x[u] = W[(size_t)org[u] * Mw + q];
+        }
+      }
 
-      // ---- pivot search over the bits of word q
+      // ---- pivot search over the bits of word q (one barrier per bit)
       int t = 0;
       uint64_t K = 0ull;
       for (int k = 0; k < nbits; ++k) {
         const int pos = R + t;
         if (pos >= n) break;
-        int fu = RPT;
+        const int buf = k & 1;
+        uint32_t mk[RPT];  // all ones where the slot's bit k is 1
+        int ustar = -1;
+        int fl = 0;
+        uint64_t cw = 0ull;
+        int corg = 0;
 #pragma unroll
-        for (int u = RPT - 1; u >= 0; --u)
-          if (base + u >= pos && base + u < n && ((x[u] >> k) & 1ull)) fu = u;
-        const uint64_t bal = __ballot(fu < RPT);
-        int cand = INT_MAX;
-        if (bal) {
-          const int fl = (int)__builtin_ctzll(bal);
-          cand = R + RPT * (64 * wv + fl) + __builtin_amdgcn_readlane(fu, fl);
+        for (int u = 0; u < RPT; ++u) {
+          mk[u] = 0u;
+          if (u < nsl) {
+            const uint32_t half = (k < 32) ? (uint32_t)x[u] : (uint32_t)(x[u] >> 32);
+            mk[u] = 0u - ((half >> (k & 31)) & 1u);
+            const bool c = mk[u] && (u > 0 || tid >= t);
+            const uint64_t bal = __ballot(c);
+            if (ustar < 0 && bal) {
+              ustar = u;
+              fl = (int)__builtin_ctzll(bal);
+              cw = rdl64b(x[u], fl);
+              corg = __builtin_amdgcn_readlane(org[u], fl);
+            }
+          }
         }
-        if (lane == 0) sh.wc[k & 1][wv] = cand;
+        if (lane == 0) {
+          sh.wc[buf][wv] = ustar >= 0 ? R + NT * ustar + 64 * wv + fl : INT_MAX;
+          sh.ww[buf][wv] = cw;
+          sh.wo[buf][wv] = corg;
+        }
+        if (tid == t) {  // position pos is slot 0 of thread t
+          sh.sw[buf] = x[0];
+          sh.so[buf] = org[0];
+        }
         __syncthreads();
-        int p = sh.wc[k & 1][0];
+        int p = sh.wc[buf][0], wbest = 0;
 #pragma unroll
-        for (int w = 1; w < NW; ++w) p = min(p, sh.wc[k & 1][w]);
+        for (int w = 1; w < NW; ++w) {
+          const int c = sh.wc[buf][w];
+          if (c < p) {
+            p = c;
+            wbest = w;
+          }
+        }
         if (p == INT_MAX) continue;  // no row has bit k: not a pivot column
-        const int tp = (p - R) / RPT, up = (p - R) % RPT;
-        const int tq = (pos - R) / RPT, uq = (pos - R) % RPT;
-        if (tid == tp) sh.pw = pick(x, up);
-        if (tid == tq) sh.sw = pick(x, uq);
-        __syncthreads();
-        const uint64_t pw = sh.pw, sw = sh.sw;
-        if (tid == tp) put(x, up, sw);
-        if (tid == tq) put(x, uq, pw);
-        if (tid == 0) {
-          const int tmp = sh.map[pos];
-          sh.map[pos] = sh.map[p];
-          sh.map[p] = tmp;
-          sh.prow[t] = k;
-        }
+        const uint64_t pw = sh.ww[buf][wbest], sw = sh.sw[buf];
+        const int porg = sh.wo[buf][wbest], sorg = sh.so[buf];
+        // reduce every later row with bit k set in the bits above k (bit k stays
+        // as its multiplier), then exchange positions pos and p
         const uint64_t hi = (k == 63) ? 0ull : (~0ull << (k + 1));
+        const uint64_t ph = pw & hi;
 #pragma unroll
-        for (int u = 0; u < RPT; ++u)
-          if (base + u > pos && base + u < n && ((x[u] >> k) & 1ull)) x[u] ^= pw & hi;
+        for (int u = 0; u < RPT; ++u) {
+          if (u < nsl) {
+            const uint32_t mm = (u > 0 || tid > t) ? mk[u] : 0u;
+            x[u] ^= ph & (((uint64_t)mm << 32) | mm);
+          }
+        }
+        const int up = (p - R) / NT, tp = (p - R) % NT;
+        if (tid == tp) {
+#pragma unroll
+          for (int u = 0; u < RPT; ++u)
+            if (u == up) {
+              x[u] = sw;
+              org[u] = sorg;
+            }
+        }
+        if (tid == t) {
+          x[0] = pw;
+          org[0] = porg;
+        }
+        if (tid == 0) sh.prow[t] = k;
         K |= 1ull << k;
         ++t;
       }
       const int r = t;
-      __syncthreads();  // map exchanges by thread 0 are visible
 
 #pragma unroll
       for (int u = 0; u < RPT; ++u) {
-        const int pos = base + u;
-        if (pos < n) W[(size_t)sh.map[pos] * Mw + q] = x[u];
-        if (pos < R + r) sh.pivw[pos - R] = x[u];
+        const int pos = R + NT * u + tid;
+        if (u < nsl && pos < n) {
+          sh.map[pos] = org[u];
+          W[(size_t)org[u] * Mw + q] = x[u];
+        }
       }
+      if (tid < r) sh.pivw[tid] = x[0];
       if (tid == 0) {
         sh.pK[q] = K;
         sh.pR[q] = R;
@@ -235,8 +274,8 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < RPT; ++u) {
-        const int pos = base + u;
-        if (pos < n) {
+        const int pos = R + NT * u + tid;
+        if (u < nsl && pos < n) {
           uint64_t c;
           if (pos < R + r) {
             const int k = sh.prow[pos - R];
@@ -323,43 +362,54 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
       for (int t = tid; t < kmin; t += NT) a.pivcols[d.c + t] = t < rank ? pcol[t] : -1;
     if (a.perm)
       for (int i = tid; i < n; i += NT) a.perm[d.p + i] = sh.map[i];
+    // 8 lanes per output row, lane w8 writing words w8, w8 + 8, ...
+    const int w8 = tid & 7;
     if (a.E) {
       uint64_t *E = a.E + d.e;
-      for (int e = tid; e < kmin * Mw; e += NT) {
-        const int t = e / Mw, w = e - t * Mw;
-        uint64_t v = 0ull;
-        if (t < rank) {
-          const int pc = pcol[t], qt = pc >> 6;
-          if (w >= qt) {
-            v = W[(size_t)sh.map[t] * Mw + w];
+      for (int t = tid >> 3; t < kmin; t += NT / 8) {
+        const int pc = t < rank ? pcol[t] : 0, qt = pc >> 6;
+        const size_t src = (size_t)sh.map[t] * Mw;
+        for (int w = w8; w < Mw; w += 8) {
+          uint64_t v = 0ull;
+          if (t < rank && w >= qt) {
+            v = W[src + w];
             if (w == qt) v &= ~0ull << (pc & 63);
           }
+          E[(size_t)t * Mw + w] = v;
         }
-        E[e] = v;
       }
     }
     if (a.L) {
       uint64_t *L = a.L + d.l;
       const int Lw = (kmin + 63) >> 6;
-      for (int e = tid; e < n * Lw; e += NT) {
-        const int i = e / Lw, lw = e - i * Lw;
-        const int c_lo = 64 * lw;
-        uint64_t v = 0ull;
-        for (int j = 0; j < nq; ++j) {
-          const int Rj = sh.pR[j], rj = sh.pr[j];
-          if (rj == 0 || i < Rj || Rj >= c_lo + 64 || Rj + rj <= c_lo) continue;
-          const uint64_t xw = W[(size_t)sh.map[i] * Mw + j];
-          uint64_t bits;
-          if (i < Rj + rj) {
-            const int s = i - Rj, kk = pcol[i] & 63;
-            bits = compress(xw & ((1ull << kk) - 1ull), sh.pK[j], sh.pmv[j]) | (1ull << s);
-          } else {
-            bits = compress(xw, sh.pK[j], sh.pmv[j]);
+      // first panel whose pivot range reaches past column 64 * lw
+      if (tid < Lw) {
+        int j = 0;
+        while (j < nq && sh.pR[j] + sh.pr[j] <= 64 * tid) ++j;
+        sh.lj0[tid] = j;
+      }
+      __syncthreads();
+      for (int i = tid >> 3; i < n; i += NT / 8) {
+        const size_t src = (size_t)sh.map[i] * Mw;
+        for (int lw = w8; lw < Lw; lw += 8) {
+          const int c_lo = 64 * lw;
+          uint64_t v = 0ull;
+          for (int j = sh.lj0[lw]; j < nq && sh.pR[j] < c_lo + 64; ++j) {
+            const int Rj = sh.pR[j], rj = sh.pr[j];
+            if (rj == 0 || i < Rj) continue;
+            const uint64_t xw = W[src + j];
+            uint64_t bits;
+            if (i < Rj + rj) {
+              const int s = i - Rj, kk = pcol[i] & 63;
+              bits = compress(xw & ((1ull << kk) - 1ull), sh.pK[j], sh.pmv[j]) | (1ull << s);
+            } else {
+              bits = compress(xw, sh.pK[j], sh.pmv[j]);
+            }
+            const int shf = Rj - c_lo;
+            v |= shf >= 0 ? (bits << shf) : (bits >> (-shf));
           }
-          const int shf = Rj - c_lo;
-          v |= shf >= 0 ? (bits << shf) : (bits >> (-shf));
+          L[(size_t)i * Lw + lw] = v;
         }
-        L[e] = v;
       }
     }
   }
