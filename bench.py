@@ -14,8 +14,8 @@ inner bits); the bound is the on-chip table-read rate: LDS reads of 256 B/clk
 per CU (gfx950) x 256 CUs x 2.4 GHz = 157.3 TB/s.
 
 cpu_baseline: the CPU oracle (plain elimination, OpenMP) timed on a bounded
-sample of the same workload (the largest dense matrix of the same distribution
-that fits the time budget, the 65536^2 matrix itself on a 16-thread host),
+sample of the same workload (dense matrices of the same distribution, the
+largest size that fits the time budget, repeated to about ten seconds),
 expressed in the same unit.
 
 batched: the 4096-matrix workload (sides uniform in [64, 2048], density 1/2 or
@@ -24,6 +24,13 @@ gf2_decompose_batched and solved by gf2_solve_batched, timed with HIP events
 over `--batch-steps` passes with the inputs resident; reported as matrices/s,
 solves/s (decomposition + solve per system) and effective bit-ops/s, beside one
 gf2_decompose call per matrix on the same GPU (same outputs, checked equal).
+
+serving: a stream of rank / solve / decompose requests (square sides
+log-uniform in [128, 16384] or 1:4 rectangles, Bernoulli(1/2), data in pinned
+host memory until admitted) through the continuous-batching loop of
+paper_1209_5198_amd/serve.py under a 64 GB admission cap: first all requests at
+once (saturated throughput), then Poisson arrivals at 50/80/95% of that rate,
+each reported with p50/p99 latency, requests/s and solves/s.
 
 HBM traffic of that kernel is read from rocprofv3 counters (FETCH_SIZE and
 WRITE_SIZE, separate runs); --copy-calibration runs only a plain 1 GiB device
@@ -65,29 +72,37 @@ def eff_bitops(n: int, m: int, pivcols: np.ndarray) -> float:
     return float(2.0 * np.sum((n - 1 - t) * (m - 1 - p)))
 
 
-def cpu_baseline(budget_s: float = 24.0):
-    """Time the oracle on a dense sample: sizes double from 2048 while the next
-    one (8x the work) is predicted to fit budget_s, up to the full 65536^2."""
+def cpu_baseline(budget_s: float = 24.0, min_s: float = 10.0):
+    """Time the oracle on a bounded dense sample: sizes double from 2048 while the
+    next one is predicted (16x the time) to fit budget_s, then the largest size is
+    repeated on fresh matrices until min_s seconds of oracle time are reached."""
     import oracle
     from paper_1209_5198_amd import synth
 
     oracle.build()
     n = 2048
-    last = None
+    stream = 7
     while True:
-        A = synth.dense(SEED, 7, n, n)
+        A = synth.dense(SEED, stream, n, n)
         t0 = time.perf_counter()
         res = oracle.ple(A, n, n, want_le=False)
         dt = time.perf_counter() - t0
-        last = (n, dt, res)
-        if dt * 8 > budget_s or n >= 65536:
+        if dt * 16 > budget_s or n >= 65536:
             break
         n *= 2
-    n, dt, res = last
-    ops = eff_bitops(n, n, res["pivcols"])
-    return {"value": ops / dt, "unit": "bit-ops/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"oracle PLE (plain elimination) of one {n}x{n} Bernoulli(1/2) matrix, "
-                      f"{dt:.2f} s, rank {res['rank']}"}
+    total_t, total_ops, runs, ranks = dt, eff_bitops(n, n, res["pivcols"]), 1, [res["rank"]]
+    while total_t < min_s:
+        stream += 1
+        A = synth.dense(SEED, stream, n, n)
+        t0 = time.perf_counter()
+        res = oracle.ple(A, n, n, want_le=False)
+        total_t += time.perf_counter() - t0
+        total_ops += eff_bitops(n, n, res["pivcols"])
+        runs += 1
+        ranks.append(res["rank"])
+    return {"value": total_ops / total_t, "unit": "bit-ops/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"oracle PLE (plain elimination) of {runs} Bernoulli(1/2) {n}x{n} matrices "
+                      f"(seed {SEED}, streams {stream - runs + 1}..{stream}), {total_t:.2f} s, ranks {ranks}"}
 
 
 BATCH_SEED, BATCH_COUNT = 4096, 4096
@@ -173,6 +188,36 @@ def batched_section(gf2, synth, steps: int, per_matrix: bool = True):
     return out
 
 
+SERVE_SEED, SERVE_COUNT = 5, 1500
+
+
+def serving_section(synth, count: int):
+    from paper_1209_5198_amd import serve
+
+    t0 = time.perf_counter()
+    specs = synth.serving_specs(SERVE_SEED, count)
+    data = serve.make_request_data(SERVE_SEED, specs)
+    gen_s = time.perf_counter() - t0
+
+    def session(arrivals):
+        srv = serve.Server(cap_bytes=64 << 30, big_streams=2)
+        return srv.run(serve.make_requests(specs, data, arrivals))
+
+    session(np.zeros(count))  # warm-up: library workspaces, kernels
+    sat = session(np.zeros(count))
+    out = {"workload": f"{count} requests, kind uniform over rank/solve/decompose, square sides log-uniform "
+                       "in [128, 16384] or 1:4 with the long side log-uniform in [512, 16384]; "
+                       f"seed {SERVE_SEED}; 64 GB admission cap; sides <= 2048 batched",
+           "data_gen_s": round(gen_s, 1), "saturated": sat, "poisson": {}}
+    rate = sat["requests_per_s"]
+    for frac in (0.5, 0.8, 0.95):
+        arr = synth.poisson_arrivals(SERVE_SEED, count, frac * rate)
+        st = session(arr)
+        st["offered_rate"] = frac * rate
+        out["poisson"][f"{int(frac * 100)}%"] = st
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +227,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving sessions")
+    ap.add_argument("--serve-count", type=int, default=SERVE_COUNT)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -275,6 +322,10 @@ def main():
         del A, L, E
         torch.cuda.empty_cache()
         out["batched"] = batched_section(gf2, synth, args.batch_steps)
+    if not args.no_serving:
+        print("# serving sessions", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        out["serving"] = serving_section(synth, args.serve_count)
     if not args.no_cpu:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

@@ -28,6 +28,9 @@ Workloads (shapes, value distributions and structure of the paper's tests):
                    uniform in [lo, hi], density 1/2 or 1/10, half of them with
                    a planted rank), ``batch_matrix`` / ``batch_rhs`` their
                    entries and right-hand sides.
+  * ``serving_specs`` a request stream: rank / solve / decompose requests,
+                   square sides log-uniform in [lo, hi] or 1:4 rectangles with
+                   the long side log-uniform in [4 lo, hi], Poisson arrivals.
 """
 from __future__ import annotations
 
@@ -169,6 +172,63 @@ def batch_rhs(seed: int, spec) -> np.ndarray:
     is bit j % 64 of word j // 64."""
     n = spec["n"]
     out = words(seed, BATCH_RHS_STREAM + spec["i"], 0, wpr(n))
+    if out.size:
+        out[-1] &= pad_mask(n)
+    return out
+
+
+# ---------------------------------------------------------------- request streams
+SERVE_SPEC_STREAM = 0x7365  # draws of the request kinds and shapes
+SERVE_ARRIVAL_STREAM = 0x7366  # draws of the inter-arrival gaps
+SERVE_MAT_STREAM = 10_000_000  # + id: entries of request id
+SERVE_RHS_STREAM = 20_000_000  # + id: right-hand side of request id
+SERVE_KINDS = ("rank", "solve", "decompose")
+
+
+def _unit(d):
+    """64-bit draws -> floats in (0, 1)."""
+    return (d >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0) + 0.5 / 9007199254740992.0
+
+
+def serving_specs(seed: int, count: int, lo: int = 128, hi: int = 16384):
+    """Request i uses draws 4i..4i+3 of stream SERVE_SPEC_STREAM: kind uniform over
+    SERVE_KINDS; square (n = m = s, s log-uniform in [lo, hi]) or, with probability
+    1/2, a 1:4 rectangle whose long side is log-uniform in [4 lo, hi], tall or wide
+    with probability 1/2 each."""
+    d = words(seed, SERVE_SPEC_STREAM, 0, 4 * count).reshape(count, 4) if count else np.zeros((0, 4), np.uint64)
+    u = _unit(d[:, 1]) if count else np.zeros(0)
+    out = []
+    for i in range(count):
+        kind = SERVE_KINDS[int(d[i, 0] % np.uint64(3))]
+        if int(d[i, 2]) & 1:
+            s_ = int(round(lo * (hi / lo) ** u[i]))
+            n = m = s_
+        else:
+            long_ = int(round(4 * lo * (hi / (4 * lo)) ** u[i]))
+            short = max(1, long_ // 4)
+            n, m = (long_, short) if (int(d[i, 2]) >> 1) & 1 else (short, long_)
+        out.append(dict(id=i, kind=kind, n=n, m=m))
+    return out
+
+
+def poisson_arrivals(seed: int, count: int, rate: float) -> np.ndarray:
+    """Arrival times (s) of a Poisson stream of the given rate (1/s): cumulative sums
+    of exponential gaps -ln(U)/rate from stream SERVE_ARRIVAL_STREAM."""
+    if count == 0:
+        return np.zeros(0)
+    gaps = -np.log(_unit(words(seed, SERVE_ARRIVAL_STREAM, 0, count))) / float(rate)
+    return np.cumsum(gaps)
+
+
+def serving_matrix(seed: int, spec) -> np.ndarray:
+    """Bernoulli(1/2) entries of request ``spec``."""
+    return dense(seed, SERVE_MAT_STREAM + spec["id"], spec["n"], spec["m"])
+
+
+def serving_rhs(seed: int, spec) -> np.ndarray:
+    """Right-hand side of request ``spec`` as a bit vector (wpr(n) words)."""
+    n = spec["n"]
+    out = words(seed, SERVE_RHS_STREAM + spec["id"], 0, wpr(n))
     if out.size:
         out[-1] &= pad_mask(n)
     return out
