@@ -32,6 +32,10 @@ paper_1209_5198_amd/serve.py under a 64 GB admission cap: first all requests at
 once (saturated throughput), then Poisson arrivals at 50/80/95% of that rate,
 each reported with p50/p99 latency, requests/s and solves/s.
 
+configs: the other single-matrix configurations on the same GPU (one 2048^2
+decomposition, the 16384^3 product, the 16384^2 decomposition and the planted
+rank-20000 32768 x 65536 decomposition), HIP-event timed, inputs resident.
+
 HBM traffic of that kernel is read from rocprofv3 counters (FETCH_SIZE and
 WRITE_SIZE, separate runs); --copy-calibration runs only a plain 1 GiB device
 copy, whose counter readings give the scale factor between counter units and
@@ -47,6 +51,12 @@ import json
 import os
 import sys
 import time
+
+# Hardware queues per process for the HIP runtime (read when it starts): the
+# serving sessions run up to 4 large requests concurrently, each with its own
+# pipeline stream pair, plus the batch and copy streams; with the default 4
+# queues, waits of unrelated streams that share a queue serialise them.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 import numpy as np
 
@@ -188,6 +198,53 @@ def batched_section(gf2, synth, steps: int, per_matrix: bool = True):
     return out
 
 
+def other_configs(gf2, synth, reps: int = 5):
+    """The remaining single-matrix configurations, device-resident, HIP-event timed."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {}
+    for n, seed in ((2048, 2048), (16384, 16384)):
+        A = gf2.Mat.from_rowmajor(synth.dense(seed, 1, n, n), n, n)
+        res = gf2.decompose(A, stream=stream)
+        ms = timed(lambda: gf2.decompose(A, stream=stream, L=res["L"], E=res["E"]))
+        ops = eff_bitops(n, n, res["pivcols"].cpu().numpy())
+        out[f"decompose_{n}"] = {"ms": ms, "eff_bitops_per_s": ops / (ms / 1e3), "rank": int(res["rank"].item())}
+        del A, res
+    n = 16384
+    A = gf2.Mat.from_rowmajor(synth.dense(16384, 2, n, n), n, n)
+    B = gf2.Mat.from_rowmajor(synth.dense(16384, 3, n, n), n, n)
+    C = gf2.Mat.zeros(n, n)
+    ms = timed(lambda: gf2.gf2_matmul(C, A, B, False, stream))
+    out["matmul_16384"] = {"ms": ms, "bitops_per_s": 2.0 * n ** 3 / (ms / 1e3)}
+    del A, B, C
+    nr, r, m = 32768, 20000, 65536
+    X, Y = synth.planted(20000, 9, nr, m, r)
+    A = gf2.matmul(gf2.Mat.from_rowmajor(X, nr, r), gf2.Mat.from_rowmajor(Y, r, m), stream=stream)
+    del X, Y
+    res = gf2.decompose(A, stream=stream)
+    ms = timed(lambda: gf2.decompose(A, stream=stream, L=res["L"], E=res["E"]))
+    ops = eff_bitops(nr, m, res["pivcols"].cpu().numpy())
+    out["decompose_planted_32768x65536_r20000"] = {"ms": ms, "eff_bitops_per_s": ops / (ms / 1e3),
+                                                   "rank": int(res["rank"].item())}
+    del A, res
+    torch.cuda.empty_cache()
+    return out
+
+
 SERVE_SEED, SERVE_COUNT = 5, 1500
 
 
@@ -200,7 +257,7 @@ def serving_section(synth, count: int):
     gen_s = time.perf_counter() - t0
 
     def session(arrivals):
-        srv = serve.Server(cap_bytes=64 << 30, big_streams=2)
+        srv = serve.Server(cap_bytes=64 << 30, big_streams=4)
         return srv.run(serve.make_requests(specs, data, arrivals))
 
     session(np.zeros(count))  # warm-up: library workspaces, kernels
@@ -228,6 +285,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sessions")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other single-matrix configurations")
     ap.add_argument("--serve-count", type=int, default=SERVE_COUNT)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
@@ -317,10 +375,13 @@ def main():
                       "n": n, "m": m, "seed": SEED, "rank": r, "eff_bitops_per_step": ops,
                       "panel_words": 8},
            "roofline": roof}
+    del A, L, E
+    torch.cuda.empty_cache()
+    if not args.no_configs:
+        print("# other configurations", file=sys.stderr, flush=True)
+        out["configs"] = other_configs(gf2, synth)
     if not args.no_batched:
         print("# batched workload", file=sys.stderr, flush=True)
-        del A, L, E
-        torch.cuda.empty_cache()
         out["batched"] = batched_section(gf2, synth, args.batch_steps)
     if not args.no_serving:
         print("# serving sessions", file=sys.stderr, flush=True)

@@ -45,17 +45,18 @@ int g_chain_cus = 0;
 // updated concurrently with the bulk update instead of before it
 double g_overlap_lookups = 1.2e9;
 
-// Per device: the two internal streams of the look-ahead pipeline.  The pivot
-// chain of panel J+1 (panel and row kernels) runs on `chain`, restricted to a
-// few CUs, while the bulk of panel J's trailing update runs on `gemm`, which
-// owns the other CUs; events order the two.
+// Per (device, caller stream): the two internal streams of the look-ahead
+// pipeline.  The pivot chain of panel J+1 runs on one while the bulk of panel
+// J's trailing update runs on the other; events order the two.  Calls made on
+// different caller streams get different pairs, so their factorizations can
+// run concurrently (each pivot chain occupies a single CU).
 struct Pipe {
   hipStream_t gemm = nullptr, chain = nullptr;
   std::vector<hipEvent_t> ring;
   size_t next = 0;
   int chain_cus = -1;
 };
-std::map<int, Pipe> g_pipes;
+std::map<std::pair<int, hipStream_t>, Pipe> g_pipes;
 
 struct Workspace {
   void *ptr = nullptr;
@@ -227,11 +228,11 @@ int run_gemm(GemmArgs &a, int64_t nrows_max, int variant, int64_t active_rows, h
   return profile_end(s, e0);
 }
 
-int get_pipe(Pipe **out) {
+int get_pipe(hipStream_t user, Pipe **out) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_mu);
-  Pipe &p = g_pipes[dev];
+  Pipe &p = g_pipes[std::make_pair(dev, user)];
   if (p.gemm && p.chain_cus != g_chain_cus) {  // re-create on a changed split
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipStreamDestroy(p.gemm));
@@ -305,7 +306,7 @@ int chain(DecWork &w, int q0, int s_eff, int flag_q0, hipStream_t s) {
 // after all the work.
 int factor(const gf2_mat *A, DecWork &w, hipStream_t user) {
   Pipe *P = nullptr;
-  int rc = get_pipe(&P);
+  int rc = get_pipe(user, &P);
   if (rc) return rc;
   hipStream_t G = P->gemm, Cs = P->chain;
   if ((rc = link(P, user, G))) return rc;

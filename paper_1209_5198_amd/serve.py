@@ -19,6 +19,12 @@ side) in host memory.  The loop:
 * detects completion with HIP events and frees the request's memory; latency
   is completion time minus arrival time.
 
+Concurrency of the side streams needs enough hardware queues: each large call
+runs on its own pair of pipeline streams (libgf2 keys them by caller stream),
+and with HIP's default of 4 queues per process, unrelated streams that share
+a queue wait for each other.  Processes that serve should start the HIP
+runtime with GPU_MAX_HW_QUEUES raised (16 measured best with 4 side streams).
+
 All arithmetic runs in libgf2's kernels; this module only schedules.
 """
 from __future__ import annotations
@@ -132,7 +138,7 @@ def _layout(r: Request):
 class Server:
     """One GPU, one arena of `cap_bytes`, one batch stream and `big_streams` side streams."""
 
-    def __init__(self, cap_bytes: int = 64 << 30, big_streams: int = 2, verify: bool = False, device="cuda"):
+    def __init__(self, cap_bytes: int = 64 << 30, big_streams: int = 4, verify: bool = False, device="cuda"):
         import torch
 
         self.torch = torch
