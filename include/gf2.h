@@ -154,6 +154,28 @@ int gf2_solve_batched(const gf2_batch_item *items, int64_t count, const uint64_t
                       void *stream);
 
 /*
+ * Autotuner (process-wide, per device of the calling thread).  Times the
+ * product-kernel tile variants on synthetic operands for every size class --
+ * active rows in [256 * 2^r, 512 * 2^r) (r = 0..8, up to max_size) crossed with
+ * 1, 2-3, 4-15 or 16+ column blocks of 1024 bits, at the decomposition's
+ * 512-bit inner dimension -- and one Strassen-Winograd level against the plain
+ * product at 32768^3 and 65536^3 (up to max_size); afterwards the trailing
+ * update and gf2_matmul use the fastest tile of each class and the measured
+ * cutoff (the smallest size where one level paid, else twice the largest size
+ * compared).  No result of any call depends on it.  Allocates its operands
+ * with hipMalloc (up to about 3.5 GB at max_size >= 65536) and synchronises
+ * `stream`.  GF2_EINVAL for max_size < 256.
+ */
+int gf2_autotune(int64_t max_size, void *stream);
+
+/*
+ * The tuned tiles, row-major over (row class r, block class c):
+ * variants[4 * r + c] for r < 9, c < 4 (-1 everywhere before gf2_autotune),
+ * and the Strassen cutoff in use.  Either pointer (host memory) may be NULL.
+ */
+int gf2_autotune_table(int32_t *variants, int64_t *strassen_cutoff);
+
+/*
  * Tuning knobs, process-wide (no knob changes any result):
  *   "panel_words"        : s, sub-panels of 64 columns per trailing-update panel (1..8)
  *   "strassen_cutoff"    : gf2_matmul recurses with Strassen-Winograd (one level
@@ -163,6 +185,8 @@ int gf2_solve_batched(const gf2_batch_item *items, int64_t count, const uint64_t
  *   "panel_gemm_variant" : product-kernel variant for the trailing update (-1 = automatic)
  *   "chain_cus"          : CUs reserved for the pivot chain through CU-masked
  *                          streams (0 = two unmasked streams, the default)
+ *   "autotuned"          : 1 = use the table measured by gf2_autotune (its
+ *                          default once measured), 0 = the built-in tile rule
  *   "overlap_lookups"    : size of a panel's bulk update (table lookups) from
  *                          which the next panel's columns are updated concurrently
  *                          with it rather than before it

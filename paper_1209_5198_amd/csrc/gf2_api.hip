@@ -44,6 +44,19 @@ int g_chain_cus = 0;
 // bulk-update size (table lookups) above which the next panel's columns are
 // updated concurrently with the bulk update instead of before it
 double g_overlap_lookups = 1.2e9;
+// Product-kernel tile per size class, written by gf2_autotune: rows class r
+// (active rows in [256 << r, 512 << r), clamped to 0..8) x column-block class c
+// (1, 2-3, 4-15, 16+ blocks of 16 words); -1 = the built-in rule.
+constexpr int kTuneRows = 9, kTuneBlocks = 4;
+int g_tuned[kTuneRows][kTuneBlocks];
+bool g_tuned_valid = false;  // a table was measured
+bool g_tuned_on = false;     // ... and is used
+int tune_row_class(int64_t rows) {
+  int r = 0;
+  while (r + 1 < kTuneRows && rows >= ((int64_t)512 << r)) ++r;
+  return r;
+}
+int tune_block_class(int blocks) { return blocks <= 1 ? 0 : (blocks <= 3 ? 1 : (blocks <= 15 ? 2 : 3)); }
 
 // Per (device, caller stream): the two internal streams of the look-ahead
 // pipeline.  The pivot chain of panel J+1 runs on one while the bulk of panel
@@ -219,6 +232,10 @@ int device_cus() {
 
 // active_rows: rows expected to do work (used only to pick a tile size)
 int run_gemm(GemmArgs &a, int64_t nrows_max, int variant, int64_t active_rows, hipStream_t s) {
+  if (variant < 0 && g_tuned_on && !(a.qc0 % 8 == 0 && a.qc1 - a.qc0 <= 8)) {
+    const int blocks = ((a.qc1 - 1) >> 4) - (a.qc0 >> 4) + 1;
+    variant = g_tuned[tune_row_class(active_rows)][tune_block_class(blocks)];
+  }
   if (variant < 0) variant = gemm_auto_variant(active_rows, a.qc0, a.qc1, device_cus());
   hipEvent_t e0 = nullptr;
   int rc = profile_begin(s, &e0);
@@ -406,6 +423,11 @@ int gf2_set_param(const char *name, int64_t value) {
   if (!strcmp(name, "panel_gemm_variant")) {
     if (value < -1 || value >= kGemmVariants) return fail(GF2_EINVAL, "panel_gemm_variant out of range");
     g_panel_gemm_variant = (int)value;
+    return GF2_OK;
+  }
+  if (!strcmp(name, "autotuned")) {
+    if (value < 0 || value > 1) return fail(GF2_EINVAL, "autotuned must be 0 or 1");
+    g_tuned_on = value == 1 && g_tuned_valid;
     return GF2_OK;
   }
   if (!strcmp(name, "overlap_lookups")) {
@@ -852,6 +874,115 @@ int gf2_solve_batched(const gf2_batch_item *items, int64_t count, const uint64_t
   a.X = X;
   a.consistent = consistent;
   HIPCHK(launch_batch_solve(a, s));
+  return GF2_OK;
+}
+
+int gf2_autotune(int64_t max_size, void *stream) {
+  if (max_size < 256) return fail(GF2_EINVAL, "gf2_autotune: max_size must be >= 256");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = GF2_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto timed = [&](auto &&launch, float *ms) -> int {
+    int r = launch();  // warm-up
+    if (r) return r;
+    HIPCHK(hipEventRecord(e0, s));
+    for (int i = 0; i < 3; ++i)
+      if ((r = launch())) return r;
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    HIPCHK(hipEventElapsedTime(ms, e0, e1));
+    return GF2_OK;
+  };
+
+  // ---- product-kernel tile per size class, at the decomposition's inner
+  // dimension (one 512-column panel) on synthetic operands
+  const int cand[4] = {7, 8, 10, 9};
+  const int bsel[kTuneBlocks] = {1, 3, 8, 32};
+  int nr = 0;
+  while (nr < kTuneRows && ((int64_t)256 << nr) <= max_size) ++nr;
+  const int64_t rows_max = ((int64_t)256 << (nr - 1)) * 3 / 2;
+  const int64_t ldA = ceil_div(rows_max, 256) * 256, ldB = 512;
+  const size_t wA = (size_t)ldA * TW, wB = (size_t)32 * ldB * TW, wC = (size_t)32 * ldA * TW;
+  uint64_t *buf = nullptr;
+  HIPCHK(hipMalloc(&buf, (wA + wB + wC) * 8));
+  uint64_t *bA = buf, *bB = buf + wA, *bC = buf + wA + wB;
+  int table[kTuneRows][kTuneBlocks];
+  do {
+    if (launch_fill_bits(buf, wA + wB + wC, 0x5eed, s) != hipSuccess) { rc = fail(GF2_EHIP, "fill"); break; }
+    for (int r = 0; r < nr && !rc; ++r) {
+      const int64_t rows = ((int64_t)256 << r) * 3 / 2;
+      for (int c = 0; c < kTuneBlocks && !rc; ++c) {
+        float best_ms = 1e30f;
+        int best = -1;
+        for (int v : cand) {
+          GemmArgs a;
+          memset(&a, 0, sizeof(a));
+          a.A = bA; a.ldA = ldA; a.a_word0 = 0;
+          a.B = bB; a.ldB = ldB; a.b_rows = 512;
+          a.C = bC; a.ldC = ldA;
+          a.row_tile0 = 0; a.row_end = rows;
+          a.kwords = 8;
+          a.qc0 = 0; a.qc1 = bsel[c] * TW;
+          a.accumulate = 1;
+          float ms = 0.f;
+          rc = timed([&]() -> int { HIPCHK(launch_gemm(a, rows, v, s)); return GF2_OK; }, &ms);
+          if (rc) break;
+          if (ms < best_ms) { best_ms = ms; best = v; }
+        }
+        table[r][c] = best;
+      }
+    }
+  } while (0);
+  (void)hipFree(buf);
+  if (rc) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return rc; }
+  for (int r = 0; r < kTuneRows; ++r)
+    for (int c = 0; c < kTuneBlocks; ++c) g_tuned[r][c] = table[r < nr ? r : nr - 1][c];
+  g_tuned_valid = g_tuned_on = true;
+
+  // ---- Strassen-Winograd cutoff: one level against the plain product on
+  // square operands; the smallest size where the level pays becomes the cutoff
+  int64_t cutoff = 0, largest = 0;
+  for (int64_t n = 32768; n <= 65536 && n <= max_size && !rc; n *= 2) {
+    largest = n;
+    const int64_t nw = n / 64;
+    const size_t wm = (size_t)n * nw, st_bytes = strassen_bytes(n, nw, nw, 1);
+    char *sb = nullptr;
+    if (hipMalloc(&sb, 3 * wm * 8 + st_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      break;  // not enough memory to compare at this size: keep the previous answer
+    }
+    uint64_t *mA = (uint64_t *)sb, *mB = mA + wm, *mC = mB + wm;
+    if (launch_fill_bits(mA, 2 * wm, 0x5eed + n, s) != hipSuccess) rc = fail(GF2_EHIP, "fill");
+    const BView Av{mA, n, n, nw}, Bv{mB, n, n, nw}, Cv{mC, n, n, nw};
+    float plain = 0.f, one = 0.f;
+    if (!rc) rc = timed([&]() -> int { return gemm_view(Cv, Av, Bv, 0, s); }, &plain);
+    if (!rc) {
+      rc = timed([&]() -> int {
+        Stack st{sb + 3 * wm * 8, 0, st_bytes};
+        return strassen(Cv, Av, Bv, 1, 0, st, s);
+      }, &one);
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(sb);
+    if (!rc && one < plain) {
+      cutoff = n;
+      break;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if (largest > 0) g_strassen_cutoff = cutoff > 0 ? cutoff : 2 * largest;
+  return GF2_OK;
+}
+
+int gf2_autotune_table(int32_t *variants, int64_t *strassen_cutoff) {
+  if (variants)
+    for (int r = 0; r < kTuneRows; ++r)
+      for (int c = 0; c < kTuneBlocks; ++c) variants[r * kTuneBlocks + c] = g_tuned_valid ? g_tuned[r][c] : -1;
+  if (strassen_cutoff) *strassen_cutoff = g_strassen_cutoff;
   return GF2_OK;
 }
 

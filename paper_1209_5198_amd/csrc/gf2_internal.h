@@ -113,6 +113,7 @@ hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, hipStr
 hipError_t launch_post(const DecWork &w, int q0, int s_eff, hipStream_t s);
 hipError_t launch_xor(uint64_t *dst, const uint64_t *a, const uint64_t *b, size_t nwords,
                       hipStream_t s);
+hipError_t launch_fill_bits(uint64_t *dst, size_t nwords, uint64_t seed, hipStream_t s);  // timing operands
 
 // A rows x (words) region of a working-layout matrix: word (i, q) at
 // p[((q / 16) * ld + i) * 16 + q % 16].  A quadrant of a view whose words are

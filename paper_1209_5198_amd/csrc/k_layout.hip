@@ -206,6 +206,25 @@ __global__ void k_xor(uint64_t *dst, const uint64_t *a, const uint64_t *b, size_
     dst[e] = a[e] ^ b[e];
 }
 
+// Words of a timing operand: the SplitMix64 output function of (seed, index),
+// a bit pattern for kernels whose run time does not depend on the values.
+__global__ void k_fill_bits(uint64_t *dst, size_t nwords, uint64_t seed) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += (size_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    dst[i] = z ^ (z >> 31);
+  }
+}
+
+hipError_t launch_fill_bits(uint64_t *dst, size_t nwords, uint64_t seed, hipStream_t s) {
+  size_t blocks = (nwords + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_fill_bits, dim3((unsigned)blocks), dim3(256), 0, s, dst, nwords, seed);
+  return hipGetLastError();
+}
+
 hipError_t launch_xor(uint64_t *dst, const uint64_t *a, const uint64_t *b, size_t nwords,
                       hipStream_t s) {
   size_t blocks = (nwords + 255) / 256;

@@ -27,7 +27,7 @@ GF2_ENOMEM = -2
 GF2_EHIP = -3
 
 EXPORTED = ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_decompose_batched",
-            "gf2_solve_batched", "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_release",
+            "gf2_solve_batched", "gf2_autotune", "gf2_autotune_table", "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_release",
             "gf2_last_error", "gf2_version")
 BATCH_MAX_DIM = 2048
 
@@ -68,6 +68,8 @@ def load():
         PB = ctypes.POINTER(BatchItem)
         lib.gf2_decompose_batched.argtypes = [PB, i64, vp, vp, vp, vp, vp, vp, vp]
         lib.gf2_solve_batched.argtypes = [PB, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.gf2_autotune.argtypes = [i64, vp]
+        lib.gf2_autotune_table.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(i64)]
         lib.gf2_set_param.argtypes = [ctypes.c_char_p, i64]
         lib.gf2_profile.argtypes = [ctypes.c_int]
         lib.gf2_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
@@ -76,8 +78,8 @@ def load():
         lib.gf2_last_error.restype = ctypes.c_char_p
         lib.gf2_version.restype = ctypes.c_char_p
         for name in ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_decompose_batched",
-                     "gf2_solve_batched", "gf2_set_param", "gf2_profile", "gf2_profile_read",
-                     "gf2_release"):
+                     "gf2_solve_batched", "gf2_autotune", "gf2_autotune_table", "gf2_set_param",
+                     "gf2_profile", "gf2_profile_read", "gf2_release"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -195,6 +197,18 @@ def gf2_decompose_batched(items, A, L, E, perm, pivcols, rank, stream=None) -> N
 def gf2_solve_batched(items, L, E, perm, pivcols, rank, B, X, consistent, stream=None) -> None:
     _check(load().gf2_solve_batched(items, len(items), _ptr(L), _ptr(E), _ptr(perm), _ptr(pivcols),
                                     _ptr(rank), _ptr(B), _ptr(X), _ptr(consistent), _stream(stream)))
+
+
+def gf2_autotune(max_size: int = 65536, stream=None) -> None:
+    _check(load().gf2_autotune(int(max_size), _stream(stream)))
+
+
+def gf2_autotune_table():
+    """(variants as a 9 x 4 list (row class x block class), strassen cutoff)."""
+    v = (ctypes.c_int32 * 36)()
+    c = ctypes.c_int64()
+    _check(load().gf2_autotune_table(v, ctypes.byref(c)))
+    return [list(v[4 * r:4 * r + 4]) for r in range(9)], c.value
 
 
 def gf2_set_param(name: str, value: int) -> None:

@@ -137,3 +137,14 @@ def test_batch_offsets_pack_the_pools():
     assert b.off == want and b.size == off
     assert [(it.rows, it.cols, it.a, it.l, it.e) for it in b.items] == [
         (n, m, w["a"], w["l"], w["e"]) for (n, m), w in zip(shapes, want)]
+
+
+def test_autotune_entry_points_without_gpu():
+    from paper_1209_5198_amd import gf2
+
+    lib = gf2.load()
+    assert lib.gf2_autotune(100, None) == gf2.GF2_EINVAL
+    table, cut = gf2.gf2_autotune_table()
+    assert table == [[-1] * 4 for _ in range(9)] and cut == 65536
+    assert lib.gf2_set_param(b"autotuned", 2) == gf2.GF2_EINVAL
+    assert lib.gf2_set_param(b"autotuned", 1) == gf2.GF2_OK  # no table yet: stays on the rule
