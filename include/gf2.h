@@ -188,8 +188,8 @@ int gf2_autotune_table(int32_t *variants, int64_t *strassen_cutoff);
  *   "autotuned"          : 1 = use the table measured by gf2_autotune (its
  *                          default once measured), 0 = the built-in tile rule
  *   "overlap_lookups"    : size of a panel's bulk update (table lookups) from
- *                          which the next panel's columns are updated concurrently
- *                          with it rather than before it
+ *                          which it starts concurrently with the next panel's
+ *                          columns rather than after them (default 0: always)
  * Returns 0, or GF2_EINVAL for an unknown name or out-of-range value.
  */
 int gf2_set_param(const char *name, int64_t value);

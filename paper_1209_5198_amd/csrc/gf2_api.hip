@@ -41,9 +41,11 @@ int g_panel_gemm_variant = -1;  // product-kernel variant for the trailing updat
 // plain streams (the default: measured faster, since a masked product launch
 // leaves the CUs of the reserved range idle and unbalances its XCD)
 int g_chain_cus = 0;
-// bulk-update size (table lookups) above which the next panel's columns are
-// updated concurrently with the bulk update instead of before it
-double g_overlap_lookups = 1.2e9;
+// bulk-update size (table lookups) from which the bulk update starts right
+// after the row exchanges, concurrently with the next panel's columns and its
+// pivot chain (0 = always; measured best on MI355X at 65536^2: 62.0 ms against
+// 63.8 ms with a 1.2e9 threshold)
+double g_overlap_lookups = 0.0;
 // Product-kernel tile per size class, written by gf2_autotune: rows class r
 // (active rows in [256 << r, 512 << r), clamped to 0..8) x column-block class c
 // (1, 2-3, 4-15, 16+ blocks of 16 words); -1 = the built-in rule.
