@@ -16,6 +16,8 @@ Functions (each cites the passage it follows; see ``gf2_oracle.c``):
   buildZ, Section 4.4), transposition swaps, no column swaps.
 * :func:`matmul` -- C = A*B from the definition of the product.
 * :func:`solve`  -- A*x = b through the decomposition, free variables zero.
+* :func:`nullspace` -- null space basis read off the reduced row echelon form
+                    (back-substitution of the echelon rows), Section 1's use.
 * :func:`pack_bits` / :func:`unpack_bits` -- the b-bit packing of Section 3
   (a_ij is bit r of word q, j = q*b + r), for any b <= 64.
 """
@@ -57,6 +59,8 @@ def _load():
         lib.or_matmul.restype = None
         lib.or_solve.argtypes = [i64, i64, i64, p64, p64, p64, p64]
         lib.or_solve.restype = i64
+        lib.or_nullspace.argtypes = [i64, i64, p64, p64, p64]
+        lib.or_nullspace.restype = i64
         lib.or_num_threads.argtypes = []
         lib.or_num_threads.restype = ctypes.c_int
         lib.or_set_threads.argtypes = [ctypes.c_int]
@@ -142,6 +146,22 @@ def solve(A, B, n: int, m: int, nrhs: int):
     if r < 0:
         raise MemoryError("oracle solve: out of memory")
     return dict(X=X[:m], consistent=cons, rank=int(r))
+
+
+def nullspace(A, n: int, m: int):
+    """Null space basis (one vector per free column, free variables unit) and the RREF.
+
+    Returns dict(N ((m - rank) x wpr(m)), R (min(n,m) x wpr(m)), nullity).
+    """
+    lib = _load()
+    A = _check(A, n, m)
+    kmin = min(n, m)
+    N = np.zeros((max(m, 1), wpr(m)), dtype=np.uint64)
+    R = np.zeros((max(kmin, 1), wpr(m)), dtype=np.uint64)
+    k = lib.or_nullspace(n, m, _u64(A), _u64(N), _u64(R))
+    if k < 0:
+        raise MemoryError("oracle nullspace: out of memory")
+    return dict(N=N[:k], R=R[:kmin], nullity=int(k))
 
 
 def rank(A, n: int, m: int) -> int:

@@ -141,6 +141,53 @@ int64_t or_ple(int64_t n, int64_t m, const uint64_t *A, uint64_t *E, uint64_t *L
   return rank;
 }
 
+/*
+ * Null space of A (n x m), the use of the row-echelon form named in Section 1.
+ * From the PLE's echelon rows E (rank r, pivot columns p_t): the reduced row
+ * echelon form R by back-substitution (pivot row t, from the last to the first,
+ * reduced by every later pivot row u whose pivot column p_u it has a 1 in);
+ * then, for the j-th free (non-pivot) column f_j in increasing order, the
+ * vector x with x_{f_j} = 1, every other free variable 0 and x_{p_t} = R[t][f_j],
+ * the unique solution of R x = 0 with that choice of free variables.
+ *   N : out, (m - r) rows of wpr(m) words (NULL: not written)
+ *   R : out, kmin x m, wpr(m) words per row; rows >= r zero (NULL: not written)
+ * Returns the nullity m - r, or -1 on allocation failure.
+ */
+int64_t or_nullspace(int64_t n, int64_t m, const uint64_t *A, uint64_t *N, uint64_t *R) {
+  const int64_t wm = wpr_of(m);
+  const int64_t kmin = n < m ? n : m;
+  uint64_t *E = (uint64_t *)calloc((size_t)(kmin * wm + 1), sizeof(uint64_t));
+  int64_t *piv = (int64_t *)malloc((size_t)(kmin + 1) * sizeof(int64_t));
+  uint8_t *is_piv = (uint8_t *)calloc((size_t)(m + 1), 1);
+  if (!E || !piv || !is_piv) { free(E); free(piv); free(is_piv); return -1; }
+  const int64_t r = or_ple(n, m, A, E, NULL, NULL, piv);
+  if (r < 0) { free(E); free(piv); free(is_piv); return -1; }
+  for (int64_t t = r - 1; t >= 0; --t) {           /* back-substitution, bottom up */
+    uint64_t *row = E + t * wm;
+    for (int64_t u = t + 1; u < r; ++u)
+      if (getbit(row, piv[u])) {
+        const uint64_t *ru = E + u * wm;
+        for (int64_t j = 0; j < wm; ++j) row[j] ^= ru[j];
+      }
+  }
+  if (R) memcpy(R, E, (size_t)(kmin * wm) * sizeof(uint64_t));
+  for (int64_t t = 0; t < r; ++t) is_piv[piv[t]] = 1;
+  if (N) {
+    memset(N, 0, (size_t)((m - r) * wm) * sizeof(uint64_t));
+    int64_t j = 0;
+    for (int64_t f = 0; f < m; ++f) {
+      if (is_piv[f]) continue;
+      uint64_t *x = N + j * wm;
+      setbit(x, f);
+      for (int64_t t = 0; t < r; ++t)
+        if (getbit(E + t * wm, f)) setbit(x, piv[t]);
+      ++j;
+    }
+  }
+  free(E); free(piv); free(is_piv);
+  return m - r;
+}
+
 /* C = A*B (accumulate = 0) or C ^= A*B (accumulate != 0).
  * A: n x k (wpr(k) words/row), B: k x m (wpr(m)), C: n x m (wpr(m)). */
 void or_matmul(int64_t n, int64_t k, int64_t m, const uint64_t *A, const uint64_t *B,

@@ -366,3 +366,54 @@ def test_solve(orc, n, m, kind, nrhs):
         assert not X[nonpiv, c].any()     # free variables are zero
     for c in range(0, nrhs, 2):
         assert cons[c] == 1
+
+
+# ---------------------------------------------------------------- null space (Section 1's use)
+@pytest.mark.parametrize("n,m,kind", [(5, 9, "dense"), (9, 5, "dense"), (7, 10, "planted"), (10, 10, "sparse"),
+                                      (1, 1, "dense"), (6, 12, "zero")])
+def test_nullspace_brute_force(orc, n, m, kind):
+    """Tiny inputs: the basis spans exactly the solutions of A x = 0, found by
+    enumerating all 2^m vectors."""
+    if kind == "dense":
+        A = synth.dense(41, n * 100 + m, n, m)
+    elif kind == "planted":
+        X, Y = synth.planted(41, 3, n, m, 3)
+        A = orc.matmul(X, Y, n, 3, m)
+    elif kind == "sparse":
+        A = synth.bernoulli(41, 5, n, m, 0.15)
+    else:
+        A = np.zeros((n, 1), dtype=np.uint64)
+    res = orc.nullspace(A, n, m)
+    Ab = to_bits(A, m)
+    sols = {x for x in range(1 << m)
+            if not np.any(gf2_mul(Ab, ints_to_bits([x], m).T) % 2)}
+    span = {0}
+    for v in (rows_as_ints(to_bits(res["N"], m)) if res["nullity"] else []):
+        span |= {s ^ v for s in span}
+    assert span == sols
+    assert res["nullity"] == m - len(rref(Ab)[1])
+
+
+@pytest.mark.parametrize("n,m,kind", [(60, 90, "dense"), (90, 60, "dense"), (130, 200, "planted"),
+                                      (200, 130, "sparse"), (64, 64, "dense")])
+def test_nullspace_structure_and_rref(orc, n, m, kind):
+    """A N^T = 0 (numpy product), N is the unit matrix on the free columns in order,
+    nullity = m - rank, and R equals an independent Gauss-Jordan RREF."""
+    if kind == "dense":
+        A = synth.dense(43, n + m, n, m)
+    elif kind == "planted":
+        X, Y = synth.planted(43, 7, n, m, 40)
+        A = orc.matmul(X, Y, n, 40, m)
+    else:
+        A = synth.bernoulli(43, 9, n, m, 0.03)
+    res = orc.nullspace(A, n, m)
+    Ab = to_bits(A, m)
+    Rref, piv = rref(Ab)
+    r = len(piv)
+    assert res["nullity"] == m - r
+    Nb = to_bits(res["N"], m) if res["nullity"] else np.zeros((0, m), np.uint8)
+    assert not np.any(gf2_mul(Ab, Nb.T))
+    free = [c for c in range(m) if c not in set(piv)]
+    assert np.array_equal(Nb[:, free], np.eye(len(free), dtype=np.uint8))
+    R = to_bits(res["R"], m)
+    assert np.array_equal(R[:r], Rref) and not np.any(R[r:])
