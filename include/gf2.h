@@ -101,6 +101,26 @@ int gf2_solve(const gf2_mat *A, const gf2_mat *B, const gf2_mat *X, uint64_t *co
               int64_t *rank, void *stream);
 
 /*
+ * Reduced row echelon form: R (min(n,m) x m) = E of gf2_decompose with every
+ * pivot column cleared above its pivot (rows >= rank zero).  pivcols
+ * (min(n,m) int64, -1 beyond the rank) and rank (1 int64) as in
+ * gf2_decompose.  R, pivcols and rank may each be NULL.  A must not be empty.
+ * Method: R = U^-1 E with U = E restricted to the pivot columns, bottom-up in
+ * blocks of 512 pivot rows (back-substitution inside a block, then one
+ * Four-Russians product per block for the rows above it).
+ */
+int gf2_rref(const gf2_mat *A, const gf2_mat *R, int64_t *pivcols, int64_t *rank, void *stream);
+
+/*
+ * Null space of A (n x m), the use of the echelon form named in Section 1.
+ * N (m x m, caller allocated): row j < nullity = m - rank is the vector x of
+ * the j-th free (non-pivot) column f_j in increasing order -- x_{f_j} = 1,
+ * every other free variable 0, x_{p_t} = R[t][f_j] -- so A x = 0; rows from
+ * nullity on are written as zero.  nullity: 1 int64.  A must not be empty.
+ */
+int gf2_nullspace(const gf2_mat *A, const gf2_mat *N, int64_t *nullity, void *stream);
+
+/*
  * ---------------------------------------------------------------- batches
  * Many independent matrices of at most GF2_BATCH_MAX_DIM rows and columns,
  * each of its own shape, factored (and solved) in one launch.  The matrices

@@ -399,6 +399,67 @@ int prepare_decomp(const gf2_mat *A, hipStream_t s, DecWork &w, size_t extra, vo
   return GF2_OK;
 }
 
+// Reduced row echelon form of A in the working layout: the decomposition's E
+// (extracted into ldE-row blocks), then R = U^-1 E bottom-up in blocks of 512
+// pivot rows (diagonal-block back-substitution, then one 512-bit-inner product
+// per block for every row above it).
+struct RrefWork {
+  uint64_t *E = nullptr;   // kmin x m, working layout, ldE rows per block: E, then R
+  int64_t ldE = 0;
+  uint64_t *G = nullptr;   // kmin x kmin: E restricted to the pivot columns
+  uint64_t *Bb = nullptr;  // 512 x m: one block of R as a product operand
+  int64_t *piv = nullptr, *rank = nullptr, *tw0 = nullptr, *freecols = nullptr;
+  uint64_t *bitmap = nullptr;
+  int64_t Mw = 0, NBE = 0, Gw = 0;
+};
+
+int rref_run(const gf2_mat *A, hipStream_t s, RrefWork &rw) {
+  const int64_t n = A->rows, m = A->cols, kmin = n < m ? n : m;
+  rw.Mw = ceil_div(m, 64);
+  rw.ldE = ceil_div(kmin, 256) * 256;
+  rw.NBE = ceil_div(rw.Mw, TW);
+  rw.Gw = ceil_div(kmin, 64);
+  const int64_t NBG = ceil_div(rw.Gw, TW);
+  const size_t bE = align256((size_t)rw.NBE * rw.ldE * TW * 8), bG = align256((size_t)NBG * rw.ldE * TW * 8),
+               bB = align256((size_t)rw.NBE * 512 * TW * 8), bI = align256((size_t)(kmin + 2) * 8),
+               bM = align256((size_t)(rw.Mw + 1) * 8), bF = align256((size_t)(m + 1) * 8);
+  DecWork w;
+  void *extra = nullptr;
+  int rc = prepare_decomp(A, s, w, bE + bG + bB + bI + 2 * bM + bF + 256, &extra);
+  if (rc) return rc;
+  char *p = (char *)extra;
+  rw.E = (uint64_t *)p; p += bE;
+  rw.G = (uint64_t *)p; p += bG;
+  rw.Bb = (uint64_t *)p; p += bB;
+  rw.piv = (int64_t *)p; p += bI;
+  rw.bitmap = (uint64_t *)p; p += bM;
+  rw.tw0 = (int64_t *)p; p += bM;
+  rw.freecols = (int64_t *)p; p += bF;
+  rw.rank = (int64_t *)p;
+  if ((rc = factor(A, w, s))) return rc;
+  HIPCHK(launch_finish(w, nullptr, rw.piv, rw.rank, s));
+  const gf2_mat Em{rw.E, kmin, m, TW, rw.ldE};
+  HIPCHK(launch_extract_E(w, Em, s));
+  HIPCHK(launch_gather_pivcols(rw.E, rw.ldE, rw.piv, rw.rank, rw.G, kmin, rw.Gw, s));
+  const int nJ = (int)ceil_div(kmin, 512);
+  for (int J = nJ - 1; J >= 0; --J) {
+    HIPCHK(launch_rref_diag(rw.E, rw.ldE, rw.G, rw.rank, J, rw.Mw, s));
+    if (J == 0) break;
+    HIPCHK(launch_copy_block_rows(rw.E, rw.ldE, rw.rank, 512ll * J, rw.Bb, rw.NBE, s));
+    GemmArgs a;
+    memset(&a, 0, sizeof(a));
+    a.A = rw.G; a.ldA = rw.ldE; a.a_word0 = 8 * J;
+    a.B = rw.Bb; a.ldB = 512; a.b_rows = 512; a.bsub = nullptr;
+    a.C = rw.E; a.ldC = rw.ldE;
+    a.row_tile0 = 0; a.row_end = 512ll * J;
+    a.kwords = (int32_t)std::min<int64_t>(8, rw.Gw - 8ll * J);
+    a.qc0 = 0; a.qc1 = (int32_t)rw.Mw;
+    a.accumulate = 1;
+    if ((rc = run_gemm(a, 512ll * J, -1, 512ll * J, s))) return rc;
+  }
+  return GF2_OK;
+}
+
 }  // namespace
 }  // namespace gf2
 
@@ -985,6 +1046,38 @@ int gf2_autotune_table(int32_t *variants, int64_t *strassen_cutoff) {
     for (int r = 0; r < kTuneRows; ++r)
       for (int c = 0; c < kTuneBlocks; ++c) variants[r * kTuneBlocks + c] = g_tuned_valid ? g_tuned[r][c] : -1;
   if (strassen_cutoff) *strassen_cutoff = g_strassen_cutoff;
+  return GF2_OK;
+}
+
+int gf2_rref(const gf2_mat *A, const gf2_mat *R, int64_t *pivcols, int64_t *rank, void *stream) {
+  int rc;
+  if ((rc = check_mat(A, "A"))) return rc;
+  const int64_t n = A->rows, m = A->cols, kmin = n < m ? n : m;
+  if (kmin == 0) return fail(GF2_EINVAL, "gf2_rref: empty matrices are not supported");
+  if (R) {
+    if ((rc = check_mat(R, "R"))) return rc;
+    if (R->rows != kmin || R->cols != m) return fail(GF2_EINVAL, "gf2_rref: R must be min(n,m) x m");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  RrefWork rw;
+  if ((rc = rref_run(A, s, rw))) return rc;
+  if (R) HIPCHK(launch_unpack(rw.E, rw.ldE, *R, s));
+  if (pivcols) HIPCHK(hipMemcpyAsync(pivcols, rw.piv, (size_t)kmin * 8, hipMemcpyDeviceToDevice, s));
+  if (rank) HIPCHK(hipMemcpyAsync(rank, rw.rank, 8, hipMemcpyDeviceToDevice, s));
+  return GF2_OK;
+}
+
+int gf2_nullspace(const gf2_mat *A, const gf2_mat *N, int64_t *nullity, void *stream) {
+  int rc;
+  if ((rc = check_mat(A, "A")) || (rc = check_mat(N, "N"))) return rc;
+  const int64_t n = A->rows, m = A->cols;
+  if (n == 0 || m == 0) return fail(GF2_EINVAL, "gf2_nullspace: empty matrices are not supported");
+  if (N->rows != m || N->cols != m) return fail(GF2_EINVAL, "gf2_nullspace: N must be m x m");
+  if (!nullity) return fail(GF2_EINVAL, "gf2_nullspace: null nullity pointer");
+  hipStream_t s = (hipStream_t)stream;
+  RrefWork rw;
+  if ((rc = rref_run(A, s, rw))) return rc;
+  HIPCHK(launch_null_basis(rw.E, rw.ldE, rw.piv, rw.rank, rw.bitmap, rw.tw0, rw.freecols, nullity, *N, s));
   return GF2_OK;
 }
 

@@ -180,4 +180,15 @@ int batch_workers(int ncu);  // workgroups of one batched launch on a device of 
 hipError_t launch_batch_dec(const BatchArgs &a, int workers, hipStream_t s);
 hipError_t launch_batch_solve(const BatchSolveArgs &a, hipStream_t s);
 
+// ---------------------------------------------------------------- reduced echelon form, null space
+hipError_t launch_gather_pivcols(const uint64_t *E, int64_t ldE, const int64_t *pivcols, const int64_t *rankp,
+                                 uint64_t *G, int64_t kmin, int64_t Gw, hipStream_t s);
+hipError_t launch_rref_diag(uint64_t *E, int64_t ldE, const uint64_t *G, const int64_t *rankp, int J, int64_t Mw,
+                            hipStream_t s);
+hipError_t launch_copy_block_rows(const uint64_t *E, int64_t ldE, const int64_t *rankp, int64_t R0, uint64_t *B,
+                                  int64_t NB, hipStream_t s);
+hipError_t launch_null_basis(const uint64_t *R, int64_t ldE, const int64_t *pivcols, const int64_t *rankp,
+                             uint64_t *bitmap, int64_t *tw0, int64_t *freecols, int64_t *nullity,
+                             const gf2_mat &N, hipStream_t s);
+
 }  // namespace gf2

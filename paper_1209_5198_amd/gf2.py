@@ -27,7 +27,7 @@ GF2_ENOMEM = -2
 GF2_EHIP = -3
 
 EXPORTED = ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_decompose_batched",
-            "gf2_solve_batched", "gf2_autotune", "gf2_autotune_table", "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_release",
+            "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_autotune", "gf2_autotune_table", "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_release",
             "gf2_last_error", "gf2_version")
 BATCH_MAX_DIM = 2048
 
@@ -68,6 +68,8 @@ def load():
         PB = ctypes.POINTER(BatchItem)
         lib.gf2_decompose_batched.argtypes = [PB, i64, vp, vp, vp, vp, vp, vp, vp]
         lib.gf2_solve_batched.argtypes = [PB, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.gf2_rref.argtypes = [P, P, vp, vp, vp]
+        lib.gf2_nullspace.argtypes = [P, P, vp, vp]
         lib.gf2_autotune.argtypes = [i64, vp]
         lib.gf2_autotune_table.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(i64)]
         lib.gf2_set_param.argtypes = [ctypes.c_char_p, i64]
@@ -78,8 +80,8 @@ def load():
         lib.gf2_last_error.restype = ctypes.c_char_p
         lib.gf2_version.restype = ctypes.c_char_p
         for name in ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_decompose_batched",
-                     "gf2_solve_batched", "gf2_autotune", "gf2_autotune_table", "gf2_set_param",
-                     "gf2_profile", "gf2_profile_read", "gf2_release"):
+                     "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_autotune",
+                     "gf2_autotune_table", "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_release"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -197,6 +199,15 @@ def gf2_decompose_batched(items, A, L, E, perm, pivcols, rank, stream=None) -> N
 def gf2_solve_batched(items, L, E, perm, pivcols, rank, B, X, consistent, stream=None) -> None:
     _check(load().gf2_solve_batched(items, len(items), _ptr(L), _ptr(E), _ptr(perm), _ptr(pivcols),
                                     _ptr(rank), _ptr(B), _ptr(X), _ptr(consistent), _stream(stream)))
+
+
+def gf2_rref(A: Mat, R, pivcols, rank, stream=None) -> None:
+    Rd = ctypes.byref(R.desc()) if R is not None else None
+    _check(load().gf2_rref(ctypes.byref(A.desc()), Rd, _ptr(pivcols), _ptr(rank), _stream(stream)))
+
+
+def gf2_nullspace(A: Mat, N: Mat, nullity, stream=None) -> None:
+    _check(load().gf2_nullspace(ctypes.byref(A.desc()), ctypes.byref(N.desc()), _ptr(nullity), _stream(stream)))
 
 
 def gf2_autotune(max_size: int = 65536, stream=None) -> None:

@@ -1,0 +1,138 @@
+"""GPU parity of gf2_rref and gf2_nullspace (the null space of Section 1's uses).
+
+Medium shapes (several 512-row blocks, ragged edges, tall and wide, dense,
+sparse and planted rank) are compared with the oracle bit for bit: the reduced
+row echelon form R, pivot columns, rank, and the null-space basis (one vector
+per free column).  At the full planted-rank size (32768 x 65536, rank 20000)
+the pivot columns must match the oracle's digest, the basis must be the unit
+matrix on the free columns, and random combinations x of basis vectors must
+satisfy A x = 0 (oracle products).
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1209_5198_amd import synth
+
+pytestmark = pytest.mark.gpu
+wpr = synth.wpr
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_hashes.json")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1209_5198_amd import gf2
+
+    gf2.load()
+    return gf2
+
+
+def gpu_rref_null(g, A, n, m):
+    import torch
+
+    k = min(n, m)
+    Am = g.Mat.from_rowmajor(A, n, m)
+    R = g.Mat.zeros(k, m)
+    piv = torch.empty(k, dtype=torch.int64, device="cuda")
+    rank = torch.empty(1, dtype=torch.int64, device="cuda")
+    g.gf2_rref(Am, R, piv, rank)
+    N = g.Mat.zeros(m, m)
+    nul = torch.empty(1, dtype=torch.int64, device="cuda")
+    g.gf2_nullspace(Am, N, nul)
+    torch.cuda.synchronize()
+    return dict(R=R.to_rowmajor(), pivcols=piv.cpu().numpy(), rank=int(rank.item()), N=N.to_rowmajor(),
+                nullity=int(nul.item()))
+
+
+CASES = [(1300, 1700, "dense"), (1700, 1300, "dense"), (2100, 2100, "planted"), (600, 3000, "sparse"),
+         (64, 64, "dense"), (1, 1, "dense"), (3000, 70, "dense"), (513, 1025, "planted"), (2048, 2048, "dense")]
+
+
+@pytest.mark.parametrize("n,m,kind", CASES)
+def test_rref_and_nullspace_parity(g, orc, n, m, kind):
+    if kind == "dense":
+        A = synth.dense(57, n + 3 * m, n, m)
+    elif kind == "sparse":
+        A = synth.bernoulli(57, 5, n, m, 0.002)
+    else:
+        r = min(n, m) // 3
+        X, Y = synth.planted(57, 11, n, m, r)
+        A = orc.matmul(X, Y, n, r, m)
+    say("rref/nullspace", n, m, kind)
+    got = gpu_rref_null(g, A, n, m)
+    ref = orc.nullspace(A, n, m)
+    ple = orc.ple(A, n, m, want_le=False)
+    assert got["rank"] == ple["rank"]
+    assert np.array_equal(got["pivcols"], ple["pivcols"])
+    assert np.array_equal(got["R"], ref["R"])
+    assert got["nullity"] == ref["nullity"] == m - ple["rank"]
+    assert np.array_equal(got["N"][:ref["nullity"]], ref["N"])
+    assert not np.any(got["N"][ref["nullity"]:])
+
+
+def digest(a) -> str:
+    a = np.ascontiguousarray(a)
+    a = a.astype("<i8", copy=False) if a.dtype == np.int64 else a.astype("<u8", copy=False)
+    return hashlib.sha256(a.tobytes()).hexdigest()
+
+
+def test_nullspace_fullsize_planted(g, orc):
+    import torch
+
+    with open(GOLD) as f:
+        ref = json.load(f).get("planted")
+    if ref is None:
+        pytest.skip("no golden digests for planted")
+    n, m, r = ref["n"], ref["m"], ref["r_planted"]
+    say("nullspace fullsize planted", n, m, r)
+    X, Y = synth.planted(ref["seed"], ref["stream"], n, m, r)
+    Am = g.matmul(g.Mat.from_rowmajor(X, n, r), g.Mat.from_rowmajor(Y, r, m))
+    del X, Y
+    N = g.Mat.zeros(m, m)
+    nul = torch.empty(1, dtype=torch.int64, device="cuda")
+    piv = torch.empty(min(n, m), dtype=torch.int64, device="cuda")
+    rank = torch.empty(1, dtype=torch.int64, device="cuda")
+    g.gf2_rref(Am, None, piv, rank)
+    g.gf2_nullspace(Am, N, nul)
+    torch.cuda.synchronize()
+    pv = piv.cpu().numpy()
+    assert int(rank.item()) == ref["rank"] and digest(pv) == ref["pivcols"]
+    k = int(nul.item())
+    assert k == m - ref["rank"]
+    free = np.setdiff1d(np.arange(m), pv[:ref["rank"]])
+    A = Am.to_rowmajor()
+    del Am
+    Nh = N.to_rowmajor()[:k]
+    del N
+    torch.cuda.empty_cache()
+    # unit matrix on the free columns, sampled rows
+    rows = np.random.default_rng(3).choice(k, size=64, replace=False)
+    for j in rows:
+        bits = (Nh[j, free >> 6] >> (free & 63).astype(np.uint64)) & np.uint64(1)
+        assert bits.sum() == 1 and bits[j] == 1
+    # A x = 0 for 64 random combinations x = c^T N of the basis
+    c = synth.dense(77, 1, 64, k)
+    Xc = orc.matmul(c, Nh, 64, k, m)          # 64 x m: each row a combination of basis vectors
+    AX = orc.matmul(A, orc_transpose(Xc, 64, m), n, m, 64)
+    assert not np.any(AX)
+
+
+def orc_transpose(M, rows, cols):
+    """Row-major bit matrix (rows x cols) -> its transpose (cols x rows), by unpacking."""
+    bits = np.unpackbits(M.view(np.uint8).reshape(rows, -1), axis=1, bitorder="little")[:, :cols]
+    return np.packbits(np.ascontiguousarray(bits.T), axis=1, bitorder="little").view(np.uint64) if rows % 64 == 0 \
+        else np.packbits(np.pad(np.ascontiguousarray(bits.T), ((0, 0), (0, (-rows) % 64))), axis=1,
+                         bitorder="little").view(np.uint64)
