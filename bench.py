@@ -55,8 +55,9 @@ import time
 # Hardware queues per process for the HIP runtime (read when it starts): the
 # serving sessions run up to 4 large requests concurrently, each with its own
 # pipeline stream pair, plus the batch and copy streams; with the default 4
-# queues, waits of unrelated streams that share a queue serialise them.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+# queues, waits of unrelated streams that share a queue serialise them.  Set
+# outright: an inherited default of 4 would otherwise win.
+os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 import numpy as np
 
