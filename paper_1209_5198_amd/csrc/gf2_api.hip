@@ -453,7 +453,9 @@ int rref_run(const gf2_mat *A, hipStream_t s, RrefWork &rw) {
     a.C = rw.E; a.ldC = rw.ldE;
     a.row_tile0 = 0; a.row_end = 512ll * J;
     a.kwords = (int32_t)std::min<int64_t>(8, rw.Gw - 8ll * J);
-    a.qc0 = 0; a.qc1 = (int32_t)rw.Mw;
+    // rows of block J are zero left of their pivots, which lie at or beyond
+    // column 512 J: only words from 8 J change
+    a.qc0 = 8 * J; a.qc1 = (int32_t)rw.Mw;
     a.accumulate = 1;
     if ((rc = run_gemm(a, 512ll * J, -1, 512ll * J, s))) return rc;
   }

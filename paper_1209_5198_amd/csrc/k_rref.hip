@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kRT) void k_rref_diag(uint64_t *E, int64_t ldE, con
   const int64_t r = *rankp, R0 = 512ll * J;
   if (R0 >= r) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, h = lane >> 4, wl = lane & 15;
-  const int blk = blockIdx.x;
+  const int blk = blockIdx.x + J / 2;  // the block's rows are zero in words < 8 J
   const int64_t qw = (int64_t)blk * TW + wl;
   const bool qok = qw < Mw;
   if (tid < 8) {
@@ -238,7 +238,9 @@ hipError_t launch_gather_pivcols(const uint64_t *E, int64_t ldE, const int64_t *
 
 hipError_t launch_rref_diag(uint64_t *E, int64_t ldE, const uint64_t *G, const int64_t *rankp, int J, int64_t Mw,
                             hipStream_t s) {
-  const unsigned nb = (unsigned)((Mw + TW - 1) / TW);
+  const int64_t nbe = (Mw + TW - 1) / TW;  // column blocks from J / 2 on (words >= 8 J)
+  if (nbe <= J / 2) return hipSuccess;
+  const unsigned nb = (unsigned)(nbe - J / 2);
   hipLaunchKernelGGL(k_rref_diag, dim3(nb), dim3(kRT), 0, s, E, ldE, G, rankp, J, Mw);
   return hipGetLastError();
 }
