@@ -276,40 +276,10 @@ def serving_section(synth, count: int):
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=65536)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
-    ap.add_argument("--batch-steps", type=int, default=10)
-    ap.add_argument("--no-serving", action="store_true", help="skip the serving sessions")
-    ap.add_argument("--no-configs", action="store_true", help="skip the other single-matrix configurations")
-    ap.add_argument("--serve-count", type=int, default=SERVE_COUNT)
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain 1 GiB device-to-device copy (counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
-        sys.exit(2)
-
+def headline_section(args, gf2, synth):
+    """The 65536^2 decomposition: timed steps, roofline of the product kernel."""
     import torch
 
-    from paper_1209_5198_amd import gf2, synth
-
-    torch.cuda.set_device(0)
-    if args.copy_calibration:
-        nbytes = 1 << 30
-        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes, "copies": 3}}),
-              flush=True)
-        return
     n = m = args.n
     print(f"# generating {n}x{m} Bernoulli(1/2) input (seed {SEED})", file=sys.stderr, flush=True)
     words = synth.dense(SEED, 1, n, m)
@@ -378,12 +348,56 @@ def main():
            "roofline": roof}
     del A, L, E
     torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving sessions")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other single-matrix configurations")
+    ap.add_argument("--no-headline", action="store_true", help="skip the 65536^2 decomposition (profiling runs)")
+    ap.add_argument("--no-per-matrix", action="store_true",
+                    help="skip the one-call-per-matrix comparison of the batched workload")
+    ap.add_argument("--serve-count", type=int, default=SERVE_COUNT)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1209_5198_amd import gf2, synth
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes, "copies": 3}}),
+              flush=True)
+        return
+    if args.no_headline:
+        out = {"metric": METRIC, "note": "headline skipped (--no-headline)"}
+    else:
+        out = headline_section(args, gf2, synth)
     if not args.no_configs:
         print("# other configurations", file=sys.stderr, flush=True)
         out["configs"] = other_configs(gf2, synth)
     if not args.no_batched:
         print("# batched workload", file=sys.stderr, flush=True)
-        out["batched"] = batched_section(gf2, synth, args.batch_steps)
+        out["batched"] = batched_section(gf2, synth, args.batch_steps, per_matrix=not args.no_per_matrix)
     if not args.no_serving:
         print("# serving sessions", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
