@@ -141,3 +141,48 @@ def test_serving_mix_equals_alone_and_oracle(g, orc):
         if not same(r.result, refs[i], r.kind):
             bad.append(("oracle", r.id, r.kind, r.n, r.m))
     assert not bad, bad[:10]
+
+
+def test_serving_full_size_range(g, orc):
+    """Requests at the serving workload's real sizes (sides 128..16384, square and
+    1:4): every result equals the request alone; a sample that includes the largest
+    requests equals the oracle."""
+    from paper_1209_5198_amd import serve
+
+    seed, count = 5, 64
+    specs = synth.serving_specs(seed, count)
+    arrivals = synth.poisson_arrivals(seed, count, 400.0)
+    data = serve.make_request_data(seed, specs)
+    reqs = serve.make_requests(specs, data, arrivals)
+    srv = serve.Server(cap_bytes=8 << 30, big_streams=4, verify=True)
+    st = srv.run(reqs)
+    say("serving full-size stats", {k: st[k] for k in ("requests_per_s", "p50_ms", "p99_ms", "small", "large")})
+    buf, offs, _ = data
+    host = buf.numpy().view(np.uint64)
+    mats = [host[offs[i]:offs[i + 1]].reshape(s["n"], wpr(s["m"])) for i, s in enumerate(specs)]
+    bad = []
+    for i, r in enumerate(reqs):
+        if not same(r.result, alone(g, r, mats[i]), r.kind):
+            bad.append(("alone", r.id, r.kind, r.n, r.m))
+    order = sorted(range(count), key=lambda i: -specs[i]["n"] * specs[i]["m"])
+    sample = sorted(set(order[:6]) | set(range(0, count, 6)))
+    with concurrent.futures.ThreadPoolExecutor(8) as ex:
+        refs = dict(zip(sample, ex.map(lambda i: oracle_mt(orc, reqs[i], mats[i]), sample)))
+    for i in sample:
+        if not same(reqs[i].result, refs[i], reqs[i].kind):
+            bad.append(("oracle", reqs[i].id, reqs[i].kind, reqs[i].n, reqs[i].m))
+    assert not bad, bad[:10]
+
+
+def oracle_mt(orc, r, A):
+    """The oracle with two threads per call (large requests)."""
+    orc.set_threads(2)
+    n, m = r.n, r.m
+    if r.kind == "solve":
+        sol = orc.solve(A, bits_to_col(r.b_bits, n), n, m, 1)
+        return dict(rank=sol["rank"], x=col_to_bits(sol["X"], m), consistent=int(sol["consistent"][0]) & 1)
+    res = orc.ple(A, n, m)
+    if r.kind == "rank":
+        return dict(rank=res["rank"])
+    res["L"] = res["L"][:, :wpr(min(n, m))]
+    return res
