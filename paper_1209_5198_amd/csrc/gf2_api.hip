@@ -963,7 +963,7 @@ int gf2_autotune(int64_t max_size, void *stream) {
 
   // ---- product-kernel tile per size class, at the decomposition's inner
   // dimension (one 512-column panel) on synthetic operands
-  const int cand[4] = {7, 8, 10, 9};
+  const int cand[4] = {13, 14, 15, 16};
   const int bsel[kTuneBlocks] = {1, 3, 8, 32};
   int nr = 0;
   while (nr < kTuneRows && ((int64_t)256 << nr) <= max_size) ++nr;

@@ -105,7 +105,7 @@ hipError_t launch_extract_L(const DecWork &w, const gf2_mat &L, hipStream_t s);
 hipError_t launch_finish(const DecWork &w, int64_t *perm, int64_t *pivcols, int64_t *rank,
                          hipStream_t s);
 
-constexpr int kGemmVariants = 13;  // product-kernel variants 0 .. kGemmVariants-1
+constexpr int kGemmVariants = 17;  // product-kernel variants 0 .. kGemmVariants-1
 hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int variant, hipStream_t s);
 int gemm_auto_variant(int64_t active_rows, int qc0, int qc1, int ncu);  // variant for a launch shape
 

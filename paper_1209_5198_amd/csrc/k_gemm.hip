@@ -600,6 +600,225 @@ __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
 }
 
 
+// k_gemm_wide with the B rows of a step staged through LDS (two 4 KB buffers)
+// instead of registers: 256 threads load the 32 rows x 16 words of a later
+// step with one 16-byte load each, store them (masked) into the free buffer
+// while the tables are built, and every thread reads its eight rows back from
+// LDS for the build.  The registers this frees hold a second set of lookups:
+// the loads of the next row pair are in flight while the current pair is
+// combined, so the table reads of a wave never wait for its own XORs.
+template <int NT, int TM>
+__global__ __launch_bounds__(NT) void k_gemm_wide2(GemmArgs a) {
+  constexpr int UB = 2;                // rows per lane looked up together
+  constexpr int NW = NT / 64;          // waves
+  constexpr int RPL = TM / (8 * NW);   // rows per lane
+  constexpr int JOBS = NT / 8;         // table-build jobs (8 threads each, one word pair per thread)
+  constexpr int EPJ = 4 * 256 / JOBS;  // entries per job
+  constexpr int LOGE = EPJ == 8 ? 3 : (EPJ == 16 ? 4 : (EPJ == 32 ? 5 : 6));
+  static_assert(RPL * 8 * NW == TM && RPL % (2 * UB) == 0, "tile");
+  static_assert(EPJ == 8 || EPJ == 16 || EPJ == 32 || EPJ == 64, "build split");
+  static_assert(TM % NT == 0 && NT >= 256, "A staging, B staging");
+  // Tables g = 2p + s stored as T[p][idx][s][word], as in k_gemm_wide.
+  __shared__ uint64_t T[2][256][2][TW];
+  __shared__ uint32_t As[2 * TM];         // the tile's A word for the current 64 inner bits
+  __shared__ ulonglong2 Bs[2][32][TW / 2];  // B rows of a step (zero past the operand), two buffers
+  __shared__ int64_t sR[kMaxPanelWords];  // pivot-row ranges of a mapped B (at most one panel)
+  __shared__ int sr[kMaxPanelWords];
+
+  if (a.skip_flag && *a.skip_flag == 0u) return;  // the Schur complement is already zero
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, G = lane >> 3, w2 = lane & 7;
+  const int blk = blockIdx.y + (a.qc0 >> 4);
+  const int64_t qw = (int64_t)blk * TW + 2 * w2;
+  const bool ok0 = qw >= a.qc0 && qw < a.qc1, ok1 = qw + 1 >= a.qc0 && qw + 1 < a.qc1;
+
+  const int64_t tile0 = a.row_tile0 + (int64_t)blockIdx.x * TM;
+  int64_t rb = tile0;
+  if (a.bsub) {  // rows below the panel's pivots: first row after the last sub-panel's pivots
+    const int64_t d = a.bsub[a.kwords - 1].R + a.bsub[a.kwords - 1].r;
+    if (d > rb) rb = d;
+  }
+  int64_t re = tile0 + TM < a.row_end ? tile0 + TM : a.row_end;
+  if (rb >= re) return;
+
+  // rows of this lane: tile0 + 8*wv + G + 8*NW*u
+  int ulo, uhi;
+  lane_rows<RPL, 8 * NW>(tile0, 8 * wv + G, rb, re, ulo, uhi);
+  uint64_t acc[RPL][2];
+  {
+    uint64_t *C = a.C;
+    asm volatile("" : "+s"(C));
+    const uint64_t *Cl = C + (((int64_t)blk * a.ldC + tile0 + 8 * wv + G) * TW + 2 * w2);
+    load_acc2<RPL, 8 * NW>(acc, Cl, a.accumulate && ok0, a.accumulate && ok1, ulo, uhi);
+  }
+
+  const int job = tid >> 3;
+  const int g_b = job / (256 / EPJ), uu = job % (256 / EPJ);
+  const int64_t bq = (int64_t)blk * TW + 2 * w2;  // this thread's word pair of B (= qw)
+  const bool bok0 = ok0, bok1 = ok1;
+
+  // B staging: thread tid < 256 loads row srow of a step, words 2*w2, 2*w2+1,
+  // from a clamped (always valid) row; the row limit is applied when it is
+  // stored into LDS, a step later.
+  const int srow = tid >> 3;
+  ulonglong2 bnext = make_ulonglong2(0ull, 0ull);
+  bool bnext_ok = false;
+  auto load_b = [&](int hh) {
+    if (tid >= 256) return;
+    const int kw = hh >> 1;
+    int64_t browR = 64ll * kw;
+    int blim;
+    if (a.bsub) {
+      browR = sR[kw];
+      blim = sr[kw];
+    } else {
+      const int64_t left = a.b_rows - 64ll * kw;
+      blim = left >= 64 ? 64 : (left > 0 ? (int)left : 0);
+    }
+    const int r = 32 * (hh & 1) + srow;
+    bnext_ok = r < blim;
+    int64_t row = browR + r;
+    row = row < a.ldB ? row : a.ldB - 1;
+    bnext = *(const ulonglong2 *)(a.B + widx(a.ldB, row, bq));
+  };
+  auto stage_b = [&](int buf) {
+    if (tid >= 256) return;
+    Bs[buf][srow][w2] = make_ulonglong2((bnext_ok && bok0) ? bnext.x : 0ull, (bnext_ok && bok1) ? bnext.y : 0ull);
+  };
+  constexpr int APT = TM / NT;
+  auto load_a = [&](int kw, uint64_t (&av)[APT]) {
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+      const int64_t i = tile0 + tid + (int64_t)j * NT;
+      av[j] = a.A[widx(a.ldA, i < a.ldA ? i : a.ldA - 1, a.a_word0 + kw)];  // masked when staged
+    }
+  };
+
+  if (a.bsub) {
+    if (tid < a.kwords) {
+      sR[tid] = a.bsub[tid].R;
+      sr[tid] = a.bsub[tid].r;
+    }
+    __syncthreads();
+  }
+  const int nh = 2 * a.kwords;
+  uint64_t av[APT];
+  load_b(0);
+  load_a(0, av);
+  stage_b(0);
+  if (nh > 1) load_b(1);
+  const char *Tb = (const char *)&T[0][0][0][0];
+  // instruction g: odd groups read table g ^ 1 (the other table of the pair)
+  uint32_t lbase[4], sel[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int gg = g ^ (G & 1);
+    lbase[g] = ((uint32_t)(gg >> 1) << 16) | ((uint32_t)(gg & 1) << 7) | ((uint32_t)w2 << 4);
+    sel[g] = 0x0C020000u | ((4u + (uint32_t)gg) << 8);  // [lane base | byte gg of A | pair | 0]
+  }
+  for (int hh = 0; hh < nh; ++hh) {
+    const int half = hh & 1;
+    __syncthreads();  // previous lookups finished: T and As are free; B rows of step hh staged
+    if (half == 0) {
+#pragma unroll
+      for (int j = 0; j < APT; ++j) {
+        const int64_t i = tile0 + tid + (int64_t)j * NT;
+        const uint64_t v = (i >= rb && i < re) ? av[j] : 0ull;
+        As[2 * (tid + j * NT)] = (uint32_t)v;
+        As[2 * (tid + j * NT) + 1] = (uint32_t)(v >> 32);
+      }
+    }
+    {
+      ulonglong2 bv[8];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) bv[b] = Bs[half][8 * g_b + b][w2];
+      uint64_t c0 = 0ull, c1 = 0ull;
+#pragma unroll
+      for (int b = LOGE; b < 8; ++b)
+        if ((uu >> (b - LOGE)) & 1) {
+          c0 ^= bv[b].x;
+          c1 ^= bv[b].y;
+        }
+#pragma unroll
+      for (int j = 0; j < EPJ; ++j) {
+        const int gj = j ^ (j >> 1);
+        *(ulonglong2 *)&T[g_b >> 1][EPJ * uu + gj][g_b & 1][2 * w2] = make_ulonglong2(c0, c1);
+        if (j < EPJ - 1) {
+          c0 ^= bv[__builtin_ctz(j + 1)].x;
+          c1 ^= bv[__builtin_ctz(j + 1)].y;
+        }
+      }
+    }
+    if (hh + 1 < nh) stage_b(half ^ 1);  // buffer half ^ 1 was last read before the previous barrier
+    if (hh + 2 < nh) load_b(hh + 2);     // in flight during the lookups
+    if (half == 0 && (hh >> 1) + 1 < a.kwords) load_a((hh >> 1) + 1, av);
+    __syncthreads();
+    // A words of a row pair are read two pairs ahead and the table reads of
+    // the next pair are issued before the current pair is combined: LDS reads
+    // complete in order, so every wait leaves the nine later reads in flight.
+    auto read_a = [&](int u0, uint32_t (&a32)[UB]) {
+#pragma unroll
+      for (int v = 0; v < UB; ++v) a32[v] = As[2 * (8 * (wv + NW * (u0 + v)) + G) + half];
+    };
+    auto issue = [&](const uint32_t (&a32)[UB], uint4 (&t)[UB][4]) {
+#pragma unroll
+      for (int v = 0; v < UB; ++v)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) t[v][g] = *(const uint4 *)(Tb + __builtin_amdgcn_perm(a32[v], lbase[g], sel[g]));
+    };
+    auto combine = [&](int u0, const uint4 (&t)[UB][4]) {
+#pragma unroll
+      for (int v = 0; v < UB; ++v) {
+        uint32_t x0 = (uint32_t)acc[u0 + v][0], x1 = (uint32_t)(acc[u0 + v][0] >> 32);
+        uint32_t x2 = (uint32_t)acc[u0 + v][1], x3 = (uint32_t)(acc[u0 + v][1] >> 32);
+        x0 = __builtin_amdgcn_bitop3_b32(x0, t[v][0].x, t[v][1].x, 0x96);
+        x1 = __builtin_amdgcn_bitop3_b32(x1, t[v][0].y, t[v][1].y, 0x96);
+        x2 = __builtin_amdgcn_bitop3_b32(x2, t[v][0].z, t[v][1].z, 0x96);
+        x3 = __builtin_amdgcn_bitop3_b32(x3, t[v][0].w, t[v][1].w, 0x96);
+        x0 = __builtin_amdgcn_bitop3_b32(x0, t[v][2].x, t[v][3].x, 0x96);
+        x1 = __builtin_amdgcn_bitop3_b32(x1, t[v][2].y, t[v][3].y, 0x96);
+        x2 = __builtin_amdgcn_bitop3_b32(x2, t[v][2].z, t[v][3].z, 0x96);
+        x3 = __builtin_amdgcn_bitop3_b32(x3, t[v][2].w, t[v][3].w, 0x96);
+        acc[u0 + v][0] = ((uint64_t)x1 << 32) | x0;
+        acc[u0 + v][1] = ((uint64_t)x3 << 32) | x2;
+      }
+    };
+    uint32_t aA[UB], aB[UB];
+    uint4 tA[UB][4], tB[UB][4];
+    read_a(0, aA);
+    read_a(UB, aB);
+    issue(aA, tA);
+#pragma unroll
+    for (int u0 = 0; u0 < RPL; u0 += 2 * UB) {
+      if (u0 + 2 * UB < RPL) read_a(u0 + 2 * UB, aA);
+      issue(aB, tB);
+      combine(u0, tA);
+      if (u0 + 3 * UB < RPL) read_a(u0 + 3 * UB, aB);
+      if (u0 + 2 * UB < RPL) issue(aA, tA);
+      combine(u0 + UB, tB);
+    }
+  }
+
+  uint64_t any;
+  {
+    uint64_t *C = a.C;
+    asm volatile("" : "+s"(C));
+    uint64_t *Cl = C + (((int64_t)blk * a.ldC + tile0 + 8 * wv + G) * TW + 2 * w2);
+    any = store_acc2<RPL, 8 * NW>(acc, Cl, ok0, ok1, ulo, uhi);
+  }
+  if (a.nzflag) {
+    if (__ballot(any != 0ull) != 0ull && lane == 0) atomicOr(a.nzflag, 1u);
+  }
+  if (a.work && tid == 0) {
+    int64_t lo = (int64_t)blk * TW, hi = lo + TW;
+    if (lo < a.qc0) lo = a.qc0;
+    if (hi > a.qc1) hi = a.qc1;
+    const unsigned long long words = hi > lo ? (unsigned long long)(hi - lo) : 0ull;
+    atomicAdd(a.work, (unsigned long long)(re - rb) * words * (unsigned long long)a.kwords * 8ull);
+  }
+}
+
+
 // Narrow product (the next panel's columns): column tiles of 8 words (chunk
 // blockIdx.y of the 8-aligned chunks covering [qc0, qc1)), 64-byte entries
 // (8 words), and a step takes a whole 64-bit A word: eight tables of 256
@@ -778,13 +997,17 @@ __global__ __launch_bounds__(NT) void k_gemm_narrow(GemmArgs a) {
 //  10: four tables with 16-byte lookups, 256 threads, 512-row tiles
 //  11: eight 64-byte-entry tables per step, 256 threads, 256 rows x 8 words
 //  12: eight 64-byte-entry tables per step, 256 threads, 512 rows x 8 words
+//  13: as 7 with the B rows staged in LDS and pipelined lookups, 512 threads, 2048-row tiles
+//  14: as 13, 512 threads, 1024-row tiles
+//  15: as 13, 256 threads, 512-row tiles
+//  16: as 13, 256 threads, 256-row tiles
 // Automatic choice: the largest tile that still gives at least one workgroup
 // per CU for the rows expected to be active; small launches get small tiles.
 int gemm_tile_rows(int v) {
   switch (v) {
-    case 2: case 4: case 7: return 2048;
-    case 5: case 10: case 12: return 512;
-    case 6: case 9: case 11: return 256;
+    case 2: case 4: case 7: case 13: return 2048;
+    case 5: case 10: case 12: case 15: return 512;
+    case 6: case 9: case 11: case 16: return 256;
     default: return 1024;
   }
 }
@@ -797,12 +1020,12 @@ int gemm_auto_variant(int64_t active_rows, int qc0, int qc1, int ncu) {
   const int64_t want = ncu;
   if (gemm_narrow_ok(qc0, qc1)) return (active_rows + 511) / 512 >= want ? 12 : 11;
   const int blocks_y = ((qc1 - 1) >> 4) - (qc0 >> 4) + 1;
-  const int order[4] = {7, 8, 10, 9};
+  const int order[4] = {13, 14, 15, 16};
   for (int i = 0; i < 4; ++i) {
     const int tm = gemm_tile_rows(order[i]);
     if (((active_rows + tm - 1) / tm) * (int64_t)blocks_y >= want) return order[i];
   }
-  return 9;
+  return 16;
 }
 
 hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t s) {
@@ -827,6 +1050,10 @@ hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t 
     case 10: hipLaunchKernelGGL((k_gemm_wide<256, 512>), grid, dim3(256), 0, s, a); break;
     case 11: hipLaunchKernelGGL((k_gemm_narrow<256, 256>), gridn, dim3(256), 0, s, a); break;
     case 12: hipLaunchKernelGGL((k_gemm_narrow<256, 512>), gridn, dim3(256), 0, s, a); break;
+    case 13: hipLaunchKernelGGL((k_gemm_wide2<512, 2048>), grid, dim3(512), 0, s, a); break;
+    case 14: hipLaunchKernelGGL((k_gemm_wide2<512, 1024>), grid, dim3(512), 0, s, a); break;
+    case 15: hipLaunchKernelGGL((k_gemm_wide2<256, 512>), grid, dim3(256), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_gemm_wide2<256, 256>), grid, dim3(256), 0, s, a); break;
     default: hipLaunchKernelGGL((k_gemm_quad<1024, 1024>), grid, dim3(1024), 0, s, a); break;
   }
   return hipGetLastError();

@@ -135,7 +135,9 @@ def test_decompose_panel_width_invariant(g, orc, panel_words):
                                         ("panel_gemm_variant", 6), ("panel_gemm_variant", 7),
                                         ("panel_gemm_variant", 8), ("panel_gemm_variant", 9),
                                         ("panel_gemm_variant", 10), ("panel_gemm_variant", 11),
-                                        ("panel_gemm_variant", 12), ("overlap_lookups", 1200000000),
+                                        ("panel_gemm_variant", 12), ("panel_gemm_variant", 13),
+                                        ("panel_gemm_variant", 14), ("panel_gemm_variant", 15),
+                                        ("panel_gemm_variant", 16), ("overlap_lookups", 1200000000),
                                         ("overlap_lookups", 10 ** 15)])
 def test_decompose_tuning_invariant(g, orc, knob, value):
     """Look-ahead split and product-kernel variant do not change any result."""
@@ -152,7 +154,7 @@ def test_decompose_tuning_invariant(g, orc, knob, value):
     assert_same_ple(got, ref, (knob, value))
 
 
-@pytest.mark.parametrize("variant", list(range(13)))
+@pytest.mark.parametrize("variant", list(range(17)))
 def test_matmul_variants(g, orc, variant):
     n, k, m = 2100, 1300, 2500
     say("matmul variant", variant)
