@@ -69,11 +69,11 @@ PAPER_BITOPS_PER_S = 1.876e14 / 86.156   # paper's best 65536^2 time (Table 4, b
 LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12   # 157.3 TB/s: 256 CUs x 256 B/clk x 2.4 GHz
 # HBM bytes per product launch in this decomposition, from rocprofv3 counters:
 # FETCH_SIZE (KiB per dispatch, x2: a plain 1 GiB copy reads 524305 KiB) and
-# WRITE_SIZE (KiB, x1: the copy reads 1048576 KiB), averaged over the 253
+# WRITE_SIZE (KiB, x1: the copy writes 1048576 KiB), averaged over the 253
 # product launches of one 65536^2 decomposition.  Valid only for the product
 # kernel source they were measured on.
-TRAFFIC = {"kernel_source_sha256": "763d5a591f6203f0e31a3b40564d2f47dfe68f327799030b82e4870e243b17ad",
-           "fetch_bytes": 55133.5 * 2 * 1024, "write_bytes": 87514.3 * 1024}
+TRAFFIC = {"kernel_source_sha256": "0e97829b79d0859a7f92a0109028a0a4dbd94660aa31446057f5825d1f1942d6",
+           "fetch_bytes": 55091.5 * 2 * 1024, "write_bytes": 87507.4 * 1024}
 SEED = 65536
 
 

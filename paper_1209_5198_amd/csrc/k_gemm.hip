@@ -708,14 +708,16 @@ __global__ __launch_bounds__(NT) void k_gemm_wide2(GemmArgs a) {
   stage_b(0);
   if (nh > 1) load_b(1);
   const char *Tb = (const char *)&T[0][0][0][0];
-  // instruction g: odd groups read table g ^ 1 (the other table of the pair)
-  uint32_t lbase[4], sel[4];
-#pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    const int gg = g ^ (G & 1);
-    lbase[g] = ((uint32_t)(gg >> 1) << 16) | ((uint32_t)(gg & 1) << 7) | ((uint32_t)w2 << 4);
-    sel[g] = 0x0C020000u | ((4u + (uint32_t)gg) << 8);  // [lane base | byte gg of A | pair | 0]
-  }
+  // Read g of a row: odd groups read table g ^ 1 (the other table of the
+  // pair), so their A words are staged with the bytes of each half swapped
+  // (byte g of the staged word is then byte g ^ 1 of A) and one selector per
+  // g serves every lane.  The entry address is [half offset | A byte | pair |
+  // 0]: the half offset is byte 0 of lb for even g and byte 3 for odd g, and
+  // the pair is byte 2 of lb (1) for g >= 2 and zero otherwise.
+  const uint32_t h_even = ((uint32_t)(G & 1) << 7) | ((uint32_t)w2 << 4);
+  const uint32_t h_odd = ((uint32_t)((G & 1) ^ 1) << 7) | ((uint32_t)w2 << 4);
+  const uint32_t lb = h_even | (1u << 16) | (h_odd << 24);
+  constexpr uint32_t kSel[4] = {0x0C0C0400u, 0x0C0C0503u, 0x0C020600u, 0x0C020703u};
   for (int hh = 0; hh < nh; ++hh) {
     const int half = hh & 1;
     __syncthreads();  // previous lookups finished: T and As are free; B rows of step hh staged
@@ -724,8 +726,13 @@ __global__ __launch_bounds__(NT) void k_gemm_wide2(GemmArgs a) {
       for (int j = 0; j < APT; ++j) {
         const int64_t i = tile0 + tid + (int64_t)j * NT;
         const uint64_t v = (i >= rb && i < re) ? av[j] : 0ull;
-        As[2 * (tid + j * NT)] = (uint32_t)v;
-        As[2 * (tid + j * NT) + 1] = (uint32_t)(v >> 32);
+        uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+        if (tid & 1) {  // the row is read by an odd group: bytes 0,1 and 2,3 swapped
+          lo = __builtin_amdgcn_perm(lo, lo, 0x02030001u);
+          hi = __builtin_amdgcn_perm(hi, hi, 0x02030001u);
+        }
+        As[2 * (tid + j * NT)] = lo;
+        As[2 * (tid + j * NT) + 1] = hi;
       }
     }
     {
@@ -764,7 +771,7 @@ __global__ __launch_bounds__(NT) void k_gemm_wide2(GemmArgs a) {
 #pragma unroll
       for (int v = 0; v < UB; ++v)
 #pragma unroll
-        for (int g = 0; g < 4; ++g) t[v][g] = *(const uint4 *)(Tb + __builtin_amdgcn_perm(a32[v], lbase[g], sel[g]));
+        for (int g = 0; g < 4; ++g) t[v][g] = *(const uint4 *)(Tb + __builtin_amdgcn_perm(a32[v], lb, kSel[g]));
     };
     auto combine = [&](int u0, const uint4 (&t)[UB][4]) {
 #pragma unroll
