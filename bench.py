@@ -276,6 +276,31 @@ def serving_section(synth, count: int):
     return out
 
 
+# Nominal MI355X figures beside which the microbenchmarks are reported (256 CUs,
+# 2.4 GHz): HBM3E 8 TB/s; 32-bit VALU 128 lanes/clk/CU = 78.6 Tops/s (the lane
+# rate behind the 157.3 TFLOP/s fp32 vector figure); LDS 64 banks x 4 B =
+# 256 B/clk/CU = 157.3 TB/s; dense matrix cores int8 5.0 POPS, fp4 10.1 PFLOP/s
+# (two operations per multiply-accumulate).
+PEAKS = (  # name, kind argument, unit, nominal, scale of the measured rate into the unit
+    ("hbm_read", dict(nbytes=2 << 30), "TB/s", 8.0, 1e-12),
+    ("hbm_copy", dict(nbytes=2 << 30), "TB/s", 8.0, 1e-12),
+    ("valu_xor32", dict(iters=2048), "Tops/s", 78.6, 1e-12),
+    ("lds_read", dict(iters=2048), "TB/s", 157.3, 1e-12),
+    ("mfma_int8", dict(iters=8192), "TOPS", 5000.0, 2e-12),
+    ("mfma_fp4", dict(iters=8192), "TFLOP/s", 10100.0, 2e-12),
+)
+
+
+def peaks_section(gf2):
+    """Measured ceilings of the units the kernels use, beside the nominal figures."""
+    out = {}
+    for name, kw, unit, nominal, scale in PEAKS:
+        rate, ms = gf2.gf2_microbench(name, **kw)
+        v = rate * scale
+        out[name] = {"measured": v, "nominal": nominal, "unit": unit, "frac": v / nominal, "ms": ms}
+    return out
+
+
 def headline_section(args, gf2, synth):
     """The 65536^2 decomposition: timed steps, roofline of the product kernel."""
     import torch
@@ -363,6 +388,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sessions")
     ap.add_argument("--no-configs", action="store_true", help="skip the other single-matrix configurations")
     ap.add_argument("--no-headline", action="store_true", help="skip the 65536^2 decomposition (profiling runs)")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the microbenchmarks of HBM, VALU, LDS, MFMA")
     ap.add_argument("--no-per-matrix", action="store_true",
                     help="skip the one-call-per-matrix comparison of the batched workload")
     ap.add_argument("--serve-count", type=int, default=SERVE_COUNT)
@@ -392,6 +418,9 @@ def main():
         out = {"metric": METRIC, "note": "headline skipped (--no-headline)"}
     else:
         out = headline_section(args, gf2, synth)
+    if not args.no_peaks:
+        print("# unit microbenchmarks", file=sys.stderr, flush=True)
+        out["peaks"] = peaks_section(gf2)
     if not args.no_configs:
         print("# other configurations", file=sys.stderr, flush=True)
         out["configs"] = other_configs(gf2, synth)

@@ -225,6 +225,23 @@ int gf2_set_param(const char *name, int64_t value);
 int gf2_profile(int enable);
 int gf2_profile_read(double *ms, int64_t *launches, double *lookups);
 
+/*
+ * Microbenchmarks of the units the kernels depend on, for comparing measured
+ * ceilings with nominal ones (not part of the decomposition path).  kind:
+ *   0 HBM read of `bytes` (16-byte loads)   -> *rate in bytes/s
+ *   1 HBM copy of bytes/2 into bytes/2      -> bytes/s (read + written)
+ *   2 32-bit VALU exclusive-or, `iters`     -> operations/s (one per lane per instruction)
+ *   3 LDS 16-byte reads, conflict-free      -> bytes/s
+ *   4 int8 matrix cores (32x32x32)          -> multiply-accumulates/s
+ *   5 fp4 (e2m1) matrix cores (32x32x64)    -> multiply-accumulates/s
+ * bytes (kinds 0, 1): a positive multiple of 65536, allocated and freed by the
+ * call; iters (kinds 2..5): 1 .. 2^24 loop trips per thread.  *ms is the mean
+ * time of three launches after one warm-up, HIP events on stream s; the call
+ * synchronizes s.  Returns 0, GF2_EINVAL for a bad kind, size or null output
+ * (nothing launched), or GF2_EHIP / GF2_ENOMEM.
+ */
+int gf2_microbench(int kind, int64_t bytes, int iters, double *rate, double *ms, hipStream_t s);
+
 /* Free the workspace of every device.  Safe to call at any time between calls. */
 int gf2_release(void);
 

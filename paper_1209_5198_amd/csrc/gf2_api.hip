@@ -544,6 +544,50 @@ int gf2_profile_read(double *ms, int64_t *launches, double *lookups) {
   return GF2_OK;
 }
 
+int gf2_microbench(int kind, int64_t bytes, int iters, double *rate, double *ms, hipStream_t s) {
+  if (kind < 0 || kind >= kProbeKinds || !rate || !ms) return fail(GF2_EINVAL, "gf2_microbench: bad kind or null output");
+  if (kind <= 1 && (bytes < 65536 || bytes % 65536 != 0))
+    return fail(GF2_EINVAL, "gf2_microbench: bytes must be a positive multiple of 65536");
+  if (kind >= 2 && (iters < 1 || iters > (1 << 24))) return fail(GF2_EINVAL, "gf2_microbench: iters out of range");
+  const int ncu = device_cus();
+  void *buf = nullptr;
+  uint32_t *sink = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = GF2_OK;
+  do {
+    hipError_t e;
+    if ((e = hipMalloc(&sink, 256)) != hipSuccess) { rc = hip_fail(e, "hipMalloc"); break; }
+    if (kind <= 1 && (e = hipMalloc(&buf, (size_t)bytes)) != hipSuccess) { rc = hip_fail(e, "hipMalloc"); break; }
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+      rc = hip_fail(e, "hipEventCreate");
+      break;
+    }
+    double work = 0.0;
+    constexpr int kReps = 3;
+    if ((e = launch_probe(kind, buf, (size_t)bytes, iters, ncu, sink, s, &work)) != hipSuccess) {  // warm-up
+      rc = hip_fail(e, "launch_probe");
+      break;
+    }
+    if ((e = hipEventRecord(e0, s)) != hipSuccess) { rc = hip_fail(e, "hipEventRecord"); break; }
+    for (int r = 0; r < kReps && e == hipSuccess; ++r) e = launch_probe(kind, buf, (size_t)bytes, iters, ncu, sink, s, &work);
+    if (e != hipSuccess) { rc = hip_fail(e, "launch_probe"); break; }
+    if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) {
+      rc = hip_fail(e, "hipEventSynchronize");
+      break;
+    }
+    float t = 0.f;
+    if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) { rc = hip_fail(e, "hipEventElapsedTime"); break; }
+    *ms = (double)t / kReps;
+    *rate = *ms > 0.0 ? work / (*ms * 1e-3) : 0.0;
+  } while (false);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (buf || sink) (void)hipStreamSynchronize(s);
+  if (buf) (void)hipFree(buf);
+  if (sink) (void)hipFree(sink);
+  return rc;
+}
+
 int gf2_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   int cur = 0;

@@ -114,6 +114,10 @@ hipError_t launch_post(const DecWork &w, int q0, int s_eff, hipStream_t s);
 hipError_t launch_xor(uint64_t *dst, const uint64_t *a, const uint64_t *b, size_t nwords,
                       hipStream_t s);
 hipError_t launch_fill_bits(uint64_t *dst, size_t nwords, uint64_t seed, hipStream_t s);  // timing operands
+// microbenchmarks (k_probe.hip): kinds 0..5, *work = bytes, operations or multiply-accumulates
+constexpr int kProbeKinds = 6;
+hipError_t launch_probe(int kind, void *buf, size_t bytes, int iters, int ncu, uint32_t *sink, hipStream_t s,
+                        double *work);
 
 // A rows x (words) region of a working-layout matrix: word (i, q) at
 // p[((q / 16) * ld + i) * 16 + q % 16].  A quadrant of a view whose words are

@@ -27,8 +27,8 @@ GF2_ENOMEM = -2
 GF2_EHIP = -3
 
 EXPORTED = ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_decompose_batched",
-            "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_autotune", "gf2_autotune_table", "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_release",
-            "gf2_last_error", "gf2_version")
+            "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_autotune", "gf2_autotune_table", "gf2_set_param",
+            "gf2_profile", "gf2_profile_read", "gf2_microbench", "gf2_release", "gf2_last_error", "gf2_version")
 BATCH_MAX_DIM = 2048
 
 
@@ -76,12 +76,15 @@ def load():
         lib.gf2_profile.argtypes = [ctypes.c_int]
         lib.gf2_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                          ctypes.POINTER(ctypes.c_double)]
+        lib.gf2_microbench.argtypes = [ctypes.c_int, i64, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double), vp]
         lib.gf2_release.argtypes = []
         lib.gf2_last_error.restype = ctypes.c_char_p
         lib.gf2_version.restype = ctypes.c_char_p
         for name in ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_decompose_batched",
                      "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_autotune",
-                     "gf2_autotune_table", "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_release"):
+                     "gf2_autotune_table", "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_microbench",
+                     "gf2_release"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -236,6 +239,20 @@ def gf2_profile_read():
     work = ctypes.c_double()
     _check(load().gf2_profile_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(work)))
     return ms.value, n.value, work.value
+
+
+MICROBENCH_KINDS = {"hbm_read": 0, "hbm_copy": 1, "valu_xor32": 2, "lds_read": 3, "mfma_int8": 4, "mfma_fp4": 5}
+
+
+def gf2_microbench(kind, nbytes=0, iters=0, stream=None):
+    """One microbenchmark (name or number, see MICROBENCH_KINDS): returns
+    (rate, ms) -- bytes/s, operations/s or multiply-accumulates/s, and the mean
+    launch time."""
+    k = MICROBENCH_KINDS[kind] if isinstance(kind, str) else int(kind)
+    rate = ctypes.c_double()
+    ms = ctypes.c_double()
+    _check(load().gf2_microbench(k, int(nbytes), int(iters), ctypes.byref(rate), ctypes.byref(ms), _stream(stream)))
+    return rate.value, ms.value
 
 
 def gf2_release() -> None:

@@ -55,6 +55,26 @@ def test_null_descriptor_rejected_without_gpu():
     assert lib.gf2_matmul(None, None, None, 0, None) == gf2.GF2_EINVAL
 
 
+def test_microbench_validation_without_gpu():
+    """Bad kinds, sizes and trip counts are rejected before anything touches the device."""
+    import ctypes
+
+    from paper_1209_5198_amd import gf2
+
+    lib = gf2.load()
+    rate, ms = ctypes.c_double(), ctypes.c_double()
+    r, t = ctypes.byref(rate), ctypes.byref(ms)
+    assert lib.gf2_microbench(-1, 0, 1, r, t, None) == gf2.GF2_EINVAL
+    assert lib.gf2_microbench(6, 0, 1, r, t, None) == gf2.GF2_EINVAL
+    assert lib.gf2_microbench(0, 1000, 0, r, t, None) == gf2.GF2_EINVAL    # not a multiple of 64 KiB
+    assert lib.gf2_microbench(1, 0, 0, r, t, None) == gf2.GF2_EINVAL       # empty copy
+    assert lib.gf2_microbench(2, 0, 0, r, t, None) == gf2.GF2_EINVAL       # no trips
+    assert lib.gf2_microbench(5, 0, 1 << 25, r, t, None) == gf2.GF2_EINVAL
+    assert lib.gf2_microbench(3, 0, 1, None, t, None) == gf2.GF2_EINVAL
+    assert b"gf2_microbench" in lib.gf2_last_error()
+    assert set(gf2.MICROBENCH_KINDS.values()) == set(range(6))
+
+
 def test_blocked_layout_matches_section3_example():
     """The Section 3 example stores the 4 x 2 word matrix column-major
     (5 1 3 4 | 3 2 1 3).  With b = 64 the same rule is the layout with w = 1:
