@@ -232,6 +232,24 @@ def other_configs(gf2, synth, reps: int = 5):
     ms = timed(lambda: gf2.gf2_matmul(C, A, B, False, stream))
     out["matmul_16384"] = {"ms": ms, "bitops_per_s": 2.0 * n ** 3 / (ms / 1e3)}
     del A, B, C
+    # products whose output is too small for the table kernels to fill the chip:
+    # the automatic choice is the fp4 matrix-core product; beside it the
+    # Four-Russians kernel the automatic rule would otherwise take (256-row tiles)
+    for (n, k, m) in ((8192, 8192, 8192), (4096, 16384, 4096)):
+        A = gf2.Mat.from_rowmajor(synth.dense(8192, 4, n, k), n, k)
+        B = gf2.Mat.from_rowmajor(synth.dense(8192, 5, k, m), k, m)
+        C = gf2.Mat.zeros(n, m)
+        ms = timed(lambda: gf2.gf2_matmul(C, A, B, False, stream))
+        ref = C.t.clone()
+        gf2.gf2_set_param("gemm_variant", 16)
+        try:
+            ms_fr = timed(lambda: gf2.gf2_matmul(C, A, B, False, stream))
+        finally:
+            gf2.gf2_set_param("gemm_variant", -1)
+        same = bool(torch.equal(ref, C.t))
+        out[f"matmul_{n}x{k}x{m}"] = {"ms": ms, "bitops_per_s": 2.0 * n * k * m / (ms / 1e3), "kernel": "fp4 MFMA",
+                                      "ms_four_russians": ms_fr, "identical": same}
+        del A, B, C, ref
     nr, r, m = 32768, 20000, 65536
     X, Y = synth.planted(20000, 9, nr, m, r)
     A = gf2.matmul(gf2.Mat.from_rowmajor(X, nr, r), gf2.Mat.from_rowmajor(Y, r, m), stream=stream)

@@ -201,7 +201,10 @@ int gf2_autotune_table(int32_t *variants, int64_t *strassen_cutoff);
  *   "strassen_cutoff"    : gf2_matmul recurses with Strassen-Winograd (one level
  *                          per halving) while every dimension of the current
  *                          product is at least this many bits (default 65536; 0 = never)
- *   "gemm_variant"       : product-kernel variant for gf2_matmul (-1 = automatic)
+ *   "gemm_variant"       : product-kernel variant for gf2_matmul (-1 = automatic;
+ *                          0..16 Four-Russians kernels, 17 the fp4 matrix-core
+ *                          product, chosen automatically when k >= 1024 and the
+ *                          output has fewer 1024 x 1024 tiles than the device has CUs)
  *   "panel_gemm_variant" : product-kernel variant for the trailing update (-1 = automatic)
  *   "chain_cus"          : CUs reserved for the pivot chain through CU-masked
  *                          streams (0 = two unmasked streams, the default)

@@ -238,12 +238,23 @@ int run_gemm(GemmArgs &a, int64_t nrows_max, int variant, int64_t active_rows, h
     const int blocks = ((a.qc1 - 1) >> 4) - (a.qc0 >> 4) + 1;
     variant = g_tuned[tune_row_class(active_rows)][tune_block_class(blocks)];
   }
-  if (variant < 0) variant = gemm_auto_variant(active_rows, a.qc0, a.qc1, device_cus());
+  if (variant < 0 || variant >= kGemmVariants) variant = gemm_auto_variant(active_rows, a.qc0, a.qc1, device_cus());
   hipEvent_t e0 = nullptr;
   int rc = profile_begin(s, &e0);
   if (rc) return rc;
   a.work = g_prof.on ? g_prof.work_dev : nullptr;
   HIPCHK(launch_gemm(a, nrows_max, variant, s));
+  return profile_end(s, e0);
+}
+
+// The fp4 matrix-core product for a plain B of bwords words per row; Bt is
+// mfma_bt_bytes(a.kwords, bwords) bytes of workspace.
+int run_gemm_mfma(GemmArgs &a, int64_t bwords, uint64_t *Bt, hipStream_t s) {
+  hipEvent_t e0 = nullptr;
+  int rc = profile_begin(s, &e0);
+  if (rc) return rc;
+  a.work = g_prof.on ? g_prof.work_dev : nullptr;
+  HIPCHK(launch_gemm_mfma(a, bwords, Bt, s));
   return profile_end(s, e0);
 }
 
@@ -481,7 +492,7 @@ int gf2_set_param(const char *name, int64_t value) {
     return GF2_OK;
   }
   if (!strcmp(name, "gemm_variant")) {
-    if (value < -1 || value >= kGemmVariants) return fail(GF2_EINVAL, "gemm_variant out of range");
+    if (value < -1 || value > kGemmMfma) return fail(GF2_EINVAL, "gemm_variant out of range");
     g_gemm_variant = (int)value;
     return GF2_OK;
   }
@@ -810,8 +821,15 @@ int gf2_matmul(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B, int accumul
   const size_t ba = align256((size_t)NBa * lda * TW * 8), bb = align256((size_t)NBb * ldb * TW * 8),
                bc = align256((size_t)NBb * lda * TW * 8);
   const size_t bs = depth ? strassen_bytes(np, NBa * TW, NBb * TW, depth) : 0;
+  // the fp4 matrix-core product when forced, or automatically where the table
+  // kernels cannot fill the chip with 1024-row tiles and the inner dimension is
+  // long enough to amortise its transpose and epilogue (measured crossover)
+  const bool mfma = depth == 0 && k > 0 &&
+                    (g_gemm_variant == kGemmMfma ||
+                     (g_gemm_variant < 0 && k >= 1024 && ceil_div(n, 1024) * ceil_div(m, 1024) < device_cus()));
+  const size_t bt = mfma ? align256(mfma_bt_bytes(Kw, Mw)) : 0;
   void *ws = nullptr;
-  if ((rc = get_workspace(s, ba + bb + bc + bs, &ws))) return rc;
+  if ((rc = get_workspace(s, ba + bb + bc + bs + bt, &ws))) return rc;
   uint64_t *Aw = (uint64_t *)ws, *Bw = (uint64_t *)((char *)ws + ba), *Cw = (uint64_t *)((char *)ws + ba + bb);
   HIPCHK(launch_pack(*A, Aw, lda, n, k, (int32_t)NBa, s));
   HIPCHK(launch_pack(*B, Bw, ldb, k, m, (int32_t)NBb, s));
@@ -830,7 +848,11 @@ int gf2_matmul(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B, int accumul
     a.kwords = (int32_t)Kw;
     a.qc0 = 0; a.qc1 = (int32_t)Mw;
     a.accumulate = accumulate ? 1 : 0;
-    if ((rc = run_gemm(a, n, g_gemm_variant, n, s))) return rc;
+    if (mfma) {
+      if ((rc = run_gemm_mfma(a, Mw, (uint64_t *)((char *)ws + ba + bb + bc), s))) return rc;
+    } else if ((rc = run_gemm(a, n, g_gemm_variant, n, s))) {
+      return rc;
+    }
   } else {
     HIPCHK(hipMemsetAsync(Cw, 0, bc, s));
   }

@@ -154,7 +154,7 @@ def test_decompose_tuning_invariant(g, orc, knob, value):
     assert_same_ple(got, ref, (knob, value))
 
 
-@pytest.mark.parametrize("variant", list(range(17)))
+@pytest.mark.parametrize("variant", list(range(18)))
 def test_matmul_variants(g, orc, variant):
     n, k, m = 2100, 1300, 2500
     say("matmul variant", variant)
@@ -167,6 +167,40 @@ def test_matmul_variants(g, orc, variant):
     finally:
         g.gf2_set_param("gemm_variant", -1)
     assert np.array_equal(C.to_rowmajor(), ref)
+
+
+@pytest.mark.parametrize("n,k,m,acc", [(1, 1, 1, False), (1, 1, 1, True), (300, 64, 500, True), (257, 130, 1025, False),
+                                        (2100, 1300, 2500, True), (64, 4100, 70, False), (1030, 2049, 1100, True),
+                                        (513, 192, 4097, False), (4096, 4096, 4096, True)])
+def test_matmul_mfma(g, orc, n, k, m, acc):
+    """The fp4 matrix-core product (gemm_variant 17): ragged shapes, one to many
+    inner words, with and without accumulation, against the oracle's product."""
+    say("matmul mfma", n, k, m, acc)
+    A = synth.dense(25, 1, n, k)
+    B = synth.dense(25, 2, k, m)
+    C0 = synth.dense(25, 3, n, m) if acc else None
+    ref = orc.matmul(A, B, n, k, m, C=C0) if acc else orc.matmul(A, B, n, k, m)
+    g.gf2_set_param("gemm_variant", 17)
+    try:
+        if acc:
+            Cg = g.Mat.from_rowmajor(C0, n, m)
+            g.gf2_matmul(Cg, g.Mat.from_rowmajor(A, n, k), g.Mat.from_rowmajor(B, k, m), accumulate=True)
+        else:
+            Cg = g.matmul(g.Mat.from_rowmajor(A, n, k), g.Mat.from_rowmajor(B, k, m))
+    finally:
+        g.gf2_set_param("gemm_variant", -1)
+    assert np.array_equal(Cg.to_rowmajor(), ref)
+
+
+@pytest.mark.parametrize("n,k,m", [(2100, 1300, 2500), (5000, 1024, 3000), (300, 3000, 17000)])
+def test_matmul_automatic_mfma(g, orc, n, k, m):
+    """Shapes the automatic rule sends to the fp4 matrix-core product (k >= 1024,
+    fewer 1024 x 1024 output tiles than CUs) against the oracle."""
+    say("matmul automatic (fp4)", n, k, m)
+    A = synth.dense(26, 1, n, k)
+    B = synth.dense(26, 2, k, m)
+    C = g.matmul(g.Mat.from_rowmajor(A, n, k), g.Mat.from_rowmajor(B, k, m))
+    assert np.array_equal(C.to_rowmajor(), orc.matmul(A, B, n, k, m))
 
 
 @pytest.mark.parametrize("variant", [-1, 11, 12])
