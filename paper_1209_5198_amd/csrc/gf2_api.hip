@@ -247,14 +247,14 @@ int run_gemm(GemmArgs &a, int64_t nrows_max, int variant, int64_t active_rows, h
   return profile_end(s, e0);
 }
 
-// The fp4 matrix-core product for a plain B of bwords words per row; Bt is
-// mfma_bt_bytes(a.kwords, bwords) bytes of workspace.
-int run_gemm_mfma(GemmArgs &a, int64_t bwords, uint64_t *Bt, hipStream_t s) {
+// The fp4 matrix-core product for a plain B of bwords words per row; ws is
+// mfma_ws_bytes(a.kwords, bwords, rows) bytes of workspace.
+int run_gemm_mfma(GemmArgs &a, int64_t bwords, uint64_t *ws, hipStream_t s) {
   hipEvent_t e0 = nullptr;
   int rc = profile_begin(s, &e0);
   if (rc) return rc;
   a.work = g_prof.on ? g_prof.work_dev : nullptr;
-  HIPCHK(launch_gemm_mfma(a, bwords, Bt, s));
+  HIPCHK(launch_gemm_mfma(a, bwords, ws, s));
   return profile_end(s, e0);
 }
 
@@ -827,7 +827,7 @@ int gf2_matmul(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B, int accumul
   const bool mfma = depth == 0 && k > 0 &&
                     (g_gemm_variant == kGemmMfma ||
                      (g_gemm_variant < 0 && k >= 1024 && ceil_div(n, 1024) * ceil_div(m, 1024) < device_cus()));
-  const size_t bt = mfma ? align256(mfma_bt_bytes(Kw, Mw)) : 0;
+  const size_t bt = mfma ? align256(mfma_ws_bytes(Kw, Mw, n)) : 0;
   void *ws = nullptr;
   if ((rc = get_workspace(s, ba + bb + bc + bs + bt, &ws))) return rc;
   uint64_t *Aw = (uint64_t *)ws, *Bw = (uint64_t *)((char *)ws + ba), *Cw = (uint64_t *)((char *)ws + ba + bb);

@@ -5,21 +5,26 @@
 // becomes an e2m1 value, 1.0 or 0.0, so one v_mfma_scale_f32_32x32x64_f8f6f4
 // (unit scales) adds 64 products per output exactly in fp32 (sums stay far below
 // 2^24), and the parity of the integer-valued result is the output bit.
-//   k_bt_transpose  B (K x m, column-blocked) -> Bt[kw][j]: word kw of column j
-//                   of B, i.e. one 64 x 64 bit transpose per wave (a butterfly
-//                   of six exchange steps across lanes).
-//   k_gemm_mfma     512 threads own 256 rows x 4 output words.  Per stage of two
-//                   64-bit inner words each thread expands one A row or one Bt
-//                   column into 2 x 32 bytes of fp4 in LDS (two buffers, one
-//                   barrier per stage); wave w runs 2 x 4 x 2 MFMAs of
-//                   32 x 32 x 64 on rows 128 (w / 4) .. +127, output word w % 4,
-//                   and expands the next stage while they execute.
-//                   Operand layout of the instruction: lane l holds row (or
-//                   column) l % 32 and inner indices 32 (l / 32) .. +31, one
-//                   nibble each in order; output register r of lane l is row
-//                   8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
-//                   At the end a ballot of the low bit of each register yields
-//                   32 columns of two rows at once, already bit-packed.
+//
+// Operand layout of the instruction: lane l holds row (or column) l % 32 and 32
+// of the 64 inner indices (half l / 32 of a word), eight per register as
+// nibbles; output register r of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4,
+// column l % 32.
+//
+// Both operands are first repacked into "quad" layout: for every group of four
+// inner words, entry (row, half) holds that half of the four words as one
+// 16-byte vector, and the 32 rows x 2 halves a wave needs for one fragment are
+// 1 KB of consecutive bytes.
+//   k_at_pack   A (column-blocked)          -> At4[kq][row][half]
+//   k_bt_pack   B (column-blocked, K x m)   -> Bt4[kq][column][half]: one 64 x 64
+//               bit transpose per inner word (a butterfly of six exchange steps
+//               across lanes), four words per wave.
+//   k_gemm_mfma every wave owns 128 rows x one output word (4 x 2 MFMAs per
+//               inner word) and builds its own fragments: one 16-byte load per
+//               fragment and quad, spread into four registers per word, loads
+//               kQuadsAhead quads ahead.  No LDS and no workgroup barrier.
+//               At the end a ballot of the low bit of each register yields 32
+//               columns of two rows at once, already bit-packed.
 #include "gf2_internal.h"
 
 namespace gf2 {
@@ -32,13 +37,12 @@ namespace {
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-// Bits 0..7 of x -> nibbles 0..7 holding e2m1 1.0 (0b0010) or 0.0.
-__device__ inline uint32_t spread8(uint32_t x) {
-  x &= 0xFFu;
-  x = (x | (x << 12)) & 0x000F000Fu;
-  x = (x | (x << 6)) & 0x03030303u;
-  x = (x | (x << 3)) & 0x11111111u;
-  return x << 1;
+// The 32 bits of x -> four registers of eight e2m1 nibbles (0b0010 = 1.0 or
+// 0.0): register r, nibble j holds bit 4 j + r.  The inner sum runs over all
+// indices of a word in any order, so rows of A and columns of B need only share
+// the placement.
+__device__ inline uint4 spread32(uint32_t x) {
+  return make_uint4((x << 1) & 0x22222222u, x & 0x22222222u, (x >> 1) & 0x22222222u, (x >> 2) & 0x22222222u);
 }
 
 __device__ inline uint64_t shfl_xor64(uint64_t x, int m) {
@@ -62,63 +66,84 @@ __device__ inline uint64_t transpose64(uint64_t x, int lane) {
   return x;
 }
 
-__global__ __launch_bounds__(256) void k_bt_transpose(const uint64_t *B, int64_t ldB, int64_t b_rows, int64_t bwords,
-                                                      uint64_t *Bt, int64_t mpad, int kwords) {
+constexpr int kQuadsAhead = 2;  // raw quads in flight per fragment (loads run this many quads ahead)
+constexpr int kWR = 2, kWC = 2;   // waves per workgroup: row groups x output words
+constexpr int kMThreads = 64 * kWR * kWC, kMRows = 128 * kWR;
+
+// Wave (kq, q): words 4 kq .. 4 kq + 3 of the 64 rows 64 w .. of B (column word
+// q), transposed; lane j then holds column 64 q + j and writes its two halves
+// of the four words.  Rows past the operand and words past bwords are zero.
+__global__ __launch_bounds__(256) void k_bt_pack(const uint64_t *B, int64_t ldB, int64_t b_rows, int64_t bwords,
+                                                 uint4 *Bt4, int64_t mpad, int kqp) {
   const int lane = threadIdx.x & 63;
   const int64_t nq = mpad / 64;
   const int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (blk >= (int64_t)kwords * nq) return;  // whole waves
-  const int64_t kw = blk / nq, q = blk % nq;
-  const int64_t row = 64 * kw + lane;
-  const uint64_t x = (row < b_rows && q < bwords) ? B[widx(ldB, row, q)] : 0ull;
-  Bt[kw * mpad + 64 * q + lane] = transpose64(x, lane);
+  if (blk >= (int64_t)kqp * nq) return;  // whole waves
+  const int64_t kq = blk / nq, q = blk % nq;
+  uint32_t lo[4], hi[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t row = 64 * (4 * kq + u) + lane;
+    const uint64_t x = (row < b_rows && q < bwords) ? B[widx(ldB, row, q)] : 0ull;
+    const uint64_t t = transpose64(x, lane);
+    lo[u] = (uint32_t)t;
+    hi[u] = (uint32_t)(t >> 32);
+  }
+  uint4 *dst = Bt4 + 2 * (kq * mpad + 64 * q + lane);
+  dst[0] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+  dst[1] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
 }
 
-constexpr int kMT = 512;   // threads
-constexpr int kMRows = 256;  // rows per tile
-constexpr int kMWords = 4;   // output words per tile
+// Thread (kq, r): words 4 kq .. 4 kq + 3 of row row0 + r of A into At4, for
+// kq < kqp and r < npad.  Four consecutive threads take four consecutive quads
+// of one row (128 contiguous bytes of a column block).  Rows past the operand
+// repeat its last row (their results are never stored); words from kwords on
+// are zero.
+__global__ __launch_bounds__(256) void k_at_pack(const uint64_t *A, int64_t ldA, int64_t a_word0, int64_t row0,
+                                                 int kwords, uint4 *At4, int64_t npad, int kqp) {
+  const int64_t nb = (kqp + 3) / 4, total = 4 * nb * npad;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t rest = e >> 2, r = rest % npad, kq = 4 * (rest / npad) + (e & 3);
+    if (kq >= kqp) continue;
+    int64_t row = row0 + r;
+    row = row < ldA ? row : ldA - 1;
+    uint32_t lo[4], hi[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t kw = 4 * kq + u;
+      const uint64_t x = kw < kwords ? A[widx(ldA, row, a_word0 + kw)] : 0ull;
+      lo[u] = (uint32_t)x;
+      hi[u] = (uint32_t)(x >> 32);
+    }
+    uint4 *dst = At4 + 2 * (kq * npad + r);
+    dst[0] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+    dst[1] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+  }
+}
 
-__global__ __launch_bounds__(kMT) void k_gemm_mfma(GemmArgs a, const uint64_t *Bt, int64_t mpad) {
-  constexpr int KS = 2;                   // inner words per stage (one barrier each)
-  __shared__ uint4 As[2][KS][kMRows][2];  // fp4 rows of A: 32 bytes per row and inner word
-  __shared__ uint4 Bs[2][KS][kMRows][2];  // fp4 columns of B
+// Wave w of a workgroup: rows 128 (w / kWC) .. +127 of its kMRows, output word
+// w % kWC of its kWC.  kqp (a multiple of kQuadsAhead) quads of At4 and Bt4 are
+// valid, npad and mpad their row and column extents.  Two waves per SIMD (the
+// 128 accumulators stay in ordinary registers).
+__global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm_mfma(
+    GemmArgs a, const uint4 *At4, int64_t npad, const uint4 *Bt4, int64_t mpad, int kqp) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wr = wv >> 2, wc = wv & 3, h = lane >> 5, li = lane & 31;
-  const int hs = h ^ ((li >> 3) & 1);  // the slot of half h in this lane's rows (row bit 3 = li bit 3)
-  const int64_t r0 = a.row_tile0 + (int64_t)blockIdx.x * kMRows;
-  const int64_t w0 = (int64_t)(a.qc0 & ~(kMWords - 1)) + (int64_t)kMWords * blockIdx.y;  // first output word
-  const int nk = a.kwords, ns = (nk + KS - 1) / KS;
-
-  // the words this thread expands: A row r0 + tid (tid < 256) or column
-  // 64 w0 + tid - 256 of B (rows past the operand read a clamped row; their
-  // results are never stored; inner words past the operand are zero)
-  const bool isA = tid < kMRows;
-  const int item = tid & (kMRows - 1);
-  int64_t arow = r0 + item;
-  arow = arow < a.ldA ? arow : a.ldA - 1;
-  const uint64_t *bsrc = Bt + 64 * w0 + item;
-  // (inner words past the operand read the last word and are zeroed, without a branch)
-  auto load = [&](int st, uint64_t (&x)[KS]) {
+  const int h = lane >> 5, li = lane & 31;
+  const int64_t rw = a.row_tile0 + (int64_t)blockIdx.x * kMRows + 128 * (wv / kWC);            // first row
+  const int64_t q = (int64_t)(a.qc0 / kWC) * kWC + (int64_t)kWC * blockIdx.y + (wv % kWC);  // output word
+  const uint4 *ap = At4 + 2 * (rw - a.row_tile0 + li) + h, *bp = Bt4 + 2 * (64 * q + li) + h;
+  auto load = [&](int kq, uint4 (&ra)[4], uint4 (&rb)[2]) {
+    const int64_t kc = kq < kqp ? kq : kqp - 1;  // (past the end: a valid quad nobody uses)
 #pragma unroll
-    for (int u = 0; u < KS; ++u) {
-      const int kw = KS * st + u, kc = kw < nk ? kw : nk - 1;
-      const uint64_t v = isA ? a.A[widx(a.ldA, arow, a.a_word0 + kc)] : bsrc[(int64_t)kc * mpad];
-      x[u] = kw < nk ? v : 0ull;
-    }
-  };
-  // Half h (inner indices 32 h .. 32 h + 31) of row t sits in slot h ^ ((t >> 3) & 1):
-  // rows t and t + 8 then use opposite 16-byte halves, so the sixteen lanes of
-  // every 16-byte access (sixteen consecutive rows, one half) cover all 64 banks.
-  const int sw = (item >> 3) & 1;
-  auto expand = [&](const uint64_t (&x)[KS], int buf) {
+    for (int i = 0; i < 4; ++i) ra[i] = ap[2 * kc * npad + 64 * i];
 #pragma unroll
-    for (int u = 0; u < KS; ++u) {
-      const uint32_t lo = (uint32_t)x[u], hi = (uint32_t)(x[u] >> 32);
-      uint4 *dst = isA ? &As[buf][u][item][0] : &Bs[buf][u][item][0];
-      dst[sw] = make_uint4(spread8(lo), spread8(lo >> 8), spread8(lo >> 16), spread8(lo >> 24));
-      dst[sw ^ 1] = make_uint4(spread8(hi), spread8(hi >> 8), spread8(hi >> 16), spread8(hi >> 24));
-    }
+    for (int j = 0; j < 2; ++j) rb[j] = bp[2 * kc * mpad + 64 * j];
   };
+  auto frag = [](uint32_t x) -> v8i {
+    const uint4 v = spread32(x);
+    return v8i{(int)v.x, (int)v.y, (int)v.z, (int)v.w, 0, 0, 0, 0};
+  };
+  auto comp = [](const uint4 &v, int u) -> uint32_t { return u == 0 ? v.x : u == 1 ? v.y : u == 2 ? v.z : v.w; };
 
   v16f acc[4][2];
 #pragma unroll
@@ -126,51 +151,35 @@ __global__ __launch_bounds__(kMT) void k_gemm_mfma(GemmArgs a, const uint64_t *B
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v16f{};
 
-  uint64_t xa[KS], xb[KS];  // stages st + 1 and st + 2
-  {
-    uint64_t x0[KS];
-    load(0, x0);
-    load(1, xa);
-    load(2, xb);
-    expand(x0, 0);
+  uint4 ra[kQuadsAhead][4], rb[kQuadsAhead][2];
+#pragma unroll
+  for (int d = 0; d < kQuadsAhead; ++d) {
+    load(d, ra[d], rb[d]);
+    __builtin_amdgcn_sched_barrier(0);  // issue in the loop's order, so the waits at its head stay partial
   }
-  __syncthreads();
-  for (int st = 0; st < ns; ++st) {
-    const int cur = st & 1;
-    // fragments of stage st (complete since the last barrier), their MFMAs, and
-    // then, while the matrix cores work, the next stage's expansion into the
-    // other buffer (last read before the previous barrier)
-    v8i fa[KS][4], fb[KS][2];
+  for (int g0 = 0; g0 < kqp; g0 += kQuadsAhead) {
 #pragma unroll
-    for (int u = 0; u < KS; ++u) {
+    for (int d = 0; d < kQuadsAhead; ++d) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint4 v = As[cur][u][128 * wr + 32 * i + li][hs];
-        fa[u][i] = v8i{(int)v.x, (int)v.y, (int)v.z, (int)v.w, 0, 0, 0, 0};
-      }
+      for (int u = 0; u < 4; ++u) {
+        v8i fa[4], fb[2];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const uint4 v = Bs[cur][u][64 * wc + 32 * j + li][hs];
-        fb[u][j] = v8i{(int)v.x, (int)v.y, (int)v.z, (int)v.w, 0, 0, 0, 0};
+        for (int i = 0; i < 4; ++i) fa[i] = frag(comp(ra[d][i], u));
+#pragma unroll
+        for (int k = 0; k < 2; ++k) fb[k] = frag(comp(rb[d][k], u));
+        if (u == 3) load(g0 + d + kQuadsAhead, ra[d], rb[d]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int k = 0; k < 2; ++k)
+            acc[i][k] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[i], fb[k], acc[i][k], 4, 4, 0, 127, 0, 127);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
-#pragma unroll
-    for (int u = 0; u < KS; ++u)
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[u][i], fb[u][j], acc[i][j], 4, 4, 0, 127, 0,
-                                                                      127);
-    expand(xa, cur ^ 1);  // (after the last stage: zeros nobody reads)
-#pragma unroll
-    for (int u = 0; u < KS; ++u) xa[u] = xb[u];
-    load(st + 3, xb);
-    __syncthreads();
   }
 
-  // parity bits: register r of block (i, j) holds rows 8 (r / 4) + r % 4 (lanes
-  // 0..31) and + 4 (lanes 32..63) of rows 32 i.., columns 32 j + lane % 32.
+  // parity bits: register r of block (i, k) holds rows 8 (r / 4) + r % 4 (lanes
+  // 0..31) and + 4 (lanes 32..63) of rows 32 i.., columns 32 k + lane % 32.
   // Row t of this wave's 128 rows goes to lane t % 64 of word pair t / 64.
   int wlo[2] = {0, 0}, whi[2] = {0, 0};
 #pragma unroll
@@ -185,12 +194,11 @@ __global__ __launch_bounds__(kMT) void k_gemm_mfma(GemmArgs a, const uint64_t *B
       wlo[tb >> 6] = gf2_mfma_writelane((int)(uint32_t)(b0 >> 32), tb & 63, wlo[tb >> 6]);
       whi[tb >> 6] = gf2_mfma_writelane((int)(uint32_t)(b1 >> 32), tb & 63, whi[tb >> 6]);
     }
-  const int64_t q = w0 + wc;
   uint64_t any = 0ull;
   if (q >= a.qc0 && q < a.qc1) {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-      const int64_t row = r0 + 128 * wr + 64 * p + lane;
+      const int64_t row = rw + 64 * p + lane;
       if (row < a.row_end) {
         uint64_t v = ((uint64_t)(uint32_t)whi[p] << 32) | (uint32_t)wlo[p];
         uint64_t *cp = a.C + widx(a.ldC, row, q);
@@ -203,38 +211,44 @@ __global__ __launch_bounds__(kMT) void k_gemm_mfma(GemmArgs a, const uint64_t *B
   if (a.nzflag) {
     if (__ballot(any != 0ull) != 0ull && lane == 0) atomicOr(a.nzflag, 1u);
   }
-  if (a.work && tid == 0) {
-    int64_t re = r0 + kMRows < a.row_end ? r0 + kMRows : a.row_end;
-    int64_t lo = w0, hi = w0 + kMWords;
-    if (lo < a.qc0) lo = a.qc0;
-    if (hi > a.qc1) hi = a.qc1;
-    const unsigned long long words = hi > lo ? (unsigned long long)(hi - lo) : 0ull;
-    if (re > r0) atomicAdd(a.work, (unsigned long long)(re - r0) * words * (unsigned long long)nk * 8ull);
+  if (a.work && lane == 0 && q >= a.qc0 && q < a.qc1) {
+    const int64_t re = rw + 128 < a.row_end ? rw + 128 : a.row_end;
+    if (re > rw) atomicAdd(a.work, (unsigned long long)(re - rw) * (unsigned long long)a.kwords * 8ull);
   }
 }
 
+int64_t quads_padded(int64_t kwords) {
+  const int64_t kq = (kwords > 0 ? kwords + 3 : 4) / 4;
+  return (kq + kQuadsAhead - 1) / kQuadsAhead * kQuadsAhead;
+}
+int64_t cols_padded(int64_t words) { return (words + kWC - 1) / kWC * kWC * 64; }
+int64_t rows_padded(int64_t rows) { return (rows + kMRows - 1) / kMRows * kMRows; }
+
 }  // namespace
 
-size_t mfma_bt_bytes(int64_t kwords, int64_t m_words) {
-  const int64_t mpad = ((m_words + kMWords - 1) / kMWords) * kMWords * 64;
-  return (size_t)(kwords > 0 ? kwords : 1) * (size_t)mpad * 8;
+size_t mfma_ws_bytes(int64_t kwords, int64_t m_words, int64_t rows) {
+  const int64_t kqp = quads_padded(kwords);
+  return (size_t)kqp * (size_t)(cols_padded(m_words) + rows_padded(rows)) * 32;
 }
 
-// C (^)= A * B with plain B (a.bsub == nullptr), Bt a workspace of
-// mfma_bt_bytes(a.kwords, words of B) bytes.
-hipError_t launch_gemm_mfma(const GemmArgs &a, int64_t bwords, uint64_t *Bt, hipStream_t s) {
+// C (^)= A * B with plain B (a.bsub == nullptr) on the matrix cores; ws is a
+// workspace of mfma_ws_bytes(a.kwords, bwords, a.row_end - a.row_tile0) bytes
+// (Bt4 first, then At4; both are whole multiples of 32 bytes per quad row).
+hipError_t launch_gemm_mfma(const GemmArgs &a, int64_t bwords, uint64_t *ws, hipStream_t s) {
   if (a.bsub || a.qc1 <= a.qc0 || a.row_end <= a.row_tile0) return a.bsub ? hipErrorInvalidValue : hipSuccess;
-  const int64_t mpad = ((int64_t)((a.qc1 + kMWords - 1) / kMWords) * kMWords) * 64;
-  const int64_t mpad_b = ((bwords + kMWords - 1) / kMWords) * kMWords * 64;
-  const int64_t mp = mpad > mpad_b ? mpad : mpad_b;
-  const int64_t blocks = ((int64_t)(a.kwords > 0 ? a.kwords : 1) * (mp / 64) + 3) / 4;
-  if (a.kwords > 0)
-    hipLaunchKernelGGL(k_bt_transpose, dim3((unsigned)blocks), dim3(256), 0, s, a.B, a.ldB, a.b_rows, bwords, Bt, mp,
-                       a.kwords);
-  const int64_t rows = a.row_end - a.row_tile0;
-  const int64_t tiles_r = (rows + kMRows - 1) / kMRows;
-  const int64_t tiles_c = ((a.qc1 - 1) / kMWords) - (a.qc0 / kMWords) + 1;
-  hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)tiles_r, (unsigned)tiles_c), dim3(kMT), 0, s, a, (const uint64_t *)Bt, mp);
+  const int64_t mp_c = cols_padded(a.qc1), mp_b = cols_padded(bwords);
+  const int64_t mp = mp_c > mp_b ? mp_c : mp_b;
+  const int64_t kqp = quads_padded(a.kwords);
+  const int64_t rows = a.row_end - a.row_tile0, npad = rows_padded(rows);
+  uint4 *Bt4 = (uint4 *)ws, *At4 = Bt4 + 2 * kqp * mp;
+  const int64_t tw = (kqp * (mp / 64) + 3) / 4;
+  hipLaunchKernelGGL(k_bt_pack, dim3((unsigned)tw), dim3(256), 0, s, a.B, a.ldB, a.b_rows, bwords, Bt4, mp, (int)kqp);
+  const int64_t ta = ((kqp + 3) / 4 * 4 * npad + 255) / 256;
+  hipLaunchKernelGGL(k_at_pack, dim3((unsigned)(ta < 16384 ? ta : 16384)), dim3(256), 0, s, a.A, a.ldA,
+                     (int64_t)a.a_word0, a.row_tile0, a.kwords, At4, npad, (int)kqp);
+  const int64_t tiles_c = ((a.qc1 - 1) / kWC) - (a.qc0 / kWC) + 1;
+  hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)(npad / kMRows), (unsigned)tiles_c), dim3(kMThreads), 0, s, a,
+                     (const uint4 *)At4, npad, (const uint4 *)Bt4, mp, (int)kqp);
   return hipGetLastError();
 }
 
