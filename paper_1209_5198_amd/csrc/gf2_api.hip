@@ -254,7 +254,7 @@ int run_gemm_mfma(GemmArgs &a, int64_t bwords, uint64_t *ws, hipStream_t s) {
   int rc = profile_begin(s, &e0);
   if (rc) return rc;
   a.work = g_prof.on ? g_prof.work_dev : nullptr;
-  HIPCHK(launch_gemm_mfma(a, bwords, ws, s));
+  HIPCHK(launch_gemm_mfma(a, bwords, ws, device_cus(), s));
   return profile_end(s, e0);
 }
 
@@ -849,6 +849,10 @@ int gf2_matmul(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B, int accumul
     a.qc0 = 0; a.qc1 = (int32_t)Mw;
     a.accumulate = accumulate ? 1 : 0;
     if (mfma) {
+      if (!accumulate && mfma_splits_inner(a, device_cus())) {  // split inner dimension: XORs into a zeroed C
+        HIPCHK(hipMemsetAsync(Cw, 0, bc, s));
+        a.accumulate = 1;
+      }
       if ((rc = run_gemm_mfma(a, Mw, (uint64_t *)((char *)ws + ba + bb + bc), s))) return rc;
     } else if ((rc = run_gemm(a, n, g_gemm_variant, n, s))) {
       return rc;

@@ -108,7 +108,8 @@ hipError_t launch_finish(const DecWork &w, int64_t *perm, int64_t *pivcols, int6
 constexpr int kGemmVariants = 17;  // product-kernel variants 0 .. kGemmVariants-1
 constexpr int kGemmMfma = 17;      // gf2_matmul only: the fp4 matrix-core product (k_mfma.hip)
 size_t mfma_ws_bytes(int64_t kwords, int64_t m_words, int64_t rows);  // its workspace
-hipError_t launch_gemm_mfma(const GemmArgs &a, int64_t bwords, uint64_t *ws, hipStream_t s);
+bool mfma_splits_inner(const GemmArgs &a, int ncu);  // the launch splits the inner dimension
+hipError_t launch_gemm_mfma(const GemmArgs &a, int64_t bwords, uint64_t *ws, int ncu, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int variant, hipStream_t s);
 int gemm_auto_variant(int64_t active_rows, int qc0, int qc1, int ncu);  // variant for a launch shape
 

@@ -125,12 +125,19 @@ __global__ __launch_bounds__(256) void k_at_pack(const uint64_t *A, int64_t ldA,
 // w % kWC of its kWC.  kqp (a multiple of kQuadsAhead) quads of At4 and Bt4 are
 // valid, npad and mpad their row and column extents.  Two waves per SIMD (the
 // 128 accumulators stay in ordinary registers).
+// Split inner dimension: workgroup z takes quads [z * per, (z + 1) * per) (per a
+// multiple of kQuadsAhead) and, when gridDim.z > 1, XORs its parity words into
+// C with atomics -- the parity of a sum is the XOR of the parities of its parts.
+// C then has to hold its initial value (zero for a plain product) and nzflag
+// is not supported.
 __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm_mfma(
-    GemmArgs a, const uint4 *At4, int64_t npad, const uint4 *Bt4, int64_t mpad, int kqp) {
+    GemmArgs a, const uint4 *At4, int64_t npad, const uint4 *Bt4, int64_t mpad, int kqp, int per) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int h = lane >> 5, li = lane & 31;
   const int64_t rw = a.row_tile0 + (int64_t)blockIdx.x * kMRows + 128 * (wv / kWC);            // first row
   const int64_t q = (int64_t)(a.qc0 / kWC) * kWC + (int64_t)kWC * blockIdx.y + (wv % kWC);  // output word
+  const int kq0 = (int)blockIdx.z * per, kq1 = kq0 + per < kqp ? kq0 + per : kqp;
+  const bool split = gridDim.z > 1;
   const uint4 *ap = At4 + 2 * (rw - a.row_tile0 + li) + h, *bp = Bt4 + 2 * (64 * q + li) + h;
   auto load = [&](int kq, uint4 (&ra)[4], uint4 (&rb)[2]) {
     const int64_t kc = kq < kqp ? kq : kqp - 1;  // (past the end: a valid quad nobody uses)
@@ -154,10 +161,10 @@ __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(2))) 
   uint4 ra[kQuadsAhead][4], rb[kQuadsAhead][2];
 #pragma unroll
   for (int d = 0; d < kQuadsAhead; ++d) {
-    load(d, ra[d], rb[d]);
+    load(kq0 + d, ra[d], rb[d]);
     __builtin_amdgcn_sched_barrier(0);  // issue in the loop's order, so the waits at its head stay partial
   }
-  for (int g0 = 0; g0 < kqp; g0 += kQuadsAhead) {
+  for (int g0 = kq0; g0 < kq1; g0 += kQuadsAhead) {
 #pragma unroll
     for (int d = 0; d < kQuadsAhead; ++d) {
 #pragma unroll
@@ -202,9 +209,13 @@ __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(2))) 
       if (row < a.row_end) {
         uint64_t v = ((uint64_t)(uint32_t)whi[p] << 32) | (uint32_t)wlo[p];
         uint64_t *cp = a.C + widx(a.ldC, row, q);
-        if (a.accumulate) v ^= *cp;
-        *cp = v;
-        any |= v;
+        if (split) {
+          atomicXor((unsigned long long *)cp, (unsigned long long)v);
+        } else {
+          if (a.accumulate) v ^= *cp;
+          *cp = v;
+          any |= v;
+        }
       }
     }
   }
@@ -213,7 +224,8 @@ __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(2))) 
   }
   if (a.work && lane == 0 && q >= a.qc0 && q < a.qc1) {
     const int64_t re = rw + 128 < a.row_end ? rw + 128 : a.row_end;
-    if (re > rw) atomicAdd(a.work, (unsigned long long)(re - rw) * (unsigned long long)a.kwords * 8ull);
+    const int w1 = 4 * kq1 < a.kwords ? 4 * kq1 : a.kwords, words = w1 - 4 * kq0;
+    if (re > rw && words > 0) atomicAdd(a.work, (unsigned long long)(re - rw) * (unsigned long long)words * 8ull);
   }
 }
 
@@ -224,7 +236,26 @@ int64_t quads_padded(int64_t kwords) {
 int64_t cols_padded(int64_t words) { return (words + kWC - 1) / kWC * kWC * 64; }
 int64_t rows_padded(int64_t rows) { return (rows + kMRows - 1) / kMRows * kMRows; }
 
+// Quads per split of the inner dimension (== kqp: no split).  Split while the
+// tiles fill fewer than the device's two resident workgroups per CU, down to
+// four quads (16 inner words) per split.
+int64_t split_quads(const GemmArgs &a, int ncu) {
+  const int64_t kqp = quads_padded(a.kwords);
+  if (a.nzflag || ncu <= 0) return kqp;
+  const int64_t tiles = (rows_padded(a.row_end - a.row_tile0) / kMRows) * (((a.qc1 - 1) / kWC) - (a.qc0 / kWC) + 1);
+  int64_t splits = 2ll * ncu / (tiles > 0 ? tiles : 1);
+  if (splits > kqp / 4) splits = kqp / 4;
+  if (splits < 2) return kqp;
+  const int64_t per = (kqp + splits - 1) / splits;
+  return (per + kQuadsAhead - 1) / kQuadsAhead * kQuadsAhead;
+}
+
 }  // namespace
+
+bool mfma_splits_inner(const GemmArgs &a, int ncu) {
+  if (a.bsub || a.qc1 <= a.qc0 || a.row_end <= a.row_tile0) return false;
+  return split_quads(a, ncu) < quads_padded(a.kwords);
+}
 
 size_t mfma_ws_bytes(int64_t kwords, int64_t m_words, int64_t rows) {
   const int64_t kqp = quads_padded(kwords);
@@ -234,7 +265,10 @@ size_t mfma_ws_bytes(int64_t kwords, int64_t m_words, int64_t rows) {
 // C (^)= A * B with plain B (a.bsub == nullptr) on the matrix cores; ws is a
 // workspace of mfma_ws_bytes(a.kwords, bwords, a.row_end - a.row_tile0) bytes
 // (Bt4 first, then At4; both are whole multiples of 32 bytes per quad row).
-hipError_t launch_gemm_mfma(const GemmArgs &a, int64_t bwords, uint64_t *ws, hipStream_t s) {
+// When mfma_splits_inner(a, ncu) holds, the inner dimension is split and C must
+// already hold its initial value: a plain product needs a zeroed C and
+// a.accumulate set.
+hipError_t launch_gemm_mfma(const GemmArgs &a, int64_t bwords, uint64_t *ws, int ncu, hipStream_t s) {
   if (a.bsub || a.qc1 <= a.qc0 || a.row_end <= a.row_tile0) return a.bsub ? hipErrorInvalidValue : hipSuccess;
   const int64_t mp_c = cols_padded(a.qc1), mp_b = cols_padded(bwords);
   const int64_t mp = mp_c > mp_b ? mp_c : mp_b;
@@ -247,8 +281,9 @@ hipError_t launch_gemm_mfma(const GemmArgs &a, int64_t bwords, uint64_t *ws, hip
   hipLaunchKernelGGL(k_at_pack, dim3((unsigned)(ta < 16384 ? ta : 16384)), dim3(256), 0, s, a.A, a.ldA,
                      (int64_t)a.a_word0, a.row_tile0, a.kwords, At4, npad, (int)kqp);
   const int64_t tiles_c = ((a.qc1 - 1) / kWC) - (a.qc0 / kWC) + 1;
-  hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)(npad / kMRows), (unsigned)tiles_c), dim3(kMThreads), 0, s, a,
-                     (const uint4 *)At4, npad, (const uint4 *)Bt4, mp, (int)kqp);
+  const int64_t per = split_quads(a, ncu), nz = (kqp + per - 1) / per;
+  hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)(npad / kMRows), (unsigned)tiles_c, (unsigned)nz), dim3(kMThreads), 0,
+                     s, a, (const uint4 *)At4, npad, (const uint4 *)Bt4, mp, (int)kqp, (int)per);
   return hipGetLastError();
 }
 

@@ -171,10 +171,14 @@ def test_matmul_variants(g, orc, variant):
 
 @pytest.mark.parametrize("n,k,m,acc", [(1, 1, 1, False), (1, 1, 1, True), (300, 64, 500, True), (257, 130, 1025, False),
                                         (2100, 1300, 2500, True), (64, 4100, 70, False), (1030, 2049, 1100, True),
-                                        (513, 192, 4097, False), (4096, 4096, 4096, True)])
+                                        (513, 192, 4097, False), (4096, 4096, 4096, True),
+                                        (512, 32768, 640, True), (700, 20000, 900, False)])
 def test_matmul_mfma(g, orc, n, k, m, acc):
     """The fp4 matrix-core product (gemm_variant 17): ragged shapes, one to many
-    inner words, with and without accumulation, against the oracle's product."""
+    inner words, with and without accumulation, against the oracle's product.
+    Few output tiles with a long inner dimension split it across workgroups
+    (64 x 4100 x 70: 3 parts, 1030 x 2049 x 1100: 2, 512 x 32768 x 640: 32,
+    700 x 20000 x 900: 20), whose parity words are XORed into C."""
     say("matmul mfma", n, k, m, acc)
     A = synth.dense(25, 1, n, k)
     B = synth.dense(25, 2, k, m)
