@@ -95,32 +95,45 @@ hipError_t launch_unpack(const uint64_t *W, int64_t ldw, const gf2_mat &dst, hip
   return hipGetLastError();
 }
 
-// E (kmin x m): row t < rank = working row t with the bits left of its pivot cleared
+// E (kmin x m): row t < rank = working row t with the bits left of its pivot
+// cleared.  Thread x of the grid owns word column q and takes the rows
+// blockIdx.y + gridDim.y * (4 k + j), four at a time (their loads issued
+// before any store): no index division, and each row's pivot column is one
+// broadcast read.
 __global__ void k_extract_E(DecWork w, gf2_mat E) {
-  const int64_t Mw = w.Mw;
-  const int64_t total = E.rows * Mw;
-  const int64_t rank = w.st->R;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
-    const int64_t t = e / Mw;
-    const int64_t q = e - t * Mw;
-    uint64_t v = 0;
-    if (t < rank) {
-      const int64_t pc = w.pivcols[t];
-      const int64_t qt = pc >> 6;
-      if (q > qt) v = w.W[widx(w.ldw, t, q)];
-      else if (q == qt) v = w.W[widx(w.ldw, t, q)] & (~0ull << (pc & 63));
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= w.Mw) return;
+  const int64_t rank = w.st->R, gy = gridDim.y;
+  const uint64_t pad = pad_mask(E.cols, q);
+  for (int64_t t0 = blockIdx.y; t0 < E.rows; t0 += 4 * gy) {
+    uint64_t v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t t = t0 + j * gy;
+      v[j] = 0;
+      if (t < rank) {
+        const int64_t pc = w.pivcols[t];
+        const int64_t qt = pc >> 6;
+        if (q >= qt) v[j] = w.W[widx(w.ldw, t, q)] & (q > qt ? ~0ull : (~0ull << (pc & 63)));
+      }
     }
-    E.data[uidx(E.w, E.ld, t, q)] = v & pad_mask(E.cols, q);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t t = t0 + j * gy;
+      if (t < E.rows) E.data[uidx(E.w, E.ld, t, q)] = v[j] & pad;
+    }
   }
 }
 
+// grid for a (words x rows) extraction: 256 word columns per workgroup, rows
+// spread over at most 4096 workgroup rows
+static dim3 extract_grid(int64_t words, int64_t rows) {
+  const int64_t gx = (words + 255) / 256, gy = rows < 4096 ? (rows > 0 ? rows : 1) : 4096;
+  return dim3((unsigned)(gx > 0 ? gx : 1), (unsigned)gy);
+}
+
 hipError_t launch_extract_E(const DecWork &w, const gf2_mat &E, hipStream_t s) {
-  int64_t total = E.rows * (int64_t)w.Mw;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_extract_E, dim3((unsigned)blocks), dim3(256), 0, s, w, E);
+  hipLaunchKernelGGL(k_extract_E, extract_grid(w.Mw, E.rows), dim3(256), 0, s, w, E);
   return hipGetLastError();
 }
 
@@ -136,46 +149,83 @@ __device__ inline int find_sub(const SubInfo *sub, int Mw, int64_t t) {
 
 // L (n x kmin): column t < rank of L is bit (t - R_q) of word q of the working
 // matrix (q = sub-panel of pivot t), below the diagonal; 1 on it; 0 above.
+// Thread x of the grid owns word column u of L.  It lists once the sub-panel
+// segments of its 64 columns (columns [cs, ce) are bits cs - R_q .. of word q;
+// at most kSeg of them, else the general walk per row), then takes the rows
+// blockIdx.y + gridDim.y * (4 k + j), four at a time.
+constexpr int kSeg = 4;
 __global__ void k_extract_L(DecWork w, gf2_mat L) {
   const int64_t Lw = (L.cols + 63) / 64;
-  const int64_t total = L.rows * Lw;
-  const int64_t rank = w.st->R;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
-    const int64_t i = e / Lw;
-    const int64_t u = e - i * Lw;
-    const int64_t t0 = 64 * u;
-    int64_t tend = t0 + 64;
-    if (tend > rank) tend = rank;
-    if (i < rank && tend > i) tend = i;  // strictly below the diagonal
-    uint64_t out = 0;
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= Lw) return;
+  const int64_t rank = w.st->R, gy = gridDim.y;
+  const int64_t t0 = 64 * u;
+  const int64_t tcols = t0 + 64 < rank ? t0 + 64 : rank;  // columns of this word that hold pivots
+  const int q_first = t0 < tcols ? find_sub(w.sub, w.Mw, t0) : 0;
+  const uint64_t pad = pad_mask(L.cols, u);
+  int nseg = 0, segq[kSeg];
+  int64_t segs[kSeg], sege[kSeg], segR[kSeg];
+  {
     int64_t t = t0;
-    if (t < tend) {
-      int q = find_sub(w.sub, w.Mw, t);
-      while (t < tend) {
-        while (q < w.Mw && (w.sub[q].r == 0 || w.sub[q].R + w.sub[q].r <= t)) ++q;
-        if (q >= w.Mw) break;
-        const int64_t Rq = w.sub[q].R;
-        const int64_t end = Rq + w.sub[q].r < tend ? Rq + w.sub[q].r : tend;
-        const int nb = (int)(end - t);
-        const uint64_t word = w.W[widx(w.ldw, i, q)] >> (t - Rq);
-        const uint64_t mask = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
-        out |= (word & mask) << (t - t0);
-        t = end;
-        ++q;
-      }
+    int q = q_first;
+    while (t < tcols) {
+      while (q < w.Mw && (w.sub[q].r == 0 || w.sub[q].R + w.sub[q].r <= t)) ++q;
+      if (q >= w.Mw) break;
+      if (nseg == kSeg) { nseg = -1; break; }
+      const int64_t Rq = w.sub[q].R, end = Rq + w.sub[q].r < tcols ? Rq + w.sub[q].r : tcols;
+      segq[nseg] = q; segs[nseg] = t; sege[nseg] = end; segR[nseg] = Rq; ++nseg;
+      t = end;
+      ++q;
     }
-    if (i < rank && i >= t0 && i < t0 + 64) out |= 1ull << (i - t0);  // unit diagonal
-    L.data[uidx(L.w, L.ld, i, u)] = out & pad_mask(L.cols, u);
+  }
+  for (int64_t i0 = blockIdx.y; i0 < L.rows; i0 += 4 * gy) {
+    uint64_t out[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t i = i0 + j * gy;
+      int64_t tend = tcols;
+      if (i < rank && tend > i) tend = i;  // strictly below the diagonal
+      uint64_t o = 0;
+      if (i < L.rows && nseg >= 0) {
+#pragma unroll
+        for (int k = 0; k < kSeg; ++k) {
+          if (k < nseg && segs[k] < tend) {
+            const int64_t end = sege[k] < tend ? sege[k] : tend;
+            const int nb = (int)(end - segs[k]);
+            const uint64_t word = w.W[widx(w.ldw, i, segq[k])] >> (segs[k] - segR[k]);
+            const uint64_t mask = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
+            o |= (word & mask) << (segs[k] - t0);
+          }
+        }
+      } else if (i < L.rows) {  // more segments than kSeg: walk the sub-panels
+        int64_t t = t0;
+        int q = q_first;
+        while (t < tend) {
+          while (q < w.Mw && (w.sub[q].r == 0 || w.sub[q].R + w.sub[q].r <= t)) ++q;
+          if (q >= w.Mw) break;
+          const int64_t Rq = w.sub[q].R;
+          const int64_t end = Rq + w.sub[q].r < tend ? Rq + w.sub[q].r : tend;
+          const int nb = (int)(end - t);
+          const uint64_t word = w.W[widx(w.ldw, i, q)] >> (t - Rq);
+          const uint64_t mask = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
+          o |= (word & mask) << (t - t0);
+          t = end;
+          ++q;
+        }
+      }
+      if (i < rank && i >= t0 && i < t0 + 64) o |= 1ull << (i - t0);  // unit diagonal
+      out[j] = o;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t i = i0 + j * gy;
+      if (i < L.rows) L.data[uidx(L.w, L.ld, i, u)] = out[j] & pad;
+    }
   }
 }
 
 hipError_t launch_extract_L(const DecWork &w, const gf2_mat &L, hipStream_t s) {
-  int64_t total = L.rows * ((L.cols + 63) / 64);
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_extract_L, dim3((unsigned)blocks), dim3(256), 0, s, w, L);
+  hipLaunchKernelGGL(k_extract_L, extract_grid((L.cols + 63) / 64, L.rows), dim3(256), 0, s, w, L);
   return hipGetLastError();
 }
 

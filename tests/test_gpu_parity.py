@@ -263,6 +263,22 @@ def test_decompose_special(g, orc):
             assert_same_ple(got, ref, (name, n, m, k))
 
 
+@pytest.mark.parametrize("s", [2, 5, 21])
+def test_decompose_spread_pivots(g, orc, s):
+    """Only every s-th column is nonzero, so a sub-panel holds about 64 / s
+    pivots and a 64-column word of L gathers its columns from about s
+    sub-panels (2: the listed-segment path of the L extraction; 5 and 21: more
+    segments than it lists, the per-row walk)."""
+    n, m = 1500, 3000
+    say("spread pivots", s)
+    bits = orc.unpack_bits(synth.dense(40 + s, 1, n, m), m)
+    bits[:, np.arange(m) % s != 0] = 0
+    A = orc.pack_bits(bits)
+    ref = orc.ple(A, n, m)
+    got = gpu_decompose(g, A, n, m)
+    assert_same_ple(got, ref, s)
+
+
 @pytest.mark.parametrize("w", [1, 2, 5])
 def test_decompose_input_layouts(g, orc, w):
     n, m = 900, 1000
