@@ -18,6 +18,8 @@ Functions (each cites the passage it follows; see ``gf2_oracle.c``):
 * :func:`solve`  -- A*x = b through the decomposition, free variables zero.
 * :func:`nullspace` -- null space basis read off the reduced row echelon form
                     (back-substitution of the echelon rows), Section 1's use.
+* :func:`inverse` -- the inverse of a square matrix from its definition
+                    A*X = I (Gauss-Jordan elimination of [A | I]).
 * :func:`pack_bits` / :func:`unpack_bits` -- the b-bit packing of Section 3
   (a_ij is bit r of word q, j = q*b + r), for any b <= 64.
 """
@@ -61,6 +63,8 @@ def _load():
         lib.or_solve.restype = i64
         lib.or_nullspace.argtypes = [i64, i64, p64, p64, p64]
         lib.or_nullspace.restype = i64
+        lib.or_inverse.argtypes = [i64, p64, p64]
+        lib.or_inverse.restype = i64
         lib.or_num_threads.argtypes = []
         lib.or_num_threads.restype = ctypes.c_int
         lib.or_set_threads.argtypes = [ctypes.c_int]
@@ -162,6 +166,20 @@ def nullspace(A, n: int, m: int):
     if k < 0:
         raise MemoryError("oracle nullspace: out of memory")
     return dict(N=N[:k], R=R[:kmin], nullity=int(k))
+
+
+def inverse(A, n: int):
+    """Inverse of a square A (n x n) by Gauss-Jordan elimination of [A | I].
+
+    Returns dict(X (n x wpr(n), zero when singular), invertible (bool)).
+    """
+    lib = _load()
+    A = _check(A, n, n)
+    X = np.zeros((max(n, 1), wpr(n)), dtype=np.uint64)
+    r = lib.or_inverse(n, _u64(A), _u64(X))
+    if r < 0:
+        raise MemoryError("oracle inverse: out of memory")
+    return dict(X=X[:n], invertible=bool(r))
 
 
 def rank(A, n: int, m: int) -> int:

@@ -28,6 +28,10 @@
  *               introduction: rank, systems): y = L_top^{-1} (P b)_top,
  *               consistent iff L_bot*y = (P b)_bot, x the solution whose
  *               non-pivot (free) variables are zero.
+ *  - or_inverse: the inverse of a square non-singular matrix over F2 (Section
+ *               4.3 builds it for the pivot blocks; here for a whole matrix)
+ *               from its definition A*X = I, by Gauss-Jordan elimination of
+ *               [A | I].
  *
  * No blocking, tables or reordering beyond what those definitions state.
  * The optional OpenMP loop only splits the independent row reductions of one
@@ -186,6 +190,42 @@ int64_t or_nullspace(int64_t n, int64_t m, const uint64_t *A, uint64_t *N, uint6
   }
   free(E); free(piv); free(is_piv);
   return m - r;
+}
+
+/* Inverse of a square A (n x n): X with A*X = I, from its definition by
+ * Gauss-Jordan elimination of [A | I]: for each column c in order, the first
+ * row at or below c with bit c set is exchanged into row c and every other row
+ * with bit c set is reduced by it; A is singular when some column has no such
+ * row.  Then [A | I] has become [I | X].
+ *   X : out, n x n, wpr(n) words per row; all zero when A is singular
+ * Returns 1 (invertible), 0 (singular) or -1 on allocation failure. */
+int64_t or_inverse(int64_t n, const uint64_t *A, uint64_t *X) {
+  const int64_t wn = wpr_of(n), w2 = wpr_of(2 * n);
+  uint64_t *M = (uint64_t *)calloc((size_t)(n * w2 + 1), sizeof(uint64_t));
+  if (!M) return -1;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t c = 0; c < n; ++c)
+      if (getbit(A + i * wn, c)) setbit(M + i * w2, c);
+    setbit(M + i * w2, n + i);
+  }
+  int64_t ok = 1;
+  for (int64_t c = 0; c < n && ok; ++c) {
+    int64_t p = c;
+    while (p < n && !getbit(M + p * w2, c)) ++p;
+    if (p == n) { ok = 0; break; }
+    swap_rows(M, w2, c, p);
+    const uint64_t *pr = M + c * w2;
+    for (int64_t i = 0; i < n; ++i)
+      if (i != c && getbit(M + i * w2, c))
+        for (int64_t j = 0; j < w2; ++j) M[i * w2 + j] ^= pr[j];
+  }
+  memset(X, 0, (size_t)(n * wn) * sizeof(uint64_t));
+  if (ok)
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t c = 0; c < n; ++c)
+        if (getbit(M + i * w2, n + c)) setbit(X + i * wn, c);
+  free(M);
+  return ok;
 }
 
 /* C = A*B (accumulate = 0) or C ^= A*B (accumulate != 0).

@@ -417,3 +417,44 @@ def test_nullspace_structure_and_rref(orc, n, m, kind):
     assert np.array_equal(Nb[:, free], np.eye(len(free), dtype=np.uint8))
     R = to_bits(res["R"], m)
     assert np.array_equal(R[:r], Rref) and not np.any(R[r:])
+
+
+# ---------------------------------------------------------------- inverse
+@pytest.mark.parametrize("n", [1, 2, 5, 63, 64, 65, 130])
+def test_inverse_closed_form(orc, n):
+    """The upper triangular all-ones matrix has inverse I + (the superdiagonal):
+    row i of U is the sum of e_i .. e_{n-1}, so e_i = U_i + U_{i+1}."""
+    U = orc.pack_bits(np.triu(np.ones((n, n), np.uint8)))
+    res = orc.inverse(U, n)
+    assert res["invertible"]
+    assert np.array_equal(to_bits(res["X"], n), np.eye(n, dtype=np.uint8) + np.eye(n, k=1, dtype=np.uint8))
+
+
+@pytest.mark.parametrize("n", [3, 40, 64, 97])
+def test_inverse_of_permutation_is_transpose(orc, n):
+    """A permutation matrix is orthogonal: its inverse is its transpose."""
+    p = np.random.default_rng(n).permutation(n)
+    P = np.eye(n, dtype=np.uint8)[p]
+    res = orc.inverse(orc.pack_bits(P), n)
+    assert res["invertible"] and np.array_equal(to_bits(res["X"], n), P.T)
+
+
+@pytest.mark.parametrize("n,seed", [(8, 1), (50, 2), (64, 3), (129, 4), (200, 5)])
+def test_inverse_definition_and_singularity(orc, n, seed):
+    """A*X = X*A = I (numpy integer products mod 2) exactly when the independent
+    Gauss-Jordan rank is n; singular matrices report so and give X = 0."""
+    A = synth.dense(seed, 50, n, n)
+    Ab = to_bits(A, n)
+    res = orc.inverse(A, n)
+    full = len(rref(Ab)[1]) == n
+    assert res["invertible"] == full
+    X = to_bits(res["X"], n)
+    if full:
+        eye = np.eye(n, dtype=np.uint8)
+        assert np.array_equal(gf2_mul(Ab, X), eye) and np.array_equal(gf2_mul(X, Ab), eye)
+    else:
+        assert not np.any(X)
+    # a repeated row makes any matrix singular
+    Ab[n - 1] = Ab[0] if n > 1 else 0
+    res = orc.inverse(orc.pack_bits(Ab), n)
+    assert not res["invertible"] and not np.any(res["X"])
