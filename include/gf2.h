@@ -121,6 +121,17 @@ int gf2_rref(const gf2_mat *A, const gf2_mat *R, int64_t *pivcols, int64_t *rank
 int gf2_nullspace(const gf2_mat *A, const gf2_mat *N, int64_t *nullity, void *stream);
 
 /*
+ * Inverse of a square A (n x n, n >= 1) over GF(2): X (n x n, caller
+ * allocated) with A*X = X*A = I.  Section 4.3 builds such inverses for the
+ * pivot blocks; here the whole matrix is done as the reduced echelon form of
+ * [A | I] (the decomposition of the n x 2n matrix, then the upward elimination
+ * of gf2_rref), which is [I | A^-1] exactly when A is invertible.
+ * invertible: optional device uint64, set to 1 or 0.  A singular A gives X = 0.
+ * Errors: GF2_EINVAL for a non-square or empty A or a mis-shaped X.
+ */
+int gf2_inverse(const gf2_mat *A, const gf2_mat *X, uint64_t *invertible, void *stream);
+
+/*
  * ---------------------------------------------------------------- batches
  * Many independent matrices of at most GF2_BATCH_MAX_DIM rows and columns,
  * each of its own shape, factored (and solved) in one launch.  The matrices

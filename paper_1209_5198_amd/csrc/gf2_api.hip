@@ -334,14 +334,17 @@ int chain(DecWork &w, int q0, int s_eff, int flag_q0, hipStream_t s) {
 // test of a panel's chain reads the flag of the panel two steps back, the last
 // one whose trailing update is certainly complete.  Returns with `user` ordered
 // after all the work.
-int factor(const gf2_mat *A, DecWork &w, hipStream_t user) {
+// identity_right: the matrix factored is [A | I] (w sized for A->cols + A->rows
+// columns, A square), the augmented form the inverse is read from.
+int factor(const gf2_mat *A, DecWork &w, hipStream_t user, bool identity_right = false) {
   Pipe *P = nullptr;
   int rc = get_pipe(user, &P);
   if (rc) return rc;
   hipStream_t G = P->gemm, Cs = P->chain;
   if ((rc = link(P, user, G))) return rc;
   HIPCHK(launch_init_state(w, G));
-  HIPCHK(launch_pack(*A, w.W, w.ldw, w.n, w.m, w.NB, G));
+  HIPCHK(launch_pack(*A, w.W, w.ldw, w.n, A->cols, w.NB, G));
+  if (identity_right) HIPCHK(launch_set_identity(w.W, w.ldw, w.n, A->cols, G));
   const int S = g_panel_words;
   int prev = -1;
   if (g_chain_cus == 0) {
@@ -424,8 +427,11 @@ struct RrefWork {
   int64_t Mw = 0, NBE = 0, Gw = 0;
 };
 
-int rref_run(const gf2_mat *A, hipStream_t s, RrefWork &rw) {
-  const int64_t n = A->rows, m = A->cols, kmin = n < m ? n : m;
+// augment: reduce [A | I] instead of A (A square), for the inverse
+int rref_run(const gf2_mat *A, hipStream_t s, RrefWork &rw, bool augment = false) {
+  gf2_mat shape = *A;
+  if (augment) shape.cols = A->cols + A->rows;
+  const int64_t n = shape.rows, m = shape.cols, kmin = n < m ? n : m;
   rw.Mw = ceil_div(m, 64);
   rw.ldE = ceil_div(kmin, 256) * 256;
   rw.NBE = ceil_div(rw.Mw, TW);
@@ -436,7 +442,7 @@ int rref_run(const gf2_mat *A, hipStream_t s, RrefWork &rw) {
                bM = align256((size_t)(rw.Mw + 1) * 8), bF = align256((size_t)(m + 1) * 8);
   DecWork w;
   void *extra = nullptr;
-  int rc = prepare_decomp(A, s, w, bE + bG + bB + bI + 2 * bM + bF + 256, &extra);
+  int rc = prepare_decomp(&shape, s, w, bE + bG + bB + bI + 2 * bM + bF + 256, &extra);
   if (rc) return rc;
   char *p = (char *)extra;
   rw.E = (uint64_t *)p; p += bE;
@@ -447,7 +453,7 @@ int rref_run(const gf2_mat *A, hipStream_t s, RrefWork &rw) {
   rw.tw0 = (int64_t *)p; p += bM;
   rw.freecols = (int64_t *)p; p += bF;
   rw.rank = (int64_t *)p;
-  if ((rc = factor(A, w, s))) return rc;
+  if ((rc = factor(A, w, s, augment))) return rc;
   HIPCHK(launch_finish(w, nullptr, rw.piv, rw.rank, s));
   const gf2_mat Em{rw.E, kmin, m, TW, rw.ldE};
   HIPCHK(launch_extract_E(w, Em, s));
@@ -1136,6 +1142,19 @@ int gf2_rref(const gf2_mat *A, const gf2_mat *R, int64_t *pivcols, int64_t *rank
   if (R) HIPCHK(launch_unpack(rw.E, rw.ldE, *R, s));
   if (pivcols) HIPCHK(hipMemcpyAsync(pivcols, rw.piv, (size_t)kmin * 8, hipMemcpyDeviceToDevice, s));
   if (rank) HIPCHK(hipMemcpyAsync(rank, rw.rank, 8, hipMemcpyDeviceToDevice, s));
+  return GF2_OK;
+}
+
+int gf2_inverse(const gf2_mat *A, const gf2_mat *X, uint64_t *invertible, void *stream) {
+  int rc;
+  if ((rc = check_mat(A, "A")) || (rc = check_mat(X, "X"))) return rc;
+  const int64_t n = A->rows;
+  if (n == 0 || A->cols != n) return fail(GF2_EINVAL, "gf2_inverse: A must be square and not empty");
+  if (X->rows != n || X->cols != n) return fail(GF2_EINVAL, "gf2_inverse: X must be n x n");
+  hipStream_t s = (hipStream_t)stream;
+  RrefWork rw;
+  if ((rc = rref_run(A, s, rw, true))) return rc;
+  HIPCHK(launch_inverse_out(rw.E, rw.ldE, rw.piv, n, *X, invertible, s));
   return GF2_OK;
 }
 

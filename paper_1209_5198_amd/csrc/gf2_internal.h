@@ -198,5 +198,8 @@ hipError_t launch_copy_block_rows(const uint64_t *E, int64_t ldE, const int64_t 
 hipError_t launch_null_basis(const uint64_t *R, int64_t ldE, const int64_t *pivcols, const int64_t *rankp,
                              uint64_t *bitmap, int64_t *tw0, int64_t *freecols, int64_t *nullity,
                              const gf2_mat &N, hipStream_t s);
+hipError_t launch_set_identity(uint64_t *W, int64_t ldw, int64_t n, int64_t col0, hipStream_t s);
+hipError_t launch_inverse_out(const uint64_t *R, int64_t ldE, const int64_t *pivcols, int64_t n, const gf2_mat &X,
+                              uint64_t *invertible, hipStream_t s);
 
 }  // namespace gf2

@@ -227,7 +227,48 @@ inline unsigned grid_for(size_t total, int threads) {
   return (unsigned)b;
 }
 
+// OR the identity into columns col0 .. col0 + n - 1 of rows 0 .. n - 1 of the
+// working layout (one bit per row, so no two threads share a word)
+__global__ void k_set_identity(uint64_t *W, int64_t ldw, int64_t n, int64_t col0) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = col0 + i;
+    W[widx(ldw, i, c >> 6)] |= 1ull << (c & 63);
+  }
+}
+
+// The reduced echelon form R of [A | I] (n x 2n) is [I | A^-1] exactly when A is
+// invertible, i.e. when the last of the n pivots lies left of column n.  Then X
+// = columns n .. 2n - 1 of R, else X = 0; *invertible (optional) gets 1 or 0.
+__global__ void k_inverse_out(const uint64_t *R, int64_t ldE, const int64_t *pivcols, int64_t n, gf2_mat X,
+                              uint64_t *invertible) {
+  const bool inv = pivcols[n - 1] < n;
+  if (invertible && blockIdx.x == 0 && threadIdx.x == 0) *invertible = inv ? 1ull : 0ull;
+  const int64_t Xw = (n + 63) / 64, Rw = (2 * n + 63) / 64, total = n * Xw;
+  const int sh = (int)(n & 63);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / Xw, q = e - i * Xw, wd = (n >> 6) + q;
+    uint64_t v = 0ull;
+    if (inv) {
+      v = R[widx(ldE, i, wd)] >> sh;
+      if (sh && wd + 1 < Rw) v |= R[widx(ldE, i, wd + 1)] << (64 - sh);
+    }
+    X.data[uidx(X.w, X.ld, i, q)] = v & pad_mask(n, q);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_set_identity(uint64_t *W, int64_t ldw, int64_t n, int64_t col0, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_identity, dim3(grid_for((size_t)n, 256)), dim3(256), 0, s, W, ldw, n, col0);
+  return hipGetLastError();
+}
+
+hipError_t launch_inverse_out(const uint64_t *R, int64_t ldE, const int64_t *pivcols, int64_t n, const gf2_mat &X,
+                              uint64_t *invertible, hipStream_t s) {
+  const size_t total = (size_t)n * (size_t)((n + 63) / 64);
+  hipLaunchKernelGGL(k_inverse_out, dim3(grid_for(total, 256)), dim3(256), 0, s, R, ldE, pivcols, n, X, invertible);
+  return hipGetLastError();
+}
 
 hipError_t launch_gather_pivcols(const uint64_t *E, int64_t ldE, const int64_t *pivcols, const int64_t *rankp,
                                  uint64_t *G, int64_t kmin, int64_t Gw, hipStream_t s) {

@@ -27,8 +27,9 @@ GF2_ENOMEM = -2
 GF2_EHIP = -3
 
 EXPORTED = ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_decompose_batched",
-            "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_autotune", "gf2_autotune_table", "gf2_set_param",
-            "gf2_profile", "gf2_profile_read", "gf2_microbench", "gf2_release", "gf2_last_error", "gf2_version")
+            "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_inverse", "gf2_autotune", "gf2_autotune_table",
+            "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_microbench", "gf2_release", "gf2_last_error",
+            "gf2_version")
 BATCH_MAX_DIM = 2048
 
 
@@ -70,6 +71,7 @@ def load():
         lib.gf2_solve_batched.argtypes = [PB, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.gf2_rref.argtypes = [P, P, vp, vp, vp]
         lib.gf2_nullspace.argtypes = [P, P, vp, vp]
+        lib.gf2_inverse.argtypes = [P, P, vp, vp]
         lib.gf2_autotune.argtypes = [i64, vp]
         lib.gf2_autotune_table.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(i64)]
         lib.gf2_set_param.argtypes = [ctypes.c_char_p, i64]
@@ -82,7 +84,7 @@ def load():
         lib.gf2_last_error.restype = ctypes.c_char_p
         lib.gf2_version.restype = ctypes.c_char_p
         for name in ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_decompose_batched",
-                     "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_autotune",
+                     "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_inverse", "gf2_autotune",
                      "gf2_autotune_table", "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_microbench",
                      "gf2_release"):
             getattr(lib, name).restype = ctypes.c_int
@@ -213,6 +215,10 @@ def gf2_nullspace(A: Mat, N: Mat, nullity, stream=None) -> None:
     _check(load().gf2_nullspace(ctypes.byref(A.desc()), ctypes.byref(N.desc()), _ptr(nullity), _stream(stream)))
 
 
+def gf2_inverse(A: Mat, X: Mat, invertible=None, stream=None) -> None:
+    _check(load().gf2_inverse(ctypes.byref(A.desc()), ctypes.byref(X.desc()), _ptr(invertible), _stream(stream)))
+
+
 def gf2_autotune(max_size: int = 65536, stream=None) -> None:
     _check(load().gf2_autotune(int(max_size), _stream(stream)))
 
@@ -289,6 +295,16 @@ def matmul(A: Mat, B: Mat, stream=None, w=None) -> Mat:
     C = Mat.zeros(A.rows, B.cols, w=w, device=A.t.device)
     gf2_matmul(C, A, B, False, stream)
     return C
+
+
+def inverse(A: Mat, stream=None):
+    """A^-1 of a square A: dict(X (Mat, zero when A is singular), invertible (1-element tensor))."""
+    import torch
+
+    X = Mat.zeros(A.rows, A.cols, device=A.t.device)
+    inv = torch.zeros(1, dtype=torch.int64, device=A.t.device)
+    gf2_inverse(A, X, inv, stream)
+    return dict(X=X, invertible=inv)
 
 
 def solve(A: Mat, B: Mat, stream=None):

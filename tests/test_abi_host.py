@@ -168,3 +168,24 @@ def test_autotune_entry_points_without_gpu():
     assert table == [[-1] * 4 for _ in range(9)] and cut == 65536
     assert lib.gf2_set_param(b"autotuned", 2) == gf2.GF2_EINVAL
     assert lib.gf2_set_param(b"autotuned", 1) == gf2.GF2_OK  # no table yet: stays on the rule
+
+
+def test_inverse_validation_without_gpu():
+    """Non-square, empty and mis-shaped inverse calls are rejected before any device work."""
+    import ctypes
+
+    from paper_1209_5198_amd import gf2
+
+    lib = gf2.load()
+    def desc(rows, cols):  # the data address is never dereferenced: the shapes fail first
+        return gf2._Mat(0x1000, rows, cols, 1, max(rows, 1))
+
+    A, X = desc(5, 6), desc(5, 6)
+    assert lib.gf2_inverse(ctypes.byref(A), ctypes.byref(X), None, None) == gf2.GF2_EINVAL
+    assert b"square" in lib.gf2_last_error()
+    A, X = desc(0, 0), desc(0, 0)
+    assert lib.gf2_inverse(ctypes.byref(A), ctypes.byref(X), None, None) == gf2.GF2_EINVAL
+    A, X = desc(7, 7), desc(7, 8)
+    assert lib.gf2_inverse(ctypes.byref(A), ctypes.byref(X), None, None) == gf2.GF2_EINVAL
+    assert b"X must be" in lib.gf2_last_error()
+    assert lib.gf2_inverse(None, None, None, None) == gf2.GF2_EINVAL

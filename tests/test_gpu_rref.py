@@ -1,4 +1,4 @@
-"""GPU parity of gf2_rref and gf2_nullspace (the null space of Section 1's uses).
+"""GPU parity of gf2_rref, gf2_nullspace (the null space of Section 1's uses) and gf2_inverse.
 
 Medium shapes (several 512-row blocks, ragged edges, tall and wide, dense,
 sparse and planted rank) are compared with the oracle bit for bit: the reduced
@@ -136,3 +136,59 @@ def orc_transpose(M, rows, cols):
     return np.packbits(np.ascontiguousarray(bits.T), axis=1, bitorder="little").view(np.uint64) if rows % 64 == 0 \
         else np.packbits(np.pad(np.ascontiguousarray(bits.T), ((0, 0), (0, (-rows) % 64))), axis=1,
                          bitorder="little").view(np.uint64)
+
+
+# ---------------------------------------------------------------- inverse
+def invertible_words(orc, seed, n):
+    """P * L * U with L unit lower and U unit upper triangular (random below and
+    above the diagonal) and P a random row permutation: always invertible."""
+    rng = np.random.default_rng(seed)
+    Lb = np.tril(rng.integers(0, 2, (n, n), dtype=np.uint8), -1) + np.eye(n, dtype=np.uint8)
+    Ub = np.triu(rng.integers(0, 2, (n, n), dtype=np.uint8), 1) + np.eye(n, dtype=np.uint8)
+    return orc.matmul(orc.pack_bits(Lb[rng.permutation(n)]), orc.pack_bits(Ub), n, n, n)
+
+
+def gpu_inverse(g, A, n):
+    import torch
+
+    out = g.inverse(g.Mat.from_rowmajor(A, n, n))
+    torch.cuda.synchronize()
+    return out["X"].to_rowmajor(), bool(out["invertible"].item())
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 700, 1300, 2049, 4096])
+def test_inverse_parity(g, orc, n):
+    """gf2_inverse against the oracle's Gauss-Jordan inverse, bit for bit, on
+    invertible matrices of one to several 512-row blocks with ragged edges."""
+    say("inverse", n)
+    A = invertible_words(orc, 70 + n, n)
+    ref = orc.inverse(A, n)
+    assert ref["invertible"]
+    X, inv = gpu_inverse(g, A, n)
+    assert inv and np.array_equal(X, ref["X"])
+
+
+@pytest.mark.parametrize("n,kind", [(1, "zero"), (64, "dup"), (700, "dup"), (1300, "lowrank"), (2100, "random"),
+                                    (513, "random"), (300, "random"), (305, "random")])
+def test_inverse_singular_and_random(g, orc, n, kind):
+    """Singular matrices (a zero matrix, a repeated row, a product through n - 1
+    columns) report 0 and give X = 0; uniformly random matrices (invertible
+    about 29% of the time: here 300 and 305 are, 513 and 2100 are not) match
+    the oracle either way."""
+    say("inverse", kind, n)
+    if kind == "zero":
+        A = np.zeros((n, wpr(n)), np.uint64)
+    elif kind == "dup":
+        A = invertible_words(orc, 90 + n, n)
+        A[n // 2] = A[n // 3]
+    elif kind == "lowrank":
+        X0, Y0 = synth.planted(91, 3, n, n, n - 1, 0.5)
+        A = orc.matmul(X0, Y0, n, n - 1, n)
+    else:
+        A = synth.dense(92 + n, 4, n, n)
+    ref = orc.inverse(A, n)
+    X, inv = gpu_inverse(g, A, n)
+    assert inv == ref["invertible"]
+    assert np.array_equal(X, ref["X"])
+    if kind != "random":
+        assert not inv and not np.any(X)
