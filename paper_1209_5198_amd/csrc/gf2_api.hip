@@ -334,17 +334,25 @@ int chain(DecWork &w, int q0, int s_eff, int flag_q0, hipStream_t s) {
 // test of a panel's chain reads the flag of the panel two steps back, the last
 // one whose trailing update is certainly complete.  Returns with `user` ordered
 // after all the work.
-// identity_right: the matrix factored is [A | I] (w sized for A->cols + A->rows
-// columns, A square), the augmented form the inverse is read from.
-int factor(const gf2_mat *A, DecWork &w, hipStream_t user, bool identity_right = false) {
+// What the working matrix holds: A; [A | I] (w sized for A->cols + A->rows
+// columns, A square: the augmented form the inverse is read from); or A^T (w
+// sized for A->cols x A->rows: the rank of a wide matrix, equal to that of its
+// transpose, with fewer panels).
+enum class Pack { kPlain, kIdentityRight, kTransposed };
+
+int factor(const gf2_mat *A, DecWork &w, hipStream_t user, Pack pack = Pack::kPlain) {
   Pipe *P = nullptr;
   int rc = get_pipe(user, &P);
   if (rc) return rc;
   hipStream_t G = P->gemm, Cs = P->chain;
   if ((rc = link(P, user, G))) return rc;
   HIPCHK(launch_init_state(w, G));
-  HIPCHK(launch_pack(*A, w.W, w.ldw, w.n, A->cols, w.NB, G));
-  if (identity_right) HIPCHK(launch_set_identity(w.W, w.ldw, w.n, A->cols, G));
+  if (pack == Pack::kTransposed) {
+    HIPCHK(launch_pack_transposed(*A, w.W, w.ldw, w.NB, G));
+  } else {
+    HIPCHK(launch_pack(*A, w.W, w.ldw, w.n, A->cols, w.NB, G));
+    if (pack == Pack::kIdentityRight) HIPCHK(launch_set_identity(w.W, w.ldw, w.n, A->cols, G));
+  }
   const int S = g_panel_words;
   int prev = -1;
   if (g_chain_cus == 0) {
@@ -453,7 +461,7 @@ int rref_run(const gf2_mat *A, hipStream_t s, RrefWork &rw, bool augment = false
   rw.tw0 = (int64_t *)p; p += bM;
   rw.freecols = (int64_t *)p; p += bF;
   rw.rank = (int64_t *)p;
-  if ((rc = factor(A, w, s, augment))) return rc;
+  if ((rc = factor(A, w, s, augment ? Pack::kIdentityRight : Pack::kPlain))) return rc;
   HIPCHK(launch_finish(w, nullptr, rw.piv, rw.rank, s));
   const gf2_mat Em{rw.E, kmin, m, TW, rw.ldE};
   HIPCHK(launch_extract_E(w, Em, s));
@@ -913,9 +921,16 @@ int gf2_rank(const gf2_mat *A, int64_t *rank, void *stream) {
     HIPCHK(hipMemsetAsync(rank, 0, sizeof(int64_t), s));
     return GF2_OK;
   }
+  // rank A = rank A^T: a wide matrix is factored transposed, which needs
+  // ceil(rows / 512) panels instead of ceil(cols / 512) (the panels past the
+  // rank still cost their launches)
+  const bool wide = A->cols > A->rows;
+  gf2_mat shape = *A;
+  if (wide) std::swap(shape.rows, shape.cols);
+  if (wide && shape.rows >= (1ll << 31)) return fail(GF2_EINVAL, "gf2_rank: cols must be < 2^31 when cols > rows");
   DecWork w;
-  if ((rc = prepare_decomp(A, s, w, 0, nullptr))) return rc;
-  if ((rc = factor(A, w, s))) return rc;
+  if ((rc = prepare_decomp(&shape, s, w, 0, nullptr))) return rc;
+  if ((rc = factor(A, w, s, wide ? Pack::kTransposed : Pack::kPlain))) return rc;
   HIPCHK(launch_finish(w, nullptr, nullptr, rank, s));
   return GF2_OK;
 }

@@ -34,6 +34,28 @@ __host__ __device__ inline uint64_t pad_mask(int64_t cols, int64_t q) {
   return (1ull << valid) - 1ull;
 }
 
+__device__ inline uint64_t shfl_xor64(uint64_t x, int m) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, m), hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), m);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// 64 x 64 bit transpose across a wave: lane k holds row k of the block (bit j =
+// column j); afterwards lane j holds column j.  The step with distance d
+// exchanges, between rows k and k + d (bit d of k clear), the d x d sub-blocks
+// off the diagonal of each 2d x 2d block.
+__device__ inline uint64_t transpose64(uint64_t x, int lane) {
+  uint64_t m = 0x00000000FFFFFFFFull;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t y = shfl_xor64(x, d);
+    const bool low = (lane & d) == 0;
+    const uint64_t t = low ? (((x >> d) ^ y) & m) : (((y >> d) ^ x) & m);
+    x ^= low ? (t << d) : t;
+    m ^= m << (d >> 1);
+  }
+  return x;
+}
+
 // ---------------------------------------------------------------- decomposition state
 // Per 64-column sub-panel q: rank before it (R), its number of pivots (r) and
 // the bit positions of its pivot columns inside word q.
@@ -99,6 +121,7 @@ struct GemmArgs {
 hipError_t launch_init_state(const DecWork &w, hipStream_t s);
 hipError_t launch_pack(const gf2_mat &src, uint64_t *W, int64_t ldw, int64_t n, int64_t m,
                        int32_t NB, hipStream_t s);
+hipError_t launch_pack_transposed(const gf2_mat &src, uint64_t *W, int64_t ldw, int32_t NB, hipStream_t s);
 hipError_t launch_unpack(const uint64_t *W, int64_t ldw, const gf2_mat &dst, hipStream_t s);
 hipError_t launch_extract_E(const DecWork &w, const gf2_mat &E, hipStream_t s);
 hipError_t launch_extract_L(const DecWork &w, const gf2_mat &L, hipStream_t s);

@@ -74,6 +74,32 @@ hipError_t launch_pack(const gf2_mat &src, uint64_t *W, int64_t ldw, int64_t n, 
   return hipGetLastError();
 }
 
+// src^T (cols x rows of src) -> working layout, every word of W written (zero
+// past the transpose).  Wave (q, p): rows 64 q .. 64 q + 63 of src, word p
+// (columns 64 p ..), one 64 x 64 bit transpose; lane j then holds row 64 p + j of
+// the transpose, word q.
+__global__ void k_pack_transposed(gf2_mat src, uint64_t *W, int64_t ldw, int64_t nq, int64_t np) {
+  const int lane = threadIdx.x & 63;
+  const int64_t srcw = (src.cols + 63) / 64;
+  const int64_t waves = nq * np;
+  for (int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; b < waves;
+       b += ((int64_t)gridDim.x * blockDim.x) >> 6) {
+    const int64_t q = b % nq, p = b / nq;  // consecutive waves: consecutive words q of the same W rows
+    const int64_t row = 64 * q + lane;
+    const uint64_t x = (row < src.rows && p < srcw) ? src.data[uidx(src.w, src.ld, row, p)] & pad_mask(src.cols, p) : 0ull;
+    W[widx(ldw, 64 * p + lane, q)] = transpose64(x, lane);
+  }
+}
+
+hipError_t launch_pack_transposed(const gf2_mat &src, uint64_t *W, int64_t ldw, int32_t NB, hipStream_t s) {
+  const int64_t nq = (int64_t)NB * TW, np = ldw / 64;  // every word of W, every 64-row group
+  int64_t blocks = (nq * np * 64 + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_pack_transposed, dim3((unsigned)blocks), dim3(256), 0, s, src, W, ldw, nq, np);
+  return hipGetLastError();
+}
+
 // working layout -> caller layout (rows [0, rows), words [0, ceil(cols/64)))
 __global__ void k_unpack(const uint64_t *W, int64_t ldw, gf2_mat dst) {
   const int64_t Mw = (dst.cols + 63) / 64;

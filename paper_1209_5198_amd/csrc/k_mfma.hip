@@ -45,27 +45,6 @@ __device__ inline uint4 spread32(uint32_t x) {
   return make_uint4((x << 1) & 0x22222222u, x & 0x22222222u, (x >> 1) & 0x22222222u, (x >> 2) & 0x22222222u);
 }
 
-__device__ inline uint64_t shfl_xor64(uint64_t x, int m) {
-  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, m), hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), m);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// Lane k holds row k of a 64 x 64 bit block (bit j = column j); afterwards lane
-// j holds column j.  Step with distance d exchanges, between rows k and k + d
-// (bit d of k clear), the d x d sub-blocks off the diagonal of each 2d x 2d block.
-__device__ inline uint64_t transpose64(uint64_t x, int lane) {
-  uint64_t m = 0x00000000FFFFFFFFull;
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const uint64_t y = shfl_xor64(x, d);
-    const bool low = (lane & d) == 0;
-    const uint64_t t = low ? (((x >> d) ^ y) & m) : (((y >> d) ^ x) & m);
-    x ^= low ? (t << d) : t;
-    m ^= m << (d >> 1);
-  }
-  return x;
-}
-
 constexpr int kQuadsAhead = 2;  // raw quads in flight per fragment (loads run this many quads ahead)
 constexpr int kWR = 2, kWC = 2;   // waves per workgroup: row groups x output words
 constexpr int kMThreads = 64 * kWR * kWC, kMRows = 128 * kWR;

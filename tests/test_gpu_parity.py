@@ -299,12 +299,26 @@ def test_decompose_repeatable(g, orc):
         assert_same_ple(again, first, "repeat")
 
 
-@pytest.mark.parametrize("kind,n,m", [("dense", 2048, 2048), ("planted", 1500, 2200), ("dense", 3000, 500)])
+@pytest.mark.parametrize("kind,n,m", [("dense", 2048, 2048), ("planted", 1500, 2200), ("dense", 3000, 500),
+                                      ("dense", 1, 700), ("dense", 70, 5000), ("dense", 1000, 1001),
+                                      ("planted", 700, 20000), ("sparse", 300, 9000), ("lead_zero", 130, 6000)])
 def test_rank_parity(g, orc, kind, n, m):
+    """Rank against the oracle.  Wider than tall matrices are factored as their
+    transpose (rank A = rank A^T): ragged edges, planted rank, sparse, and pivots
+    only in the last columns (the first 5000 columns zero)."""
     import torch
 
     say("rank", kind, n, m)
-    A = synth.dense(3, 1, n, m) if kind == "dense" else planted_words(orc, 3, n, m, 777)
+    if kind == "dense":
+        A = synth.dense(3, 1, n, m)
+    elif kind == "planted":
+        A = planted_words(orc, 3, n, m, min(n, m) // 2)
+    elif kind == "sparse":
+        A = synth.bernoulli(3, 2, n, m, 0.001)
+    else:
+        bits = orc.unpack_bits(synth.dense(3, 3, n, m), m)
+        bits[:, :5000] = 0
+        A = orc.pack_bits(bits)
     r = torch.empty(1, dtype=torch.int64, device="cuda")
     g.gf2_rank(g.Mat.from_rowmajor(A, n, m), r)
     assert int(r.item()) == orc.rank(A, n, m)
