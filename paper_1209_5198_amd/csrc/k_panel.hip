@@ -618,20 +618,22 @@ hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, hipStr
 
 // ---------------------------------------------------------------- after the chain
 // One launch per panel, two kinds of workgroups (1024 threads each):
-//   * one per 16-word column block: the panel's net row permutation applied to
-//     the block's words outside the panel (P^(j) applied to all columns), then,
-//     for trailing words, the pivot rows in echelon form E = L_pp^{-1} * rows
-//     (block forward substitution over the sub-panels).  Both touch only the
-//     block's own words, so the permutation finishes before the solve reads.
+//   * one per half (8 words) of a 16-word column block: the panel's net row
+//     permutation applied to its words outside the panel (P^(j) applied to all
+//     columns), then, for trailing words, the pivot rows in echelon form
+//     E = L_pp^{-1} * rows (block forward substitution over the sub-panels).
+//     Both touch only the workgroup's own words, so the permutation finishes
+//     before the solve reads.
 //   * one per 512 rows: every row below the pivots gets the sub-panels it still
 //     lacks, so its panel words hold its multipliers y_c (the Y of D*Z = Y,
 //     eq. (Aj) restricted to the panel).  These touch only panel words.
 constexpr int kPostThreads = 1024;
 constexpr int kRowsPerWG = kPostThreads / 2;
+constexpr int kPW = TW / 2;  // words per column workgroup
 
 struct TrsmShared {
-  uint64_t X[kMaxPanelWords * 64][TW];              // 64 KB: pivot rows, this block
-  uint64_t T[16][16][TW];                           // 32 KB: 4-bit tables
+  uint64_t X[kMaxPanelWords * 64][kPW];             // 32 KB: pivot rows, this half block
+  uint64_t T[16][16][kPW];                          // 16 KB: 4-bit tables
   uint64_t Cf[kMaxPanelWords * 64][kMaxPanelWords]; // 32 KB: multipliers L_cb
   uint64_t Li[kMaxPanelWords][64];                  // 4 KB: Linv_b
   SubInfo Sb[kMaxPanelWords];
@@ -642,36 +644,38 @@ union PostShared {
 };
 
 // the row now at listed position p comes from position bp_src[p] at the panel start
-__device__ void post_swap(const DecWork &w, int q0, int s_eff, int blk) {
+__device__ void post_swap(const DecWork &w, int q0, int s_eff, int blk, int half) {
   const int cnt = w.st->bp_count;
   if (cnt == 0) return;
-  const int tid = threadIdx.x, wl = tid & 15, e0 = tid >> 4;
-  const int64_t qw = (int64_t)blk * TW + wl;
+  const int tid = threadIdx.x, wl = tid % kPW, e0 = tid / kPW;
+  const int64_t qw = (int64_t)blk * TW + kPW * half + wl;
   const bool act = qw < w.Mw && !(qw >= q0 && qw < q0 + s_eff);
-  constexpr int PER = (kMaxPanelWords * 64 * 2) / (kPostThreads / 16);
+  constexpr int PER = (kMaxPanelWords * 64 * 2) / (kPostThreads / kPW);
   uint64_t vals[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int e = e0 + (kPostThreads / 16) * u;
+    const int e = e0 + (kPostThreads / kPW) * u;
     vals[u] = (act && e < cnt) ? w.W[widx(w.ldw, w.bp_src[w.bp_list[e]], qw)] : 0ull;
   }
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int e = e0 + (kPostThreads / 16) * u;
+    const int e = e0 + (kPostThreads / kPW) * u;
     if (act && e < cnt) w.W[widx(w.ldw, w.bp_list[e], qw)] = vals[u];
   }
   __syncthreads();
 }
 
-// Pivot rows of the panel, words of column block blk right of the panel:
+// Pivot rows of the panel, words of half `half` of column block blk right of
+// the panel:
 //   E_b = Linv_b * X_b, then X_c ^= L_cb * E_b for later sub-panels c,
 // with L_cb = word q0+b of the pivot rows of sub-panel c (their multipliers for
-// the pivots of sub-panel b).  16-lane groups over the block, 4-bit tables.
-__device__ void post_trsm(const DecWork &w, int q0, int s_eff, int blk, TrsmShared &sh) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, h = lane >> 4, wl = lane & 15;
+// the pivots of sub-panel b).  8-lane groups over the half block, 4-bit tables.
+__device__ void post_trsm(const DecWork &w, int q0, int s_eff, int blk, int half, TrsmShared &sh) {
+  constexpr int G = kPostThreads / kPW;  // row groups
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, h = lane / kPW, wl = lane % kPW;
   const int qc0 = q0 + s_eff;
-  const int64_t qw = (int64_t)blk * TW + wl;
+  const int64_t qw = (int64_t)blk * TW + kPW * half + wl;
   const bool qok = qw >= qc0 && qw < w.Mw;
   const int64_t ldw = w.ldw;
   uint64_t *W = w.W;
@@ -680,7 +684,7 @@ __device__ void post_trsm(const DecWork &w, int q0, int s_eff, int blk, TrsmShar
   int rtot = 0;
   for (int b = 0; b < s_eff; ++b) rtot += sh.Sb[b].r;
   if (rtot == 0) return;
-  for (int ri = tid >> 4; ri < 64 * s_eff; ri += kPostThreads / 16) {
+  for (int ri = tid / kPW; ri < 64 * s_eff; ri += G) {
     const int b = ri >> 6, t = ri & 63;
     sh.X[ri][wl] = (qok && t < sh.Sb[b].r) ? W[widx(ldw, sh.Sb[b].R + t, qw)] : 0ull;
   }
@@ -693,8 +697,8 @@ __device__ void post_trsm(const DecWork &w, int q0, int s_eff, int blk, TrsmShar
     sh.Li[e >> 6][e & 63] = w.Linv[(size_t)(q0 + (e >> 6)) * 64 + (e & 63)];
   __syncthreads();
   auto tables = [&](int b) {  // 16 tables of 16 entries over the 64 rows of X_b
-    if (tid < 256) {
-      const int g = tid >> 4, c = tid & 15;
+    if (tid < 16 * kPW) {
+      const int g = tid / kPW, c = tid % kPW;
       uint64_t v[4];
       for (int j = 0; j < 4; ++j) v[j] = sh.X[64 * b + 4 * g + j][c];
       uint64_t cur = 0ull;
@@ -710,7 +714,7 @@ __device__ void post_trsm(const DecWork &w, int q0, int s_eff, int blk, TrsmShar
     if (rb == 0) continue;
     tables(b);
     {
-      const int t = 4 * wv + h;  // 16 waves x 4 groups = 64 rows
+      const int t = (64 / kPW) * wv + h;  // waves 0..7 x 8 groups = 64 rows
       if (t < rb) {
         const uint64_t l = sh.Li[b][t];
         uint64_t v = 0ull;
@@ -723,7 +727,7 @@ __device__ void post_trsm(const DecWork &w, int q0, int s_eff, int blk, TrsmShar
     if (b == s_eff - 1) break;
     tables(b);
     // multipliers have no bits at or beyond rb, so unused tables contribute entry 0 = 0
-    for (int ri = 64 * (b + 1) + 4 * wv + h; ri < 64 * s_eff; ri += kPostThreads / 16) {
+    for (int ri = 64 * (b + 1) + (64 / kPW) * wv + h; ri < 64 * s_eff; ri += G) {
       const int c = ri >> 6, t = ri & 63;
       if (t < sh.Sb[c].r) {
         const uint64_t l = sh.Cf[ri][b];
@@ -735,7 +739,7 @@ __device__ void post_trsm(const DecWork &w, int q0, int s_eff, int blk, TrsmShar
     }
     __syncthreads();
   }
-  for (int ri = tid >> 4; ri < 64 * s_eff; ri += kPostThreads / 16) {
+  for (int ri = tid / kPW; ri < 64 * s_eff; ri += G) {
     const int b = ri >> 6, t = ri & 63;
     if (qok && t < sh.Sb[b].r) W[widx(ldw, sh.Sb[b].R + t, qw)] = sh.X[ri][wl];
   }
@@ -769,20 +773,20 @@ __device__ void post_rows(const DecWork &w, int q0, int s_eff, int64_t blk0, Pan
 
 __global__ __launch_bounds__(kPostThreads) void k_post(DecWork w, int q0, int s_eff) {
   __shared__ PostShared sh;
-  const int nb = w.NB;
-  if ((int)blockIdx.x < nb) {
-    const int blk = blockIdx.x;
-    post_swap(w, q0, s_eff, blk);
+  const int nc = 2 * w.NB;  // column workgroups: two per 16-word block
+  if ((int)blockIdx.x < nc) {
+    const int blk = blockIdx.x >> 1, half = blockIdx.x & 1;
+    post_swap(w, q0, s_eff, blk, half);
     const int qc0 = q0 + s_eff;
-    if (qc0 < w.Mw && blk >= (qc0 >> 4)) post_trsm(w, q0, s_eff, blk, sh.t);
+    if (qc0 < w.Mw && (int64_t)blk * TW + kPW * half + kPW - 1 >= qc0) post_trsm(w, q0, s_eff, blk, half, sh.t);
   } else {
-    post_rows(w, q0, s_eff, (int64_t)(blockIdx.x - nb) * kRowsPerWG, sh.pt);
+    post_rows(w, q0, s_eff, (int64_t)(blockIdx.x - nc) * kRowsPerWG, sh.pt);
   }
 }
 
 hipError_t launch_post(const DecWork &w, int q0, int s_eff, hipStream_t s) {
   const int64_t rows_wg = (w.n + kRowsPerWG - 1) / kRowsPerWG;
-  const int64_t blocks = (int64_t)w.NB + rows_wg;
+  const int64_t blocks = 2ll * w.NB + rows_wg;
   hipLaunchKernelGGL(k_post, dim3((unsigned)blocks), dim3(kPostThreads), 0, s, w, q0, s_eff);
   return hipGetLastError();
 }
