@@ -714,7 +714,7 @@ __device__ void post_trsm(const DecWork &w, int q0, int s_eff, int blk, int half
     if (rb == 0) continue;
     tables(b);
     {
-      const int t = (64 / kPW) * wv + h;  // waves 0..7 x 8 groups = 64 rows
+      const int t = (64 / kPW) * wv + h;  // the first kPW waves, 64 / kPW groups each: 64 rows
       if (t < rb) {
         const uint64_t l = sh.Li[b][t];
         uint64_t v = 0ull;
@@ -773,9 +773,10 @@ __device__ void post_rows(const DecWork &w, int q0, int s_eff, int64_t blk0, Pan
 
 __global__ __launch_bounds__(kPostThreads) void k_post(DecWork w, int q0, int s_eff) {
   __shared__ PostShared sh;
-  const int nc = 2 * w.NB;  // column workgroups: two per 16-word block
+  constexpr int kParts = TW / kPW;
+  const int nc = kParts * w.NB;  // column workgroups: kParts per 16-word block
   if ((int)blockIdx.x < nc) {
-    const int blk = blockIdx.x >> 1, half = blockIdx.x & 1;
+    const int blk = blockIdx.x / kParts, half = blockIdx.x % kParts;
     post_swap(w, q0, s_eff, blk, half);
     const int qc0 = q0 + s_eff;
     if (qc0 < w.Mw && (int64_t)blk * TW + kPW * half + kPW - 1 >= qc0) post_trsm(w, q0, s_eff, blk, half, sh.t);
@@ -786,7 +787,7 @@ __global__ __launch_bounds__(kPostThreads) void k_post(DecWork w, int q0, int s_
 
 hipError_t launch_post(const DecWork &w, int q0, int s_eff, hipStream_t s) {
   const int64_t rows_wg = (w.n + kRowsPerWG - 1) / kRowsPerWG;
-  const int64_t blocks = 2ll * w.NB + rows_wg;
+  const int64_t blocks = (int64_t)(TW / kPW) * w.NB + rows_wg;
   hipLaunchKernelGGL(k_post, dim3((unsigned)blocks), dim3(kPostThreads), 0, s, w, q0, s_eff);
   return hipGetLastError();
 }
