@@ -224,6 +224,10 @@ int gf2_autotune_table(int32_t *variants, int64_t *strassen_cutoff);
  *   "overlap_lookups"    : size of a panel's bulk update (table lookups) from
  *                          which it starts concurrently with the next panel's
  *                          columns rather than after them (default 0: always)
+ *   "post_follow_lookups": size of a panel's bulk update (table lookups) from
+ *                          which the next panel's row exchanges and pivot-row
+ *                          solve run on the bulk update's stream right after it
+ *                          (default 1.5e9; -1 = never, 0 = always)
  * Returns 0, or GF2_EINVAL for an unknown name or out-of-range value.
  */
 int gf2_set_param(const char *name, int64_t value);

@@ -46,6 +46,13 @@ int g_chain_cus = 0;
 // pivot chain (0 = always; measured best on MI355X at 65536^2: 62.0 ms against
 // 63.8 ms with a 1.2e9 threshold)
 double g_overlap_lookups = 0.0;
+// bulk-update size (table lookups) from which the next panel's k_post runs on
+// the bulk stream right after that update (then waiting for the next chain),
+// instead of on the main stream after a hop from the bulk stream: where the
+// bulk update is the longer path this takes two stream hops per panel off it
+// (-1 = never; measured on MI355X at 65536^2: 57.1-57.4 ms at 1.5e9 against
+// 58.2 ms never, 59.5 ms always, 58.2 ms at 5e9)
+double g_post_follow_lookups = 1.5e9;
 // Product-kernel tile per size class, written by gf2_autotune: rows class r
 // (active rows in [256 << r, 512 << r), clamped to 0..8) x column-block class c
 // (1, 2-3, 4-15, 16+ blocks of 16 words); -1 = the built-in rule.
@@ -362,23 +369,34 @@ int factor(const gf2_mat *A, DecWork &w, hipStream_t user, Pack pack = Pack::kPl
     // runs beside the next panel's columns and the chain), else after the next
     // panel's columns.  post(J+1) waits for it.
     if ((rc = chain(w, 0, w.Mw < S ? w.Mw : S, -1, G))) return rc;
+    bool post_on_cs = false;  // k_post of this panel follows the previous bulk update on Cs
     for (int q0 = 0; q0 < w.Mw; q0 += S) {
       const int s_eff = (w.Mw - q0) < S ? (w.Mw - q0) : S;
-      HIPCHK(launch_post(w, q0, s_eff, G));  // row exchanges, multipliers, pivot rows in echelon form
+      if (post_on_cs) {
+        // Cs already follows the previous bulk update; wait for this chain
+        if ((rc = link(P, G, Cs))) return rc;
+        HIPCHK(launch_post(w, q0, s_eff, Cs));
+        if ((rc = link(P, Cs, G))) return rc;
+      } else {
+        HIPCHK(launch_post(w, q0, s_eff, G));  // row exchanges, multipliers, pivot rows in echelon form
+      }
       const int nq0 = q0 + s_eff;
+      bool next_on_cs = false;
       if (nq0 < w.Mw) {
         const int ns = (w.Mw - nq0) < S ? (w.Mw - nq0) : S;
         // lookups of the bulk update (rows left >= n - 64 * sub-panels done)
         const int64_t rows_left = w.n - 64ll * nq0;
         const double bulk = (double)(rows_left > 0 ? rows_left : 0) * (double)(w.Mw - nq0 - ns) * 8.0 * s_eff;
         const bool early = bulk >= g_overlap_lookups;
-        if (early && (rc = link(P, G, Cs))) return rc;
+        if (early && !post_on_cs && (rc = link(P, G, Cs))) return rc;
         if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0, nq0 + ns, G))) return rc;  // next panel's columns
         if (!early && (rc = link(P, G, Cs))) return rc;
         if ((rc = chain(w, nq0, ns, prev, G))) return rc;                           // look-ahead
         if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0 + ns, w.Mw, Cs))) return rc; // the rest
-        if ((rc = link(P, Cs, G))) return rc;
+        next_on_cs = g_post_follow_lookups >= 0.0 && bulk >= g_post_follow_lookups;
+        if (!next_on_cs && (rc = link(P, Cs, G))) return rc;
       }
+      post_on_cs = next_on_cs;
       prev = q0;
     }
     return link(P, G, user);
@@ -518,6 +536,11 @@ int gf2_set_param(const char *name, int64_t value) {
   if (!strcmp(name, "autotuned")) {
     if (value < 0 || value > 1) return fail(GF2_EINVAL, "autotuned must be 0 or 1");
     g_tuned_on = value == 1 && g_tuned_valid;
+    return GF2_OK;
+  }
+  if (!strcmp(name, "post_follow_lookups")) {
+    if (value < -1) return fail(GF2_EINVAL, "post_follow_lookups must be >= -1");
+    g_post_follow_lookups = (double)value;
     return GF2_OK;
   }
   if (!strcmp(name, "overlap_lookups")) {
