@@ -367,7 +367,9 @@ int factor(const gf2_mat *A, DecWork &w, hipStream_t user, Pack pack = Pack::kPl
     // stream hop before the chain).  Bulk stream Cs: the rest of panel J's
     // update, started after post(J) when it clearly outlasts the chain (it then
     // runs beside the next panel's columns and the chain), else after the next
-    // panel's columns.  post(J+1) waits for it.
+    // panel's columns.  post(J+1) waits for it: on G, or, after a bulk update of
+    // at least g_post_follow_lookups, on Cs right behind it (then waiting for
+    // chain(J+1) instead), with G continuing after post(J+1).
     if ((rc = chain(w, 0, w.Mw < S ? w.Mw : S, -1, G))) return rc;
     bool post_on_cs = false;  // k_post of this panel follows the previous bulk update on Cs
     for (int q0 = 0; q0 < w.Mw; q0 += S) {
