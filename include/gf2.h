@@ -85,7 +85,12 @@ int gf2_matmul(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B, int accumul
 int gf2_decompose(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t *perm,
                   int64_t *pivcols, int64_t *rank, void *stream);
 
-/* rank(A) = number of rows of E = sum of the panel ranks r_j (Lemma 4.1). */
+/*
+ * rank(A) = number of rows of E = sum of the panel ranks r_j (Lemma 4.1).
+ * rank: device int64.  A matrix with more columns than rows is factored as its
+ * transpose (rank A = rank A^T), which needs fewer column panels; its column
+ * count must then be below 2^31.
+ */
 int gf2_rank(const gf2_mat *A, int64_t *rank, void *stream);
 
 /*
