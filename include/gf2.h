@@ -228,7 +228,7 @@ int gf2_autotune_table(int32_t *variants, int64_t *strassen_cutoff);
  *                          default once measured), 0 = the built-in tile rule
  *   "overlap_lookups"    : size of a panel's bulk update (table lookups) from
  *                          which it starts concurrently with the next panel's
- *                          columns rather than after them (default 0: always)
+ *                          columns rather than after them (default 3e8; 0: always)
  *   "post_follow_lookups": size of a panel's bulk update (table lookups) from
  *                          which the next panel's row exchanges and pivot-row
  *                          solve run on the bulk update's stream right after it

@@ -43,9 +43,11 @@ int g_panel_gemm_variant = -1;  // product-kernel variant for the trailing updat
 int g_chain_cus = 0;
 // bulk-update size (table lookups) from which the bulk update starts right
 // after the row exchanges, concurrently with the next panel's columns and its
-// pivot chain (0 = always; measured best on MI355X at 65536^2: 62.0 ms against
-// 63.8 ms with a 1.2e9 threshold)
-double g_overlap_lookups = 0.0;
+// pivot chain (0 = always).  Measured on MI355X at 65536^2: 62.0 ms at 0
+// against 63.8 ms at 1.2e9 with the post-chain kernel always on the main
+// stream; with the post-follow schedule 56.7-56.75 ms at 3e8 against
+// 56.8-57.1 ms at 0 and 57.8-57.9 ms at 1e9.
+double g_overlap_lookups = 3e8;
 // bulk-update size (table lookups) from which the next panel's k_post runs on
 // the bulk stream right after that update (then waiting for the next chain),
 // instead of on the main stream after a hop from the bulk stream: where the
@@ -931,8 +933,19 @@ int gf2_decompose(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t 
   DecWork w;
   if ((rc = prepare_decomp(A, s, w, 0, nullptr))) return rc;
   if ((rc = factor(A, w, s))) return rc;
-  if (E) HIPCHK(launch_extract_E(w, *E, s));
-  if (L) HIPCHK(launch_extract_L(w, *L, s));
+  if (E && L) {
+    // both outputs are HBM-bound copies of disjoint parts of the working
+    // matrix: E on the pipe's main stream beside L on the caller's stream
+    Pipe *P = nullptr;
+    if ((rc = get_pipe(s, &P))) return rc;
+    if ((rc = link(P, s, P->gemm))) return rc;
+    HIPCHK(launch_extract_E(w, *E, P->gemm));
+    HIPCHK(launch_extract_L(w, *L, s));
+    if ((rc = link(P, P->gemm, s))) return rc;
+  } else {
+    if (E) HIPCHK(launch_extract_E(w, *E, s));
+    if (L) HIPCHK(launch_extract_L(w, *L, s));
+  }
   HIPCHK(launch_finish(w, perm, pivcols, rank, s));
   return GF2_OK;
 }

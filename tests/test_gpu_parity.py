@@ -138,7 +138,8 @@ def test_decompose_panel_width_invariant(g, orc, panel_words):
                                         ("panel_gemm_variant", 12), ("panel_gemm_variant", 13),
                                         ("panel_gemm_variant", 14), ("panel_gemm_variant", 15),
                                         ("panel_gemm_variant", 16), ("overlap_lookups", 1200000000),
-                                        ("overlap_lookups", 10 ** 15), ("post_follow_lookups", 0),
+                                        ("overlap_lookups", 10 ** 15), ("overlap_lookups", 0),
+                                        ("post_follow_lookups", 0),
                                         ("post_follow_lookups", 30000000), ("post_follow_lookups", -1)])
 def test_decompose_tuning_invariant(g, orc, knob, value):
     """Look-ahead split and product-kernel variant do not change any result."""
@@ -146,7 +147,7 @@ def test_decompose_tuning_invariant(g, orc, knob, value):
     say("tuning", knob, value)
     A = synth.dense(17, 1, n, m)
     ref = orc.ple(A, n, m)
-    defaults = {"chain_cus": 0, "panel_gemm_variant": -1, "overlap_lookups": 0, "post_follow_lookups": 1500000000}
+    defaults = {"chain_cus": 0, "panel_gemm_variant": -1, "overlap_lookups": 300000000, "post_follow_lookups": 1500000000}
     g.gf2_set_param(knob, value)
     try:
         got = gpu_decompose(g, A, n, m)
