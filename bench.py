@@ -72,8 +72,8 @@ LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12   # 157.3 TB/s: 256 CUs x 256 B/clk x 2.
 # WRITE_SIZE (KiB, x1: the copy writes 1048576 KiB), averaged over the 253
 # product launches of one 65536^2 decomposition.  Valid only for the product
 # kernel source they were measured on.
-TRAFFIC = {"kernel_source_sha256": "0e97829b79d0859a7f92a0109028a0a4dbd94660aa31446057f5825d1f1942d6",
-           "fetch_bytes": 55091.5 * 2 * 1024, "write_bytes": 87507.4 * 1024}
+TRAFFIC = {"kernel_source_sha256": "da6bb8d96d6688417a9893d5151d76b85200097f657bd9a9befdbdc72ee6942c",
+           "fetch_bytes": 55103.8 * 2 * 1024, "write_bytes": 87507.2 * 1024}
 SEED = 65536
 
 

@@ -92,9 +92,12 @@ std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 struct ProfState {
   bool on = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  std::vector<hipEvent_t> pool;  // events created once and reused by later profiling sessions
+  size_t used = 0;               // events of the pool taken in this session
   unsigned long long *work_dev = nullptr;
   int64_t launches = 0;
 } g_prof;
+
 
 // Descriptors of a batch travel through one pinned host buffer; a copy is
 // complete (event) before the buffer is refilled by the next batched call.
@@ -212,9 +215,21 @@ void carve_decomp(Carver &c, DecWork &w) {
   w.ptab = c.take<uint64_t>(kPanelTabWords);
 }
 
+// the next event of the profiling pool (created the first time it is needed)
+int prof_event(hipEvent_t *e) {
+  if (g_prof.used == g_prof.pool.size()) {
+    hipEvent_t n = nullptr;
+    HIPCHK(hipEventCreate(&n));
+    g_prof.pool.push_back(n);
+  }
+  *e = g_prof.pool[g_prof.used++];
+  return GF2_OK;
+}
+
 int profile_begin(hipStream_t s, hipEvent_t *a) {
   if (!g_prof.on) return GF2_OK;
-  HIPCHK(hipEventCreate(a));
+  int rc = prof_event(a);
+  if (rc) return rc;
   HIPCHK(hipEventRecord(*a, s));
   return GF2_OK;
 }
@@ -222,7 +237,8 @@ int profile_begin(hipStream_t s, hipEvent_t *a) {
 int profile_end(hipStream_t s, hipEvent_t a) {
   if (!g_prof.on) return GF2_OK;
   hipEvent_t b;
-  HIPCHK(hipEventCreate(&b));
+  int rc = prof_event(&b);
+  if (rc) return rc;
   HIPCHK(hipEventRecord(b, s));
   g_prof.ev.emplace_back(a, b);
   g_prof.launches += 1;
@@ -248,12 +264,19 @@ int run_gemm(GemmArgs &a, int64_t nrows_max, int variant, int64_t active_rows, h
     variant = g_tuned[tune_row_class(active_rows)][tune_block_class(blocks)];
   }
   if (variant < 0 || variant >= kGemmVariants) variant = gemm_auto_variant(active_rows, a.qc0, a.qc1, device_cus());
-  hipEvent_t e0 = nullptr;
-  int rc = profile_begin(s, &e0);
-  if (rc) return rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (g_prof.on) {  // the launch records the kernel's own start and end
+    int rc = prof_event(&e0);
+    if (!rc) rc = prof_event(&e1);
+    if (rc) return rc;
+  }
   a.work = g_prof.on ? g_prof.work_dev : nullptr;
-  HIPCHK(launch_gemm(a, nrows_max, variant, s));
-  return profile_end(s, e0);
+  HIPCHK(launch_gemm(a, nrows_max, variant, s, e0, e1));
+  if (g_prof.on) {
+    g_prof.ev.emplace_back(e0, e1);
+    g_prof.launches += 1;
+  }
+  return GF2_OK;
 }
 
 // The fp4 matrix-core product for a plain B of bwords words per row; ws is
@@ -566,11 +589,10 @@ int gf2_set_param(const char *name, int64_t value) {
 }
 
 int gf2_profile(int enable) {
-  for (auto &p : g_prof.ev) {
-    (void)hipEventDestroy(p.first);
-    (void)hipEventDestroy(p.second);
-  }
+  // a new session reuses the pool's events once the previous session's are done
+  for (auto &p : g_prof.ev) HIPCHK(hipEventSynchronize(p.second));
   g_prof.ev.clear();
+  g_prof.used = 0;
   g_prof.launches = 0;
   if (enable && !g_prof.work_dev) {
     HIPCHK(hipMalloc((void **)&g_prof.work_dev, sizeof(unsigned long long)));
@@ -653,6 +675,12 @@ int gf2_release(void) {
   }
   g_ws.clear();
   HIPCHK(hipSetDevice(cur));
+  if (!g_prof.on) {
+    for (hipEvent_t e : g_prof.pool) HIPCHK(hipEventDestroy(e));
+    g_prof.pool.clear();
+    g_prof.ev.clear();
+    g_prof.used = 0;
+  }
   {
     std::lock_guard<std::mutex> ls(g_stage_mu);
     if (g_stage.ev) {

@@ -133,7 +133,9 @@ constexpr int kGemmMfma = 17;      // gf2_matmul only: the fp4 matrix-core produ
 size_t mfma_ws_bytes(int64_t kwords, int64_t m_words, int64_t rows);  // its workspace
 bool mfma_splits_inner(const GemmArgs &a, int ncu);  // the launch splits the inner dimension
 hipError_t launch_gemm_mfma(const GemmArgs &a, int64_t bwords, uint64_t *ws, int ncu, hipStream_t s);
-hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int variant, hipStream_t s);
+// e0, e1: optional timing events the launch records itself (start, end)
+hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int variant, hipStream_t s, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
 int gemm_auto_variant(int64_t active_rows, int qc0, int qc1, int ncu);  // variant for a launch shape
 
 hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, hipStream_t s);

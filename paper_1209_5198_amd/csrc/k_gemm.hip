@@ -22,6 +22,8 @@
 //   k_gemm_db    two tables per stage, double-buffered.
 // The byte address of a table entry is formed by one byte permute of (A bits,
 // lane base), and the XORs use the three-input bitwise instruction.
+#include <hip/hip_ext.h>
+
 #include "gf2_internal.h"
 
 namespace gf2 {
@@ -1035,8 +1037,16 @@ int gemm_auto_variant(int64_t active_rows, int qc0, int qc1, int ncu) {
   return 16;
 }
 
-hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t s) {
-  if (nrows_max <= 0 || a.qc1 <= a.qc0) return hipSuccess;
+// With timing events (e0, e1 both set) the launch itself records the kernel's
+// start and end, instead of two marker packets around it on the stream.
+hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (nrows_max <= 0 || a.qc1 <= a.qc0) {
+    if (e0 && e1) {  // an empty interval, so the pair stays valid
+      hipError_t r = hipEventRecord(e0, s);
+      return r != hipSuccess ? r : hipEventRecord(e1, s);
+    }
+    return hipSuccess;
+  }
 
   const int TM = gemm_tile_rows(v);
   const int64_t tiles = (nrows_max + TM - 1) / TM;
@@ -1044,25 +1054,33 @@ hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t 
   const dim3 grid((unsigned)tiles, (unsigned)blocks_y);
   const int chunks = ((a.qc1 - 1) >> 3) - (a.qc0 >> 3) + 1;  // 8-word chunks (narrow kernels)
   const dim3 gridn((unsigned)tiles, (unsigned)chunks);
+#define GF2_LAUNCH(K, GRID, NT)                                              \
+  do {                                                                       \
+    if (e0 && e1)                                                            \
+      hipExtLaunchKernelGGL(K, GRID, dim3(NT), 0, s, e0, e1, 0, a);          \
+    else                                                                     \
+      hipLaunchKernelGGL(K, GRID, dim3(NT), 0, s, a);                        \
+  } while (0)
   switch (v) {
-    case 1: hipLaunchKernelGGL((k_gemm_quad<512, 1024>), grid, dim3(512), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_gemm_quad<512, 2048>), grid, dim3(512), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_gemm_db<1024, 1024>), grid, dim3(1024), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_gemm_db<512, 2048>), grid, dim3(512), 0, s, a); break;
-    case 5: hipLaunchKernelGGL((k_gemm_quad<256, 512>), grid, dim3(256), 0, s, a); break;
-    case 6: hipLaunchKernelGGL((k_gemm_quad<256, 256>), grid, dim3(256), 0, s, a); break;
-    case 7: hipLaunchKernelGGL((k_gemm_wide<512, 2048>), grid, dim3(512), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_gemm_wide<512, 1024>), grid, dim3(512), 0, s, a); break;
-    case 9: hipLaunchKernelGGL((k_gemm_wide<256, 256>), grid, dim3(256), 0, s, a); break;
-    case 10: hipLaunchKernelGGL((k_gemm_wide<256, 512>), grid, dim3(256), 0, s, a); break;
-    case 11: hipLaunchKernelGGL((k_gemm_narrow<256, 256>), gridn, dim3(256), 0, s, a); break;
-    case 12: hipLaunchKernelGGL((k_gemm_narrow<256, 512>), gridn, dim3(256), 0, s, a); break;
-    case 13: hipLaunchKernelGGL((k_gemm_wide2<512, 2048>), grid, dim3(512), 0, s, a); break;
-    case 14: hipLaunchKernelGGL((k_gemm_wide2<512, 1024>), grid, dim3(512), 0, s, a); break;
-    case 15: hipLaunchKernelGGL((k_gemm_wide2<256, 512>), grid, dim3(256), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_gemm_wide2<256, 256>), grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_gemm_quad<1024, 1024>), grid, dim3(1024), 0, s, a); break;
+    case 1: GF2_LAUNCH((k_gemm_quad<512, 1024>), grid, 512); break;
+    case 2: GF2_LAUNCH((k_gemm_quad<512, 2048>), grid, 512); break;
+    case 3: GF2_LAUNCH((k_gemm_db<1024, 1024>), grid, 1024); break;
+    case 4: GF2_LAUNCH((k_gemm_db<512, 2048>), grid, 512); break;
+    case 5: GF2_LAUNCH((k_gemm_quad<256, 512>), grid, 256); break;
+    case 6: GF2_LAUNCH((k_gemm_quad<256, 256>), grid, 256); break;
+    case 7: GF2_LAUNCH((k_gemm_wide<512, 2048>), grid, 512); break;
+    case 8: GF2_LAUNCH((k_gemm_wide<512, 1024>), grid, 512); break;
+    case 9: GF2_LAUNCH((k_gemm_wide<256, 256>), grid, 256); break;
+    case 10: GF2_LAUNCH((k_gemm_wide<256, 512>), grid, 256); break;
+    case 11: GF2_LAUNCH((k_gemm_narrow<256, 256>), gridn, 256); break;
+    case 12: GF2_LAUNCH((k_gemm_narrow<256, 512>), gridn, 256); break;
+    case 13: GF2_LAUNCH((k_gemm_wide2<512, 2048>), grid, 512); break;
+    case 14: GF2_LAUNCH((k_gemm_wide2<512, 1024>), grid, 512); break;
+    case 15: GF2_LAUNCH((k_gemm_wide2<256, 512>), grid, 256); break;
+    case 16: GF2_LAUNCH((k_gemm_wide2<256, 256>), grid, 256); break;
+    default: GF2_LAUNCH((k_gemm_quad<1024, 1024>), grid, 1024); break;
   }
+#undef GF2_LAUNCH
   return hipGetLastError();
 }
 
