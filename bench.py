@@ -6,9 +6,11 @@ pivot columns and the rank.  Effective bit-ops = 2 * sum_t (n-1-t)(m-1-p_t)
 (one AND and one XOR per multiply-add of textbook elimination, from the pivot
 columns p_t the run returns); value = effective bit-ops / seconds per step.
 
-Roofline of the dominant kernel (the trailing-update Four-Russians product):
-its launches are bracketed by HIP events inside the library on the launch
-stream during the timed steps; its algorithmic work is one 8-byte LDS table
+The timed steps run with the library's profiling off (events between steps
+give min / median); a separate instrumented pass of --profile-steps steps then
+measures the dominant kernel (the trailing-update Four-Russians product): each
+of its launches records its own start and end (HIP events on the launch
+stream) and its lookup count; its algorithmic work is one 8-byte LDS table
 read and one 64-bit XOR per table lookup (one lookup per output word per 8
 inner bits); the bound is the on-chip table-read rate: LDS reads of 256 B/clk
 per CU (gfx950) x 256 CUs x 2.4 GHz = 157.3 TB/s.
@@ -75,6 +77,13 @@ LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12   # 157.3 TB/s: 256 CUs x 256 B/clk x 2.
 TRAFFIC = {"kernel_source_sha256": "da6bb8d96d6688417a9893d5151d76b85200097f657bd9a9befdbdc72ee6942c",
            "fetch_bytes": 55103.8 * 2 * 1024, "write_bytes": 87507.2 * 1024}
 SEED = 65536
+# The oracle on the bench's own 65536^2 input (seed 65536), run once on the
+# whole matrix (about 7e11 word operations, minutes of CPU time, so this script
+# does not repeat it): 43.2 s with 16 threads on a GPU host; 186.4 s with the
+# 8 threads of the build host when tests/golden/make_fullsize_hashes.py wrote
+# the digests (its record holds the time and thread count).
+ORACLE_65536_ONCE = [{"s": 43.2, "cores": 16, "host": "GPU host (MI355X box)"},
+                     {"s": 186.4, "cores": 8, "host": "build host (tests/golden/fullsize_hashes.json)"}]
 
 
 def eff_bitops(n: int, m: int, pivcols: np.ndarray) -> float:
@@ -241,7 +250,7 @@ def other_configs(gf2, synth, reps: int = 5):
         C = gf2.Mat.zeros(n, m)
         ms = timed(lambda: gf2.gf2_matmul(C, A, B, False, stream))
         ref = C.t.clone()
-        gf2.gf2_set_param("gemm_variant", 16)
+        gf2.gf2_set_param("gemm_variant", 3)
         try:
             ms_fr = timed(lambda: gf2.gf2_matmul(C, A, B, False, stream))
         finally:
@@ -343,21 +352,28 @@ def headline_section(args, gf2, synth):
         step()
         torch.cuda.synchronize()
         print(f"# warmup {i} done", file=sys.stderr, flush=True)
-    gf2.gf2_profile(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    # timed steps, library profiling off; an event between consecutive steps
+    # gives each step's own duration (min / median)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
+    evs[0].record(stream)
+    for i in range(args.steps):
         step()
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
+    step_ms = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+    print(f"# timed {args.steps} steps: wall {wall*1e3:.1f} ms, events {step_ms.sum():.1f} ms", file=sys.stderr,
+          flush=True)
+    # a separate instrumented pass: every product launch records its own start
+    # and end (HIP events on its launch stream) and its lookup count
+    gf2.gf2_profile(True)
+    for _ in range(args.profile_steps):
+        step()
+    torch.cuda.synchronize()
     kms, klaunch, lookups = gf2.gf2_profile_read()
     gf2.gf2_profile(False)
-    print(f"# timed {args.steps} steps: wall {wall*1e3:.1f} ms, events {gpu_ms:.1f} ms", file=sys.stderr, flush=True)
 
     r = int(rank.item())
     pc = piv.cpu().numpy()
@@ -374,12 +390,12 @@ def headline_section(args, gf2, synth):
         with open(src, "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() == TRAFFIC["kernel_source_sha256"]:
                 traffic = TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
-    roof = {"bound": "alu", "achieved": achieved_tbs, "peak": LDS_PEAK_TBS, "unit": "TB/s",
+    roof = {"bound": "lds", "achieved": achieved_tbs, "peak": LDS_PEAK_TBS, "unit": "TB/s",
             "frac": achieved_tbs / LDS_PEAK_TBS, "traffic": traffic,
-            "kernel": "k_gemm_m4rm (trailing-update Four-Russians product)",
+            "kernel": "k_gemm_wide / k_gemm_narrow (trailing-update Four-Russians product)",
             "work_per_launch": {"lookups": lookups_per_launch, "lds_bytes": 8.0 * lookups_per_launch},
-            "avg_launch_ms": per_launch_ms, "launches": klaunch,
-            "kernel_share_of_step": (kms / args.steps) / ms_per_step if ms_per_step > 0 else None}
+            "avg_launch_ms": per_launch_ms, "launches": klaunch, "profiled_steps": args.profile_steps,
+            "kernel_share_of_step": (kms / args.profile_steps) / ms_per_step if ms_per_step > 0 else None}
 
     out = {"metric": METRIC, "value": value, "unit": "bit-ops/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -388,6 +404,8 @@ def headline_section(args, gf2, synth):
            "config": {"workload": f"gf2_decompose {n}x{m} Bernoulli(1/2), P*A=L*E with L, E, perm, pivcols, rank",
                       "n": n, "m": m, "seed": SEED, "rank": r, "eff_bitops_per_step": ops,
                       "panel_words": 8},
+           "step_ms": {"min": float(step_ms.min()), "median": float(np.median(step_ms)),
+                       "max": float(step_ms.max())},
            "roofline": roof}
     del A, L, E
     torch.cuda.empty_cache()
@@ -399,6 +417,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--profile-steps", type=int, default=3,
+                    help="steps of the separate instrumented pass that measures the product launches")
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
@@ -452,6 +472,10 @@ def main():
     if not args.no_cpu:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
+        ops65536 = out.get("config", {}).get("eff_bitops_per_step") if args.n == 65536 else None
+        out["cpu_baseline"]["full_size_once"] = [
+            dict(r, input="65536x65536 Bernoulli(1/2), seed 65536 (the headline matrix), run once, cached",
+                 eff_bitops_per_s=(ops65536 / r["s"]) if ops65536 else None) for r in ORACLE_65536_ONCE]
     print(json.dumps(out), flush=True)
 
 

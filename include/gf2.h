@@ -26,10 +26,12 @@
  * ---------------------------------------------------------------- calls
  * Every call is asynchronous on `stream` (a hipStream_t; NULL = the default
  * stream).  Pointer arguments other than the gf2_mat descriptors themselves
- * are device pointers.  The library never frees caller memory.  It owns one
- * workspace per device, grown on demand with hipMalloc (so these calls must
- * not be captured into a graph) and released by gf2_release().  Calls that
- * share a device must not run concurrently from several host threads.
+ * are device pointers.  The library never frees caller memory.  The plain
+ * calls use a workspace per (device, stream) that the library grows on demand
+ * with hipMalloc and releases in gf2_release(); the *_ws forms take a
+ * caller-owned workspace instead (sizes from gf2_workspace_bytes) and never
+ * allocate.  Calls that share a device must not run concurrently from several
+ * host threads.
  *
  * Return value: 0 on success, or a negative GF2_E* code; gf2_last_error()
  * then returns a message (thread-local, valid until the next call).  An
@@ -127,7 +129,7 @@ int gf2_nullspace(const gf2_mat *A, const gf2_mat *N, int64_t *nullity, void *st
 
 /*
  * Inverse of a square A (n x n, n >= 1) over GF(2): X (n x n, caller
- * allocated) with A*X = X*A = I.  Section 4.3 builds such inverses for the
+ * allocated) with A*X = X*A = I.  Section 4.2 builds such inverses for the
  * pivot blocks; here the whole matrix is done as the reduced echelon form of
  * [A | I] (the decomposition of the n x 2n matrix, then the upward elimination
  * of gf2_rref), which is [I | A^-1] exactly when A is invertible.
@@ -218,12 +220,13 @@ int gf2_autotune_table(int32_t *variants, int64_t *strassen_cutoff);
  *                          per halving) while every dimension of the current
  *                          product is at least this many bits (default 65536; 0 = never)
  *   "gemm_variant"       : product-kernel variant for gf2_matmul (-1 = automatic;
- *                          0..16 Four-Russians kernels, 17 the fp4 matrix-core
- *                          product, chosen automatically when k >= 1024 and the
- *                          output has fewer 1024 x 1024 tiles than the device has CUs)
+ *                          0..5 Four-Russians kernels -- 0..3 tiles of 2048, 1024,
+ *                          512, 256 rows x 16 words, 4..5 tiles of 256, 512 rows x
+ *                          8 words --, 6 the fp4 matrix-core product, chosen
+ *                          automatically when k >= 1024 and the output has fewer
+ *                          1024 x 1024 tiles than the device has CUs)
  *   "panel_gemm_variant" : product-kernel variant for the trailing update (-1 = automatic)
- *   "chain_cus"          : CUs reserved for the pivot chain through CU-masked
- *                          streams (0 = two unmasked streams, the default)
+ *   "chain_cus"          : must be 0 (CU-masked chain streams are not supported)
  *   "autotuned"          : 1 = use the table measured by gf2_autotune (its
  *                          default once measured), 0 = the built-in tile rule
  *   "overlap_lookups"    : size of a panel's bulk update (table lookups) from
@@ -259,13 +262,64 @@ int gf2_profile_read(double *ms, int64_t *launches, double *lookups);
  *   5 fp4 (e2m1) matrix cores (32x32x64)    -> multiply-accumulates/s
  * bytes (kinds 0, 1): a positive multiple of 65536, allocated and freed by the
  * call; iters (kinds 2..5): 1 .. 2^24 loop trips per thread.  *ms is the mean
- * time of three launches after one warm-up, HIP events on stream s; the call
- * synchronizes s.  Returns 0, GF2_EINVAL for a bad kind, size or null output
+ * time of three launches after one warm-up, HIP events on `stream`; the call
+ * synchronizes it.  Returns 0, GF2_EINVAL for a bad kind, size or null output
  * (nothing launched), or GF2_EHIP / GF2_ENOMEM.
  */
-int gf2_microbench(int kind, int64_t bytes, int iters, double *rate, double *ms, hipStream_t s);
+int gf2_microbench(int kind, int64_t bytes, int iters, double *rate, double *ms, void *stream);
 
-/* Free the workspace of every device.  Safe to call at any time between calls. */
+/*
+ * ---------------------------------------------------------------- caller workspace
+ * Device bytes of workspace a call needs (the working copy of the matrix in
+ * the column-blocked layout of Section 3, the per-panel state of the block
+ * decomposition of Section 4, product operands and Strassen temporaries):
+ *   GF2_OP_MATMUL            C rows x cols, inner dimension k (with the current
+ *                            strassen_cutoff and gemm_variant settings)
+ *   GF2_OP_DECOMPOSE         A rows x cols (k ignored); also gf2_decompose_noalloc
+ *   GF2_OP_RANK              A rows x cols (k ignored)
+ *   GF2_OP_SOLVE             A rows x cols, k right-hand sides
+ *   GF2_OP_DECOMPOSE_BATCHED rows = number of items, cols and k = the largest
+ *                            item's columns and rows (at most GF2_BATCH_MAX_DIM)
+ *   GF2_OP_SOLVE_BATCHED     rows = number of items (cols, k ignored)
+ * The sizes depend on the current device (its CU count) and knobs only through
+ * the choices named above.  Returns SIZE_MAX (and sets gf2_last_error) for an
+ * unknown op or a negative or out-of-range size.
+ */
+#define GF2_OP_MATMUL 0
+#define GF2_OP_DECOMPOSE 1
+#define GF2_OP_RANK 2
+#define GF2_OP_SOLVE 3
+#define GF2_OP_DECOMPOSE_BATCHED 4
+#define GF2_OP_SOLVE_BATCHED 5
+size_t gf2_workspace_bytes(int op, int64_t rows, int64_t cols, int64_t k);
+
+/*
+ * The calls above with a caller-owned workspace: `workspace` is device memory,
+ * 256-byte aligned, of at least gf2_workspace_bytes(op, ...) bytes; the library
+ * neither allocates nor frees it and keeps nothing in it between calls.  These
+ * forms never allocate device memory and never synchronise the device (the
+ * look-ahead streams and events of a caller stream are created once, on its
+ * first call).  Two calls whose work overlaps in time must not share a
+ * workspace.  Results are identical to the allocating forms.  Errors as those,
+ * plus GF2_EINVAL for a null, misaligned or too small workspace.
+ */
+int gf2_matmul_ws(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B, int accumulate, void *workspace,
+                  size_t workspace_bytes, void *stream);
+int gf2_decompose_ws(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t *perm, int64_t *pivcols,
+                     int64_t *rank, void *workspace, size_t workspace_bytes, void *stream);
+int gf2_rank_ws(const gf2_mat *A, int64_t *rank, void *workspace, size_t workspace_bytes, void *stream);
+int gf2_solve_ws(const gf2_mat *A, const gf2_mat *B, const gf2_mat *X, uint64_t *consistent, int64_t *rank,
+                 void *workspace, size_t workspace_bytes, void *stream);
+int gf2_decompose_batched_ws(const gf2_batch_item *items, int64_t count, const uint64_t *A, uint64_t *L, uint64_t *E,
+                             int64_t *perm, int64_t *pivcols, int64_t *rank, void *workspace,
+                             size_t workspace_bytes, void *stream);
+int gf2_solve_batched_ws(const gf2_batch_item *items, int64_t count, const uint64_t *L, const uint64_t *E,
+                         const int64_t *perm, const int64_t *pivcols, const int64_t *rank, const uint64_t *B,
+                         uint64_t *X, int32_t *consistent, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Free the library-owned workspace, look-ahead streams and events of every
+ * device (after synchronising those devices).  Safe to call at any time
+ * between calls; later calls create what they need again. */
 int gf2_release(void);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -29,7 +29,7 @@
  *               consistent iff L_bot*y = (P b)_bot, x the solution whose
  *               non-pivot (free) variables are zero.
  *  - or_inverse: the inverse of a square non-singular matrix over F2 (Section
- *               4.3 builds it for the pivot blocks; here for a whole matrix)
+ *               4.2 builds it for the pivot blocks; here for a whole matrix)
  *               from its definition A*X = I, by Gauss-Jordan elimination of
  *               [A | I].
  *

@@ -37,10 +37,6 @@ int g_panel_words = 8;
 int64_t g_strassen_cutoff = 65536;
 int g_gemm_variant = -1;        // product-kernel variant for gf2_matmul (-1: automatic)
 int g_panel_gemm_variant = -1;  // product-kernel variant for the trailing update (-1: automatic)
-// CUs reserved for the pivot chain through a CU-masked stream pair; 0 = two
-// plain streams (the default: measured faster, since a masked product launch
-// leaves the CUs of the reserved range idle and unbalances its XCD)
-int g_chain_cus = 0;
 // bulk-update size (table lookups) from which the bulk update starts right
 // after the row exchanges, concurrently with the next panel's columns and its
 // pivot chain (0 = always).  Measured on MI355X at 65536^2: 62.0 ms at 0
@@ -73,12 +69,12 @@ int tune_block_class(int blocks) { return blocks <= 1 ? 0 : (blocks <= 3 ? 1 : (
 // pipeline.  The pivot chain of panel J+1 runs on one while the bulk of panel
 // J's trailing update runs on the other; events order the two.  Calls made on
 // different caller streams get different pairs, so their factorizations can
-// run concurrently (each pivot chain occupies a single CU).
+// run concurrently (each pivot chain occupies a single CU).  Both streams have
+// the default priority and no CU mask.  gf2_release() destroys them.
 struct Pipe {
   hipStream_t gemm = nullptr, chain = nullptr;
   std::vector<hipEvent_t> ring;
   size_t next = 0;
-  int chain_cus = -1;
 };
 std::map<std::pair<int, hipStream_t>, Pipe> g_pipes;
 
@@ -263,7 +259,7 @@ int run_gemm(GemmArgs &a, int64_t nrows_max, int variant, int64_t active_rows, h
     const int blocks = ((a.qc1 - 1) >> 4) - (a.qc0 >> 4) + 1;
     variant = g_tuned[tune_row_class(active_rows)][tune_block_class(blocks)];
   }
-  if (variant < 0 || variant >= kGemmVariants) variant = gemm_auto_variant(active_rows, a.qc0, a.qc1, device_cus());
+  if (variant < 0 || variant >= kGemmVariants) variant = gemm_auto_variant(active_rows, a.qc0, a.qc1, gf2::device_cus());
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g_prof.on) {  // the launch records the kernel's own start and end
     int rc = prof_event(&e0);
@@ -286,7 +282,7 @@ int run_gemm_mfma(GemmArgs &a, int64_t bwords, uint64_t *ws, hipStream_t s) {
   int rc = profile_begin(s, &e0);
   if (rc) return rc;
   a.work = g_prof.on ? g_prof.work_dev : nullptr;
-  HIPCHK(launch_gemm_mfma(a, bwords, ws, device_cus(), s));
+  HIPCHK(launch_gemm_mfma(a, bwords, ws, gf2::device_cus(), s));
   return profile_end(s, e0);
 }
 
@@ -295,41 +291,43 @@ int get_pipe(hipStream_t user, Pipe **out) {
   HIPCHK(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_mu);
   Pipe &p = g_pipes[std::make_pair(dev, user)];
-  if (p.gemm && p.chain_cus != g_chain_cus) {  // re-create on a changed split
-    HIPCHK(hipDeviceSynchronize());
-    HIPCHK(hipStreamDestroy(p.gemm));
-    HIPCHK(hipStreamDestroy(p.chain));
-    p.gemm = p.chain = nullptr;
-  }
   if (!p.gemm) {
-    hipDeviceProp_t prop;
-    HIPCHK(hipGetDeviceProperties(&prop, dev));
-    const int ncu = prop.multiProcessorCount;
-    const int nchain = (g_chain_cus > 0 && g_chain_cus < ncu) ? g_chain_cus : 0;
-    if (nchain == 0) {
-      HIPCHK(hipStreamCreateWithFlags(&p.gemm, hipStreamNonBlocking));
-      HIPCHK(hipStreamCreateWithFlags(&p.chain, hipStreamNonBlocking));
-    } else {
-      const int nw = (ncu + 31) / 32;
-      std::vector<uint32_t> mg(nw, 0u), mc(nw, 0u);
-      for (int c = 0; c < ncu; ++c) {
-        if (c < nchain) mc[c >> 5] |= 1u << (c & 31);
-        else mg[c >> 5] |= 1u << (c & 31);
-      }
-      HIPCHK(hipExtStreamCreateWithCUMask(&p.gemm, (uint32_t)nw, mg.data()));
-      HIPCHK(hipExtStreamCreateWithCUMask(&p.chain, (uint32_t)nw, mc.data()));
-    }
-    p.chain_cus = g_chain_cus;
-    p.ring.resize(64);
+    HIPCHK(hipStreamCreateWithFlags(&p.gemm, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&p.chain, hipStreamNonBlocking));
+    p.ring.assign(64, nullptr);
     for (auto &e : p.ring) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   *out = &p;
   return GF2_OK;
 }
 
-// make `waiter` wait for everything enqueued so far on `signaller`
-int link(Pipe *p, hipStream_t signaller, hipStream_t waiter) {
-  hipEvent_t e = p->ring[p->next++ % p->ring.size()];
+// Where a call's launches go: the caller's stream and the two look-ahead
+// streams of its pipe, or (P == nullptr) everything in order on the caller's
+// stream, which needs no stream or event of the library's own.
+struct Exec {
+  hipStream_t user = nullptr, G = nullptr, Cs = nullptr;
+  Pipe *P = nullptr;
+};
+
+int make_exec(hipStream_t user, bool single, Exec &x) {
+  x.user = user;
+  if (single) {
+    x.G = x.Cs = user;
+    x.P = nullptr;
+    return GF2_OK;
+  }
+  int rc = get_pipe(user, &x.P);
+  if (rc) return rc;
+  x.G = x.P->gemm;
+  x.Cs = x.P->chain;
+  return GF2_OK;
+}
+
+// make `waiter` wait for everything enqueued so far on `signaller` (nothing to
+// do when both are the same stream)
+int link(const Exec &x, hipStream_t signaller, hipStream_t waiter) {
+  if (signaller == waiter) return GF2_OK;
+  hipEvent_t e = x.P->ring[x.P->next++ % x.P->ring.size()];
   HIPCHK(hipEventRecord(e, signaller));
   HIPCHK(hipStreamWaitEvent(waiter, e, 0));
   return GF2_OK;
@@ -372,12 +370,10 @@ int chain(DecWork &w, int q0, int s_eff, int flag_q0, hipStream_t s) {
 // transpose, with fewer panels).
 enum class Pack { kPlain, kIdentityRight, kTransposed };
 
-int factor(const gf2_mat *A, DecWork &w, hipStream_t user, Pack pack = Pack::kPlain) {
-  Pipe *P = nullptr;
-  int rc = get_pipe(user, &P);
-  if (rc) return rc;
-  hipStream_t G = P->gemm, Cs = P->chain;
-  if ((rc = link(P, user, G))) return rc;
+int factor(const gf2_mat *A, DecWork &w, const Exec &x, Pack pack = Pack::kPlain) {
+  int rc;
+  const hipStream_t G = x.G, Cs = x.Cs;
+  if ((rc = link(x, x.user, G))) return rc;
   HIPCHK(launch_init_state(w, G));
   if (pack == Pack::kTransposed) {
     HIPCHK(launch_pack_transposed(*A, w.W, w.ldw, w.NB, G));
@@ -387,82 +383,80 @@ int factor(const gf2_mat *A, DecWork &w, hipStream_t user, Pack pack = Pack::kPl
   }
   const int S = g_panel_words;
   int prev = -1;
-  if (g_chain_cus == 0) {
-    // Main stream G: post(J), next panel's columns, chain(J+1), in order (no
-    // stream hop before the chain).  Bulk stream Cs: the rest of panel J's
-    // update, started after post(J) when it clearly outlasts the chain (it then
-    // runs beside the next panel's columns and the chain), else after the next
-    // panel's columns.  post(J+1) waits for it: on G, or, after a bulk update of
-    // at least g_post_follow_lookups, on Cs right behind it (then waiting for
-    // chain(J+1) instead), with G continuing after post(J+1).
-    if ((rc = chain(w, 0, w.Mw < S ? w.Mw : S, -1, G))) return rc;
-    bool post_on_cs = false;  // k_post of this panel follows the previous bulk update on Cs
-    for (int q0 = 0; q0 < w.Mw; q0 += S) {
-      const int s_eff = (w.Mw - q0) < S ? (w.Mw - q0) : S;
-      if (post_on_cs) {
-        // Cs already follows the previous bulk update; wait for this chain
-        if ((rc = link(P, G, Cs))) return rc;
-        HIPCHK(launch_post(w, q0, s_eff, Cs));
-        if ((rc = link(P, Cs, G))) return rc;
-      } else {
-        HIPCHK(launch_post(w, q0, s_eff, G));  // row exchanges, multipliers, pivot rows in echelon form
-      }
-      const int nq0 = q0 + s_eff;
-      bool next_on_cs = false;
-      if (nq0 < w.Mw) {
-        const int ns = (w.Mw - nq0) < S ? (w.Mw - nq0) : S;
-        // lookups of the bulk update (rows left >= n - 64 * sub-panels done)
-        const int64_t rows_left = w.n - 64ll * nq0;
-        const double bulk = (double)(rows_left > 0 ? rows_left : 0) * (double)(w.Mw - nq0 - ns) * 8.0 * s_eff;
-        const bool early = bulk >= g_overlap_lookups;
-        if (early && !post_on_cs && (rc = link(P, G, Cs))) return rc;
-        if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0, nq0 + ns, G))) return rc;  // next panel's columns
-        if (!early && (rc = link(P, G, Cs))) return rc;
-        if ((rc = chain(w, nq0, ns, prev, G))) return rc;                           // look-ahead
-        if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0 + ns, w.Mw, Cs))) return rc; // the rest
-        next_on_cs = g_post_follow_lookups >= 0.0 && bulk >= g_post_follow_lookups;
-        if (!next_on_cs && (rc = link(P, Cs, G))) return rc;
-      }
-      post_on_cs = next_on_cs;
-      prev = q0;
-    }
-    return link(P, G, user);
-  }
-  // CU-masked pair: the chain runs on its reserved CUs (stream Cs).
-  if ((rc = link(P, G, Cs))) return rc;
-  if ((rc = chain(w, 0, w.Mw < S ? w.Mw : S, -1, Cs))) return rc;
+  // Main stream G: post(J), next panel's columns, chain(J+1), in order (no
+  // stream hop before the chain).  Bulk stream Cs: the rest of panel J's
+  // update, started after post(J) when it clearly outlasts the chain (it then
+  // runs beside the next panel's columns and the chain), else after the next
+  // panel's columns.  post(J+1) waits for it: on G, or, after a bulk update of
+  // at least g_post_follow_lookups, on Cs right behind it (then waiting for
+  // chain(J+1) instead), with G continuing after post(J+1).  On a single
+  // stream the same launches run in this order, one after the other.
+  if ((rc = chain(w, 0, w.Mw < S ? w.Mw : S, -1, G))) return rc;
+  bool post_on_cs = false;  // k_post of this panel follows the previous bulk update on Cs
   for (int q0 = 0; q0 < w.Mw; q0 += S) {
     const int s_eff = (w.Mw - q0) < S ? (w.Mw - q0) : S;
-    if ((rc = link(P, Cs, G))) return rc;  // panel J's chain is done
-    HIPCHK(launch_post(w, q0, s_eff, G));  // row exchanges, multipliers, pivot rows in echelon form
+    if (post_on_cs) {
+      // Cs already follows the previous bulk update; wait for this chain
+      if ((rc = link(x, G, Cs))) return rc;
+      HIPCHK(launch_post(w, q0, s_eff, Cs));
+      if ((rc = link(x, Cs, G))) return rc;
+    } else {
+      HIPCHK(launch_post(w, q0, s_eff, G));  // row exchanges, multipliers, pivot rows in echelon form
+    }
     const int nq0 = q0 + s_eff;
+    bool next_on_cs = false;
     if (nq0 < w.Mw) {
       const int ns = (w.Mw - nq0) < S ? (w.Mw - nq0) : S;
-      if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0, nq0 + ns, G))) return rc;   // next panel's columns
-      if ((rc = link(P, G, Cs))) return rc;
-      if ((rc = chain(w, nq0, ns, prev, Cs))) return rc;                           // look-ahead
-      if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0 + ns, w.Mw, G))) return rc;  // the rest
+      // lookups of the bulk update (rows left >= n - 64 * sub-panels done)
+      const int64_t rows_left = w.n - 64ll * nq0;
+      const double bulk = (double)(rows_left > 0 ? rows_left : 0) * (double)(w.Mw - nq0 - ns) * 8.0 * s_eff;
+      const bool early = bulk >= g_overlap_lookups;
+      if (early && !post_on_cs && (rc = link(x, G, Cs))) return rc;
+      if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0, nq0 + ns, G))) return rc;  // next panel's columns
+      if (!early && (rc = link(x, G, Cs))) return rc;
+      if ((rc = chain(w, nq0, ns, prev, G))) return rc;                           // look-ahead
+      if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0 + ns, w.Mw, Cs))) return rc; // the rest
+      next_on_cs = g_post_follow_lookups >= 0.0 && bulk >= g_post_follow_lookups;
+      if (!next_on_cs && (rc = link(x, Cs, G))) return rc;
     }
+    post_on_cs = next_on_cs;
     prev = q0;
   }
-  return link(P, G, user);
+  return link(x, G, x.user);
 }
 
-int prepare_decomp(const gf2_mat *A, hipStream_t s, DecWork &w, size_t extra, void **extra_ptr) {
-  const int64_t n = A->rows, m = A->cols;
+// Working state of an n x m factorization carved from `ws` (at least
+// decomp_bytes(n, m) + extra bytes); *extra_ptr receives the extra bytes.
+void layout_decomp(int64_t n, int64_t m, DecWork &w) {
   memset(&w, 0, sizeof(w));
   w.n = n;
   w.m = m;
   w.Mw = (int32_t)ceil_div(m, 64);
   w.NB = (int32_t)ceil_div(w.Mw, TW);
   w.ldw = ceil_div(n > 0 ? n : 1, 256) * 256;
-  const size_t need = decomp_bytes(n, m, w.ldw, w.Mw, w.NB) + align256(extra);
-  void *ws = nullptr;
-  int rc = get_workspace(s, need, &ws);
-  if (rc) return rc;
+}
+
+size_t decomp_bytes(int64_t n, int64_t m) {
+  DecWork w;
+  layout_decomp(n, m, w);
+  return decomp_bytes(n, m, w.ldw, w.Mw, w.NB);
+}
+
+void prepare_decomp(int64_t n, int64_t m, void *ws, DecWork &w, size_t extra, void **extra_ptr) {
+  layout_decomp(n, m, w);
   Carver c(ws);
   carve_decomp(c, w);
   if (extra_ptr) *extra_ptr = c.take<char>(extra);
+}
+
+// A caller workspace must be 256-byte aligned and at least `need` bytes.
+int check_ws(const void *ws, size_t ws_bytes, size_t need, const char *who) {
+  if (need == 0) return GF2_OK;
+  if (!ws) return fail(GF2_EINVAL, std::string(who) + ": null workspace");
+  if (((uintptr_t)ws & 255u) != 0) return fail(GF2_EINVAL, std::string(who) + ": workspace must be 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(GF2_EINVAL, std::string(who) + ": workspace of " + std::to_string(ws_bytes) + " bytes, " +
+                                std::to_string(need) + " needed");
   return GF2_OK;
 }
 
@@ -493,10 +487,15 @@ int rref_run(const gf2_mat *A, hipStream_t s, RrefWork &rw, bool augment = false
   const size_t bE = align256((size_t)rw.NBE * rw.ldE * TW * 8), bG = align256((size_t)NBG * rw.ldE * TW * 8),
                bB = align256((size_t)rw.NBE * 512 * TW * 8), bI = align256((size_t)(kmin + 2) * 8),
                bM = align256((size_t)(rw.Mw + 1) * 8), bF = align256((size_t)(m + 1) * 8);
+  const size_t extra_bytes = bE + bG + bB + bI + 2 * bM + bF + 256;
+  void *ws = nullptr;
+  int rc = get_workspace(s, decomp_bytes(n, m) + align256(extra_bytes), &ws);
+  if (rc) return rc;
   DecWork w;
   void *extra = nullptr;
-  int rc = prepare_decomp(&shape, s, w, bE + bG + bB + bI + 2 * bM + bF + 256, &extra);
-  if (rc) return rc;
+  prepare_decomp(n, m, ws, w, extra_bytes, &extra);
+  Exec x;
+  if ((rc = make_exec(s, false, x))) return rc;
   char *p = (char *)extra;
   rw.E = (uint64_t *)p; p += bE;
   rw.G = (uint64_t *)p; p += bG;
@@ -506,7 +505,7 @@ int rref_run(const gf2_mat *A, hipStream_t s, RrefWork &rw, bool augment = false
   rw.tw0 = (int64_t *)p; p += bM;
   rw.freecols = (int64_t *)p; p += bF;
   rw.rank = (int64_t *)p;
-  if ((rc = factor(A, w, s, augment ? Pack::kIdentityRight : Pack::kPlain))) return rc;
+  if ((rc = factor(A, w, x, augment ? Pack::kIdentityRight : Pack::kPlain))) return rc;
   HIPCHK(launch_finish(w, nullptr, rw.piv, rw.rank, s));
   const gf2_mat Em{rw.E, kmin, m, TW, rw.ldE};
   HIPCHK(launch_extract_E(w, Em, s));
@@ -576,8 +575,9 @@ int gf2_set_param(const char *name, int64_t value) {
     return GF2_OK;
   }
   if (!strcmp(name, "chain_cus")) {
-    if (value < 0 || value > 128) return fail(GF2_EINVAL, "chain_cus must be in 0..128");
-    g_chain_cus = (int)value;
+    // CU-masked chain streams were removed: a masked product launch left the
+    // reserved CUs idle and unbalanced their XCD (measured slower)
+    if (value != 0) return fail(GF2_EINVAL, "chain_cus: CU-masked streams are not supported (only 0)");
     return GF2_OK;
   }
   if (!strcmp(name, "strassen_cutoff")) {
@@ -618,12 +618,13 @@ int gf2_profile_read(double *ms, int64_t *launches, double *lookups) {
   return GF2_OK;
 }
 
-int gf2_microbench(int kind, int64_t bytes, int iters, double *rate, double *ms, hipStream_t s) {
+int gf2_microbench(int kind, int64_t bytes, int iters, double *rate, double *ms, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
   if (kind < 0 || kind >= kProbeKinds || !rate || !ms) return fail(GF2_EINVAL, "gf2_microbench: bad kind or null output");
   if (kind <= 1 && (bytes < 65536 || bytes % 65536 != 0))
     return fail(GF2_EINVAL, "gf2_microbench: bytes must be a positive multiple of 65536");
   if (kind >= 2 && (iters < 1 || iters > (1 << 24))) return fail(GF2_EINVAL, "gf2_microbench: iters out of range");
-  const int ncu = device_cus();
+  const int ncu = gf2::device_cus();
   void *buf = nullptr;
   uint32_t *sink = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -666,14 +667,31 @@ int gf2_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   int cur = 0;
   HIPCHK(hipGetDevice(&cur));
+  // every device that holds a workspace or a pipe finishes its work first
+  std::vector<int> devs;
+  for (auto &kv : g_ws) devs.push_back(kv.first.first);
+  for (auto &kv : g_pipes) devs.push_back(kv.first.first);
+  std::sort(devs.begin(), devs.end());
+  devs.erase(std::unique(devs.begin(), devs.end()), devs.end());
+  for (int d : devs) {
+    HIPCHK(hipSetDevice(d));
+    HIPCHK(hipDeviceSynchronize());
+  }
   for (auto &kv : g_ws) {
     if (kv.second.ptr) {
       HIPCHK(hipSetDevice(kv.first.first));
-      HIPCHK(hipDeviceSynchronize());
       HIPCHK(hipFree(kv.second.ptr));
     }
   }
   g_ws.clear();
+  for (auto &kv : g_pipes) {
+    HIPCHK(hipSetDevice(kv.first.first));
+    for (hipEvent_t e : kv.second.ring)
+      if (e) HIPCHK(hipEventDestroy(e));
+    if (kv.second.gemm) HIPCHK(hipStreamDestroy(kv.second.gemm));
+    if (kv.second.chain) HIPCHK(hipStreamDestroy(kv.second.chain));
+  }
+  g_pipes.clear();
   HIPCHK(hipSetDevice(cur));
   if (!g_prof.on) {
     for (hipEvent_t e : g_prof.pool) HIPCHK(hipEventDestroy(e));
@@ -692,6 +710,8 @@ int gf2_release(void) {
   }
   return GF2_OK;
 }
+
+}  // extern "C"
 
 namespace {
 
@@ -864,77 +884,97 @@ int strassen(const BView &C, const BView &A, const BView &B, int depth, int acc,
   return GF2_OK;
 }
 
-}  // namespace
+// ---------------------------------------------------------------- plans and bodies of the calls
+// Everything a gf2_matmul call lays out in its workspace.
+struct MatmulPlan {
+  int depth = 0;
+  bool mfma = false;
+  int64_t np = 0, kp = 0, mp = 0, Kw = 0, Mw = 0, NBa = 0, NBb = 0, lda = 0, ldb = 0;
+  size_t ba = 0, bb = 0, bc = 0, bs = 0, bt = 0;
+  size_t total() const { return ba + bb + bc + bs + bt; }
+};
 
-int gf2_matmul(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B, int accumulate, void *stream) {
+MatmulPlan matmul_plan(int64_t n, int64_t k, int64_t m) {
+  MatmulPlan p;
+  if (n == 0 || m == 0) return p;
+  // Strassen-Winograd levels: while every dimension of the (halved) problem is
+  // at least the cutoff (Section 6: the recursion pays only for large products)
+  if (g_strassen_cutoff > 0)
+    while (p.depth < 4 && std::min(n, std::min(k, m)) >> p.depth >= g_strassen_cutoff) ++p.depth;
+  // padded shape: rows a multiple of 256 * 2^depth, inner and output columns of
+  // 1024 * 2^depth bits (so every quadrant is a whole number of 16-word blocks)
+  const int64_t rq = (int64_t)256 << p.depth, cq = (int64_t)1024 << p.depth;
+  p.np = ceil_div(n, rq) * rq;
+  p.kp = p.depth ? ceil_div(k, cq) * cq : k;
+  p.mp = p.depth ? ceil_div(m, cq) * cq : m;
+  p.Kw = ceil_div(p.kp, 64);
+  p.Mw = ceil_div(p.mp, 64);
+  p.NBa = ceil_div(p.Kw > 0 ? p.Kw : 1, TW);
+  p.NBb = ceil_div(p.Mw, TW);
+  p.lda = p.np;
+  p.ldb = ceil_div(p.kp > 0 ? p.kp : 1, 256) * 256;
+  p.ba = align256((size_t)p.NBa * p.lda * TW * 8);
+  p.bb = align256((size_t)p.NBb * p.ldb * TW * 8);
+  p.bc = align256((size_t)p.NBb * p.lda * TW * 8);
+  p.bs = p.depth ? strassen_bytes(p.np, p.NBa * TW, p.NBb * TW, p.depth) : 0;
+  // the fp4 matrix-core product when forced, or automatically where the table
+  // kernels cannot fill the chip with 1024-row tiles and the inner dimension is
+  // long enough to amortise its transpose and epilogue (measured crossover)
+  p.mfma = p.depth == 0 && k > 0 &&
+           (g_gemm_variant == kGemmMfma ||
+            (g_gemm_variant < 0 && k >= 1024 && ceil_div(n, 1024) * ceil_div(m, 1024) < gf2::device_cus()));
+  p.bt = p.mfma ? align256(mfma_ws_bytes(p.Kw, p.Mw, n)) : 0;
+  return p;
+}
+
+int matmul_check(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B) {
   int rc;
   if ((rc = check_mat(C, "C")) || (rc = check_mat(A, "A")) || (rc = check_mat(B, "B"))) return rc;
   if (A->cols != B->rows || C->rows != A->rows || C->cols != B->cols)
     return fail(GF2_EINVAL, "gf2_matmul: shapes do not match (C n x m, A n x k, B k x m)");
-  hipStream_t s = (hipStream_t)stream;
+  return GF2_OK;
+}
+
+int matmul_body(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B, int accumulate, const MatmulPlan &p, void *ws,
+                hipStream_t s) {
+  int rc;
   const int64_t n = A->rows, k = A->cols, m = B->cols;
   if (n == 0 || m == 0) return GF2_OK;
-  // Strassen-Winograd levels: while every dimension of the (halved) problem is
-  // at least the cutoff (Section 6: the recursion pays only for large products)
-  int depth = 0;
-  if (g_strassen_cutoff > 0)
-    while (depth < 4 && std::min(n, std::min(k, m)) >> depth >= g_strassen_cutoff) ++depth;
-  // padded shape: rows a multiple of 256 * 2^depth, inner and output columns of
-  // 1024 * 2^depth bits (so every quadrant is a whole number of 16-word blocks)
-  const int64_t rq = (int64_t)256 << depth, cq = (int64_t)1024 << depth;
-  const int64_t np = ceil_div(n, rq) * rq;
-  const int64_t kp = depth ? ceil_div(k, cq) * cq : k, mp = depth ? ceil_div(m, cq) * cq : m;
-  const int64_t Kw = ceil_div(kp, 64), Mw = ceil_div(mp, 64);
-  const int64_t NBa = ceil_div(Kw > 0 ? Kw : 1, TW), NBb = ceil_div(Mw, TW);
-  const int64_t lda = np, ldb = ceil_div(kp > 0 ? kp : 1, 256) * 256;
-  const size_t ba = align256((size_t)NBa * lda * TW * 8), bb = align256((size_t)NBb * ldb * TW * 8),
-               bc = align256((size_t)NBb * lda * TW * 8);
-  const size_t bs = depth ? strassen_bytes(np, NBa * TW, NBb * TW, depth) : 0;
-  // the fp4 matrix-core product when forced, or automatically where the table
-  // kernels cannot fill the chip with 1024-row tiles and the inner dimension is
-  // long enough to amortise its transpose and epilogue (measured crossover)
-  const bool mfma = depth == 0 && k > 0 &&
-                    (g_gemm_variant == kGemmMfma ||
-                     (g_gemm_variant < 0 && k >= 1024 && ceil_div(n, 1024) * ceil_div(m, 1024) < device_cus()));
-  const size_t bt = mfma ? align256(mfma_ws_bytes(Kw, Mw, n)) : 0;
-  void *ws = nullptr;
-  if ((rc = get_workspace(s, ba + bb + bc + bs + bt, &ws))) return rc;
-  uint64_t *Aw = (uint64_t *)ws, *Bw = (uint64_t *)((char *)ws + ba), *Cw = (uint64_t *)((char *)ws + ba + bb);
-  HIPCHK(launch_pack(*A, Aw, lda, n, k, (int32_t)NBa, s));
-  HIPCHK(launch_pack(*B, Bw, ldb, k, m, (int32_t)NBb, s));
-  if (accumulate) HIPCHK(launch_pack(*C, Cw, lda, n, m, (int32_t)NBb, s));
-  if (depth > 0) {
-    Stack st{(char *)ws + ba + bb + bc, 0, bs};
-    const BView Cv{Cw, lda, np, NBb * TW}, Av{Aw, lda, np, NBa * TW}, Bv{Bw, ldb, NBa * TW * 64, NBb * TW};
-    if ((rc = strassen(Cv, Av, Bv, depth, accumulate ? 1 : 0, st, s))) return rc;
+  uint64_t *Aw = (uint64_t *)ws, *Bw = (uint64_t *)((char *)ws + p.ba), *Cw = (uint64_t *)((char *)ws + p.ba + p.bb);
+  HIPCHK(launch_pack(*A, Aw, p.lda, n, k, (int32_t)p.NBa, s));
+  HIPCHK(launch_pack(*B, Bw, p.ldb, k, m, (int32_t)p.NBb, s));
+  if (accumulate) HIPCHK(launch_pack(*C, Cw, p.lda, n, m, (int32_t)p.NBb, s));
+  if (p.depth > 0) {
+    Stack st{(char *)ws + p.ba + p.bb + p.bc, 0, p.bs};
+    const BView Cv{Cw, p.lda, p.np, p.NBb * TW}, Av{Aw, p.lda, p.np, p.NBa * TW}, Bv{Bw, p.ldb, p.NBa * TW * 64, p.NBb * TW};
+    if ((rc = strassen(Cv, Av, Bv, p.depth, accumulate ? 1 : 0, st, s))) return rc;
   } else if (k > 0 || accumulate) {
     GemmArgs a;
     memset(&a, 0, sizeof(a));
-    a.A = Aw; a.ldA = lda; a.a_word0 = 0;
-    a.B = Bw; a.ldB = ldb; a.b_rows = k; a.bsub = nullptr;
-    a.C = Cw; a.ldC = lda;
+    a.A = Aw; a.ldA = p.lda; a.a_word0 = 0;
+    a.B = Bw; a.ldB = p.ldb; a.b_rows = k; a.bsub = nullptr;
+    a.C = Cw; a.ldC = p.lda;
     a.row_tile0 = 0; a.row_end = n;
-    a.kwords = (int32_t)Kw;
-    a.qc0 = 0; a.qc1 = (int32_t)Mw;
+    a.kwords = (int32_t)p.Kw;
+    a.qc0 = 0; a.qc1 = (int32_t)p.Mw;
     a.accumulate = accumulate ? 1 : 0;
-    if (mfma) {
-      if (!accumulate && mfma_splits_inner(a, device_cus())) {  // split inner dimension: XORs into a zeroed C
-        HIPCHK(hipMemsetAsync(Cw, 0, bc, s));
+    if (p.mfma) {
+      if (!accumulate && mfma_splits_inner(a, gf2::device_cus())) {  // split inner dimension: XORs into a zeroed C
+        HIPCHK(launch_zero(Cw, p.bc / 8, s));
         a.accumulate = 1;
       }
-      if ((rc = run_gemm_mfma(a, Mw, (uint64_t *)((char *)ws + ba + bb + bc), s))) return rc;
+      if ((rc = run_gemm_mfma(a, p.Mw, (uint64_t *)((char *)ws + p.ba + p.bb + p.bc), s))) return rc;
     } else if ((rc = run_gemm(a, n, g_gemm_variant, n, s))) {
       return rc;
     }
   } else {
-    HIPCHK(hipMemsetAsync(Cw, 0, bc, s));
+    HIPCHK(launch_zero(Cw, p.bc / 8, s));
   }
-  HIPCHK(launch_unpack(Cw, lda, *C, s));
+  HIPCHK(launch_unpack(Cw, p.lda, *C, s));
   return GF2_OK;
 }
 
-int gf2_decompose(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t *perm,
-                  int64_t *pivcols, int64_t *rank, void *stream) {
+int decompose_check(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E) {
   int rc;
   if ((rc = check_mat(A, "A"))) return rc;
   const int64_t n = A->rows, m = A->cols, kmin = n < m ? n : m;
@@ -946,30 +986,34 @@ int gf2_decompose(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t 
     if ((rc = check_mat(E, "E"))) return rc;
     if (E->rows != kmin || E->cols != m) return fail(GF2_EINVAL, "gf2_decompose: E must be min(n,m) x m");
   }
-  hipStream_t s = (hipStream_t)stream;
-  if (n == 0 || m == 0) {
-    if (rank) HIPCHK(hipMemsetAsync(rank, 0, sizeof(int64_t), s));
-    if (perm && n > 0) {
-      std::vector<int64_t> id(n);
-      for (int64_t i = 0; i < n; ++i) id[i] = i;
-      HIPCHK(hipMemcpyAsync(perm, id.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s));
-      HIPCHK(hipStreamSynchronize(s));
-    }
-    if (L && n > 0 && kmin > 0) HIPCHK(hipMemsetAsync(L->data, 0, 8 * (size_t)L->ld * L->w * ceil_div(ceil_div(kmin, 64), L->w), s));
+  return GF2_OK;
+}
+
+size_t decompose_need(const gf2_mat *A) {
+  return (A->rows == 0 || A->cols == 0) ? 0 : decomp_bytes(A->rows, A->cols);
+}
+
+// single: every launch in order on the caller's stream (no look-ahead streams)
+int decompose_body(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t *perm, int64_t *pivcols,
+                   int64_t *rank, void *ws, hipStream_t s, bool single) {
+  int rc;
+  const int64_t n = A->rows, m = A->cols;
+  if (n == 0 || m == 0) {  // rank 0, P = I; L and E have no entries (min(n, m) = 0)
+    HIPCHK(launch_empty_outputs(perm, n, rank, s));
     return GF2_OK;
   }
   DecWork w;
-  if ((rc = prepare_decomp(A, s, w, 0, nullptr))) return rc;
-  if ((rc = factor(A, w, s))) return rc;
-  if (E && L) {
+  prepare_decomp(n, m, ws, w, 0, nullptr);
+  Exec x;
+  if ((rc = make_exec(s, single, x))) return rc;
+  if ((rc = factor(A, w, x))) return rc;
+  if (E && L && x.P) {
     // both outputs are HBM-bound copies of disjoint parts of the working
     // matrix: E on the pipe's main stream beside L on the caller's stream
-    Pipe *P = nullptr;
-    if ((rc = get_pipe(s, &P))) return rc;
-    if ((rc = link(P, s, P->gemm))) return rc;
-    HIPCHK(launch_extract_E(w, *E, P->gemm));
+    if ((rc = link(x, s, x.G))) return rc;
+    HIPCHK(launch_extract_E(w, *E, x.G));
     HIPCHK(launch_extract_L(w, *L, s));
-    if ((rc = link(P, P->gemm, s))) return rc;
+    if ((rc = link(x, x.G, s))) return rc;
   } else {
     if (E) HIPCHK(launch_extract_E(w, *E, s));
     if (L) HIPCHK(launch_extract_L(w, *L, s));
@@ -978,46 +1022,70 @@ int gf2_decompose(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t 
   return GF2_OK;
 }
 
-int gf2_rank(const gf2_mat *A, int64_t *rank, void *stream) {
+int rank_check(const gf2_mat *A, const int64_t *rank) {
   int rc;
   if ((rc = check_mat(A, "A"))) return rc;
   if (!rank) return fail(GF2_EINVAL, "gf2_rank: null rank pointer");
-  hipStream_t s = (hipStream_t)stream;
+  if (A->cols > A->rows && A->cols >= (1ll << 31)) return fail(GF2_EINVAL, "gf2_rank: cols must be < 2^31 when cols > rows");
+  return GF2_OK;
+}
+
+// rank A = rank A^T: a wide matrix is factored transposed, which needs
+// ceil(rows / 512) panels instead of ceil(cols / 512) (the panels past the
+// rank still cost their launches)
+size_t rank_need(const gf2_mat *A) {
+  if (A->rows == 0 || A->cols == 0) return 0;
+  const bool wide = A->cols > A->rows;
+  return wide ? decomp_bytes(A->cols, A->rows) : decomp_bytes(A->rows, A->cols);
+}
+
+int rank_body(const gf2_mat *A, int64_t *rank, void *ws, hipStream_t s) {
+  int rc;
   if (A->rows == 0 || A->cols == 0) {
-    HIPCHK(hipMemsetAsync(rank, 0, sizeof(int64_t), s));
+    HIPCHK(launch_empty_outputs(nullptr, 0, rank, s));
     return GF2_OK;
   }
-  // rank A = rank A^T: a wide matrix is factored transposed, which needs
-  // ceil(rows / 512) panels instead of ceil(cols / 512) (the panels past the
-  // rank still cost their launches)
   const bool wide = A->cols > A->rows;
-  gf2_mat shape = *A;
-  if (wide) std::swap(shape.rows, shape.cols);
-  if (wide && shape.rows >= (1ll << 31)) return fail(GF2_EINVAL, "gf2_rank: cols must be < 2^31 when cols > rows");
   DecWork w;
-  if ((rc = prepare_decomp(&shape, s, w, 0, nullptr))) return rc;
-  if ((rc = factor(A, w, s, wide ? Pack::kTransposed : Pack::kPlain))) return rc;
+  if (wide) prepare_decomp(A->cols, A->rows, ws, w, 0, nullptr);
+  else prepare_decomp(A->rows, A->cols, ws, w, 0, nullptr);
+  Exec x;
+  if ((rc = make_exec(s, false, x))) return rc;
+  if ((rc = factor(A, w, x, wide ? Pack::kTransposed : Pack::kPlain))) return rc;
   HIPCHK(launch_finish(w, nullptr, nullptr, rank, s));
   return GF2_OK;
 }
 
-int gf2_solve(const gf2_mat *A, const gf2_mat *B, const gf2_mat *X, uint64_t *consistent,
-              int64_t *rank, void *stream) {
+int solve_check(const gf2_mat *A, const gf2_mat *B, const gf2_mat *X, const uint64_t *consistent) {
   int rc;
   if ((rc = check_mat(A, "A")) || (rc = check_mat(B, "B")) || (rc = check_mat(X, "X"))) return rc;
   if (!consistent) return fail(GF2_EINVAL, "gf2_solve: null consistent pointer");
   const int64_t n = A->rows, m = A->cols, k = B->cols;
   if (B->rows != n || X->rows != m || X->cols != k)
     return fail(GF2_EINVAL, "gf2_solve: shapes do not match (A n x m, B n x k, X m x k)");
-  if (n == 0 || m == 0 || k == 0)
-    return fail(GF2_EINVAL, "gf2_solve: empty systems are not supported");
-  hipStream_t s = (hipStream_t)stream;
+  if (n == 0 || m == 0 || k == 0) return fail(GF2_EINVAL, "gf2_solve: empty systems are not supported");
+  return GF2_OK;
+}
+
+// right-hand sides after P, then Y (n x ceil(k/64) words), and the residual flags
+size_t solve_extra(int64_t n, int64_t k) {
   const int64_t kw = ceil_div(k, 64);
-  const size_t ybytes = align256((size_t)n * kw * 8) + align256((size_t)kw * 8);
+  return align256((size_t)n * kw * 8) + align256((size_t)kw * 8);
+}
+
+size_t solve_need(int64_t n, int64_t m, int64_t k) { return decomp_bytes(n, m) + align256(solve_extra(n, k)); }
+
+int solve_body(const gf2_mat *A, const gf2_mat *B, const gf2_mat *X, uint64_t *consistent, int64_t *rank, void *ws,
+               hipStream_t s) {
+  int rc;
+  const int64_t n = A->rows, m = A->cols, k = B->cols;
+  const int64_t kw = ceil_div(k, 64);
   DecWork w;
   void *extra = nullptr;
-  if ((rc = prepare_decomp(A, s, w, ybytes, &extra))) return rc;
-  if ((rc = factor(A, w, s))) return rc;
+  prepare_decomp(n, m, ws, w, solve_extra(n, k), &extra);
+  Exec x;
+  if ((rc = make_exec(s, false, x))) return rc;
+  if ((rc = factor(A, w, x))) return rc;
   SolveWork sw;
   sw.Y = (uint64_t *)extra;
   sw.kw = kw;
@@ -1028,25 +1096,20 @@ int gf2_solve(const gf2_mat *A, const gf2_mat *B, const gf2_mat *X, uint64_t *co
   return GF2_OK;
 }
 
-int gf2_decompose_batched(const gf2_batch_item *items, int64_t count, const uint64_t *A,
-                          uint64_t *L, uint64_t *E, int64_t *perm, int64_t *pivcols,
-                          int64_t *rank, void *stream) {
-  std::vector<BatchDesc> descs;
-  int64_t maxw = 0;
-  int rc = batch_descs(items, count, false, descs, &maxw);
-  if (rc) return rc;
-  if (count == 0) return GF2_OK;
-  if (!rank) return fail(GF2_EINVAL, "gf2_decompose_batched: null rank");
-  if (maxw > 0 && !A) return fail(GF2_EINVAL, "gf2_decompose_batched: null A");
-  hipStream_t s = (hipStream_t)stream;
-  int ncu = 1;
-  if ((rc = device_cus(&ncu))) return rc;
-  const int workers = (int)std::min<int64_t>(count, batch_workers(ncu));
-  const int64_t wslot = (std::max<int64_t>(maxw, 1) + 31) / 32 * 32;
-  const size_t need = align256((size_t)count * sizeof(BatchDesc)) + 256 +
-                      align256((size_t)workers * (size_t)wslot * 8);
-  void *ws = nullptr;
-  if ((rc = get_workspace(s, need, &ws))) return rc;
+// A batched decomposition's workspace: the sorted descriptors, the queue head
+// and one working-copy slot per persistent workgroup (slot sized for the
+// largest item, rounded to 32 words).
+size_t batch_dec_need(int64_t count, int64_t max_words, int workers) {
+  if (count <= 0) return 0;
+  const int64_t wslot = (std::max<int64_t>(max_words, 1) + 31) / 32 * 32;
+  return align256((size_t)count * sizeof(BatchDesc)) + 256 + align256((size_t)workers * (size_t)wslot * 8);
+}
+
+int batch_dec_body(const std::vector<BatchDesc> &descs, int64_t max_words, int workers, const uint64_t *A, uint64_t *L,
+                   uint64_t *E, int64_t *perm, int64_t *pivcols, int64_t *rank, void *ws, hipStream_t s) {
+  int rc;
+  const int64_t count = (int64_t)descs.size();
+  const int64_t wslot = (std::max<int64_t>(max_words, 1) + 31) / 32 * 32;
   Carver c(ws);
   BatchDesc *dd = c.take<BatchDesc>((size_t)count);
   uint32_t *ctr = c.take<uint32_t>(64);
@@ -1068,25 +1131,23 @@ int gf2_decompose_batched(const gf2_batch_item *items, int64_t count, const uint
   return GF2_OK;
 }
 
-int gf2_solve_batched(const gf2_batch_item *items, int64_t count, const uint64_t *L,
-                      const uint64_t *E, const int64_t *perm, const int64_t *pivcols,
-                      const int64_t *rank, const uint64_t *B, uint64_t *X, int32_t *consistent,
-                      void *stream) {
-  std::vector<BatchDesc> descs;
-  int64_t maxw = 0;
-  int rc = batch_descs(items, count, true, descs, &maxw);
+int batch_workers_for(int64_t count, int *workers) {
+  int ncu = 1;
+  int rc = device_cus(&ncu);
   if (rc) return rc;
-  if (count == 0) return GF2_OK;
-  if (!L || !E || !perm || !pivcols || !rank || !B || !X || !consistent)
-    return fail(GF2_EINVAL, "gf2_solve_batched: null pointer argument");
-  hipStream_t s = (hipStream_t)stream;
-  void *ws = nullptr;
-  if ((rc = get_workspace(s, align256((size_t)count * sizeof(BatchDesc)), &ws))) return rc;
+  *workers = (int)std::min<int64_t>(std::max<int64_t>(count, 1), batch_workers(ncu));
+  return GF2_OK;
+}
+
+int batch_solve_body(const std::vector<BatchDesc> &descs, const uint64_t *L, const uint64_t *E, const int64_t *perm,
+                     const int64_t *pivcols, const int64_t *rank, const uint64_t *B, uint64_t *X, int32_t *consistent,
+                     void *ws, hipStream_t s) {
+  int rc;
   BatchDesc *dd = (BatchDesc *)ws;
   if ((rc = stage_descs(descs, dd, s))) return rc;
   BatchSolveArgs a;
   a.d = dd;
-  a.count = (int32_t)count;
+  a.count = (int32_t)descs.size();
   a.L = L;
   a.E = E;
   a.perm = perm;
@@ -1097,6 +1158,193 @@ int gf2_solve_batched(const gf2_batch_item *items, int64_t count, const uint64_t
   a.consistent = consistent;
   HIPCHK(launch_batch_solve(a, s));
   return GF2_OK;
+}
+
+}  // namespace
+
+namespace {
+int batch_dec_check(const gf2_batch_item *items, int64_t count, const uint64_t *A, const int64_t *rank,
+                    std::vector<BatchDesc> &descs, int64_t *maxw) {
+  int rc = batch_descs(items, count, false, descs, maxw);
+  if (rc) return rc;
+  if (count == 0) return GF2_OK;
+  if (!rank) return fail(GF2_EINVAL, "gf2_decompose_batched: null rank");
+  if (*maxw > 0 && !A) return fail(GF2_EINVAL, "gf2_decompose_batched: null A");
+  return GF2_OK;
+}
+
+int batch_solve_check(const gf2_batch_item *items, int64_t count, const uint64_t *L, const uint64_t *E,
+                      const int64_t *perm, const int64_t *pivcols, const int64_t *rank, const uint64_t *B,
+                      const uint64_t *X, const int32_t *consistent, std::vector<BatchDesc> &descs) {
+  int64_t maxw = 0;
+  int rc = batch_descs(items, count, true, descs, &maxw);
+  if (rc) return rc;
+  if (count == 0) return GF2_OK;
+  if (!L || !E || !perm || !pivcols || !rank || !B || !X || !consistent)
+    return fail(GF2_EINVAL, "gf2_solve_batched: null pointer argument");
+  return GF2_OK;
+}
+}  // namespace
+
+extern "C" {
+
+size_t gf2_workspace_bytes(int op, int64_t rows, int64_t cols, int64_t k) {
+  if (rows < 0 || cols < 0 || k < 0) {
+    fail(GF2_EINVAL, "gf2_workspace_bytes: negative size");
+    return SIZE_MAX;
+  }
+  switch (op) {
+    case GF2_OP_MATMUL:
+      return matmul_plan(rows, k, cols).total();
+    case GF2_OP_DECOMPOSE:
+      return (rows == 0 || cols == 0) ? 0 : decomp_bytes(rows, cols);
+    case GF2_OP_RANK: {
+      gf2_mat a{nullptr, rows, cols, 1, rows};
+      return rank_need(&a);
+    }
+    case GF2_OP_SOLVE:
+      return (rows == 0 || cols == 0 || k == 0) ? 0 : solve_need(rows, cols, k);
+    case GF2_OP_DECOMPOSE_BATCHED: {
+      if (cols > GF2_BATCH_MAX_DIM || k > GF2_BATCH_MAX_DIM) break;
+      int workers = 1;
+      if (batch_workers_for(rows, &workers)) return SIZE_MAX;
+      return batch_dec_need(rows, k * ceil_div(cols, 64), workers);
+    }
+    case GF2_OP_SOLVE_BATCHED:
+      return rows > 0 ? align256((size_t)rows * sizeof(BatchDesc)) : 0;
+    default:
+      break;
+  }
+  fail(GF2_EINVAL, "gf2_workspace_bytes: unknown operation or size out of range");
+  return SIZE_MAX;
+}
+
+int gf2_matmul(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B, int accumulate, void *stream) {
+  int rc;
+  if ((rc = matmul_check(C, A, B))) return rc;
+  const MatmulPlan p = matmul_plan(A->rows, A->cols, B->cols);
+  void *ws = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  if (p.total() && (rc = get_workspace(s, p.total(), &ws))) return rc;
+  return matmul_body(C, A, B, accumulate, p, ws, s);
+}
+
+int gf2_matmul_ws(const gf2_mat *C, const gf2_mat *A, const gf2_mat *B, int accumulate, void *workspace,
+                  size_t workspace_bytes, void *stream) {
+  int rc;
+  if ((rc = matmul_check(C, A, B))) return rc;
+  const MatmulPlan p = matmul_plan(A->rows, A->cols, B->cols);
+  if ((rc = check_ws(workspace, workspace_bytes, p.total(), "gf2_matmul_ws"))) return rc;
+  return matmul_body(C, A, B, accumulate, p, workspace, (hipStream_t)stream);
+}
+
+int gf2_decompose(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t *perm,
+                  int64_t *pivcols, int64_t *rank, void *stream) {
+  int rc;
+  if ((rc = decompose_check(A, L, E))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  void *ws = nullptr;
+  const size_t need = decompose_need(A);
+  if (need && (rc = get_workspace(s, need, &ws))) return rc;
+  return decompose_body(A, L, E, perm, pivcols, rank, ws, s, false);
+}
+
+int gf2_decompose_ws(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t *perm, int64_t *pivcols,
+                     int64_t *rank, void *workspace, size_t workspace_bytes, void *stream) {
+  int rc;
+  if ((rc = decompose_check(A, L, E))) return rc;
+  if ((rc = check_ws(workspace, workspace_bytes, decompose_need(A), "gf2_decompose_ws"))) return rc;
+  return decompose_body(A, L, E, perm, pivcols, rank, workspace, (hipStream_t)stream, false);
+}
+
+int gf2_rank(const gf2_mat *A, int64_t *rank, void *stream) {
+  int rc;
+  if ((rc = rank_check(A, rank))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  void *ws = nullptr;
+  const size_t need = rank_need(A);
+  if (need && (rc = get_workspace(s, need, &ws))) return rc;
+  return rank_body(A, rank, ws, s);
+}
+
+int gf2_rank_ws(const gf2_mat *A, int64_t *rank, void *workspace, size_t workspace_bytes, void *stream) {
+  int rc;
+  if ((rc = rank_check(A, rank))) return rc;
+  if ((rc = check_ws(workspace, workspace_bytes, rank_need(A), "gf2_rank_ws"))) return rc;
+  return rank_body(A, rank, workspace, (hipStream_t)stream);
+}
+
+int gf2_solve(const gf2_mat *A, const gf2_mat *B, const gf2_mat *X, uint64_t *consistent,
+              int64_t *rank, void *stream) {
+  int rc;
+  if ((rc = solve_check(A, B, X, consistent))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  void *ws = nullptr;
+  if ((rc = get_workspace(s, solve_need(A->rows, A->cols, B->cols), &ws))) return rc;
+  return solve_body(A, B, X, consistent, rank, ws, s);
+}
+
+int gf2_solve_ws(const gf2_mat *A, const gf2_mat *B, const gf2_mat *X, uint64_t *consistent, int64_t *rank,
+                 void *workspace, size_t workspace_bytes, void *stream) {
+  int rc;
+  if ((rc = solve_check(A, B, X, consistent))) return rc;
+  if ((rc = check_ws(workspace, workspace_bytes, solve_need(A->rows, A->cols, B->cols), "gf2_solve_ws"))) return rc;
+  return solve_body(A, B, X, consistent, rank, workspace, (hipStream_t)stream);
+}
+
+
+int gf2_decompose_batched(const gf2_batch_item *items, int64_t count, const uint64_t *A,
+                          uint64_t *L, uint64_t *E, int64_t *perm, int64_t *pivcols,
+                          int64_t *rank, void *stream) {
+  std::vector<BatchDesc> descs;
+  int64_t maxw = 0;
+  int rc = batch_dec_check(items, count, A, rank, descs, &maxw);
+  if (rc || count == 0) return rc;
+  int workers = 1;
+  if ((rc = batch_workers_for(count, &workers))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  void *ws = nullptr;
+  if ((rc = get_workspace(s, batch_dec_need(count, maxw, workers), &ws))) return rc;
+  return batch_dec_body(descs, maxw, workers, A, L, E, perm, pivcols, rank, ws, s);
+}
+
+int gf2_decompose_batched_ws(const gf2_batch_item *items, int64_t count, const uint64_t *A, uint64_t *L, uint64_t *E,
+                             int64_t *perm, int64_t *pivcols, int64_t *rank, void *workspace,
+                             size_t workspace_bytes, void *stream) {
+  std::vector<BatchDesc> descs;
+  int64_t maxw = 0;
+  int rc = batch_dec_check(items, count, A, rank, descs, &maxw);
+  if (rc || count == 0) return rc;
+  int workers = 1;
+  if ((rc = batch_workers_for(count, &workers))) return rc;
+  if ((rc = check_ws(workspace, workspace_bytes, batch_dec_need(count, maxw, workers), "gf2_decompose_batched_ws")))
+    return rc;
+  return batch_dec_body(descs, maxw, workers, A, L, E, perm, pivcols, rank, workspace, (hipStream_t)stream);
+}
+
+int gf2_solve_batched(const gf2_batch_item *items, int64_t count, const uint64_t *L,
+                      const uint64_t *E, const int64_t *perm, const int64_t *pivcols,
+                      const int64_t *rank, const uint64_t *B, uint64_t *X, int32_t *consistent,
+                      void *stream) {
+  std::vector<BatchDesc> descs;
+  int rc = batch_solve_check(items, count, L, E, perm, pivcols, rank, B, X, consistent, descs);
+  if (rc || count == 0) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  void *ws = nullptr;
+  if ((rc = get_workspace(s, align256((size_t)count * sizeof(BatchDesc)), &ws))) return rc;
+  return batch_solve_body(descs, L, E, perm, pivcols, rank, B, X, consistent, ws, s);
+}
+
+int gf2_solve_batched_ws(const gf2_batch_item *items, int64_t count, const uint64_t *L, const uint64_t *E,
+                         const int64_t *perm, const int64_t *pivcols, const int64_t *rank, const uint64_t *B,
+                         uint64_t *X, int32_t *consistent, void *workspace, size_t workspace_bytes, void *stream) {
+  std::vector<BatchDesc> descs;
+  int rc = batch_solve_check(items, count, L, E, perm, pivcols, rank, B, X, consistent, descs);
+  if (rc || count == 0) return rc;
+  if ((rc = check_ws(workspace, workspace_bytes, align256((size_t)count * sizeof(BatchDesc)),
+                     "gf2_solve_batched_ws")))
+    return rc;
+  return batch_solve_body(descs, L, E, perm, pivcols, rank, B, X, consistent, workspace, (hipStream_t)stream);
 }
 
 int gf2_autotune(int64_t max_size, void *stream) {
@@ -1120,7 +1368,7 @@ int gf2_autotune(int64_t max_size, void *stream) {
 
   // ---- product-kernel tile per size class, at the decomposition's inner
   // dimension (one 512-column panel) on synthetic operands
-  const int cand[4] = {13, 14, 15, 16};
+  const int cand[4] = {0, 1, 2, 3};
   const int bsel[kTuneBlocks] = {1, 3, 8, 32};
   int nr = 0;
   while (nr < kTuneRows && ((int64_t)256 << nr) <= max_size) ++nr;

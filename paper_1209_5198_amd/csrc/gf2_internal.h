@@ -128,8 +128,8 @@ hipError_t launch_extract_L(const DecWork &w, const gf2_mat &L, hipStream_t s);
 hipError_t launch_finish(const DecWork &w, int64_t *perm, int64_t *pivcols, int64_t *rank,
                          hipStream_t s);
 
-constexpr int kGemmVariants = 17;  // product-kernel variants 0 .. kGemmVariants-1
-constexpr int kGemmMfma = 17;      // gf2_matmul only: the fp4 matrix-core product (k_mfma.hip)
+constexpr int kGemmVariants = 6;   // product-kernel variants 0 .. kGemmVariants-1
+constexpr int kGemmMfma = 6;       // gf2_matmul only: the fp4 matrix-core product (k_mfma.hip)
 size_t mfma_ws_bytes(int64_t kwords, int64_t m_words, int64_t rows);  // its workspace
 bool mfma_splits_inner(const GemmArgs &a, int ncu);  // the launch splits the inner dimension
 hipError_t launch_gemm_mfma(const GemmArgs &a, int64_t bwords, uint64_t *ws, int ncu, hipStream_t s);
@@ -142,6 +142,10 @@ hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, hipStr
 hipError_t launch_post(const DecWork &w, int q0, int s_eff, hipStream_t s);
 hipError_t launch_xor(uint64_t *dst, const uint64_t *a, const uint64_t *b, size_t nwords,
                       hipStream_t s);
+// dst[0 .. nwords) = 0 by a kernel (no memset node where a caller captures the launches)
+hipError_t launch_zero(uint64_t *dst, size_t nwords, hipStream_t s);
+// outputs of an empty factorization: perm[i] = i for i < n (perm may be null), *rank = 0 (rank may be null)
+hipError_t launch_empty_outputs(int64_t *perm, int64_t n, int64_t *rank, hipStream_t s);
 hipError_t launch_fill_bits(uint64_t *dst, size_t nwords, uint64_t seed, hipStream_t s);  // timing operands
 // microbenchmarks (k_probe.hip): kinds 0..5, *work = bytes, operations or multiply-accumulates
 constexpr int kProbeKinds = 6;

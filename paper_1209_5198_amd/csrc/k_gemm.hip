@@ -9,17 +9,17 @@
 // gfx950 mapping.  A workgroup owns a tile of TM rows x one 16-word column
 // block of C (1024 columns); four tables (32 inner bits) are built per step in
 // LDS (128 KB) and every row of the tile then does its four lookups, with two
-// barriers per step.  B rows and A words of the next step are prefetched into
-// registers during the lookups, and the accumulators stay in registers for the
-// whole inner loop, so C is read and written once per launch.
-//   k_gemm_wide  (the default) eight 8-lane groups per wave; lane w2 of a
-//                group owns words 2*w2, 2*w2+1 of its group's row and one
-//                16-byte read fetches them from a 128-byte table entry.
-//                Adjacent groups read the two interleaved tables of a pair in
-//                the same instruction, so 16 lanes cover 256 contiguous bytes
-//                (no bank conflicts at the full 16-byte read rate).
-//   k_gemm_quad  four 16-lane groups per wave, one 8-byte read per lookup.
-//   k_gemm_db    two tables per stage, double-buffered.
+// barriers per step.  B rows and A words of the next step are prefetched during
+// the lookups, and the accumulators stay in registers for the whole inner loop,
+// so C is read and written once per launch.
+//   k_gemm_wide    eight 8-lane groups per wave; lane w2 of a group owns words
+//                  2*w2, 2*w2+1 of its group's row and one 16-byte read fetches
+//                  them from a 128-byte table entry.  Adjacent groups read the
+//                  two interleaved tables of a pair in the same instruction, so
+//                  16 lanes cover 256 contiguous bytes (no bank conflicts at the
+//                  full 16-byte read rate).
+//   k_gemm_narrow  the next panel's 8 words: 64-byte entries, eight tables (a
+//                  whole 64-bit A word) per step.
 // The byte address of a table entry is formed by one byte permute of (A bits,
 // lane base), and the XORs use the three-input bitwise instruction.
 #include <hip/hip_ext.h>
@@ -29,20 +29,8 @@
 namespace gf2 {
 
 // Rows owned by one lane of a product tile: tile0 + l0 + S*u for u in [0, RPL)
-// (l0 = 4 * wave + group, S = 4 * waves).  [ulo, uhi) are the u whose row lies
-// in [rb, re).  Row u of the lane's column word sits at Cl + u*S*16 with
-// Cl = &C[(blk * ldC + tile0 + l0) * 16 + word].  The base pointer passes
-// through an empty asm statement so that the compiler forms the 64 per-row
-// addresses next to their loads and stores instead of keeping them alive
-// across the inner loop (which spilled registers to scratch).
-// x ^ y ^ z on each 32-bit half with one three-input bitwise instruction
-// (truth table 0x96 is the three-way exclusive or).
-__device__ inline uint64_t xor3(uint64_t x, uint64_t y, uint64_t z) {
-  const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)x, (uint32_t)y, (uint32_t)z, 0x96);
-  const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(x >> 32), (uint32_t)(y >> 32), (uint32_t)(z >> 32), 0x96);
-  return ((uint64_t)hi << 32) | lo;
-}
-
+// (l0 = the lane's group index in the workgroup, S = groups per workgroup).
+// [ulo, uhi) are the u whose row lies in [rb, re).
 template <int RPL, int S>
 __device__ inline void lane_rows(int64_t tile0, int l0, int64_t rb, int64_t re, int &ulo, int &uhi) {
   const int64_t b = tile0 + l0;
@@ -53,321 +41,9 @@ __device__ inline void lane_rows(int64_t tile0, int l0, int64_t rb, int64_t re, 
   uhi = (int)(hi < RPL ? hi : RPL);
 }
 
-__device__ inline uint64_t *lane_c_base(const GemmArgs &a, int blk, int64_t tile0, int l0, int wl) {
-  uint64_t *C = a.C;
-  asm volatile("" : "+s"(C));
-  return C + (((int64_t)blk * a.ldC + tile0 + l0) * TW + wl);
-}
-
-template <int RPL, int S>
-__device__ inline void load_acc(uint64_t (&acc)[RPL], const uint64_t *Cl, bool on, int ulo, int uhi) {
-#pragma unroll
-  for (int u = 0; u < RPL; ++u) acc[u] = (on && u >= ulo && u < uhi) ? Cl[(int64_t)u * S * TW] : 0ull;
-}
-
-template <int RPL, int S>
-__device__ inline uint64_t store_acc(const uint64_t (&acc)[RPL], uint64_t *Cl, bool on, int ulo, int uhi) {
-  uint64_t any = 0;
-#pragma unroll
-  for (int u = 0; u < RPL; ++u)
-    if (on && u >= ulo && u < uhi) {
-      Cl[(int64_t)u * S * TW] = acc[u];
-      any |= acc[u];
-    }
-  return any;
-}
-
-// Four tables (32 inner bits) per step, two barriers per step.
-template <int NT, int TM>
-__global__ __launch_bounds__(NT) void k_gemm_quad(GemmArgs a) {
-  constexpr int NW = NT / 64;          // waves
-  constexpr int RPL = TM / (4 * NW);   // rows per lane
-  constexpr int JOBS = NT / 16;        // table-build jobs (16 threads each, one per word)
-  constexpr int EPJ = 4 * 256 / JOBS;  // entries per job
-  constexpr int LOGE = EPJ == 16 ? 4 : (EPJ == 32 ? 5 : 6);
-  static_assert(RPL * 4 * NW == TM && RPL % 4 == 0, "tile");
-  static_assert(EPJ == 16 || EPJ == 32 || EPJ == 64, "build split");
-  static_assert(TM % NT == 0, "A staging");
-  // Four tables of 256 entries x 16 words (128 KB).  Tables g = 2p + s are stored
-  // as T[p][idx][s][word], so the byte address of entry idx of table g for word
-  // wl is p*65536 + idx*256 + s*128 + wl*8: byte 1 of the address is the index
-  // itself, and one byte permute of (A bits, lane base) yields the address.
-  __shared__ uint64_t T[2][256][2][TW];
-  __shared__ uint32_t As[2 * TM];      // the tile's A word for the current 64 inner bits
-
-  if (a.skip_flag && *a.skip_flag == 0u) return;  // the Schur complement is already zero
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6, h = lane >> 4, wl = lane & 15;
-  const int blk = blockIdx.y + (a.qc0 >> 4);
-  const int64_t q = (int64_t)blk * TW + wl;
-  const bool qok = q >= a.qc0 && q < a.qc1;
-
-  const int64_t tile0 = a.row_tile0 + (int64_t)blockIdx.x * TM;
-  int64_t rb = tile0;
-  if (a.bsub) {  // rows below the panel's pivots: first row after the last sub-panel's pivots
-    const int64_t d = a.bsub[a.kwords - 1].R + a.bsub[a.kwords - 1].r;
-    if (d > rb) rb = d;
-  }
-  int64_t re = tile0 + TM < a.row_end ? tile0 + TM : a.row_end;
-  if (rb >= re) return;
-
-  int ulo, uhi;
-  lane_rows<RPL, 4 * NW>(tile0, 4 * wv + h, rb, re, ulo, uhi);
-  uint64_t acc[RPL];
-  load_acc<RPL, 4 * NW>(acc, lane_c_base(a, blk, tile0, 4 * wv + h, wl), a.accumulate && qok, ulo, uhi);
-
-  const int bw = tid & 15;
-  const int job = tid >> 4;
-  const int g_b = job / (256 / EPJ), uu = job % (256 / EPJ);
-  const int64_t bq = (int64_t)blk * TW + bw;
-  const bool bq_ok = bq >= a.qc0 && bq < a.qc1;
-
-  auto load_b = [&](int hh, uint64_t (&bv)[8]) {
-    const int kw = hh >> 1, half = hh & 1;
-    int64_t browR = 64ll * kw;
-    int blim;
-    if (a.bsub) {
-      browR = a.bsub[kw].R;
-      blim = a.bsub[kw].r;
-    } else {
-      const int64_t left = a.b_rows - 64ll * kw;
-      blim = left >= 64 ? 64 : (left > 0 ? (int)left : 0);
-    }
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int t = 32 * half + 8 * g_b + b;
-      bv[b] = (bq_ok && t < blim) ? a.B[widx(a.ldB, browR + t, bq)] : 0ull;
-    }
-  };
-  constexpr int APT = TM / NT;
-  auto load_a = [&](int kw, uint64_t (&av)[APT]) {
-#pragma unroll
-    for (int j = 0; j < APT; ++j) {
-      const int64_t i = tile0 + tid + (int64_t)j * NT;
-      av[j] = (i >= rb && i < re) ? a.A[widx(a.ldA, i, a.a_word0 + kw)] : 0ull;
-    }
-  };
-
-  uint64_t bv[8], av[APT];
-  load_b(0, bv);
-  load_a(0, av);
-  const char *Tb = (const char *)&T[0][0][0][0];
-  uint32_t lbase[4];
-#pragma unroll
-  for (int g = 0; g < 4; ++g) lbase[g] = ((uint32_t)(g >> 1) << 16) | ((uint32_t)(g & 1) << 7) | ((uint32_t)wl << 3);
-  const int nh = 2 * a.kwords;
-  for (int hh = 0; hh < nh; ++hh) {
-    const int half = hh & 1;
-    __syncthreads();  // previous lookups finished: T and As are free
-    if (half == 0) {
-#pragma unroll
-      for (int j = 0; j < APT; ++j) {
-        As[2 * (tid + j * NT)] = (uint32_t)av[j];
-        As[2 * (tid + j * NT) + 1] = (uint32_t)(av[j] >> 32);
-      }
-    }
-    {
-      uint64_t cur = 0ull;
-#pragma unroll
-      for (int b = LOGE; b < 8; ++b)
-        if ((uu >> (b - LOGE)) & 1) cur ^= bv[b];
-#pragma unroll
-      for (int j = 0; j < EPJ; ++j) {
-        const int gj = j ^ (j >> 1);
-        T[g_b >> 1][EPJ * uu + gj][g_b & 1][bw] = cur;
-        if (j < EPJ - 1) cur ^= bv[__builtin_ctz(j + 1)];
-      }
-    }
-    if (hh + 1 < nh) load_b(hh + 1, bv);  // in flight during the lookups
-    if (half == 0 && (hh >> 1) + 1 < a.kwords) load_a((hh >> 1) + 1, av);
-    __syncthreads();
-#pragma unroll
-    for (int u0 = 0; u0 < RPL; u0 += 4) {
-      uint32_t a32[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) a32[v] = As[2 * (4 * (wv + NW * (u0 + v)) + h) + half];
-      uint64_t t[4][4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          // address bytes: [lane base | byte g of a32 | table pair | 0]
-          const uint32_t addr = __builtin_amdgcn_perm(a32[v], lbase[g], 0x0C020000u | ((4u + g) << 8));
-          t[v][g] = *(const uint64_t *)(Tb + addr);
-        }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u0 + v] = xor3(xor3(acc[u0 + v], t[v][0], t[v][1]), t[v][2], t[v][3]);
-    }
-  }
-
-  const uint64_t any = store_acc<RPL, 4 * NW>(acc, lane_c_base(a, blk, tile0, 4 * wv + h, wl), qok, ulo, uhi);
-  if (a.nzflag) {
-    if (__ballot(any != 0ull) != 0ull && lane == 0) atomicOr(a.nzflag, 1u);
-  }
-  if (a.work && tid == 0) {
-    int64_t lo = (int64_t)blk * TW, hi = lo + TW;
-    if (lo < a.qc0) lo = a.qc0;
-    if (hi > a.qc1) hi = a.qc1;
-    const unsigned long long words = hi > lo ? (unsigned long long)(hi - lo) : 0ull;
-    atomicAdd(a.work, (unsigned long long)(re - rb) * words * (unsigned long long)a.kwords * 8ull);
-  }
-}
-
-template <int NT, int TM>
-__global__ __launch_bounds__(NT) void k_gemm_db(GemmArgs a) {
-  constexpr int NW = NT / 64;          // waves
-  constexpr int RPL = TM / (4 * NW);   // rows per lane
-  constexpr int EPT = 2 * 256 * TW / NT;  // table entries built per thread per stage
-  constexpr int LOGE = EPT == 8 ? 3 : (EPT == 16 ? 4 : 5);
-  static_assert(RPL * 4 * NW == TM && RPL % 4 == 0, "tile");
-  static_assert(EPT == 8 || EPT == 16 || EPT == 32, "build split");
-  static_assert(TM % NT == 0, "A staging");
-  // Two buffers of two tables (256 entries x 16 words each).  Entry idx of table
-  // s in buffer b, word wl, sits at byte b*65536 + idx*256 + s*128 + wl*8: byte 1
-  // of the address is the index, so one byte permute of (A bits, lane base)
-  // forms the address.
-  __shared__ uint64_t T[2][256][2][TW];
-  __shared__ uint32_t As[2][2 * TM];   // A word of each row, double-buffered by 64-bit step
-
-  if (a.skip_flag && *a.skip_flag == 0u) return;  // the Schur complement is already zero
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6, h = lane >> 4, wl = lane & 15;
-  const int blk = blockIdx.y + (a.qc0 >> 4);
-  const int64_t q = (int64_t)blk * TW + wl;
-  const bool qok = q >= a.qc0 && q < a.qc1;
-
-  const int64_t tile0 = a.row_tile0 + (int64_t)blockIdx.x * TM;
-  int64_t rb = tile0;
-  if (a.bsub) {  // rows below the panel's pivots: first row after the last sub-panel's pivots
-    const int64_t d = a.bsub[a.kwords - 1].R + a.bsub[a.kwords - 1].r;
-    if (d > rb) rb = d;
-  }
-  int64_t re = tile0 + TM < a.row_end ? tile0 + TM : a.row_end;
-  if (rb >= re) return;
-
-  int ulo, uhi;
-  lane_rows<RPL, 4 * NW>(tile0, 4 * wv + h, rb, re, ulo, uhi);
-  uint64_t acc[RPL];
-  load_acc<RPL, 4 * NW>(acc, lane_c_base(a, blk, tile0, 4 * wv + h, wl), a.accumulate && qok, ulo, uhi);
-
-  // table-build role: table sb of the stage, word bw, entries [EPT*uu, EPT*uu + EPT)
-  const int bw = tid & 15;
-  const int sb = tid / (NT / 2);
-  const int uu = (tid >> 4) % (256 / EPT);
-  const int64_t bq = (int64_t)blk * TW + bw;
-  const bool bq_ok = bq >= a.qc0 && bq < a.qc1;
-
-  // B rows of table sb of stage st (inner bits [16 st + 8 sb, +8))
-  auto load_b = [&](int st, uint64_t (&bv)[8]) {
-    const int kw = st >> 2;
-    int64_t browR = 64ll * kw;
-    int blim;
-    if (a.bsub) {
-      browR = a.bsub[kw].R;
-      blim = a.bsub[kw].r;
-    } else {
-      const int64_t left = a.b_rows - 64ll * kw;
-      blim = left >= 64 ? 64 : (left > 0 ? (int)left : 0);
-    }
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int t = 16 * (st & 3) + 8 * sb + b;
-      bv[b] = (bq_ok && t < blim) ? a.B[widx(a.ldB, browR + t, bq)] : 0ull;
-    }
-  };
-  constexpr int APT = TM / NT;  // A rows staged per thread
-  auto load_a = [&](int kw, uint64_t (&av)[APT]) {
-#pragma unroll
-    for (int j = 0; j < APT; ++j) {
-      const int64_t i = tile0 + tid + (int64_t)j * NT;
-      av[j] = (i >= rb && i < re) ? a.A[widx(a.ldA, i, a.a_word0 + kw)] : 0ull;
-    }
-  };
-  auto build = [&](int buf, const uint64_t (&bv)[8]) {
-    uint64_t cur = 0ull;
-#pragma unroll
-    for (int b = LOGE; b < 8; ++b)
-      if ((uu >> (b - LOGE)) & 1) cur ^= bv[b];
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const int gj = j ^ (j >> 1);
-      T[buf][EPT * uu + gj][sb][bw] = cur;
-      if (j < EPT - 1) cur ^= bv[__builtin_ctz(j + 1)];
-    }
-  };
-  auto stage_a = [&](int buf, const uint64_t (&av)[APT]) {
-#pragma unroll
-    for (int j = 0; j < APT; ++j) {
-      As[buf][2 * (tid + j * NT)] = (uint32_t)av[j];
-      As[buf][2 * (tid + j * NT) + 1] = (uint32_t)(av[j] >> 32);
-    }
-  };
-
-  const char *Tb = (const char *)&T[0][0][0][0];
-  uint32_t lbase[2];
-#pragma unroll
-  for (int s2 = 0; s2 < 2; ++s2) lbase[s2] = ((uint32_t)s2 << 7) | ((uint32_t)wl << 3);
-
-  const int nst = 4 * a.kwords;  // stages of 16 inner bits
-  uint64_t bv[8], av[APT];
-  load_b(0, bv);
-  load_a(0, av);
-  stage_a(0, av);
-  build(0, bv);
-  if (nst > 1) load_b(1, bv);
-  if (a.kwords > 1) load_a(1, av);
-  for (int st = 0; st < nst; ++st) {
-    __syncthreads();  // stage st's tables and A words are complete; buffer st+1 is free
-    if (st + 1 < nst) {
-      if (((st + 1) & 3) == 0) stage_a(((st + 1) >> 2) & 1, av);
-      build((st + 1) & 1, bv);
-      if (st + 2 < nst) load_b(st + 2, bv);
-      if (((st + 1) & 3) == 0 && ((st + 1) >> 2) + 1 < a.kwords) load_a(((st + 1) >> 2) + 1, av);
-    }
-    // ---- lookups of stage st: two 8-byte reads and two XORs per output word
-    const uint32_t *Ast = As[(st >> 2) & 1];
-    const int sh = 16 * (st & 1);           // 16-bit half of the 32-bit A half
-    const int ah = (st >> 1) & 1;           // which 32-bit half of the A word
-    const uint32_t bbase = (uint32_t)(st & 1) << 16;
-#pragma unroll
-    for (int u0 = 0; u0 < RPL; u0 += 4) {
-      uint32_t a16[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) a16[v] = Ast[2 * (4 * (wv + NW * (u0 + v)) + h) + ah] >> sh;
-      uint64_t t[4][2];
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2) {
-          // address bytes: [lane base | byte s2 of the 16 A bits | buffer | 0]
-          const uint32_t addr = __builtin_amdgcn_perm(a16[v], lbase[s2] | bbase, 0x0C020000u | ((4u + s2) << 8));
-          t[v][s2] = *(const uint64_t *)(Tb + addr);
-        }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u0 + v] = xor3(acc[u0 + v], t[v][0], t[v][1]);
-    }
-  }
-
-  const uint64_t any = store_acc<RPL, 4 * NW>(acc, lane_c_base(a, blk, tile0, 4 * wv + h, wl), qok, ulo, uhi);
-  if (a.nzflag) {
-    if (__ballot(any != 0ull) != 0ull && lane == 0) atomicOr(a.nzflag, 1u);
-  }
-  if (a.work && tid == 0) {
-    int64_t lo = (int64_t)blk * TW, hi = lo + TW;
-    if (lo < a.qc0) lo = a.qc0;
-    if (hi > a.qc1) hi = a.qc1;
-    const unsigned long long words = hi > lo ? (unsigned long long)(hi - lo) : 0ull;
-    atomicAdd(a.work, (unsigned long long)(re - rb) * words * (unsigned long long)a.kwords * 8ull);
-  }
-}
-
-
-// Four tables per step like k_gemm_quad, read with 16-byte lookups: a wave is
-// eight 8-lane groups, lane w2 of a group owns words 2*w2 and 2*w2+1 of its
-// group's row, and one ds_read_b128 fetches 16 bytes of a 128-byte entry.
-// Adjacent groups read the two tables of a pair (entries 128 bytes apart) in
-// the same instruction, so every 16 lanes cover 256 contiguous bytes: the
-// conflict-free pattern that sustains the highest LDS read rate on gfx950.
+// Accumulators of a lane that owns words 2*w2, 2*w2+1 of its rows: C is read
+// (accumulate) and written as one 16-byte access per row where both words lie
+// in the written column range.
 template <int RPL, int S>
 __device__ inline void load_acc2(uint64_t (&acc)[RPL][2], const uint64_t *Cl, bool ok0, bool ok1, int ulo,
                                  int uhi) {
@@ -408,209 +84,15 @@ __device__ inline uint64_t store_acc2(const uint64_t (&acc)[RPL][2], uint64_t *C
   return any;
 }
 
+// Four tables (32 inner bits) per step.  The B rows of a step are staged
+// through LDS (two 4 KB buffers): 256 threads load the 32 rows x 16 words of a
+// later step with one 16-byte load each, store them (masked) into the free
+// buffer while the tables are built, and every thread reads its eight rows back
+// from LDS for the build.  The registers this leaves free hold a second set of
+// lookups: the loads of the next row pair are in flight while the current pair
+// is combined, so the table reads of a wave never wait for its own XORs.
 template <int NT, int TM>
 __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
-  constexpr int UB = 2;                // rows per lane looked up together
-  constexpr int NW = NT / 64;          // waves
-  constexpr int RPL = TM / (8 * NW);   // rows per lane
-  constexpr int JOBS = NT / 8;         // table-build jobs (8 threads each, one word pair per thread)
-  constexpr int EPJ = 4 * 256 / JOBS;  // entries per job
-  constexpr int LOGE = EPJ == 8 ? 3 : (EPJ == 16 ? 4 : (EPJ == 32 ? 5 : 6));
-  static_assert(RPL * 8 * NW == TM && RPL % UB == 0, "tile");
-  static_assert(EPJ == 8 || EPJ == 16 || EPJ == 32 || EPJ == 64, "build split");
-  static_assert(TM % NT == 0, "A staging");
-  // Tables g = 2p + s stored as T[p][idx][s][word]: entry idx of table g, word w
-  // at byte p*65536 + idx*256 + s*128 + w*8.
-  __shared__ uint64_t T[2][256][2][TW];
-  __shared__ uint32_t As[2 * TM];      // the tile's A word for the current 64 inner bits
-  __shared__ int64_t sR[kMaxPanelWords];  // pivot-row ranges of a mapped B (at most one panel)
-  __shared__ int sr[kMaxPanelWords];
-
-  if (a.skip_flag && *a.skip_flag == 0u) return;  // the Schur complement is already zero
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6, G = lane >> 3, w2 = lane & 7;
-  const int blk = blockIdx.y + (a.qc0 >> 4);
-  const int64_t qw = (int64_t)blk * TW + 2 * w2;
-  const bool ok0 = qw >= a.qc0 && qw < a.qc1, ok1 = qw + 1 >= a.qc0 && qw + 1 < a.qc1;
-
-  const int64_t tile0 = a.row_tile0 + (int64_t)blockIdx.x * TM;
-  int64_t rb = tile0;
-  if (a.bsub) {  // rows below the panel's pivots: first row after the last sub-panel's pivots
-    const int64_t d = a.bsub[a.kwords - 1].R + a.bsub[a.kwords - 1].r;
-    if (d > rb) rb = d;
-  }
-  int64_t re = tile0 + TM < a.row_end ? tile0 + TM : a.row_end;
-  if (rb >= re) return;
-
-  // rows of this lane: tile0 + 8*wv + G + 8*NW*u
-  int ulo, uhi;
-  lane_rows<RPL, 8 * NW>(tile0, 8 * wv + G, rb, re, ulo, uhi);
-  uint64_t acc[RPL][2];
-  {
-    uint64_t *C = a.C;
-    asm volatile("" : "+s"(C));
-    const uint64_t *Cl = C + (((int64_t)blk * a.ldC + tile0 + 8 * wv + G) * TW + 2 * w2);
-    load_acc2<RPL, 8 * NW>(acc, Cl, a.accumulate && ok0, a.accumulate && ok1, ulo, uhi);
-  }
-
-  const int bw2 = tid & 7;
-  const int job = tid >> 3;
-  const int g_b = job / (256 / EPJ), uu = job % (256 / EPJ);
-  const int64_t bq = (int64_t)blk * TW + 2 * bw2;
-  const bool bok0 = bq >= a.qc0 && bq < a.qc1, bok1 = bq + 1 >= a.qc0 && bq + 1 < a.qc1;
-
-  // B rows of table g_b for step hh (inner bits [32 hh + 8 g_b, +8)): raw
-  // 16-byte loads from a clamped (always valid) row; rows past the operand are
-  // masked when the table is built, a full step later, so the loads stay in
-  // flight during the lookups.
-  int bl_lim = 0, bl_half = 0;  // row limit and half of the loaded step
-  auto load_b = [&](int hh, uint64_t (&bv)[8][2]) {
-    const int kw = hh >> 1;
-    int64_t browR = 64ll * kw;
-    int blim;
-    if (a.bsub) {
-      browR = sR[kw];
-      blim = sr[kw];
-    } else {
-      const int64_t left = a.b_rows - 64ll * kw;
-      blim = left >= 64 ? 64 : (left > 0 ? (int)left : 0);
-    }
-    bl_lim = blim;
-    bl_half = hh & 1;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      int64_t row = browR + 32 * (hh & 1) + 8 * g_b + b;
-      row = row < a.ldB ? row : a.ldB - 1;
-      const ulonglong2 v = *(const ulonglong2 *)(a.B + widx(a.ldB, row, bq));
-      bv[b][0] = v.x;
-      bv[b][1] = v.y;
-    }
-  };
-  constexpr int APT = TM / NT;
-  auto load_a = [&](int kw, uint64_t (&av)[APT]) {
-#pragma unroll
-    for (int j = 0; j < APT; ++j) {
-      const int64_t i = tile0 + tid + (int64_t)j * NT;
-      av[j] = a.A[widx(a.ldA, i < a.ldA ? i : a.ldA - 1, a.a_word0 + kw)];  // masked when staged
-    }
-  };
-
-  if (a.bsub) {
-    if (tid < a.kwords) {
-      sR[tid] = a.bsub[tid].R;
-      sr[tid] = a.bsub[tid].r;
-    }
-    __syncthreads();
-  }
-  uint64_t bv[8][2], av[APT];
-  load_b(0, bv);
-  load_a(0, av);
-  const char *Tb = (const char *)&T[0][0][0][0];
-  // instruction g: odd groups read table g ^ 1 (the other table of the pair)
-  uint32_t lbase[4], sel[4];
-#pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    const int gg = g ^ (G & 1);
-    lbase[g] = ((uint32_t)(gg >> 1) << 16) | ((uint32_t)(gg & 1) << 7) | ((uint32_t)w2 << 4);
-    sel[g] = 0x0C020000u | ((4u + (uint32_t)gg) << 8);  // [lane base | byte gg of A | pair | 0]
-  }
-  const int nh = 2 * a.kwords;
-  for (int hh = 0; hh < nh; ++hh) {
-    const int half = hh & 1;
-    __syncthreads();  // previous lookups finished: T and As are free
-    if (half == 0) {
-#pragma unroll
-      for (int j = 0; j < APT; ++j) {
-        const int64_t i = tile0 + tid + (int64_t)j * NT;
-        const uint64_t v = (i >= rb && i < re) ? av[j] : 0ull;
-        As[2 * (tid + j * NT)] = (uint32_t)v;
-        As[2 * (tid + j * NT) + 1] = (uint32_t)(v >> 32);
-      }
-    }
-    {
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {  // rows past the operand, words outside [qc0, qc1): zero
-        const bool ok = 32 * bl_half + 8 * g_b + b < bl_lim;
-        bv[b][0] = (ok && bok0) ? bv[b][0] : 0ull;
-        bv[b][1] = (ok && bok1) ? bv[b][1] : 0ull;
-      }
-      uint64_t c0 = 0ull, c1 = 0ull;
-#pragma unroll
-      for (int b = LOGE; b < 8; ++b)
-        if ((uu >> (b - LOGE)) & 1) {
-          c0 ^= bv[b][0];
-          c1 ^= bv[b][1];
-        }
-#pragma unroll
-      for (int j = 0; j < EPJ; ++j) {
-        const int gj = j ^ (j >> 1);
-        *(ulonglong2 *)&T[g_b >> 1][EPJ * uu + gj][g_b & 1][2 * bw2] = make_ulonglong2(c0, c1);
-        if (j < EPJ - 1) {
-          c0 ^= bv[__builtin_ctz(j + 1)][0];
-          c1 ^= bv[__builtin_ctz(j + 1)][1];
-        }
-      }
-    }
-    if (hh + 1 < nh) load_b(hh + 1, bv);  // in flight during the lookups
-    if (half == 0 && (hh >> 1) + 1 < a.kwords) load_a((hh >> 1) + 1, av);
-    __syncthreads();
-#pragma unroll
-    for (int u0 = 0; u0 < RPL; u0 += UB) {
-      uint32_t a32[UB];
-#pragma unroll
-      for (int v = 0; v < UB; ++v) a32[v] = As[2 * (8 * (wv + NW * (u0 + v)) + G) + half];
-      uint4 t[UB][4];
-#pragma unroll
-      for (int v = 0; v < UB; ++v)
-#pragma unroll
-        for (int g = 0; g < 4; ++g) t[v][g] = *(const uint4 *)(Tb + __builtin_amdgcn_perm(a32[v], lbase[g], sel[g]));
-#pragma unroll
-      for (int v = 0; v < UB; ++v) {
-        uint32_t x0 = (uint32_t)acc[u0 + v][0], x1 = (uint32_t)(acc[u0 + v][0] >> 32);
-        uint32_t x2 = (uint32_t)acc[u0 + v][1], x3 = (uint32_t)(acc[u0 + v][1] >> 32);
-        x0 = __builtin_amdgcn_bitop3_b32(x0, t[v][0].x, t[v][1].x, 0x96);
-        x1 = __builtin_amdgcn_bitop3_b32(x1, t[v][0].y, t[v][1].y, 0x96);
-        x2 = __builtin_amdgcn_bitop3_b32(x2, t[v][0].z, t[v][1].z, 0x96);
-        x3 = __builtin_amdgcn_bitop3_b32(x3, t[v][0].w, t[v][1].w, 0x96);
-        x0 = __builtin_amdgcn_bitop3_b32(x0, t[v][2].x, t[v][3].x, 0x96);
-        x1 = __builtin_amdgcn_bitop3_b32(x1, t[v][2].y, t[v][3].y, 0x96);
-        x2 = __builtin_amdgcn_bitop3_b32(x2, t[v][2].z, t[v][3].z, 0x96);
-        x3 = __builtin_amdgcn_bitop3_b32(x3, t[v][2].w, t[v][3].w, 0x96);
-        acc[u0 + v][0] = ((uint64_t)x1 << 32) | x0;
-        acc[u0 + v][1] = ((uint64_t)x3 << 32) | x2;
-      }
-    }
-  }
-
-  uint64_t any;
-  {
-    uint64_t *C = a.C;
-    asm volatile("" : "+s"(C));
-    uint64_t *Cl = C + (((int64_t)blk * a.ldC + tile0 + 8 * wv + G) * TW + 2 * w2);
-    any = store_acc2<RPL, 8 * NW>(acc, Cl, ok0, ok1, ulo, uhi);
-  }
-  if (a.nzflag) {
-    if (__ballot(any != 0ull) != 0ull && lane == 0) atomicOr(a.nzflag, 1u);
-  }
-  if (a.work && tid == 0) {
-    int64_t lo = (int64_t)blk * TW, hi = lo + TW;
-    if (lo < a.qc0) lo = a.qc0;
-    if (hi > a.qc1) hi = a.qc1;
-    const unsigned long long words = hi > lo ? (unsigned long long)(hi - lo) : 0ull;
-    atomicAdd(a.work, (unsigned long long)(re - rb) * words * (unsigned long long)a.kwords * 8ull);
-  }
-}
-
-
-// k_gemm_wide with the B rows of a step staged through LDS (two 4 KB buffers)
-// instead of registers: 256 threads load the 32 rows x 16 words of a later
-// step with one 16-byte load each, store them (masked) into the free buffer
-// while the tables are built, and every thread reads its eight rows back from
-// LDS for the build.  The registers this frees hold a second set of lookups:
-// the loads of the next row pair are in flight while the current pair is
-// combined, so the table reads of a wave never wait for its own XORs.
-template <int NT, int TM>
-__global__ __launch_bounds__(NT) void k_gemm_wide2(GemmArgs a) {
   constexpr int UB = 2;                // rows per lane looked up together
   constexpr int NW = NT / 64;          // waves
   constexpr int RPL = TM / (8 * NW);   // rows per lane
@@ -993,31 +475,20 @@ __global__ __launch_bounds__(NT) void k_gemm_narrow(GemmArgs a) {
 
 // Product-kernel variants (same results; chosen per call by a tuning knob, or
 // automatically when the knob is -1):
-//   0: four tables / 32 inner bits, 1024 threads, 1024-row tiles
-//   1: four tables, 512 threads, 1024-row tiles
-//   2: four tables, 512 threads, 2048-row tiles
-//   3: double-buffered table pairs, 1024 threads, 1024-row tiles
-//   4: double-buffered table pairs, 512 threads, 2048-row tiles
-//   5: four tables, 256 threads, 512-row tiles
-//   6: four tables, 256 threads, 256-row tiles
-//   7: four tables with 16-byte lookups, 512 threads, 2048-row tiles
-//   8: four tables with 16-byte lookups, 512 threads, 1024-row tiles
-//   9: four tables with 16-byte lookups, 256 threads, 256-row tiles
-//  10: four tables with 16-byte lookups, 256 threads, 512-row tiles
-//  11: eight 64-byte-entry tables per step, 256 threads, 256 rows x 8 words
-//  12: eight 64-byte-entry tables per step, 256 threads, 512 rows x 8 words
-//  13: as 7 with the B rows staged in LDS and pipelined lookups, 512 threads, 2048-row tiles
-//  14: as 13, 512 threads, 1024-row tiles
-//  15: as 13, 256 threads, 512-row tiles
-//  16: as 13, 256 threads, 256-row tiles
+//   0: k_gemm_wide, 512 threads, 2048-row tiles
+//   1: k_gemm_wide, 512 threads, 1024-row tiles
+//   2: k_gemm_wide, 256 threads, 512-row tiles
+//   3: k_gemm_wide, 256 threads, 256-row tiles
+//   4: k_gemm_narrow, 256 threads, 256 rows x 8 words
+//   5: k_gemm_narrow, 256 threads, 512 rows x 8 words
 // Automatic choice: the largest tile that still gives at least one workgroup
 // per CU for the rows expected to be active; small launches get small tiles.
 int gemm_tile_rows(int v) {
   switch (v) {
-    case 2: case 4: case 7: case 13: return 2048;
-    case 5: case 10: case 12: case 15: return 512;
-    case 6: case 9: case 11: case 16: return 256;
-    default: return 1024;
+    case 0: return 2048;
+    case 1: return 1024;
+    case 2: case 5: return 512;
+    default: return 256;
   }
 }
 
@@ -1027,14 +498,13 @@ bool gemm_narrow_ok(int qc0, int qc1) { return qc0 % 8 == 0 && qc1 > qc0 && qc1 
 
 int gemm_auto_variant(int64_t active_rows, int qc0, int qc1, int ncu) {
   const int64_t want = ncu;
-  if (gemm_narrow_ok(qc0, qc1)) return (active_rows + 511) / 512 >= want ? 12 : 11;
+  if (gemm_narrow_ok(qc0, qc1)) return (active_rows + 511) / 512 >= want ? 5 : 4;
   const int blocks_y = ((qc1 - 1) >> 4) - (qc0 >> 4) + 1;
-  const int order[4] = {13, 14, 15, 16};
-  for (int i = 0; i < 4; ++i) {
-    const int tm = gemm_tile_rows(order[i]);
-    if (((active_rows + tm - 1) / tm) * (int64_t)blocks_y >= want) return order[i];
+  for (int v = 0; v < 4; ++v) {
+    const int tm = gemm_tile_rows(v);
+    if (((active_rows + tm - 1) / tm) * (int64_t)blocks_y >= want) return v;
   }
-  return 16;
+  return 3;
 }
 
 // With timing events (e0, e1 both set) the launch itself records the kernel's
@@ -1062,23 +532,12 @@ hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t 
       hipLaunchKernelGGL(K, GRID, dim3(NT), 0, s, a);                        \
   } while (0)
   switch (v) {
-    case 1: GF2_LAUNCH((k_gemm_quad<512, 1024>), grid, 512); break;
-    case 2: GF2_LAUNCH((k_gemm_quad<512, 2048>), grid, 512); break;
-    case 3: GF2_LAUNCH((k_gemm_db<1024, 1024>), grid, 1024); break;
-    case 4: GF2_LAUNCH((k_gemm_db<512, 2048>), grid, 512); break;
-    case 5: GF2_LAUNCH((k_gemm_quad<256, 512>), grid, 256); break;
-    case 6: GF2_LAUNCH((k_gemm_quad<256, 256>), grid, 256); break;
-    case 7: GF2_LAUNCH((k_gemm_wide<512, 2048>), grid, 512); break;
-    case 8: GF2_LAUNCH((k_gemm_wide<512, 1024>), grid, 512); break;
-    case 9: GF2_LAUNCH((k_gemm_wide<256, 256>), grid, 256); break;
-    case 10: GF2_LAUNCH((k_gemm_wide<256, 512>), grid, 256); break;
-    case 11: GF2_LAUNCH((k_gemm_narrow<256, 256>), gridn, 256); break;
-    case 12: GF2_LAUNCH((k_gemm_narrow<256, 512>), gridn, 256); break;
-    case 13: GF2_LAUNCH((k_gemm_wide2<512, 2048>), grid, 512); break;
-    case 14: GF2_LAUNCH((k_gemm_wide2<512, 1024>), grid, 512); break;
-    case 15: GF2_LAUNCH((k_gemm_wide2<256, 512>), grid, 256); break;
-    case 16: GF2_LAUNCH((k_gemm_wide2<256, 256>), grid, 256); break;
-    default: GF2_LAUNCH((k_gemm_quad<1024, 1024>), grid, 1024); break;
+    case 0: GF2_LAUNCH((k_gemm_wide<512, 2048>), grid, 512); break;
+    case 1: GF2_LAUNCH((k_gemm_wide<512, 1024>), grid, 512); break;
+    case 2: GF2_LAUNCH((k_gemm_wide<256, 512>), grid, 256); break;
+    case 4: GF2_LAUNCH((k_gemm_narrow<256, 256>), gridn, 256); break;
+    case 5: GF2_LAUNCH((k_gemm_narrow<256, 512>), gridn, 256); break;
+    default: GF2_LAUNCH((k_gemm_wide<256, 256>), grid, 256); break;
   }
 #undef GF2_LAUNCH
   return hipGetLastError();

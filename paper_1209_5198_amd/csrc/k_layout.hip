@@ -293,6 +293,35 @@ __global__ void k_fill_bits(uint64_t *dst, size_t nwords, uint64_t seed) {
   }
 }
 
+__global__ void k_zero(uint64_t *dst, size_t nwords) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = 0ull;
+}
+
+hipError_t launch_zero(uint64_t *dst, size_t nwords, hipStream_t s) {
+  if (nwords == 0) return hipSuccess;
+  size_t blocks = (nwords + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, dst, nwords);
+  return hipGetLastError();
+}
+
+__global__ void k_empty_outputs(int64_t *perm, int64_t n, int64_t *rank) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (perm)
+    for (int64_t i = g; i < n; i += (int64_t)gridDim.x * blockDim.x) perm[i] = i;
+  if (rank && g == 0) *rank = 0;
+}
+
+hipError_t launch_empty_outputs(int64_t *perm, int64_t n, int64_t *rank, hipStream_t s) {
+  if (!rank && (!perm || n <= 0)) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_empty_outputs, dim3((unsigned)blocks), dim3(256), 0, s, perm, n, rank);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_bits(uint64_t *dst, size_t nwords, uint64_t seed, hipStream_t s) {
   size_t blocks = (nwords + 255) / 256;
   if (blocks > 65536) blocks = 65536;

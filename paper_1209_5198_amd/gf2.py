@@ -13,6 +13,7 @@ words between that layout and plain row-major numpy arrays.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -28,8 +29,12 @@ GF2_EHIP = -3
 
 EXPORTED = ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_decompose_batched",
             "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_inverse", "gf2_autotune", "gf2_autotune_table",
-            "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_microbench", "gf2_release", "gf2_last_error",
-            "gf2_version")
+            "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_microbench", "gf2_workspace_bytes",
+            "gf2_matmul_ws", "gf2_decompose_ws", "gf2_rank_ws", "gf2_solve_ws", "gf2_decompose_batched_ws",
+            "gf2_solve_batched_ws", "gf2_release", "gf2_last_error", "gf2_version")
+# operation codes of gf2_workspace_bytes
+OP_MATMUL, OP_DECOMPOSE, OP_RANK, OP_SOLVE, OP_DECOMPOSE_BATCHED, OP_SOLVE_BATCHED = range(6)
+SIZE_MAX = 2 ** 64 - 1
 BATCH_MAX_DIM = 2048
 
 
@@ -80,16 +85,37 @@ def load():
                                          ctypes.POINTER(ctypes.c_double)]
         lib.gf2_microbench.argtypes = [ctypes.c_int, i64, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double), vp]
+        sz = ctypes.c_size_t
+        lib.gf2_workspace_bytes.argtypes = [ctypes.c_int, i64, i64, i64]
+        lib.gf2_workspace_bytes.restype = sz
+        lib.gf2_matmul_ws.argtypes = [P, P, P, ctypes.c_int, vp, sz, vp]
+        lib.gf2_decompose_ws.argtypes = [P, P, P, vp, vp, vp, vp, sz, vp]
+        lib.gf2_rank_ws.argtypes = [P, vp, vp, sz, vp]
+        lib.gf2_solve_ws.argtypes = [P, P, P, vp, vp, vp, sz, vp]
+        lib.gf2_decompose_batched_ws.argtypes = [PB, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        lib.gf2_solve_batched_ws.argtypes = [PB, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         lib.gf2_release.argtypes = []
         lib.gf2_last_error.restype = ctypes.c_char_p
         lib.gf2_version.restype = ctypes.c_char_p
         for name in ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_decompose_batched",
                      "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_inverse", "gf2_autotune",
                      "gf2_autotune_table", "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_microbench",
-                     "gf2_release"):
+                     "gf2_matmul_ws", "gf2_decompose_ws", "gf2_rank_ws", "gf2_solve_ws", "gf2_decompose_batched_ws",
+                     "gf2_solve_batched_ws", "gf2_release"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
+        atexit.register(_release_at_exit)
     return _lib
+
+
+def _release_at_exit():
+    """Free the library's streams, events and workspace while the HIP runtime
+    is still fully alive (only if this process used a GPU)."""
+    import sys
+
+    torch = sys.modules.get("torch")
+    if _lib is not None and torch is not None and torch.cuda.is_initialized():
+        _lib.gf2_release()
 
 
 def _check(rc: int):
@@ -259,6 +285,58 @@ def gf2_microbench(kind, nbytes=0, iters=0, stream=None):
     ms = ctypes.c_double()
     _check(load().gf2_microbench(k, int(nbytes), int(iters), ctypes.byref(rate), ctypes.byref(ms), _stream(stream)))
     return rate.value, ms.value
+
+
+def gf2_workspace_bytes(op: int, rows: int, cols: int, k: int = 0) -> int:
+    """Device bytes a *_ws call needs (op: one of the OP_* codes)."""
+    v = load().gf2_workspace_bytes(int(op), int(rows), int(cols), int(k))
+    if v == SIZE_MAX:
+        raise Gf2Error(GF2_EINVAL, load().gf2_last_error().decode())
+    return int(v)
+
+
+def _ws(workspace):
+    """(pointer, bytes) of a caller workspace tensor (or (None, 0))."""
+    if workspace is None:
+        return None, 0
+    return ctypes.c_void_p(int(workspace.data_ptr())), int(workspace.numel() * workspace.element_size())
+
+
+def gf2_matmul_ws(C: Mat, A: Mat, B: Mat, accumulate: bool, workspace, stream=None) -> None:
+    p, nb = _ws(workspace)
+    _check(load().gf2_matmul_ws(ctypes.byref(C.desc()), ctypes.byref(A.desc()), ctypes.byref(B.desc()),
+                                1 if accumulate else 0, p, nb, _stream(stream)))
+
+
+def gf2_decompose_ws(A: Mat, L, E, perm, pivcols, rank, workspace, stream=None) -> None:
+    Ld = ctypes.byref(L.desc()) if L is not None else None
+    Ed = ctypes.byref(E.desc()) if E is not None else None
+    p, nb = _ws(workspace)
+    _check(load().gf2_decompose_ws(ctypes.byref(A.desc()), Ld, Ed, _ptr(perm), _ptr(pivcols), _ptr(rank), p, nb,
+                                   _stream(stream)))
+
+
+def gf2_rank_ws(A: Mat, rank, workspace, stream=None) -> None:
+    p, nb = _ws(workspace)
+    _check(load().gf2_rank_ws(ctypes.byref(A.desc()), _ptr(rank), p, nb, _stream(stream)))
+
+
+def gf2_solve_ws(A: Mat, B: Mat, X: Mat, consistent, rank, workspace, stream=None) -> None:
+    p, nb = _ws(workspace)
+    _check(load().gf2_solve_ws(ctypes.byref(A.desc()), ctypes.byref(B.desc()), ctypes.byref(X.desc()),
+                               _ptr(consistent), _ptr(rank), p, nb, _stream(stream)))
+
+
+def gf2_decompose_batched_ws(items, A, L, E, perm, pivcols, rank, workspace, stream=None) -> None:
+    p, nb = _ws(workspace)
+    _check(load().gf2_decompose_batched_ws(items, len(items), _ptr(A), _ptr(L), _ptr(E), _ptr(perm),
+                                           _ptr(pivcols), _ptr(rank), p, nb, _stream(stream)))
+
+
+def gf2_solve_batched_ws(items, L, E, perm, pivcols, rank, B, X, consistent, workspace, stream=None) -> None:
+    p, nb = _ws(workspace)
+    _check(load().gf2_solve_batched_ws(items, len(items), _ptr(L), _ptr(E), _ptr(perm), _ptr(pivcols),
+                                       _ptr(rank), _ptr(B), _ptr(X), _ptr(consistent), p, nb, _stream(stream)))
 
 
 def gf2_release() -> None:

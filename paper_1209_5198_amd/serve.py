@@ -4,18 +4,23 @@ Requests of mixed sizes arrive over time with their matrix (and right-hand
 side) in host memory.  The loop:
 
 * **admits** requests in arrival order by HBM footprint: every admitted request
-  gets its input, outputs and a reserve for library workspace carved from one
-  device arena whose size is the admission cap, so admission is allocation and
-  a request waits until its footprint fits; its data is copied to the device on
-  a copy stream as soon as it is admitted;
+  gets its input, outputs and (for a single-matrix call) the library workspace
+  of that call carved from one device arena whose size is the admission cap, so
+  admission is allocation and a request waits until its footprint fits; its
+  data is copied to the device on a copy stream as soon as it is admitted;
 * **batches continuously**: whenever the batch stream is idle, every admitted
   small request (both sides at most GF2_BATCH_MAX_DIM) whose data has arrived
   is packed into one gf2_decompose_batched launch (rank requests in a second,
   output-free one) followed by one gf2_solve_batched launch for the solve
-  requests; requests that arrive meanwhile join the next launch;
-* runs each **large** request as one call (gf2_rank / gf2_decompose /
-  gf2_solve) on one of a few side streams, so large and small work overlap on
-  the device;
+  requests, their workspace carved from the arena for the batch's lifetime;
+  requests that arrive meanwhile join the next launch;
+* runs each **large** request as one call (gf2_rank_ws / gf2_decompose_ws /
+  gf2_solve_ws, with the workspace from its own arena block) on one of a few
+  side streams, so large and small work overlap on the device;
+
+Every byte of device memory the library works in comes from the arena, so the
+admission cap bounds the device memory of the whole loop (the library's
+per-stream look-ahead streams and events hold no buffers).
 * detects completion with HIP events and frees the request's memory; latency
   is completion time minus arrival time.
 
@@ -125,14 +130,30 @@ def _layout(r: Request):
     if r.kind == "solve":
         parts += [("b", wpr(n)), ("x", wpr(m))] if r.small else [("b", n), ("x", m)]
     parts += [("rank", 1), ("cons", 1)]
+    if not r.small:  # the single-matrix call's library workspace, carved from the block
+        op = {"rank": gf2.OP_RANK, "decompose": gf2.OP_DECOMPOSE, "solve": gf2.OP_SOLVE}[r.kind]
+        parts += [("ws", (gf2.gf2_workspace_bytes(op, n, m, 1 if r.kind == "solve" else 0) + 7) // 8)]
     off, pos = {}, 0
     for name, w in parts:
         off[name] = pos
         pos += Arena.size(w)
-    # library workspace of a single-matrix call (working matrix in 16-word
-    # blocks of rows padded to 256, plus state), charged but not carved
-    reserve = 0 if r.small else ((n + 255) // 256 * 256) * ((wpr(m) + 15) // 16 * 16) + 16 * n + 4096
-    return off, pos, reserve
+    return off, pos
+
+
+def _batch_ws_words(groups) -> int:
+    """Arena words of the workspace the launches of one batch need (they run in
+    order on one stream, so they share it): groups = lists of (rows, cols)."""
+    need = 0
+    for shapes, op in groups:
+        if not shapes:
+            continue
+        cnt = len(shapes)
+        if op == gf2.OP_DECOMPOSE_BATCHED:
+            b = gf2.gf2_workspace_bytes(op, cnt, max(m for _, m in shapes), max(n for n, _ in shapes))
+        else:
+            b = gf2.gf2_workspace_bytes(op, cnt, 0, 0)
+        need = max(need, b)
+    return (need + 7) // 8
 
 
 class Server:
@@ -151,13 +172,13 @@ class Server:
 
     # ---------------------------------------------------------------- memory
     def _admit(self, r: Request) -> bool:
-        off, span, reserve = _layout(r)
-        if span + reserve > self.arena.cap:
+        off, span = _layout(r)
+        if span > self.arena.cap:
             raise ValueError(f"request {r.id} ({r.n} x {r.m}) exceeds the admission cap")
-        base = self.arena.alloc(span + reserve)
+        base = self.arena.alloc(span)
         if base is None:
             return False
-        r.base, r.span, r.off = base, span + reserve, off
+        r.base, r.span, r.off = base, span, off
         t = self.arena.t
         with self.torch.cuda.stream(self.copy):
             a = r.A if hasattr(r.A, "data_ptr") else self.torch.from_numpy(np.ascontiguousarray(r.A).view(np.int64))
@@ -195,17 +216,18 @@ class Server:
         o = r.base
         A = self._mat(r, "A", r.n, r.m)
         rank = t[o + r.off["rank"]:o + r.off["rank"] + 1]
+        ws = t[o + r.off["ws"]:o + r.span]
         if r.kind == "rank":
-            gf2.gf2_rank(A, rank, s)
+            gf2.gf2_rank_ws(A, rank, ws, s)
         elif r.kind == "decompose":
             k = min(r.n, r.m)
-            gf2.gf2_decompose(A, self._mat(r, "L", r.n, k), self._mat(r, "E", k, r.m),
-                              t[o + r.off["perm"]:], t[o + r.off["pivcols"]:], rank, s)
+            gf2.gf2_decompose_ws(A, self._mat(r, "L", r.n, k), self._mat(r, "E", k, r.m),
+                                 t[o + r.off["perm"]:], t[o + r.off["pivcols"]:], rank, ws, s)
         else:
             B = gf2.Mat(t[o + r.off["b"]:o + r.off["b"] + max(r.n, 1)], r.n, 1, 1, max(r.n, 1))
             X = gf2.Mat(t[o + r.off["x"]:o + r.off["x"] + max(r.m, 1)], r.m, 1, 1, max(r.m, 1))
             cons = t[o + r.off["cons"]:o + r.off["cons"] + 1]
-            gf2.gf2_solve(A, B, X, cons, rank, s)
+            gf2.gf2_solve_ws(A, B, X, cons, rank, ws, s)
         ev = self.torch.cuda.Event()
         ev.record(s)
         return ev
@@ -224,29 +246,53 @@ class Server:
         return items
 
     def _launch_batch(self, reqs, s):
+        """Launch one batch: (event, outputs), or None while its block does not fit.
+        The block holds the library workspace of its launches (they run in order
+        on one stream, so they share it) and the per-item ranks and flags."""
         torch = self.torch
         t = self.arena.t
         solve = [r for r in reqs if r.kind == "solve"]
         full = solve + [r for r in reqs if r.kind == "decompose"]
         ranko = [r for r in reqs if r.kind == "rank"]
-        out = {}
+        sh = lambda rs: [(r.n, r.m) for r in rs]  # noqa: E731
+        ws_words = _batch_ws_words([(sh(full), gf2.OP_DECOMPOSE_BATCHED), (sh(solve), gf2.OP_SOLVE_BATCHED),
+                                    (sh(ranko), gf2.OP_DECOMPOSE_BATCHED)])
+        o_rank = Arena.size(ws_words)
+        o_rank2 = o_rank + Arena.size(len(full))
+        o_cons = o_rank2 + Arena.size(len(ranko))
+        total = o_cons + Arena.size((len(solve) + 1) // 2)
+        base = self.arena.alloc(total)
+        if base is None:
+            return None
+        ws = t[base:base + o_rank]
+        out = {"block": (base, total)}
         if full:
             items = self._items(full, True)
-            rank = torch.empty(len(full), dtype=torch.int64, device=t.device)
-            gf2.gf2_decompose_batched(items, t, t, t, t, t, rank, s)
+            rank = t[base + o_rank:base + o_rank + len(full)]
+            gf2.gf2_decompose_batched_ws(items, t, t, t, t, t, rank, ws, s)
             out["full"] = (full, rank)
             if solve:  # the solve requests lead `full`, so rank[j] is theirs
-                cons = torch.empty(len(solve), dtype=torch.int32, device=t.device)
-                gf2.gf2_solve_batched(self._items(solve, True), t, t, t, t, rank, t, t, cons, s)
+                cons = t[base + o_cons:base + o_cons + (len(solve) + 1) // 2].view(torch.int32)[:len(solve)]
+                gf2.gf2_solve_batched_ws(self._items(solve, True), t, t, t, t, rank, t, t, cons, ws, s)
                 out["cons"] = cons
         if ranko:
-            rank2 = torch.empty(len(ranko), dtype=torch.int64, device=t.device)
-            gf2.gf2_decompose_batched(self._items(ranko, False), t, None, None, None, None, rank2, s)
+            rank2 = t[base + o_rank2:base + o_rank2 + len(ranko)]
+            gf2.gf2_decompose_batched_ws(self._items(ranko, False), t, None, None, None, None, rank2, ws, s)
             out["rank"] = (ranko, rank2)
         ev = torch.cuda.Event()
         ev.record(s)
         self.batches.append(len(reqs))
         return ev, out
+
+    def _launch_fitting_batch(self, ready, s):
+        """The largest leading part of `ready` (halving) whose batch block fits."""
+        k = len(ready)
+        while k >= 1:
+            launched = self._launch_batch(ready[:k], s)
+            if launched is not None:
+                return ready[:k], launched
+            k //= 2
+        return [], None
 
     # ---------------------------------------------------------------- results (verify mode)
     def _fetch_large(self, r):
@@ -314,6 +360,7 @@ class Server:
                 ev, out, members, _ = batch
                 if self.verify:
                     self._collect_batch(out)
+                self.arena.release(*out["block"])
                 for r in members:
                     r.t_done = tdone
                     self._release(r)
@@ -323,13 +370,15 @@ class Server:
             if batch is None and waiting_small:
                 flags = [r.ready_ev.query() for r in waiting_small]
                 ready = [r for r, f in zip(waiting_small, flags) if f]
-                if ready:
-                    waiting_small = [r for r, f in zip(waiting_small, flags) if not f]
+                ready, launched = self._launch_fitting_batch(ready, self.sb) if ready else ([], None)
+                if launched is not None:
+                    taken = set(id(r) for r in ready)
+                    waiting_small = [r for r in waiting_small if id(r) not in taken]
                     ts = time.perf_counter() - t0
-                    bid = len(self.batches)
+                    bid = len(self.batches) - 1
                     for r in ready:
                         r.t_start, r.batch_id = ts, bid
-                    ev, out = self._launch_batch(ready, self.sb)
+                    ev, out = launched
                     batch = (ev, out, ready, ts)
                     progressed = True
             # side streams

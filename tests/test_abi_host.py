@@ -189,3 +189,63 @@ def test_inverse_validation_without_gpu():
     assert lib.gf2_inverse(ctypes.byref(A), ctypes.byref(X), None, None) == gf2.GF2_EINVAL
     assert b"X must be" in lib.gf2_last_error()
     assert lib.gf2_inverse(None, None, None, None) == gf2.GF2_EINVAL
+
+
+def test_header_compiles_as_plain_c_and_cpp(tmp_path):
+    """include/gf2.h is plain C: it compiles with gcc -std=c99 and with g++,
+    neither of which sees a HIP header."""
+    import shutil
+    import subprocess
+
+    src_c = tmp_path / "use.c"
+    src_c.write_text('#include "gf2.h"\nint main(void) { gf2_mat m; (void)m; return (int)gf2_workspace_bytes(0, 0, 0, 0); }\n')
+    inc = os.path.join(ROOT, "include")
+    for cc, std, src in (("gcc", "-std=c99", src_c), ("g++", "-std=c++11", src_c)):
+        exe = shutil.which(cc)
+        assert exe, cc
+        cmd = [exe, std, "-Wall", "-Werror", "-pedantic", "-fsyntax-only", "-I", inc]
+        if cc == "g++":
+            cmd += ["-x", "c++"]
+        r = subprocess.run(cmd + [str(src)], capture_output=True, text=True)
+        assert r.returncode == 0, (cc, r.stderr)
+
+
+def test_workspace_bytes_without_gpu():
+    """Sizes of the caller workspace: the working copy in 16-word column blocks
+    plus the per-panel state, exact growth with the matrix, and invalid requests."""
+    from paper_1209_5198_amd import gf2
+
+    lib = gf2.load()
+    d = gf2.gf2_workspace_bytes(gf2.OP_DECOMPOSE, 16384, 16384)
+    assert 32 * 2 ** 20 <= d < 34 * 2 ** 20, d
+    assert gf2.gf2_workspace_bytes(gf2.OP_DECOMPOSE, 0, 100) == 0
+    assert gf2.gf2_workspace_bytes(gf2.OP_RANK, 0, 100) == 0
+    # a wide matrix is factored as its transpose
+    assert gf2.gf2_workspace_bytes(gf2.OP_RANK, 1000, 70000) == gf2.gf2_workspace_bytes(gf2.OP_DECOMPOSE, 70000, 1000)
+    s1 = gf2.gf2_workspace_bytes(gf2.OP_SOLVE, 4096, 4096, 1)
+    s2 = gf2.gf2_workspace_bytes(gf2.OP_SOLVE, 4096, 4096, 200)
+    assert s2 - s1 == 4096 * 8 * 3  # four words of right-hand sides per row instead of one
+    assert gf2.gf2_workspace_bytes(gf2.OP_SOLVE_BATCHED, 10, 0) >= 10 * 64
+    assert gf2.gf2_workspace_bytes(gf2.OP_MATMUL, 300, 200, 100) > 0
+    for args in ((99, 1, 1, 1), (gf2.OP_DECOMPOSE, -1, 5, 0)):
+        assert lib.gf2_workspace_bytes(*args) == gf2.SIZE_MAX
+    assert lib.gf2_workspace_bytes(gf2.OP_DECOMPOSE_BATCHED, 4, 4096, 64) == gf2.SIZE_MAX  # above the batch limit
+
+
+def test_caller_workspace_validation_without_gpu():
+    """A *_ws call rejects a null, misaligned or short workspace before any launch."""
+    import ctypes
+
+    from paper_1209_5198_amd import gf2
+
+    lib = gf2.load()
+    fake = ctypes.c_void_p(1 << 40)  # never dereferenced: the call fails on the host first
+    A = gf2._Mat(fake, 64, 64, 1, 64)
+    need = gf2.gf2_workspace_bytes(gf2.OP_DECOMPOSE, 64, 64)
+    for ws, nb, what in ((None, need, b"null"), (ctypes.c_void_p((1 << 40) + 8), need, b"aligned"),
+                         (fake, need - 256, b"needed")):
+        assert lib.gf2_decompose_ws(ctypes.byref(A), None, None, None, None, fake, ws, nb, None) == gf2.GF2_EINVAL
+        assert what in lib.gf2_last_error(), lib.gf2_last_error()
+        assert lib.gf2_rank_ws(ctypes.byref(A), fake, ws, nb, None) == gf2.GF2_EINVAL
+    assert lib.gf2_set_param(b"chain_cus", 8) == gf2.GF2_EINVAL
+    assert lib.gf2_set_param(b"chain_cus", 0) == gf2.GF2_OK
