@@ -317,6 +317,24 @@ int gf2_solve_batched_ws(const gf2_batch_item *items, int64_t count, const uint6
                          const int64_t *perm, const int64_t *pivcols, const int64_t *rank, const uint64_t *B,
                          uint64_t *X, int32_t *consistent, void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * Allocation-free decomposition, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, outputs and errors as gf2_decompose, but
+ * the working state lives in a static device array of GF2_NOALLOC_MAX_BYTES
+ * that the library holds on every GPU it runs on until the process ends, and
+ * every launch goes in order onto `stream`: the call makes no hipMalloc, no
+ * hipFree, creates no stream or event and records no profiling event.
+ * GF2_EINVAL if the working state of an n x m decomposition
+ * (gf2_workspace_bytes(GF2_OP_DECOMPOSE, n, m)) exceeds GF2_NOALLOC_MAX_BYTES
+ * (16384 x 16384 fits).  All calls on one GPU share that GPU's array: calls
+ * that overlap in time on one GPU (other streams, other host threads) race
+ * and give wrong results; calls ordered on one stream are safe.
+ */
+#define GF2_NOALLOC_MAX_BYTES ((size_t)36 << 20)
+int gf2_decompose_noalloc(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t *perm, int64_t *pivcols,
+                          int64_t *rank, void *stream);
+
 /* Free the library-owned workspace, look-ahead streams and events of every
  * device (after synchronising those devices).  Safe to call at any time
  * between calls; later calls create what they need again. */

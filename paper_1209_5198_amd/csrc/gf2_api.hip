@@ -30,6 +30,8 @@ namespace gf2 {
 namespace {
 
 thread_local std::string g_err;
+// set for the duration of an allocation-free call: no profiling events
+thread_local bool g_noalloc = false;
 int g_panel_words = 8;
 // Strassen-Winograd recursion while every dimension of the current product is
 // at least this many bits (0: never).  Measured on MI355X: one level pays at
@@ -222,8 +224,10 @@ int prof_event(hipEvent_t *e) {
   return GF2_OK;
 }
 
+bool prof_on() { return g_prof.on && !g_noalloc; }
+
 int profile_begin(hipStream_t s, hipEvent_t *a) {
-  if (!g_prof.on) return GF2_OK;
+  if (!prof_on()) return GF2_OK;
   int rc = prof_event(a);
   if (rc) return rc;
   HIPCHK(hipEventRecord(*a, s));
@@ -231,7 +235,7 @@ int profile_begin(hipStream_t s, hipEvent_t *a) {
 }
 
 int profile_end(hipStream_t s, hipEvent_t a) {
-  if (!g_prof.on) return GF2_OK;
+  if (!prof_on()) return GF2_OK;
   hipEvent_t b;
   int rc = prof_event(&b);
   if (rc) return rc;
@@ -261,14 +265,15 @@ int run_gemm(GemmArgs &a, int64_t nrows_max, int variant, int64_t active_rows, h
   }
   if (variant < 0 || variant >= kGemmVariants) variant = gemm_auto_variant(active_rows, a.qc0, a.qc1, gf2::device_cus());
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (g_prof.on) {  // the launch records the kernel's own start and end
+  const bool prof = prof_on();
+  if (prof) {  // the launch records the kernel's own start and end
     int rc = prof_event(&e0);
     if (!rc) rc = prof_event(&e1);
     if (rc) return rc;
   }
-  a.work = g_prof.on ? g_prof.work_dev : nullptr;
+  a.work = prof ? g_prof.work_dev : nullptr;
   HIPCHK(launch_gemm(a, nrows_max, variant, s, e0, e1));
-  if (g_prof.on) {
+  if (prof) {
     g_prof.ev.emplace_back(e0, e1);
     g_prof.launches += 1;
   }
@@ -281,7 +286,7 @@ int run_gemm_mfma(GemmArgs &a, int64_t bwords, uint64_t *ws, hipStream_t s) {
   hipEvent_t e0 = nullptr;
   int rc = profile_begin(s, &e0);
   if (rc) return rc;
-  a.work = g_prof.on ? g_prof.work_dev : nullptr;
+  a.work = prof_on() ? g_prof.work_dev : nullptr;
   HIPCHK(launch_gemm_mfma(a, bwords, ws, gf2::device_cus(), s));
   return profile_end(s, e0);
 }
@@ -1022,6 +1027,39 @@ int decompose_body(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t
   return GF2_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free decomposition
+// The working state of gf2_decompose_noalloc lives in this file-scope device
+// array: every GPU the library runs on holds its own copy from the time the
+// code object is loaded there until the process ends.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in for the
+// symbol): the device address comes from hipGetSymbolAddress, once per device,
+// with that device current.
+constexpr size_t kScratchBytes = GF2_NOALLOC_MAX_BYTES;
+static_assert(kScratchBytes % 256 == 0, "scratch size");
+static __device__ __align__(256) uint64_t scratch[kScratchBytes / 8];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// the current device's copy of `scratch`
+int scratch_ptr(void **out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(GF2_EINVAL, "gf2_decompose_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "gf2_decompose_noalloc: hipGetSymbolAddress(scratch)");
+    if (!p || ((uintptr_t)p & 255u) != 0)
+      return fail(GF2_EHIP, "gf2_decompose_noalloc: scratch address is null or not 256-byte aligned");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GF2_OK;
+}
+
 int rank_check(const gf2_mat *A, const int64_t *rank) {
   int rc;
   if ((rc = check_mat(A, "A"))) return rc;
@@ -1255,6 +1293,25 @@ int gf2_decompose_ws(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64
   if ((rc = decompose_check(A, L, E))) return rc;
   if ((rc = check_ws(workspace, workspace_bytes, decompose_need(A), "gf2_decompose_ws"))) return rc;
   return decompose_body(A, L, E, perm, pivcols, rank, workspace, (hipStream_t)stream, false);
+}
+
+int gf2_decompose_noalloc(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t *perm, int64_t *pivcols,
+                          int64_t *rank, void *stream) {
+  int rc;
+  if ((rc = decompose_check(A, L, E))) return rc;
+  const size_t need = decompose_need(A);
+  if (need > kScratchBytes)
+    return fail(GF2_EINVAL, "gf2_decompose_noalloc: a " + std::to_string(A->rows) + " x " +
+                                std::to_string(A->cols) + " decomposition needs " + std::to_string(need) +
+                                " bytes of working state; the static scratch holds " +
+                                std::to_string(kScratchBytes) + " (GF2_NOALLOC_MAX_BYTES)");
+  void *ws = nullptr;
+  if (need && (rc = scratch_ptr(&ws))) return rc;
+  // every launch in order on the caller's stream, no profiling events
+  g_noalloc = true;
+  rc = decompose_body(A, L, E, perm, pivcols, rank, ws, (hipStream_t)stream, true);
+  g_noalloc = false;
+  return rc;
 }
 
 int gf2_rank(const gf2_mat *A, int64_t *rank, void *stream) {

@@ -31,7 +31,7 @@ EXPORTED = ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_decompo
             "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_inverse", "gf2_autotune", "gf2_autotune_table",
             "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_microbench", "gf2_workspace_bytes",
             "gf2_matmul_ws", "gf2_decompose_ws", "gf2_rank_ws", "gf2_solve_ws", "gf2_decompose_batched_ws",
-            "gf2_solve_batched_ws", "gf2_release", "gf2_last_error", "gf2_version")
+            "gf2_solve_batched_ws", "gf2_decompose_noalloc", "gf2_release", "gf2_last_error", "gf2_version")
 # operation codes of gf2_workspace_bytes
 OP_MATMUL, OP_DECOMPOSE, OP_RANK, OP_SOLVE, OP_DECOMPOSE_BATCHED, OP_SOLVE_BATCHED = range(6)
 SIZE_MAX = 2 ** 64 - 1
@@ -94,6 +94,7 @@ def load():
         lib.gf2_solve_ws.argtypes = [P, P, P, vp, vp, vp, sz, vp]
         lib.gf2_decompose_batched_ws.argtypes = [PB, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         lib.gf2_solve_batched_ws.argtypes = [PB, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        lib.gf2_decompose_noalloc.argtypes = [P, P, P, vp, vp, vp, vp]
         lib.gf2_release.argtypes = []
         lib.gf2_last_error.restype = ctypes.c_char_p
         lib.gf2_version.restype = ctypes.c_char_p
@@ -101,7 +102,7 @@ def load():
                      "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_inverse", "gf2_autotune",
                      "gf2_autotune_table", "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_microbench",
                      "gf2_matmul_ws", "gf2_decompose_ws", "gf2_rank_ws", "gf2_solve_ws", "gf2_decompose_batched_ws",
-                     "gf2_solve_batched_ws", "gf2_release"):
+                     "gf2_solve_batched_ws", "gf2_decompose_noalloc", "gf2_release"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
         atexit.register(_release_at_exit)
@@ -314,6 +315,14 @@ def gf2_decompose_ws(A: Mat, L, E, perm, pivcols, rank, workspace, stream=None) 
     p, nb = _ws(workspace)
     _check(load().gf2_decompose_ws(ctypes.byref(A.desc()), Ld, Ed, _ptr(perm), _ptr(pivcols), _ptr(rank), p, nb,
                                    _stream(stream)))
+
+
+def gf2_decompose_noalloc(A: Mat, L, E, perm, pivcols, rank, stream=None) -> None:
+    """gf2_decompose with the library's static scratch (no device allocation)."""
+    Ld = ctypes.byref(L.desc()) if L is not None else None
+    Ed = ctypes.byref(E.desc()) if E is not None else None
+    _check(load().gf2_decompose_noalloc(ctypes.byref(A.desc()), Ld, Ed, _ptr(perm), _ptr(pivcols), _ptr(rank),
+                                        _stream(stream)))
 
 
 def gf2_rank_ws(A: Mat, rank, workspace, stream=None) -> None:
