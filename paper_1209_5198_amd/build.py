@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgf2.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["k_layout.hip", "k_gemm.hip", "k_panel.hip", "k_solve.hip", "k_batch.hip", "k_rref.hip", "k_probe.hip",
+SOURCES = ["k_layout.hip", "k_gemm.hip", "k_panel.hip", "k_super.hip", "k_solve.hip", "k_batch.hip", "k_rref.hip", "k_probe.hip",
            "k_mfma.hip", "gf2_api.hip"]
 ARCH = "gfx950"
 

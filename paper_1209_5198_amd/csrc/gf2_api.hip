@@ -39,19 +39,22 @@ int g_panel_words = 8;
 int64_t g_strassen_cutoff = 65536;
 int g_gemm_variant = -1;        // product-kernel variant for gf2_matmul (-1: automatic)
 int g_panel_gemm_variant = -1;  // product-kernel variant for the trailing update (-1: automatic)
-// bulk-update size (table lookups) from which the bulk update starts right
-// after the row exchanges, concurrently with the next panel's columns and its
-// pivot chain (0 = always).  Measured on MI355X at 65536^2: 62.0 ms at 0
-// against 63.8 ms at 1.2e9 with the post-chain kernel always on the main
-// stream; with the post-follow schedule 56.7-56.75 ms at 3e8 against
-// 56.8-57.1 ms at 0 and 57.8-57.9 ms at 1e9.
+// Panels per super-panel (0: the one-level schedule): the words outside a
+// super-panel and the next one are updated once per super-panel, by products
+// of inner dimension up to 64 * panel_words * sp_panels bits (at most
+// kSpSubMax sub-panels).  Measured on MI355X at 65536^2: 56.7 ms one-level
+// against 65.3 (2), 66.4 (1) and 69.1 ms (4) with super-panels.
+int g_sp_panels = 0;
+// near-update size (table lookups) from which a panel's update of the near
+// words beyond the next panel starts right after the row exchanges, beside
+// the next panel's columns and its pivot chain, instead of after them
 double g_overlap_lookups = 3e8;
-// bulk-update size (table lookups) from which the next panel's k_post runs on
-// the bulk stream right after that update (then waiting for the next chain),
-// instead of on the main stream after a hop from the bulk stream: where the
-// bulk update is the longer path this takes two stream hops per panel off it
-// (-1 = never; measured on MI355X at 65536^2: 57.1-57.4 ms at 1.5e9 against
-// 58.2 ms never, 59.5 ms always, 58.2 ms at 5e9)
+// (one-level schedule) bulk-update size (table lookups) from which the next
+// panel's k_post runs on the bulk stream right after that update (then waiting
+// for the next chain), instead of on the main stream after a hop from the bulk
+// stream: where the bulk update is the longer path this takes two stream hops
+// per panel off it (-1 = never; measured on MI355X at 65536^2: 57.1-57.4 ms at
+// 1.5e9 against 58.2 ms never, 59.5 ms always, 58.2 ms at 5e9)
 double g_post_follow_lookups = 1.5e9;
 // Product-kernel tile per size class, written by gf2_autotune: rows class r
 // (active rows in [256 << r, 512 << r), clamped to 0..8) x column-block class c
@@ -68,11 +71,12 @@ int tune_row_class(int64_t rows) {
 int tune_block_class(int blocks) { return blocks <= 1 ? 0 : (blocks <= 3 ? 1 : (blocks <= 15 ? 2 : 3)); }
 
 // Per (device, caller stream): the two internal streams of the look-ahead
-// pipeline.  The pivot chain of panel J+1 runs on one while the bulk of panel
-// J's trailing update runs on the other; events order the two.  Calls made on
-// different caller streams get different pairs, so their factorizations can
-// run concurrently (each pivot chain occupies a single CU).  Both streams have
-// the default priority and no CU mask.  gf2_release() destroys them.
+// pipeline of a decomposition (main: row exchanges, next panel's columns and
+// pivot chains; bulk: each panel's update of the other near words and the
+// super-panels' far work); events order them.  Calls made on
+// different caller streams get different sets, so their factorizations can
+// run concurrently.  All streams have the default priority and no CU mask.
+// gf2_release() destroys them.
 struct Pipe {
   hipStream_t gemm = nullptr, chain = nullptr;
   std::vector<hipEvent_t> ring;
@@ -190,9 +194,12 @@ size_t decomp_bytes(int64_t n, int64_t m, int64_t ldw, int64_t Mw, int64_t NB) {
   b += align256((size_t)Mw * 64 * 8);
   b += 2 * align256((size_t)n * 4);
   b += align256((size_t)kMaxPanelWords * 64 * 2 * 4);
-  b += align256((size_t)Mw * 4);
+  b += align256((size_t)(Mw + 1) * 4);
   b += align256((size_t)n * 4);
   b += align256((size_t)kPanelTabWords * 8);
+  b += 2 * align256((size_t)2 * n * 4);
+  b += align256((size_t)2 * kSpListMax * 4);
+  b += align256((size_t)2 * 4);
   (void)m;
   return b;
 }
@@ -208,9 +215,13 @@ void carve_decomp(Carver &c, DecWork &w) {
   w.bp_src = c.take<int32_t>(w.n);
   w.bp_mark = c.take<int32_t>(w.n);
   w.bp_list = c.take<int32_t>((size_t)kMaxPanelWords * 64 * 2);
-  w.nzflag = c.take<uint32_t>(w.Mw);
+  w.nzflag = c.take<uint32_t>((size_t)w.Mw + 1);
   w.lvl = c.take<int32_t>(w.n);
   w.ptab = c.take<uint64_t>(kPanelTabWords);
+  w.sp_src = c.take<int32_t>((size_t)2 * w.n);
+  w.sp_mark = c.take<int32_t>((size_t)2 * w.n);
+  w.sp_list = c.take<int32_t>((size_t)2 * kSpListMax);
+  w.sp_count = c.take<int32_t>(2);
 }
 
 // the next event of the profiling pool (created the first time it is needed)
@@ -328,17 +339,35 @@ int make_exec(hipStream_t user, bool single, Exec &x) {
   return GF2_OK;
 }
 
+// an event marking everything enqueued so far on s (null on a single stream)
+int mark(const Exec &x, hipStream_t s, hipEvent_t *e) {
+  *e = nullptr;
+  if (!x.P) return GF2_OK;
+  *e = x.P->ring[x.P->next++ % x.P->ring.size()];
+  HIPCHK(hipEventRecord(*e, s));
+  return GF2_OK;
+}
+
+int wait_mark(hipStream_t waiter, hipEvent_t e) {
+  if (e) HIPCHK(hipStreamWaitEvent(waiter, e, 0));
+  return GF2_OK;
+}
+
 // make `waiter` wait for everything enqueued so far on `signaller` (nothing to
 // do when both are the same stream)
 int link(const Exec &x, hipStream_t signaller, hipStream_t waiter) {
   if (signaller == waiter) return GF2_OK;
-  hipEvent_t e = x.P->ring[x.P->next++ % x.P->ring.size()];
-  HIPCHK(hipEventRecord(e, signaller));
-  HIPCHK(hipStreamWaitEvent(waiter, e, 0));
-  return GF2_OK;
+  hipEvent_t e = nullptr;
+  int rc = mark(x, signaller, &e);
+  return rc ? rc : wait_mark(waiter, e);
 }
 
-int trailing_gemm(DecWork &w, int q0, int s_eff, int prev, int qc0, int qc1, hipStream_t s) {
+// C words [qc0, qc1) of every row below the pivots of sub-panels [q0, q0 + nsub)
+// ^= (their multipliers in words [q0, q0 + nsub)) * (the pivot rows' words):
+// eq. (Aj) for those sub-panels.  nz: flag slot ORed with "a written word is
+// nonzero"; skip: flag slot whose zero means the Schur complement is zero
+// (-1: none).
+int trailing_gemm(DecWork &w, int q0, int nsub, int nz, int skip, int qc0, int qc1, hipStream_t s) {
   if (qc1 <= qc0) return GF2_OK;
   GemmArgs a;
   memset(&a, 0, sizeof(a));
@@ -346,36 +375,87 @@ int trailing_gemm(DecWork &w, int q0, int s_eff, int prev, int qc0, int qc1, hip
   a.B = w.W; a.ldB = w.ldw; a.b_rows = 0; a.bsub = w.sub + q0;
   a.C = w.W; a.ldC = w.ldw;
   a.row_tile0 = 0; a.row_end = w.n;
-  a.kwords = s_eff;
+  a.kwords = nsub;
   a.qc0 = qc0; a.qc1 = qc1;
   a.accumulate = 1;
-  a.nzflag = w.nzflag + q0;
-  a.skip_flag = prev >= 0 ? w.nzflag + prev : nullptr;
+  a.nzflag = w.nzflag + nz;
+  a.skip_flag = skip >= 0 ? w.nzflag + skip : nullptr;
   // at most 64 pivots per sub-panel so far: a lower bound on the rows left
-  int64_t active = w.n - 64ll * (q0 + s_eff);
+  int64_t active = w.n - 64ll * (q0 + nsub);
   if (active < 1) active = 1;
-  return run_gemm(a, w.n, g_panel_gemm_variant, active, s);
+  int v = g_panel_gemm_variant;
+  if (v < 0 && !g_tuned_on && g_sp_panels > 0) v = gemm_wall_variant(active, qc0, qc1, gf2::device_cus());
+  return run_gemm(a, w.n, v, active, s);
 }
 
-int chain(DecWork &w, int q0, int s_eff, int flag_q0, hipStream_t s) {
-  HIPCHK(launch_panel(w, q0, s_eff, flag_q0, s));
+int chain(DecWork &w, int q0, int s_eff, int flag, int spb, hipStream_t s) {
+  HIPCHK(launch_panel(w, q0, s_eff, flag, spb, s));
   return GF2_OK;
 }
 
 // Factor A into the working state w (which the caller sized with decomp_bytes).
-// Look-ahead: once panel J's row exchanges, pivot rows and the columns of panel
-// J+1 are updated, the pivot chain of panel J+1 starts on the chain stream while
-// the rest of panel J's trailing update runs on the gemm stream.  The zero-tail
-// test of a panel's chain reads the flag of the panel two steps back, the last
-// one whose trailing update is certainly complete.  Returns with `user` ordered
-// after all the work.
+//
+// Columns go in super-panels of sp_panels panels (SPW words); the near words
+// of super-panel k are its own and those of super-panel k+1.  Per panel J:
+//   G:  post(J)     row exchanges and pivot rows in echelon form on the near
+//                   words, the rows' multipliers in the panel words
+//       narrow      the next panel's columns get panel J's update
+//       chain(J+1)  pivots of the next panel (look-ahead)
+//   Cs: near bulk   the other near words right of the next panel get panel
+//                   J's update, then a slice of the previous super-panel's
+//                   far work; post(J+1) waits for Cs
+// so the bulk work overlaps only the pivot chain (one workgroup), never the
+// row exchanges or the next panel's columns.  Closing super-panel k (Cs, after
+// its last near bulk): its net permutation on all other words (they kept the
+// super-panel's starting row order), its pivot rows in echelon form on the
+// far words and the update of super-panel k+2's words, which become near for
+// super-panel k+1, with inner dimension 64 * SPW; the update of the remaining
+// far words follows in slices during super-panel k+1's panels.
+// Zero test: flag slot k is ORed by the products that write the final state
+// of super-panel k's Schur complement (its last panel's near products and
+// its far products), so slot k == 0 means that everything after is zero; a
+// launch only reads a slot whose writers are certainly finished.  Returns
+// with `user` ordered after all the work.
 // What the working matrix holds: A; [A | I] (w sized for A->cols + A->rows
 // columns, A square: the augmented form the inverse is read from); or A^T (w
 // sized for A->cols x A->rows: the rank of a wide matrix, equal to that of its
 // transpose, with fewer panels).
 enum class Pack { kPlain, kIdentityRight, kTransposed };
 
-int factor(const gf2_mat *A, DecWork &w, const Exec &x, Pack pack = Pack::kPlain) {
+// far words [q0, q1) of super-panel k (sub-panels [s0, s0 + nsub)) still to
+// be brought up to date, in `left` slices
+struct FarWork {
+  int k = -1, s0 = 0, nsub = 0, q0 = 0, q1 = 0, left = 0;
+};
+
+int far_slice(DecWork &w, FarWork &f, hipStream_t s) {
+  if (f.left <= 0 || f.q1 <= f.q0) {
+    f.left = 0;
+    return GF2_OK;
+  }
+  // whole 16-word blocks where possible
+  int take = (f.q1 - f.q0 + f.left - 1) / f.left;
+  take = (take + TW - 1) / TW * TW;
+  const int qe = f.q0 + take < f.q1 ? f.q0 + take : f.q1;
+  int rc = trailing_gemm(w, f.s0, f.nsub, f.k, f.k >= 1 ? f.k - 1 : -1, f.q0, qe, s);
+  f.q0 = qe;
+  --f.left;
+  return rc;
+}
+
+// One-level schedule (sp_panels = 0): every panel's update of all words right
+// of the next panel is one product of inner dimension 64 * panel_words.
+// Main stream G: post(J), next panel's columns, chain(J+1), in order (no
+// stream hop before the chain).  Bulk stream Cs: the rest of panel J's
+// update, started after post(J) when it clearly outlasts the chain (it then
+// runs beside the next panel's columns and the chain), else after the next
+// panel's columns.  post(J+1) waits for it: on G, or, after a bulk update of
+// at least g_post_follow_lookups, on Cs right behind it (then waiting for
+// chain(J+1) instead), with G continuing after post(J+1).  On a single
+// stream the same launches run in this order, one after the other.  The
+// zero-tail test of a panel's chain reads the flag of the panel two steps
+// back, the last one whose trailing update is certainly complete.
+int factor_panels(const gf2_mat *A, DecWork &w, const Exec &x, Pack pack) {
   int rc;
   const hipStream_t G = x.G, Cs = x.Cs;
   if ((rc = link(x, x.user, G))) return rc;
@@ -396,17 +476,17 @@ int factor(const gf2_mat *A, DecWork &w, const Exec &x, Pack pack = Pack::kPlain
   // at least g_post_follow_lookups, on Cs right behind it (then waiting for
   // chain(J+1) instead), with G continuing after post(J+1).  On a single
   // stream the same launches run in this order, one after the other.
-  if ((rc = chain(w, 0, w.Mw < S ? w.Mw : S, -1, G))) return rc;
+  if ((rc = chain(w, 0, w.Mw < S ? w.Mw : S, -1, -1, G))) return rc;
   bool post_on_cs = false;  // k_post of this panel follows the previous bulk update on Cs
   for (int q0 = 0; q0 < w.Mw; q0 += S) {
     const int s_eff = (w.Mw - q0) < S ? (w.Mw - q0) : S;
     if (post_on_cs) {
       // Cs already follows the previous bulk update; wait for this chain
       if ((rc = link(x, G, Cs))) return rc;
-      HIPCHK(launch_post(w, q0, s_eff, Cs));
+      HIPCHK(launch_post(w, q0, s_eff, 0, w.Mw, Cs));
       if ((rc = link(x, Cs, G))) return rc;
     } else {
-      HIPCHK(launch_post(w, q0, s_eff, G));  // row exchanges, multipliers, pivot rows in echelon form
+      HIPCHK(launch_post(w, q0, s_eff, 0, w.Mw, G));  // row exchanges, multipliers, pivot rows in echelon form
     }
     const int nq0 = q0 + s_eff;
     bool next_on_cs = false;
@@ -417,16 +497,91 @@ int factor(const gf2_mat *A, DecWork &w, const Exec &x, Pack pack = Pack::kPlain
       const double bulk = (double)(rows_left > 0 ? rows_left : 0) * (double)(w.Mw - nq0 - ns) * 8.0 * s_eff;
       const bool early = bulk >= g_overlap_lookups;
       if (early && !post_on_cs && (rc = link(x, G, Cs))) return rc;
-      if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0, nq0 + ns, G))) return rc;  // next panel's columns
+      if ((rc = trailing_gemm(w, q0, s_eff, q0, prev, nq0, nq0 + ns, G))) return rc;  // next panel's columns
       if (!early && (rc = link(x, G, Cs))) return rc;
-      if ((rc = chain(w, nq0, ns, prev, G))) return rc;                           // look-ahead
-      if ((rc = trailing_gemm(w, q0, s_eff, prev, nq0 + ns, w.Mw, Cs))) return rc; // the rest
+      if ((rc = chain(w, nq0, ns, prev, -1, G))) return rc;                           // look-ahead
+      if ((rc = trailing_gemm(w, q0, s_eff, q0, prev, nq0 + ns, w.Mw, Cs))) return rc; // the rest
       next_on_cs = g_post_follow_lookups >= 0.0 && bulk >= g_post_follow_lookups;
       if (!next_on_cs && (rc = link(x, Cs, G))) return rc;
     }
     post_on_cs = next_on_cs;
     prev = q0;
   }
+  return link(x, G, x.user);
+}
+
+int factor(const gf2_mat *A, DecWork &w, const Exec &x, Pack pack = Pack::kPlain) {
+  if (g_sp_panels <= 0) return factor_panels(A, w, x, pack);
+  int rc;
+  const hipStream_t G = x.G, Cs = x.Cs;
+  if ((rc = link(x, x.user, G))) return rc;
+  HIPCHK(launch_init_state(w, G));
+  if (pack == Pack::kTransposed) {
+    HIPCHK(launch_pack_transposed(*A, w.W, w.ldw, w.NB, G));
+  } else {
+    HIPCHK(launch_pack(*A, w.W, w.ldw, w.n, A->cols, w.NB, G));
+    if (pack == Pack::kIdentityRight) HIPCHK(launch_set_identity(w.W, w.ldw, w.n, A->cols, G));
+  }
+  const int S = g_panel_words;
+  int P = g_sp_panels;
+  if (P * S > kSpSubMax) P = kSpSubMax / S;
+  const int SPW = P * S;
+  const int Mw = w.Mw, dummy = Mw;  // flag slot that nothing reads
+  // flag slot a launch of super-panel k may read: the products of k-2 (k-3
+  // for the first chain of k, which is launched before k's first post)
+  auto zslot = [](int k, int back) { return k - back >= 0 ? k - back : -1; };
+  FarWork far;
+  if ((rc = chain(w, 0, Mw < S ? Mw : S, -1, 0, G))) return rc;
+  int k = 0;
+  for (int sp0 = 0; sp0 < Mw; sp0 += SPW, ++k) {
+    const int sp1 = sp0 + SPW < Mw ? sp0 + SPW : Mw;
+    const int n1 = sp1 + SPW < Mw ? sp1 + SPW : Mw;
+    for (int q0 = sp0; q0 < sp1; q0 += S) {
+      const int s_eff = sp1 - q0 < S ? sp1 - q0 : S;
+      const bool last = q0 + s_eff == sp1;
+      if ((rc = link(x, Cs, G))) return rc;  // the previous bulk work
+      HIPCHK(launch_post(w, q0, s_eff, sp0, n1, G));
+      const int nq0 = q0 + s_eff;
+      if (nq0 < Mw) {
+        const int ns = Mw - nq0 < S ? Mw - nq0 : S;
+        const int nz = last ? k : dummy, skip = zslot(k, 2);
+        const int nk = last ? k + 1 : k;  // super-panel of the next panel
+        const double near =
+            (double)(w.n - 64ll * nq0 > 0 ? w.n - 64ll * nq0 : 0) * (double)(n1 - nq0 - ns) * 8.0 * s_eff;
+        const bool early = near >= g_overlap_lookups;
+        if (early && (rc = link(x, G, Cs))) return rc;
+        if ((rc = trailing_gemm(w, q0, s_eff, nz, skip, nq0, nq0 + ns, G))) return rc;  // next panel's columns
+        if (!early && (rc = link(x, G, Cs))) return rc;
+        if ((rc = chain(w, nq0, ns, zslot(nk, last ? 3 : 2), nk & 1, G))) return rc;
+        if ((rc = trailing_gemm(w, q0, s_eff, nz, skip, nq0 + ns, n1, Cs))) return rc;  // the other near words
+      } else if ((rc = link(x, G, Cs))) {
+        return rc;
+      }
+      // a slice of the previous super-panel's far words (the last panel takes what is left)
+      if (last)
+        while (far.left > 0)
+          if ((rc = far_slice(w, far, Cs))) return rc;
+      if ((rc = far_slice(w, far, Cs))) return rc;
+    }
+    // ---- close super-panel k (Cs, after its last near bulk and the previous
+    // super-panel's far work)
+    HIPCHK(launch_sp_swap(w, k & 1, sp0, n1, Cs));
+    HIPCHK(launch_sp_reset(w, k & 1, Cs));
+    if (n1 < Mw) {
+      const int nsub = sp1 - sp0, n2 = n1 + SPW < Mw ? n1 + SPW : Mw;
+      HIPCHK(launch_trsm_far(w, sp0, nsub, n1, Mw, Cs));  // all far words: one word per workgroup
+      if ((rc = trailing_gemm(w, sp0, nsub, k, zslot(k, 1), n1, n2, Cs))) return rc;
+      far.k = k;
+      far.s0 = sp0;
+      far.nsub = nsub;
+      far.q0 = n2;
+      far.q1 = Mw;
+      far.left = n2 < Mw ? P : 0;
+    }
+  }
+  while (far.left > 0)
+    if ((rc = far_slice(w, far, Cs))) return rc;
+  if ((rc = link(x, Cs, G))) return rc;
   return link(x, G, x.user);
 }
 
@@ -567,6 +722,16 @@ int gf2_set_param(const char *name, int64_t value) {
   if (!strcmp(name, "autotuned")) {
     if (value < 0 || value > 1) return fail(GF2_EINVAL, "autotuned must be 0 or 1");
     g_tuned_on = value == 1 && g_tuned_valid;
+    return GF2_OK;
+  }
+  if (!strcmp(name, "sp_panels")) {
+    if (value < 0 || value > kSpSubMax) return fail(GF2_EINVAL, "sp_panels must be in 0..32");
+    g_sp_panels = (int)value;
+    return GF2_OK;
+  }
+  if (!strcmp(name, "wide_threads")) {
+    if (value != 512 && value != 1024) return fail(GF2_EINVAL, "wide_threads must be 512 or 1024");
+    g_wide_threads = (int)value;
     return GF2_OK;
   }
   if (!strcmp(name, "post_follow_lookups")) {

@@ -91,9 +91,20 @@ struct DecWork {
   uint32_t *nzflag;  // [Mw]  trailing-update nonzero flag per panel
   int32_t *lvl;      // [n]   16*q0 + L: sub-panels 0..L-1 of the panel at q0 applied to row p
   uint64_t *ptab;    // [kPanelTabWords] 4-bit tables of the current panel (written by its chain)
+  // net row permutation of the current super-panel, two buffers (super-panel
+  // parity): position p holds the row that was at sp_src[p] when it started;
+  // sp_list holds the sp_count positions that changed (sp_mark[p] = 1)
+  int32_t *sp_src;   // [2 * n]
+  int32_t *sp_mark;  // [2 * n]
+  int32_t *sp_list;  // [2 * kSpListMax]
+  int32_t *sp_count; // [2]
 };
 
 constexpr int kMaxPanelWords = 8;       // s <= 8 sub-panels per trailing-update panel
+// A super-panel is at most kSpSubMax sub-panels (whole panels); its far
+// update is one product of inner dimension 64 * (sub-panels)
+constexpr int kSpSubMax = 32;
+constexpr int kSpListMax = 2 * 64 * kSpSubMax;  // positions a super-panel can move
 constexpr int kWin = 128;               // window rows examined per sub-panel
 // words of one panel's 4-bit tables: Tz (y = x * Zc_c) for 8 sub-panels and Te
 // (y * E_c[w]) for the 28 sub-panel / later-word pairs, 16 x 16 entries each
@@ -105,7 +116,7 @@ struct GemmArgs {
   const uint64_t *B; int64_t ldB; int64_t b_rows;    // plain B: row k for k < b_rows
   const SubInfo *bsub;                               // mapped B: row (kw, t) -> bsub[kw].R + t, t < bsub[kw].r;
                                                      // then also rows >= bsub[kwords-1].R + bsub[kwords-1].r;
-                                                     // with bsub, kwords <= kMaxPanelWords
+                                                     // with bsub, kwords <= kSpSubMax
   uint64_t *C; int64_t ldC;
   int64_t row_tile0;                                 // first row of tile 0
   int64_t row_end;                                   // rows < row_end
@@ -137,9 +148,16 @@ hipError_t launch_gemm_mfma(const GemmArgs &a, int64_t bwords, uint64_t *ws, int
 hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int variant, hipStream_t s, hipEvent_t e0 = nullptr,
                        hipEvent_t e1 = nullptr);
 int gemm_auto_variant(int64_t active_rows, int qc0, int qc1, int ncu);  // variant for a launch shape
+int gemm_wall_variant(int64_t active_rows, int qc0, int qc1, int ncu);  // ... minimising its wall time
+extern int g_wide_threads;  // threads of the 2048-row product tile (512 or 1024)
 
-hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, hipStream_t s);
-hipError_t launch_post(const DecWork &w, int q0, int s_eff, hipStream_t s);
+hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, int spb, hipStream_t s);
+hipError_t launch_post(const DecWork &w, int q0, int s_eff, int wlo, int whi, hipStream_t s);
+// closing a super-panel (k_super.hip): net permutation on the words outside
+// [lo, hi), list reset, pivot rows in echelon form on the far words [qa, qb)
+hipError_t launch_sp_swap(const DecWork &w, int buf, int lo, int hi, hipStream_t s);
+hipError_t launch_sp_reset(const DecWork &w, int buf, hipStream_t s);
+hipError_t launch_trsm_far(const DecWork &w, int s0, int nsub, int qa, int qb, hipStream_t s);
 hipError_t launch_xor(uint64_t *dst, const uint64_t *a, const uint64_t *b, size_t nwords,
                       hipStream_t s);
 // dst[0 .. nwords) = 0 by a kernel (no memset node where a caller captures the launches)

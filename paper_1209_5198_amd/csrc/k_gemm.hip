@@ -93,7 +93,7 @@ __device__ inline uint64_t store_acc2(const uint64_t (&acc)[RPL][2], uint64_t *C
 // is combined, so the table reads of a wave never wait for its own XORs.
 template <int NT, int TM>
 __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
-  constexpr int UB = 2;                // rows per lane looked up together
+  constexpr int UB = NT >= 1024 ? 1 : 2;  // rows per lane looked up together (registers: 4 waves per SIMD at 1024)
   constexpr int NW = NT / 64;          // waves
   constexpr int RPL = TM / (8 * NW);   // rows per lane
   constexpr int JOBS = NT / 8;         // table-build jobs (8 threads each, one word pair per thread)
@@ -106,8 +106,8 @@ __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
   __shared__ uint64_t T[2][256][2][TW];
   __shared__ uint32_t As[2 * TM];         // the tile's A word for the current 64 inner bits
   __shared__ ulonglong2 Bs[2][32][TW / 2];  // B rows of a step (zero past the operand), two buffers
-  __shared__ int64_t sR[kMaxPanelWords];  // pivot-row ranges of a mapped B (at most one panel)
-  __shared__ int sr[kMaxPanelWords];
+  __shared__ int64_t sR[kSpSubMax];  // pivot-row ranges of a mapped B (at most one super-panel)
+  __shared__ int sr[kSpSubMax];
 
   if (a.skip_flag && *a.skip_flag == 0u) return;  // the Schur complement is already zero
   const int tid = threadIdx.x;
@@ -483,6 +483,10 @@ __global__ __launch_bounds__(NT) void k_gemm_narrow(GemmArgs a) {
 //   5: k_gemm_narrow, 256 threads, 512 rows x 8 words
 // Automatic choice: the largest tile that still gives at least one workgroup
 // per CU for the rows expected to be active; small launches get small tiles.
+// threads of the 2048-row tile (variant 0): 512 (8 waves, two rows per
+// lookup group) or 1024 (16 waves, one row per lookup group)
+int g_wide_threads = 512;
+
 int gemm_tile_rows(int v) {
   switch (v) {
     case 0: return 2048;
@@ -505,6 +509,29 @@ int gemm_auto_variant(int64_t active_rows, int qc0, int qc1, int ncu) {
     if (((active_rows + tm - 1) / tm) * (int64_t)blocks_y >= want) return v;
   }
   return 3;
+}
+
+// Tile for a product whose wall time matters (a decomposition's updates run
+// between two dependent launches): the tile minimising rounds x (time of one
+// 32-bit step of a workgroup), with the step time alpha * TM + beta fitted to
+// MI355X measurements of the wide kernel (0.00212 us per row: the lookups;
+// 1.66 us: the table build, barriers and staging), one workgroup per CU.
+int gemm_wall_variant(int64_t active_rows, int qc0, int qc1, int ncu) {
+  if (gemm_narrow_ok(qc0, qc1)) return gemm_auto_variant(active_rows, qc0, qc1, ncu);
+  const int blocks_y = ((qc1 - 1) >> 4) - (qc0 >> 4) + 1;
+  int best = 0;
+  double best_t = 1e300;
+  for (int v = 0; v < 4; ++v) {
+    const int tm = gemm_tile_rows(v);
+    const int64_t wgs = ((active_rows + tm - 1) / tm) * (int64_t)blocks_y;
+    const double rounds = (double)((wgs + ncu - 1) / ncu);
+    const double t = rounds * (0.00212 * tm + 1.66);
+    if (t < best_t) {
+      best_t = t;
+      best = v;
+    }
+  }
+  return best;
 }
 
 // With timing events (e0, e1 both set) the launch itself records the kernel's
@@ -532,7 +559,12 @@ hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t 
       hipLaunchKernelGGL(K, GRID, dim3(NT), 0, s, a);                        \
   } while (0)
   switch (v) {
-    case 0: GF2_LAUNCH((k_gemm_wide<512, 2048>), grid, 512); break;
+    case 0:
+      if (g_wide_threads == 1024)
+        GF2_LAUNCH((k_gemm_wide<1024, 2048>), grid, 1024);
+      else
+        GF2_LAUNCH((k_gemm_wide<512, 2048>), grid, 512);
+      break;
     case 1: GF2_LAUNCH((k_gemm_wide<512, 1024>), grid, 512); break;
     case 2: GF2_LAUNCH((k_gemm_wide<256, 512>), grid, 256); break;
     case 4: GF2_LAUNCH((k_gemm_narrow<256, 256>), gridn, 256); break;

@@ -23,10 +23,15 @@ __global__ void k_init_state(DecWork w) {
     w.bp_src[i] = (int32_t)i;
     w.bp_mark[i] = 0;
     w.lvl[i] = -1;
+    w.sp_src[i] = (int32_t)i;
+    w.sp_src[w.n + i] = (int32_t)i;
+    w.sp_mark[i] = 0;
+    w.sp_mark[w.n + i] = 0;
   }
   for (int64_t i = g; i < (int64_t)w.Mw * 64; i += stride) w.pivcols[i] = -1;
-  for (int64_t i = g; i < w.Mw; i += stride) {
+  for (int64_t i = g; i <= w.Mw; i += stride) {
     w.nzflag[i] = 0;
+    if (i == w.Mw) continue;
     w.sub[i].R = 0;
     w.sub[i].r = 0;
     w.sub[i].pad = 0;
@@ -36,11 +41,13 @@ __global__ void k_init_state(DecWork w) {
     w.st->R = 0;
     w.st->bp_count = 0;
     w.st->pad0 = 0;
+    w.sp_count[0] = 0;
+    w.sp_count[1] = 0;
   }
 }
 
 hipError_t launch_init_state(const DecWork &w, hipStream_t s) {
-  int64_t work = w.n > (int64_t)w.Mw * 64 ? w.n : (int64_t)w.Mw * 64;
+  int64_t work = w.n > (int64_t)w.Mw * 64 + 1 ? w.n : (int64_t)w.Mw * 64 + 1;
   int blocks = (int)((work + 255) / 256);
   if (blocks < 1) blocks = 1;
   if (blocks > 4096) blocks = 4096;

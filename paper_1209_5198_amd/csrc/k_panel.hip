@@ -49,6 +49,18 @@ __device__ inline uint64_t rdl64(uint64_t v, int l) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// lane l's value of the 64-bit pair (lo, hi), as a wave-uniform value
+__device__ inline uint64_t rdl64p(uint32_t lo, uint32_t hi, int l) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)hi, l) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)lo, l);
+}
+
+// bit s (uniform, 0..63) of the 64-bit pair (lo, hi): 0 or all ones
+__device__ inline uint32_t lanebit(uint32_t lo, uint32_t hi, int s) {
+  const uint64_t v = (((uint64_t)hi << 32) | lo) >> s;
+  return (uint32_t)__builtin_amdgcn_sbfe((int)(uint32_t)v, 0, 1);
+}
+
 // ---------------------------------------------------------------- panel-local update
 // Inside a panel, rows are updated lazily ("left-looking"): row p carries a
 // level lvl[p] = 16*q0 + L meaning sub-panels 0..L-1 of the panel starting at
@@ -144,12 +156,15 @@ struct ChainShared {
   unsigned long long scan_F;
   int nmv;
   int ctl_need, ctl_k, ctl_ib;
+  int sp_new, sp_base;
 };
 // end-of-panel staging, placed over the (then dead) tables
 struct ChainMoved {
   int64_t perm[kBlkMax + kMbMax];
   int pos[kBlkMax + kMbMax];
   int src[kBlkMax + kMbMax];
+  int sps[kBlkMax + kMbMax];
+  int spi[kBlkMax + kMbMax];
 };
 static_assert(sizeof(ChainMoved) <= sizeof(PanelTables), "staging fits in the table area");
 
@@ -171,7 +186,7 @@ __device__ inline uint64_t table4_entry(const uint64_t *src, int e) {
   return acc;
 }
 
-__global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int s_eff, int flag_q0) {
+__global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int s_eff, int flag_q0, int spb) {
   constexpr int NT = kChainThreads;
   __shared__ ChainShared sh;
   // (wave index made visibly uniform, so the pivot wave's loop stays scalar)
@@ -594,25 +609,50 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
       mv.pos[e] = pos;
       mv.src[e] = src;
       mv.perm[e] = w.perm[src];
+      mv.sps[e] = spb >= 0 ? w.sp_src[(size_t)spb * n + src] : 0;
     }
   }
   __syncthreads();
   const int nmv = sh.nmv;
+  // the super-panel's net permutation (spb >= 0: its buffer): the row now at
+  // pos was at position sp_src[pos] when the super-panel started; pos joins
+  // its list once
+  const int spv = spb >= 0 ? spb : 0;
+  int32_t *sp_src = w.sp_src + (size_t)spv * n, *sp_mark = w.sp_mark + (size_t)spv * n;
+  int32_t *sp_list = w.sp_list + (size_t)spv * kSpListMax;
+  if (tid == 0) sh.sp_new = 0;
+  __syncthreads();
   for (int e = tid; e < nmv; e += NT) {
     const int pos = mv.pos[e];
     w.perm[pos] = mv.perm[e];
     w.bp_src[pos] = mv.src[e];
     w.bp_mark[pos] = 1;
     w.bp_list[e] = pos;
+    mv.spi[e] = -1;
+    if (spb < 0) continue;
+    sp_src[pos] = mv.sps[e];
+    if (!sp_mark[pos]) {
+      sp_mark[pos] = 1;
+      mv.spi[e] = atomicAdd(&sh.sp_new, 1);
+    }
   }
+  __syncthreads();
   if (tid == 0) {
     w.st->bp_count = nmv;
     w.st->R = R0 + wb;
+    if (spb >= 0) {
+      const int base = w.sp_count[spb];
+      sh.sp_base = base;
+      w.sp_count[spb] = base + sh.sp_new;
+    }
   }
+  __syncthreads();
+  for (int e = tid; e < nmv; e += NT)
+    if (mv.spi[e] >= 0) sp_list[sh.sp_base + mv.spi[e]] = mv.pos[e];
 }
 
-hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, hipStream_t s) {
-  hipLaunchKernelGGL(k_chain, dim3(1), dim3(kChainThreads), 0, s, w, q0, s_eff, flag_q0);
+hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, int spb, hipStream_t s) {
+  hipLaunchKernelGGL(k_chain, dim3(1), dim3(kChainThreads), 0, s, w, q0, s_eff, flag_q0, spb);
   return hipGetLastError();
 }
 
@@ -644,12 +684,12 @@ union PostShared {
 };
 
 // the row now at listed position p comes from position bp_src[p] at the panel start
-__device__ void post_swap(const DecWork &w, int q0, int s_eff, int blk, int half) {
+__device__ void post_swap(const DecWork &w, int q0, int s_eff, int blk, int half, int wlo, int whi) {
   const int cnt = w.st->bp_count;
   if (cnt == 0) return;
   const int tid = threadIdx.x, wl = tid % kPW, e0 = tid / kPW;
   const int64_t qw = (int64_t)blk * TW + kPW * half + wl;
-  const bool act = qw < w.Mw && !(qw >= q0 && qw < q0 + s_eff);
+  const bool act = qw < w.Mw && qw >= wlo && qw < whi && !(qw >= q0 && qw < q0 + s_eff);
   constexpr int PER = (kMaxPanelWords * 64 * 2) / (kPostThreads / kPW);
   uint64_t vals[PER];
 #pragma unroll
@@ -671,12 +711,12 @@ __device__ void post_swap(const DecWork &w, int q0, int s_eff, int blk, int half
 //   E_b = Linv_b * X_b, then X_c ^= L_cb * E_b for later sub-panels c,
 // with L_cb = word q0+b of the pivot rows of sub-panel c (their multipliers for
 // the pivots of sub-panel b).  8-lane groups over the half block, 4-bit tables.
-__device__ void post_trsm(const DecWork &w, int q0, int s_eff, int blk, int half, TrsmShared &sh) {
+__device__ void post_trsm(const DecWork &w, int q0, int s_eff, int blk, int half, int whi, TrsmShared &sh) {
   constexpr int G = kPostThreads / kPW;  // row groups
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, h = lane / kPW, wl = lane % kPW;
   const int qc0 = q0 + s_eff;
   const int64_t qw = (int64_t)blk * TW + kPW * half + wl;
-  const bool qok = qw >= qc0 && qw < w.Mw;
+  const bool qok = qw >= qc0 && qw < whi;
   const int64_t ldw = w.ldw;
   uint64_t *W = w.W;
   if (tid < s_eff) sh.Sb[tid] = w.sub[q0 + tid];
@@ -771,24 +811,27 @@ __device__ void post_rows(const DecWork &w, int q0, int s_eff, int64_t blk0, Pan
     if (j >= L && j < s_eff) w.W[widx(w.ldw, i, q0 + j)] = x[j];
 }
 
-__global__ __launch_bounds__(kPostThreads) void k_post(DecWork w, int q0, int s_eff) {
+// Words [wlo, whi) (wlo <= q0, whi <= Mw): the column workgroups cover the
+// blocks that meet them.
+__global__ __launch_bounds__(kPostThreads) void k_post(DecWork w, int q0, int s_eff, int wlo, int whi) {
   __shared__ PostShared sh;
   constexpr int kParts = TW / kPW;
-  const int nc = kParts * w.NB;  // column workgroups: kParts per 16-word block
+  const int blk0 = wlo / TW;
+  const int nc = kParts * ((whi - 1) / TW - blk0 + 1);  // column workgroups: kParts per 16-word block
   if ((int)blockIdx.x < nc) {
-    const int blk = blockIdx.x / kParts, half = blockIdx.x % kParts;
-    post_swap(w, q0, s_eff, blk, half);
+    const int blk = blk0 + (int)blockIdx.x / kParts, half = blockIdx.x % kParts;
+    post_swap(w, q0, s_eff, blk, half, wlo, whi);
     const int qc0 = q0 + s_eff;
-    if (qc0 < w.Mw && (int64_t)blk * TW + kPW * half + kPW - 1 >= qc0) post_trsm(w, q0, s_eff, blk, half, sh.t);
+    if (qc0 < whi && blk * TW + kPW * half + kPW - 1 >= qc0) post_trsm(w, q0, s_eff, blk, half, whi, sh.t);
   } else {
     post_rows(w, q0, s_eff, (int64_t)(blockIdx.x - nc) * kRowsPerWG, sh.pt);
   }
 }
 
-hipError_t launch_post(const DecWork &w, int q0, int s_eff, hipStream_t s) {
+hipError_t launch_post(const DecWork &w, int q0, int s_eff, int wlo, int whi, hipStream_t s) {
   const int64_t rows_wg = (w.n + kRowsPerWG - 1) / kRowsPerWG;
-  const int64_t blocks = (int64_t)(TW / kPW) * w.NB + rows_wg;
-  hipLaunchKernelGGL(k_post, dim3((unsigned)blocks), dim3(kPostThreads), 0, s, w, q0, s_eff);
+  const int64_t blocks = (int64_t)(TW / kPW) * ((whi - 1) / TW - wlo / TW + 1) + rows_wg;
+  hipLaunchKernelGGL(k_post, dim3((unsigned)blocks), dim3(kPostThreads), 0, s, w, q0, s_eff, wlo, whi);
   return hipGetLastError();
 }
 

@@ -73,15 +73,20 @@ def check_decomposition(g, A, n, m, ref):
     assert digest(L) == ref["L"]
 
 
-@pytest.mark.parametrize("case", ["dense16384", "dense65536"])
-def test_fullsize_dense_decompose(g, gold, case):
+@pytest.mark.parametrize("case,sp", [("dense16384", 0), ("dense65536", 0), ("dense16384", 2), ("dense65536", 4)])
+def test_fullsize_dense_decompose(g, gold, case, sp):
+    """Full-size digests with the one-level schedule and with super-panels."""
     ref = gold.get(case)
     if ref is None:
         pytest.skip(f"no golden digests for {case}")
     n, m = ref["n"], ref["m"]
-    say("fullsize", case, n, m)
+    say("fullsize", case, n, m, "sp_panels", sp)
     A = g.Mat.from_rowmajor(synth.dense(ref["seed"], ref["stream"], n, m), n, m)
-    check_decomposition(g, A, n, m, ref)
+    g.gf2_set_param("sp_panels", sp)
+    try:
+        check_decomposition(g, A, n, m, ref)
+    finally:
+        g.gf2_set_param("sp_panels", 0)
 
 
 def test_fullsize_planted_rank(g, gold):

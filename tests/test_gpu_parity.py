@@ -129,16 +129,24 @@ def test_decompose_panel_width_invariant(g, orc, panel_words):
     assert_same_ple(got, ref, panel_words)
 
 
-KNOB_DEFAULTS = {"panel_gemm_variant": -1, "overlap_lookups": 300000000, "post_follow_lookups": 1500000000}
+KNOB_DEFAULTS = {"panel_gemm_variant": -1, "overlap_lookups": 300000000, "post_follow_lookups": 1500000000,
+                 "sp_panels": 0, "panel_words": 8}
 
 
 @pytest.mark.parametrize("knobs", [{"panel_gemm_variant": v} for v in range(6)] + [
-    {"overlap_lookups": 0}, {"overlap_lookups": 10 ** 15}, {"post_follow_lookups": -1},
-    # the early bulk update and the post-follow schedule active on every panel at once
-    {"overlap_lookups": 0, "post_follow_lookups": 0},
-    {"overlap_lookups": 10 ** 15, "post_follow_lookups": 0}])
+    # one-level schedule: the early bulk update and the post-follow schedule
+    # on every panel at once, or neither
+    {"overlap_lookups": 0, "post_follow_lookups": 0}, {"overlap_lookups": 10 ** 15, "post_follow_lookups": -1},
+    {"overlap_lookups": 10 ** 15, "post_follow_lookups": 0},
+    # super-panels of 1, 2 and 3 panels: far words (beyond this super-panel and
+    # the next) exist at 2900 columns, so the deferred row exchanges, the far
+    # pivot-row solve and the far products all run
+    {"sp_panels": 1}, {"sp_panels": 2}, {"sp_panels": 3},
+    {"sp_panels": 1, "overlap_lookups": 0}, {"sp_panels": 2, "overlap_lookups": 10 ** 15},
+    # narrow panels: many super-panels, partial last ones
+    {"sp_panels": 3, "panel_words": 1}, {"sp_panels": 5, "panel_words": 2}, {"sp_panels": 32, "panel_words": 3}])
 def test_decompose_tuning_invariant(g, orc, knobs):
-    """Look-ahead schedule and product-kernel variant do not change any result."""
+    """Look-ahead schedule, super-panel width and product-kernel variant do not change any result."""
     n, m = 2300, 2900
     say("tuning", knobs)
     A = synth.dense(17, 1, n, m)
@@ -151,6 +159,29 @@ def test_decompose_tuning_invariant(g, orc, knobs):
         for k in knobs:
             g.gf2_set_param(k, KNOB_DEFAULTS[k])
     assert_same_ple(got, ref, knobs)
+
+
+@pytest.mark.parametrize("kind,sp", [("sparse", 1), ("planted", 1), ("planted", 2), ("dense", 2), ("sparse", 4),
+                                     ("planted", 4), ("dense", 0)])
+def test_decompose_super_panels(g, orc, kind, sp):
+    """Far words at several super-panel widths on inputs whose pivots fall far
+    from the diagonal (sparse), stop early (planted rank) or are dense, with
+    more rows than columns."""
+    n, m = 3100, 4700
+    say("super-panels", kind, sp)
+    if kind == "sparse":
+        A = synth.bernoulli(91, 1, n, m, 0.002)
+    elif kind == "planted":
+        A = planted_words(orc, 92, n, m, 1700)
+    else:
+        A = synth.dense(93, 1, n, m)
+    ref = orc.ple(A, n, m)
+    g.gf2_set_param("sp_panels", sp)
+    try:
+        got = gpu_decompose(g, A, n, m)
+    finally:
+        g.gf2_set_param("sp_panels", 0)
+    assert_same_ple(got, ref, (kind, sp))
 
 
 def test_chain_cus_rejected(g):
