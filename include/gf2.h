@@ -335,6 +335,25 @@ int gf2_solve_batched_ws(const gf2_batch_item *items, int64_t count, const uint6
 int gf2_decompose_noalloc(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t *perm, int64_t *pivcols,
                           int64_t *rank, void *stream);
 
+/*
+ * Captured decomposition.  gf2_decompose_graph records one gf2_decompose_ws
+ * call with these arguments into a HIP graph (stream capture on `stream`,
+ * which must not be the null stream; every launch in order on that stream,
+ * without the look-ahead streams) and instantiates it; nothing runs and
+ * nothing is allocated on the device.
+ * gf2_graph_launch replays the whole decomposition on `stream` with the same
+ * pointers: the caller refills A between replays, and every output and the
+ * workspace are rewritten by each replay (the workspace must stay allocated
+ * and must not be used by other calls while a replay runs).  Errors as
+ * gf2_decompose_ws, plus GF2_EHIP when capture or instantiation fails.
+ * gf2_graph_destroy releases the graph (NULL is accepted).
+ */
+typedef struct gf2_graph_s *gf2_graph;
+int gf2_decompose_graph(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t *perm, int64_t *pivcols,
+                        int64_t *rank, void *workspace, size_t workspace_bytes, void *stream, gf2_graph *graph);
+int gf2_graph_launch(gf2_graph graph, void *stream);
+int gf2_graph_destroy(gf2_graph graph);
+
 /* Free the library-owned workspace, look-ahead streams and events of every
  * device (after synchronising those devices).  Safe to call at any time
  * between calls; later calls create what they need again. */

@@ -45,6 +45,9 @@ int g_panel_gemm_variant = -1;  // product-kernel variant for the trailing updat
 // kSpSubMax sub-panels).  Measured on MI355X at 65536^2: 56.7 ms one-level
 // against 65.3 (2), 66.4 (1) and 69.1 ms (4) with super-panels.
 int g_sp_panels = 0;
+// one-level schedule: product tiles by the wall-time rule instead of the
+// largest tile that still gives every CU a workgroup
+bool g_wall_tiles = false;
 // near-update size (table lookups) from which a panel's update of the near
 // words beyond the next panel starts right after the row exchanges, beside
 // the next panel's columns and its pivot chain, instead of after them
@@ -384,7 +387,8 @@ int trailing_gemm(DecWork &w, int q0, int nsub, int nz, int skip, int qc0, int q
   int64_t active = w.n - 64ll * (q0 + nsub);
   if (active < 1) active = 1;
   int v = g_panel_gemm_variant;
-  if (v < 0 && !g_tuned_on && g_sp_panels > 0) v = gemm_wall_variant(active, qc0, qc1, gf2::device_cus());
+  if (v < 0 && !g_tuned_on && (g_sp_panels > 0 || g_wall_tiles))
+    v = gemm_wall_variant(active, qc0, qc1, gf2::device_cus());
   return run_gemm(a, w.n, v, active, s);
 }
 
@@ -727,6 +731,11 @@ int gf2_set_param(const char *name, int64_t value) {
   if (!strcmp(name, "sp_panels")) {
     if (value < 0 || value > kSpSubMax) return fail(GF2_EINVAL, "sp_panels must be in 0..32");
     g_sp_panels = (int)value;
+    return GF2_OK;
+  }
+  if (!strcmp(name, "wall_tiles")) {
+    if (value < 0 || value > 1) return fail(GF2_EINVAL, "wall_tiles must be 0 or 1");
+    g_wall_tiles = value == 1;
     return GF2_OK;
   }
   if (!strcmp(name, "wide_threads")) {
@@ -1476,6 +1485,66 @@ int gf2_decompose_noalloc(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, 
   g_noalloc = true;
   rc = decompose_body(A, L, E, perm, pivcols, rank, ws, (hipStream_t)stream, true);
   g_noalloc = false;
+  return rc;
+}
+
+// A captured decomposition: the instantiated graph of one gf2_decompose_ws
+// call with every launch in order on the capturing stream.  (Capturing the
+// look-ahead streams through their events ended in a host-side crash inside
+// the runtime during capture on MI355X; that form is not used.)
+struct gf2_graph_s {
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+};
+
+int gf2_decompose_graph(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t *perm, int64_t *pivcols,
+                        int64_t *rank, void *workspace, size_t workspace_bytes, void *stream, gf2_graph *graph) {
+  int rc;
+  if (!graph) return fail(GF2_EINVAL, "gf2_decompose_graph: null graph pointer");
+  *graph = nullptr;
+  if (!stream) return fail(GF2_EINVAL, "gf2_decompose_graph: capture needs a stream other than the null stream");
+  if ((rc = decompose_check(A, L, E))) return rc;
+  if ((rc = check_ws(workspace, workspace_bytes, decompose_need(A), "gf2_decompose_graph"))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  const bool prof = g_noalloc;
+  g_noalloc = true;  // no profiling events inside a capture
+  rc = decompose_body(A, L, E, perm, pivcols, rank, workspace, s, true);
+  g_noalloc = prof;
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(s, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (ec != hipSuccess) return hip_fail(ec, "gf2_decompose_graph: hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return hip_fail(ei, "gf2_decompose_graph: hipGraphInstantiate");
+  gf2_graph h = new gf2_graph_s;
+  h->exec = exec;
+  h->device = dev;
+  *graph = h;
+  return GF2_OK;
+}
+
+int gf2_graph_launch(gf2_graph graph, void *stream) {
+  if (!graph || !graph->exec) return fail(GF2_EINVAL, "gf2_graph_launch: null graph");
+  HIPCHK(hipGraphLaunch(graph->exec, (hipStream_t)stream));
+  return GF2_OK;
+}
+
+int gf2_graph_destroy(gf2_graph graph) {
+  if (!graph) return GF2_OK;
+  int rc = GF2_OK;
+  if (graph->exec) {
+    const hipError_t e = hipGraphExecDestroy(graph->exec);
+    if (e != hipSuccess) rc = hip_fail(e, "gf2_graph_destroy");
+  }
+  delete graph;
   return rc;
 }
 

@@ -260,6 +260,10 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
   };
 
   int wb = 0;  // block index of position Rb
+  // The update of the block rows by sub-panel b runs in two parts: the next
+  // window's word b + 1 (all the next search reads) right away, the rest by
+  // waves 1..7 while wave 0 searches the pivots of sub-panel b + 1.
+  int def_b = -1, def_win = 0;  // deferred sub-panel; rows [wb, def_win) hold word b + 1 already
   for (int b = 0; b < s_eff; ++b) {
     const int q = q0 + b;
     const int64_t Rb = R0 + wb;
@@ -289,14 +293,18 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
     // (RREF of the pivots so far) and the coefficient map, free slots.
     // mm: lanes j of earlier pivots whose M_j has bit k.
     auto commit = [&](int k, uint32_t p_lo, uint32_t p_hi, uint64_t mm) {
-      const bool up = __builtin_amdgcn_inverse_ballot_w64(mm);
       const uint64_t tb = 1ull << ib;
       const uint32_t t_lo = (uint32_t)tb, t_hi = (uint32_t)(tb >> 32);
-      const uint32_t xm_lo = m_lo ^ p_lo, xm_hi = m_hi ^ p_hi, xy_lo = y_lo ^ t_lo, xy_hi = y_hi ^ t_hi;
-      m_lo = wrlane(p_lo, k, up ? xm_lo : m_lo);
-      m_hi = wrlane(p_hi, k, up ? xm_hi : m_hi);
-      y_lo = wrlane(t_lo, k, up ? xy_lo : y_lo);
-      y_hi = wrlane(t_hi, k, up ? xy_hi : y_hi);
+      if (__builtin_amdgcn_inverse_ballot_w64(mm)) {  // (exec-masked XORs)
+        m_lo ^= p_lo;
+        m_hi ^= p_hi;
+        y_lo ^= t_lo;
+        y_hi ^= t_hi;
+      }
+      m_lo = wrlane(p_lo, k, m_lo);
+      m_hi = wrlane(p_hi, k, m_hi);
+      y_lo = wrlane(t_lo, k, y_lo);
+      y_hi = wrlane(t_hi, k, y_hi);
       const uint64_t kb = 1ull << k;
       pivmask |= kb;
       act0 &= ~tb;
@@ -322,14 +330,19 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
         const int p_org = __builtin_amdgcn_readlane(org0, sp);
         const uint32_t i_lo = __builtin_amdgcn_readlane(a_lo, ib), i_hi = __builtin_amdgcn_readlane(a_hi, ib);
         const int i_org = __builtin_amdgcn_readlane(org0, ib);
-        const bool r0 = __builtin_amdgcn_inverse_ballot_w64(c0 & ~(1ull << sp));
-        const uint32_t xa_lo = a_lo ^ p_lo, xa_hi = a_hi ^ p_hi;
-        a_lo = r0 ? xa_lo : a_lo;
-        a_hi = r0 ? xa_hi : a_hi;
-        // (slot ib holds no candidate unless ib == sp; then both writes store the pivot)
-        a_lo = wrlane(p_lo, ib, wrlane(i_lo, sp, a_lo));
-        a_hi = wrlane(p_hi, ib, wrlane(i_hi, sp, a_hi));
-        org0 = wrlane(p_org, ib, wrlane(i_org, sp, org0));
+        if (__builtin_amdgcn_inverse_ballot_w64(c0 & ~(1ull << sp))) {  // (exec-masked XORs)
+          a_lo ^= p_lo;
+          a_hi ^= p_hi;
+        }
+        // (slot ib holds no candidate unless ib == sp; then both writes store
+        // the pivot); the writes are grouped by lane so the lane register is
+        // set twice
+        a_lo = wrlane(i_lo, sp, a_lo);
+        a_hi = wrlane(i_hi, sp, a_hi);
+        org0 = wrlane(i_org, sp, org0);
+        a_lo = wrlane(p_lo, ib, a_lo);
+        a_hi = wrlane(p_hi, ib, a_hi);
+        org0 = wrlane(p_org, ib, org0);
         commit(k, p_lo, p_hi, __ballot(((HI ? m_hi : m_lo) & bit) != 0u));
       }
     };
@@ -381,6 +394,18 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
     };
 
     int k = 0;
+    if (wv != 0 && def_b >= 0) {  // the rest of sub-panel def_b's block-row update
+      for (int i = wb + tid - 64; i < nblk; i += NT - 64) {
+        uint64_t x[kMaxPanelWords];
+#pragma unroll
+        for (int j = 0; j < kMaxPanelWords; ++j) x[j] = sh.blk[i][j];
+        panel_update(x, def_b, def_b + 1, s_eff - 1, sh.pt);
+#pragma unroll
+        for (int j = 0; j < kMaxPanelWords; ++j)
+          if (j != def_b + 1 || i >= def_win) sh.blk[i][j] = x[j];
+      }
+    }
+    def_b = -1;
     while (true) {
       if (wv == 0) {
         const bool need = pivot_wave(k);
@@ -516,10 +541,15 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
     uint64_t yx = 0ull;
     if (wv == 0) {
       if (lane < r) yx = proj4(sh.Tp, sh.blk[wb + lane][b]);
+      // Linv = L_pp^{-1} by forward substitution over t: every row s > t whose
+      // multipliers include pivot t XORs in the finished row t.  The rows
+      // that take row t are lane t of the transposed strictly lower part,
+      // so each step is two lane reads and one masked XOR.
       uint64_t li = lane < r ? (1ull << lane) : 0ull;
+      const uint64_t ycol = transpose64(lane < r ? (yx & ((1ull << lane) - 1ull)) : 0ull, lane);
       for (int t = 0; t < r; ++t) {
         const uint64_t row = rdl64(li, t);
-        if (lane > t && lane < r && ((yx >> t) & 1ull)) li ^= row;
+        if (__builtin_amdgcn_inverse_ballot_w64(rdl64(ycol, t))) li ^= row;
       }
       sh.Li[lane] = li;
       w.Zc[(size_t)q * 64 + lane] = yM;
@@ -562,13 +592,30 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
       sh.pt.Te[pidx(b, wd)][g][v] = acc;
     }
     __syncthreads();
-    for (int i = wb + r + tid; i < nblk; i += NT) {
-      uint64_t x[kMaxPanelWords];
+    if (b + 1 < s_eff) {
+      // word b + 1 of the next window's rows: y = (word b) * Zc_b, then
+      // word b + 1 ^= y * E_b[b + 1] (4-bit tables); the rest is deferred
+      const int we = wb + r + kWin < nblk ? wb + r + kWin : nblk;
+      for (int i = wb + r + tid; i < we; i += NT) {
+        uint64_t y = 0ull;
 #pragma unroll
-      for (int j = 0; j < kMaxPanelWords; ++j) x[j] = sh.blk[i][j];
-      panel_update(x, b, b + 1, s_eff - 1, sh.pt);
+        for (int g = 0; g < 16; ++g) y ^= sh.pt.Tz[b][g][(sh.blk[i][b] >> (4 * g)) & 15u];
+        uint64_t v = 0ull;
 #pragma unroll
-      for (int j = 0; j < kMaxPanelWords; ++j) sh.blk[i][j] = x[j];
+        for (int g = 0; g < 16; ++g) v ^= sh.pt.Te[pidx(b, b + 1)][g][(y >> (4 * g)) & 15u];
+        sh.blk[i][b + 1] ^= v;
+      }
+      def_b = b;
+      def_win = we;
+    } else {
+      for (int i = wb + r + tid; i < nblk; i += NT) {
+        uint64_t x[kMaxPanelWords];
+#pragma unroll
+        for (int j = 0; j < kMaxPanelWords; ++j) x[j] = sh.blk[i][j];
+        panel_update(x, b, b + 1, s_eff - 1, sh.pt);
+#pragma unroll
+        for (int j = 0; j < kMaxPanelWords; ++j) sh.blk[i][j] = x[j];
+      }
     }
     __syncthreads();
     wb += r;

@@ -31,7 +31,8 @@ EXPORTED = ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_decompo
             "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_inverse", "gf2_autotune", "gf2_autotune_table",
             "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_microbench", "gf2_workspace_bytes",
             "gf2_matmul_ws", "gf2_decompose_ws", "gf2_rank_ws", "gf2_solve_ws", "gf2_decompose_batched_ws",
-            "gf2_solve_batched_ws", "gf2_decompose_noalloc", "gf2_release", "gf2_last_error", "gf2_version")
+            "gf2_solve_batched_ws", "gf2_decompose_noalloc", "gf2_decompose_graph", "gf2_graph_launch",
+            "gf2_graph_destroy", "gf2_release", "gf2_last_error", "gf2_version")
 # operation codes of gf2_workspace_bytes
 OP_MATMUL, OP_DECOMPOSE, OP_RANK, OP_SOLVE, OP_DECOMPOSE_BATCHED, OP_SOLVE_BATCHED = range(6)
 SIZE_MAX = 2 ** 64 - 1
@@ -95,6 +96,9 @@ def load():
         lib.gf2_decompose_batched_ws.argtypes = [PB, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         lib.gf2_solve_batched_ws.argtypes = [PB, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         lib.gf2_decompose_noalloc.argtypes = [P, P, P, vp, vp, vp, vp]
+        lib.gf2_decompose_graph.argtypes = [P, P, P, vp, vp, vp, vp, sz, vp, ctypes.POINTER(vp)]
+        lib.gf2_graph_launch.argtypes = [vp, vp]
+        lib.gf2_graph_destroy.argtypes = [vp]
         lib.gf2_release.argtypes = []
         lib.gf2_last_error.restype = ctypes.c_char_p
         lib.gf2_version.restype = ctypes.c_char_p
@@ -102,7 +106,8 @@ def load():
                      "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_inverse", "gf2_autotune",
                      "gf2_autotune_table", "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_microbench",
                      "gf2_matmul_ws", "gf2_decompose_ws", "gf2_rank_ws", "gf2_solve_ws", "gf2_decompose_batched_ws",
-                     "gf2_solve_batched_ws", "gf2_decompose_noalloc", "gf2_release"):
+                     "gf2_solve_batched_ws", "gf2_decompose_noalloc", "gf2_decompose_graph", "gf2_graph_launch",
+                     "gf2_graph_destroy", "gf2_release"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
         atexit.register(_release_at_exit)
@@ -323,6 +328,27 @@ def gf2_decompose_noalloc(A: Mat, L, E, perm, pivcols, rank, stream=None) -> Non
     Ed = ctypes.byref(E.desc()) if E is not None else None
     _check(load().gf2_decompose_noalloc(ctypes.byref(A.desc()), Ld, Ed, _ptr(perm), _ptr(pivcols), _ptr(rank),
                                         _stream(stream)))
+
+
+class DecomposeGraph:
+    """gf2_decompose_graph: one captured decomposition, replayed by launch()."""
+
+    def __init__(self, A: Mat, L, E, perm, pivcols, rank, workspace, stream):
+        Ld = ctypes.byref(L.desc()) if L is not None else None
+        Ed = ctypes.byref(E.desc()) if E is not None else None
+        p, nb = _ws(workspace)
+        h = ctypes.c_void_p()
+        _check(load().gf2_decompose_graph(ctypes.byref(A.desc()), Ld, Ed, _ptr(perm), _ptr(pivcols), _ptr(rank), p,
+                                          nb, _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def launch(self, stream=None):
+        _check(load().gf2_graph_launch(self.h, _stream(stream)))
+
+    def close(self):
+        if self.h:
+            _check(load().gf2_graph_destroy(self.h))
+            self.h = None
 
 
 def gf2_rank_ws(A: Mat, rank, workspace, stream=None) -> None:
