@@ -72,10 +72,10 @@ LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12   # 157.3 TB/s: 256 CUs x 256 B/clk x 2.
 # HBM bytes per product launch in this decomposition, from rocprofv3 counters:
 # FETCH_SIZE (KiB per dispatch, x2: a plain 1 GiB copy reads 524305 KiB) and
 # WRITE_SIZE (KiB, x1: the copy writes 1048576 KiB), averaged over the 253
-# product launches of one 65536^2 decomposition.  Valid only for the product
-# kernel source they were measured on.
-TRAFFIC = {"kernel_source_sha256": "da6bb8d96d6688417a9893d5151d76b85200097f657bd9a9befdbdc72ee6942c",
-           "fetch_bytes": 55103.8 * 2 * 1024, "write_bytes": 87507.2 * 1024}
+# product launches of one 65536^2 decomposition (four decompositions counted).
+# Valid only for the product kernel source they were measured on.
+TRAFFIC = {"kernel_source_sha256": "1c4330f1d299f3a7f826ecfec0f4ad62aa87a27189fa265d4d45c918376aec46",
+           "fetch_bytes": 57864.25 * 2 * 1024, "write_bytes": 93534.79 * 1024}
 SEED = 65536
 # The oracle on the bench's own 65536^2 input (seed 65536), run once on the
 # whole matrix (about 7e11 word operations, minutes of CPU time, so this script
