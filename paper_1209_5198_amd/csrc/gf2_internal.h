@@ -7,6 +7,10 @@
 
 #include "../../include/gf2.h"
 
+// v_writelane_b32 (lane `lane` of `old` receives the uniform value `val`): an
+// LLVM intrinsic that clang does not expose as a builtin.
+extern "C" __device__ int gf2_llvm_writelane(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 namespace gf2 {
 
 // ---------------------------------------------------------------- working layout
@@ -33,6 +37,11 @@ __host__ __device__ inline uint64_t pad_mask(int64_t cols, int64_t q) {
   if (valid <= 0) return 0ull;
   return (1ull << valid) - 1ull;
 }
+
+__device__ inline uint32_t wrlane(uint32_t val, int lane, uint32_t old) {
+  return (uint32_t)gf2_llvm_writelane((int)val, lane, (int)old);
+}
+__device__ inline int wrlane(int val, int lane, int old) { return gf2_llvm_writelane(val, lane, old); }
 
 __device__ inline uint64_t shfl_xor64(uint64_t x, int m) {
   const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, m), hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), m);

@@ -35,15 +35,36 @@ namespace gf2 {
 namespace {
 
 constexpr int NT = kBatchThreads;          // threads per workgroup
-constexpr int RPT = kBatchMaxDim / NT;     // panel positions per thread in the pivot search
 constexpr int NW = NT / 64;                // waves per workgroup
+constexpr int kWin = 128;                  // window rows of the pivot search, two per lane of wave 0
+constexpr int RB = (kBatchMaxDim - kWin + NT - 1) / NT;  // rows beyond the window per thread
 constexpr int kChunk = 8;                  // later words per table build
-static_assert(RPT * NT == kBatchMaxDim, "positions per thread");
 
 __device__ inline uint64_t rdl64b(uint64_t v, int l) {
   const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
   const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
   return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline uint64_t wrl64b(uint64_t old, uint64_t v, int l) {
+  const uint32_t lo = wrlane((uint32_t)v, l, (uint32_t)old);
+  const uint32_t hi = wrlane((uint32_t)(v >> 32), l, (uint32_t)(old >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline uint64_t wave_or64(uint64_t v) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    lo |= (uint32_t)__shfl_xor((int)lo, o);
+    hi |= (uint32_t)__shfl_xor((int)hi, o);
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+// x times the 64 x 64 matrix whose sixteen 4-bit tables are tab (Section 6, c = 4)
+__device__ inline uint64_t apply16(const uint64_t (&tab)[16][16], uint64_t x) {
+  uint64_t acc = 0ull;
+#pragma unroll
+  for (int g = 0; g < 16; ++g) acc ^= tab[g][(x >> (4 * g)) & 15u];
+  return acc;
 }
 
 // Bit compression (gather the bits of x selected by mask into the low bits, in
@@ -79,21 +100,33 @@ __device__ inline uint64_t compress(uint64_t x, uint64_t m, const uint64_t *mv) 
 struct BatchShared {
   int32_t map[kBatchMaxDim];          // position -> row of the working copy
   uint64_t cvec[kBatchMaxDim];        // canonical multipliers of positions R.. (then pivot columns)
-  uint64_t T[16][16][kChunk];         // 4-bit tables of the current chunk
-  uint64_t U[64][kChunk];             // pivot rows' chunk words, by pivot bit position
+  union {
+    struct {
+      uint64_t T[16][16][kChunk];     // 4-bit tables of the current chunk
+      uint64_t U[64][kChunk];         // pivot rows' chunk words, by pivot bit position
+    } up;
+    struct {
+      uint64_t ninv[64];              // row k of (I + N)^-1 (bit-position space)
+      uint64_t Nt[16][16];            // its 4-bit tables
+    } fin;
+  } tr;
   uint64_t Tt[16][16];                // 4-bit tables of the rows of T^-1
   uint64_t tinv[64];                  // row k of T^-1 (bit-position space)
-  uint64_t pivw[64];                  // panel words of the panel's pivot rows
+  uint64_t pivw[64];                  // panel words of the panel's pivot rows, as found
   uint64_t pK[kBatchMaxPanels];       // pivot mask of each panel
   uint64_t pmv[kBatchMaxPanels][6];   // compress masks of each panel's pivot mask
   int32_t pR[kBatchMaxPanels];        // rank before each panel
   int32_t pr[kBatchMaxPanels];        // pivots of each panel
   int32_t prow[64];                   // pivot t of the current panel -> bit position
-  int32_t wc[2][NW];                  // per-wave first candidate position (double-buffered by bit)
-  uint64_t ww[2][NW];                 // ... its word
-  int32_t wo[2][NW];                  // ... its row
-  uint64_t sw[2];                     // word at the next free position
-  int32_t so[2];                      // ... its row
+  uint64_t fb[NW];                    // per-wave OR of the rows' words
+  int32_t cand[NW];                   // per-wave first beyond row with the requested bit
+  uint64_t candw[NW];                 // ... its word
+  int32_t cando[NW];                  // ... its row
+  uint64_t kmask;                     // pivot mask so far
+  uint64_t xfer_x;                    // word of the row leaving the window
+  int32_t xfer_o;                     // ... its row
+  int32_t cmd;                        // bit the window has no candidate for, or -1 when done
+  int32_t tcnt;                       // pivots so far
   int32_t lj0[kBatchMaxPanels];       // first panel whose pivots reach L word lw
   int32_t job;
 };
@@ -126,111 +159,195 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
     for (int q = 0; q < Mw && R < n; ++q) {
       nq = q + 1;
       const int nbits = (m - 64 * q) < 64 ? (m - 64 * q) : 64;
-      // Position R + NT*u + tid is slot u of thread tid; slots at or beyond
-      // nsl hold no row for any thread and are skipped with uniform branches.
-      const int nsl = (n - R + NT - 1) / NT;
-      uint64_t x[RPT];
-      int org[RPT];
-#pragma unroll
-      for (int u = 0; u < RPT; ++u) {
-        x[u] = 0ull;
-        org[u] = 0;
-        const int pos = R + NT * u + tid;
-        if (u < nsl && pos < n) {
-          org[u] = sh.map[pos];
-          x[u] = W[(size_t)org[u] * Mw + q];
+      const int nrest = n - R;  // rows at or below the next free position
+      // Positions R .. R + kWin - 1 form the window: position R + 64 * s + l is
+      // slot s of lane l of wave 0.  Position R + kWin + NT * u + tid is slot u
+      // of thread tid ("beyond" rows); slots at or beyond nslb hold no row.
+      const int nslb = nrest > kWin ? (nrest - kWin + NT - 1) / NT : 0;
+      uint64_t xw0 = 0ull, xw1 = 0ull;
+      int ow0 = 0, ow1 = 0;
+      uint64_t f = 0ull;
+      if (wv == 0) {
+        if (lane < nrest) {
+          ow0 = sh.map[R + lane];
+          xw0 = W[(size_t)ow0 * Mw + q];
         }
+        if (64 + lane < nrest) {
+          ow1 = sh.map[R + 64 + lane];
+          xw1 = W[(size_t)ow1 * Mw + q];
+        }
+        f = xw0 | xw1;
       }
-
-      // ---- pivot search over the bits of word q (one barrier per bit)
-      int t = 0;
-      uint64_t K = 0ull;
-      for (int k = 0; k < nbits; ++k) {
-        const int pos = R + t;
-        if (pos >= n) break;
-        const int buf = k & 1;
-        uint32_t mk[RPT];  // all ones where the slot's bit k is 1
-        int ustar = -1;
-        int fl = 0;
-        uint64_t cw = 0ull;
-        int corg = 0;
+      uint64_t xb[RB];
+      int ob[RB];
 #pragma unroll
-        for (int u = 0; u < RPT; ++u) {
-          mk[u] = 0u;
-          if (u < nsl) {
-            const uint32_t half = (k < 32) ? (uint32_t)x[u] : (uint32_t)(x[u] >> 32);
-            mk[u] = 0u - ((half >> (k & 31)) & 1u);
-            const bool c = mk[u] && (u > 0 || tid >= t);
-            const uint64_t bal = __ballot(c);
-            if (ustar < 0 && bal) {
-              ustar = u;
-              fl = (int)__builtin_ctzll(bal);
-              cw = rdl64b(x[u], fl);
-              corg = __builtin_amdgcn_readlane(org[u], fl);
+      for (int u = 0; u < RB; ++u) {
+        xb[u] = 0ull;
+        ob[u] = 0;
+        const int pos = R + kWin + NT * u + tid;
+        if (u < nslb && pos < n) {
+          ob[u] = sh.map[pos];
+          xb[u] = W[(size_t)ob[u] * Mw + q];
+        }
+        f |= xb[u];
+      }
+      // F: the bits some row at or below the next free position has.  A bit
+      // that no such row has cannot become a pivot later in this word: every
+      // reduction XORs one of these rows into another.
+      f = wave_or64(f);
+      if (lane == 0) sh.fb[wv] = f;
+      __syncthreads();
+      uint64_t F = 0ull;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) F |= sh.fb[w];
+
+      // ---- pivot search over the bits of word q.  Wave 0 decides from the
+      // window alone while it holds a candidate for the current bit; the beyond
+      // rows are reduced lazily, by the pivots logged since their last catch-up,
+      // only when the window has none (then the whole workgroup takes part).
+      int t = 0, k = 0, lstart = 0, xfer = -1;
+      uint64_t K = 0ull;
+      for (;;) {
+        if (wv == 0) {
+          int need = -1;
+          while (k < nbits && R + t < n) {
+            if (!((F >> k) & 1ull)) {
+              ++k;
+              continue;
             }
+            const uint32_t b0 = (uint32_t)(xw0 >> k) & 1u, b1 = (uint32_t)(xw1 >> k) & 1u;
+            const uint64_t bal0 = __ballot(b0 && lane >= t);
+            const uint64_t bal1 = __ballot(b1);
+            if (!(bal0 | bal1)) {
+              if (nslb > 0) {
+                need = k;
+                break;
+              }
+              ++k;  // the window is every remaining row: not a pivot column
+              continue;
+            }
+            int p;
+            uint64_t pw;
+            int porg;
+            if (bal0) {
+              p = (int)__builtin_ctzll(bal0);
+              pw = rdl64b(xw0, p);
+              porg = __builtin_amdgcn_readlane(ow0, p);
+            } else {
+              p = 64 + (int)__builtin_ctzll(bal1);
+              pw = rdl64b(xw1, p - 64);
+              porg = __builtin_amdgcn_readlane(ow1, p - 64);
+            }
+            // every later row with bit k is reduced in the bits above k (rows
+            // between t and p have no bit k; the pivot row itself is kept)
+            const uint64_t ph = (k == 63) ? 0ull : (pw & (~0ull << (k + 1)));
+            if (b0 && lane > p) xw0 ^= ph;
+            if (b1 && 64 + lane > p) xw1 ^= ph;
+            if (p != t) {  // exchange positions R + t and R + p (t < 64)
+              const uint64_t xt = rdl64b(xw0, t);
+              const int ot = __builtin_amdgcn_readlane(ow0, t);
+              if (p < 64) {
+                xw0 = wrl64b(xw0, xt, p);
+                ow0 = wrlane(ot, p, ow0);
+              } else {
+                xw1 = wrl64b(xw1, xt, p - 64);
+                ow1 = wrlane(ot, p - 64, ow1);
+              }
+              xw0 = wrl64b(xw0, pw, t);
+              ow0 = wrlane(porg, t, ow0);
+            }
+            if (lane == 0) {
+              sh.pivw[t] = pw;
+              sh.prow[t] = k;
+            }
+            K |= 1ull << k;
+            ++t;
+            ++k;
           }
-        }
-        if (lane == 0) {
-          sh.wc[buf][wv] = ustar >= 0 ? R + NT * ustar + 64 * wv + fl : INT_MAX;
-          sh.ww[buf][wv] = cw;
-          sh.wo[buf][wv] = corg;
-        }
-        if (tid == t) {  // position pos is slot 0 of thread t
-          sh.sw[buf] = x[0];
-          sh.so[buf] = org[0];
+          if (lane == 0) {
+            sh.cmd = need;
+            sh.tcnt = t;
+            sh.kmask = K;
+          }
         }
         __syncthreads();
-        int p = sh.wc[buf][0], wbest = 0;
+        const int cmd = sh.cmd, tt = sh.tcnt;
+        if (xfer >= 0) {  // the row that left the window for beyond position xfer
+          const int j = xfer - R - kWin, jt = j % NT, ju = j / NT;
+          if (tid == jt) {
 #pragma unroll
-        for (int w = 1; w < NW; ++w) {
-          const int c = sh.wc[buf][w];
-          if (c < p) {
-            p = c;
-            wbest = w;
+            for (int u = 0; u < RB; ++u)
+              if (u == ju) {
+                xb[u] = sh.xfer_x;
+                ob[u] = sh.xfer_o;
+              }
           }
+          xfer = -1;
         }
-        if (p == INT_MAX) continue;  // no row has bit k: not a pivot column
-        const uint64_t pw = sh.ww[buf][wbest], sw = sh.sw[buf];
-        const int porg = sh.wo[buf][wbest], sorg = sh.so[buf];
-        // reduce every later row with bit k set in the bits above k (bit k stays
-        // as its multiplier), then exchange positions pos and p
-        const uint64_t hi = (k == 63) ? 0ull : (~0ull << (k + 1));
-        const uint64_t ph = pw & hi;
+        if (cmd < 0) break;
+        // catch the beyond rows up with the pivots found since their last one
+        for (int i = lstart; i < tt; ++i) {
+          const int kk = sh.prow[i];
+          const uint64_t P = (kk == 63) ? 0ull : (sh.pivw[i] & (~0ull << (kk + 1)));
 #pragma unroll
-        for (int u = 0; u < RPT; ++u) {
-          if (u < nsl) {
-            const uint32_t mm = (u > 0 || tid > t) ? mk[u] : 0u;
-            x[u] ^= ph & (((uint64_t)mm << 32) | mm);
-          }
+          for (int u = 0; u < RB; ++u)
+            if (u < nslb) xb[u] ^= P & (0ull - ((xb[u] >> kk) & 1ull));
         }
-        const int up = (p - R) / NT, tp = (p - R) % NT;
-        if (tid == tp) {
+        lstart = tt;
+        // first beyond row with bit cmd, and the bits the beyond rows still have
+        int first = INT_MAX, co = 0;
+        uint64_t cw = 0ull, fo = 0ull;
 #pragma unroll
-          for (int u = 0; u < RPT; ++u)
-            if (u == up) {
-              x[u] = sw;
-              org[u] = sorg;
+        for (int u = 0; u < RB; ++u) {
+          if (u < nslb) {
+            fo |= xb[u];
+            const uint64_t bal = __ballot((xb[u] >> cmd) & 1ull);
+            if (first == INT_MAX && bal) {
+              const int l = (int)__builtin_ctzll(bal);
+              first = R + kWin + NT * u + 64 * wv + l;
+              cw = rdl64b(xb[u], l);
+              co = __builtin_amdgcn_readlane(ob[u], l);
             }
+          }
         }
-        if (tid == t) {
-          x[0] = pw;
-          org[0] = porg;
+        fo = wave_or64(fo);
+        if (lane == 0) {
+          sh.cand[wv] = first;
+          sh.candw[wv] = cw;
+          sh.cando[wv] = co;
+          sh.fb[wv] = fo;
         }
-        if (tid == 0) sh.prow[t] = k;
-        K |= 1ull << k;
-        ++t;
-      }
-      const int r = t;
-
+        __syncthreads();
+        int p = sh.cand[0], wb = 0;
 #pragma unroll
-      for (int u = 0; u < RPT; ++u) {
-        const int pos = R + NT * u + tid;
-        if (u < nsl && pos < n) {
-          sh.map[pos] = org[u];
-          W[(size_t)org[u] * Mw + q] = x[u];
+        for (int w = 1; w < NW; ++w)
+          if (sh.cand[w] < p) {
+            p = sh.cand[w];
+            wb = w;
+          }
+        if (p != INT_MAX) xfer = p;
+        if (wv == 0) {
+          uint64_t fw = wave_or64((lane >= t ? xw0 : 0ull) | xw1);
+#pragma unroll
+          for (int w = 0; w < NW; ++w) fw |= sh.fb[w];
+          F = (cmd == 63) ? 0ull : (fw & (~0ull << (cmd + 1)));
+          k = cmd + 1;
+          if (p != INT_MAX) {  // the candidate enters the window at position t
+            const uint64_t xt = rdl64b(xw0, t);
+            const int ot = __builtin_amdgcn_readlane(ow0, t);
+            if (lane == 0) {
+              sh.xfer_x = xt;
+              sh.xfer_o = ot;
+            }
+            xw0 = wrl64b(xw0, sh.candw[wb], t);
+            ow0 = wrlane(sh.cando[wb], t, ow0);
+            F |= 1ull << cmd;
+            k = cmd;
+          }
         }
       }
-      if (tid < r) sh.pivw[tid] = x[0];
+      const int r = sh.tcnt;
+      K = sh.kmask;
       if (tid == 0) {
         sh.pK[q] = K;
         sh.pR[q] = R;
@@ -242,10 +359,16 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
 #pragma unroll
         for (int i = 0; i < 6; ++i) sh.pmv[q][i] = mv[i];
       }
-      __syncthreads();
-      if (r == 0) continue;
+      if (r == 0) {  // no row has a bit of this word: nothing moved or changed
+        __syncthreads();
+        continue;
+      }
 
-      // ---- T^-1 in bit-position space (wave 0, lane = bit position)
+      // ---- T^-1 (wave 0) and the inverse of I + N (wave 1), in bit-position
+      // space (lane = bit position).  T is the unit lower matrix of the pivot
+      // rows' multipliers; N holds, for each pivot the beyond rows still owe,
+      // its row's bits at the later pivot positions, so a beyond row's
+      // multipliers are its pivot-position bits times (I + N)^-1.
       if (wv == 0) {
         uint64_t trow = 0ull, tv = 0ull;
         const uint64_t below = (1ull << lane) - 1ull;
@@ -255,38 +378,73 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
         }
         uint64_t Kr = K;
         while (Kr) {
-          const int k = (int)__builtin_ctzll(Kr);
+          const int kk = (int)__builtin_ctzll(Kr);
           Kr &= Kr - 1ull;
-          const uint64_t v = rdl64b(tv, k);
-          if ((trow >> k) & 1ull) tv ^= v;
+          const uint64_t v = rdl64b(tv, kk);
+          if ((trow >> kk) & 1ull) tv ^= v;
         }
         sh.tinv[lane] = tv;
+      } else if (wv == 1) {
+        uint64_t nrow = 0ull, nv = 0ull;
+        const uint64_t below = (1ull << lane) - 1ull;
+        if ((K >> lane) & 1ull) {
+          const int i = __popcll(K & below);
+          nv = 1ull << lane;
+          if (i >= lstart) nrow = sh.pivw[i] & K & ~below & ~(1ull << lane);
+        }
+        uint64_t Kp = K;  // pivots lstart .. r-1
+        for (int i = 0; i < lstart; ++i) Kp &= Kp - 1ull;
+        while (Kp) {
+          const int kk = 63 - (int)__builtin_clzll(Kp);
+          Kp &= ~(1ull << kk);
+          const uint64_t v = rdl64b(nv, kk);
+          if ((nrow >> kk) & 1ull) nv ^= v;
+        }
+        sh.tr.fin.ninv[lane] = nv;
       }
       __syncthreads();
       {
         const int g = tid >> 4, v = tid & 15;
-        uint64_t acc = 0ull;
+        uint64_t a0 = 0ull, a1 = 0ull;
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-          if ((v >> b) & 1) acc ^= sh.tinv[4 * g + b];
-        sh.Tt[g][v] = acc;
+          if ((v >> b) & 1) {
+            a0 ^= sh.tinv[4 * g + b];
+            a1 ^= sh.tr.fin.ninv[4 * g + b];
+          }
+        sh.Tt[g][v] = a0;
+        sh.tr.fin.Nt[g][v] = a1;
       }
       __syncthreads();
-#pragma unroll
-      for (int u = 0; u < RPT; ++u) {
-        const int pos = R + NT * u + tid;
-        if (u < nsl && pos < n) {
+      // ---- canonical multipliers c (the trailing update applies c to the
+      // unreduced pivot rows); words, positions written back
+      if (wv == 0) {
+        if (lane < nrest) {
           uint64_t c;
-          if (pos < R + r) {
-            const int k = sh.prow[pos - R];
-            c = sh.tinv[k] & ~(1ull << k);
+          if (lane < r) {
+            const int kk = sh.prow[lane];
+            c = sh.tinv[kk] & ~(1ull << kk);
           } else {
-            const uint64_t xx = x[u] & K;
-            c = 0ull;
-#pragma unroll
-            for (int g = 0; g < 16; ++g) c ^= sh.Tt[g][(xx >> (4 * g)) & 15u];
+            c = apply16(sh.Tt, xw0 & K);
           }
-          sh.cvec[pos - R] = c;
+          sh.cvec[lane] = c;
+          sh.map[R + lane] = ow0;
+          W[(size_t)ow0 * Mw + q] = xw0;
+        }
+        if (64 + lane < nrest) {
+          sh.cvec[64 + lane] = apply16(sh.Tt, xw1 & K);
+          sh.map[R + 64 + lane] = ow1;
+          W[(size_t)ow1 * Mw + q] = xw1;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int pos = R + kWin + NT * u + tid;
+        if (u < nslb && pos < n) {
+          const uint64_t mm = apply16(sh.tr.fin.Nt, xb[u] & K);
+          sh.cvec[pos - R] = apply16(sh.Tt, mm);
+          sh.map[pos] = ob[u];
+          W[(size_t)ob[u] * Mw + q] = mm;
         }
       }
 
@@ -301,7 +459,7 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
             const int s = __popcll(K & ((1ull << k) - 1ull));
             v = W[(size_t)sh.map[R + s] * Mw + c0 + w];
           }
-          sh.U[k][w] = v;
+          sh.tr.up.U[k][w] = v;
         }
         __syncthreads();
         for (int e = tid; e < 16 * 16 * kChunk; e += NT) {
@@ -309,8 +467,8 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
           uint64_t acc = 0ull;
 #pragma unroll
           for (int b = 0; b < 4; ++b)
-            if ((v >> b) & 1) acc ^= sh.U[4 * g + b][w];
-          sh.T[g][v][w] = acc;
+            if ((v >> b) & 1) acc ^= sh.tr.up.U[4 * g + b][w];
+          sh.tr.up.T[g][v][w] = acc;
         }
         __syncthreads();
         const int grp = tid / kChunk, w = tid % kChunk;
@@ -335,7 +493,7 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
             for (int j = 0; j < 4; ++j) {
               uint64_t acc = 0ull;
 #pragma unroll
-              for (int g = 0; g < 16; ++g) acc ^= sh.T[g][(cc[j] >> (4 * g)) & 15u][w];
+              for (int g = 0; g < 16; ++g) acc ^= sh.tr.up.T[g][(cc[j] >> (4 * g)) & 15u][w];
               if (i0 + j * G < n) W[off[j]] = old[j] ^ acc;
             }
           }

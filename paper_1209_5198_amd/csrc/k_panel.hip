@@ -32,16 +32,7 @@
 
 #include "gf2_internal.h"
 
-// v_writelane_b32 (lane `lane` of `old` receives the uniform value `val`): an
-// LLVM intrinsic that clang does not expose as a builtin.
-extern "C" __device__ int gf2_llvm_writelane(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
-
 namespace gf2 {
-
-__device__ inline uint32_t wrlane(uint32_t val, int lane, uint32_t old) {
-  return (uint32_t)gf2_llvm_writelane((int)val, lane, (int)old);
-}
-__device__ inline int wrlane(int val, int lane, int old) { return gf2_llvm_writelane(val, lane, old); }
 
 __device__ inline uint64_t rdl64(uint64_t v, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);

@@ -164,6 +164,20 @@ def edge_inputs(orc):
     add(np.zeros((100, 2)), 100, 100)
     add(synth.dense(3, 7, 63, 65), 63, 65)
     add(synth.dense(3, 8, 129, 64), 129, 64)
+    # rows whose ones lie below the first 128 candidates of every pivot search:
+    # the top 400 rows zero, then dense rows
+    top0 = synth.dense(3, 10, 700, 150)
+    top0[:400] = 0
+    add(top0, 700, 150)
+    # one dense row in every 130, the rest zero (at most one candidate near the top)
+    sparse_rows = synth.dense(3, 11, 2048, 130)
+    sparse_rows[np.arange(2048) % 130 != 129] = 0
+    add(sparse_rows, 2048, 130)
+    # sparse columns, so that the top rows often lack a pivot bit
+    add(synth.bernoulli(3, 12, 1500, 300, 0.003), 1500, 300)
+    # the top 100 rows repeated below: after they are used, their copies reduce to zero
+    rep = synth.dense(3, 13, 100, 200)
+    add(np.concatenate([rep, rep, synth.dense(3, 14, 300, 200)]), 500, 200)
     shapes = [(n, m) for _, n, m in cases]
     mats = [A for A, _, _ in cases]
     omats = list(mats)
