@@ -45,6 +45,14 @@ __device__ inline uint64_t rdl64b(uint64_t v, int l) {
   const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
   return ((uint64_t)hi << 32) | lo;
 }
+// Values every lane of a wave holds alike (LDS words read at one address), made
+// scalar so that the compiler keeps the loops they control uniform.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline uint64_t uni64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
 __device__ inline uint64_t wrl64b(uint64_t old, uint64_t v, int l) {
   const uint32_t lo = wrlane((uint32_t)v, l, (uint32_t)old);
   const uint32_t hi = wrlane((uint32_t)(v >> 32), l, (uint32_t)(old >> 32));
@@ -141,7 +149,7 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
     __syncthreads();  // the previous matrix is finished with the shared state
     if (tid == 0) sh.job = (int)atomicAdd(a.counter, 1u);
     __syncthreads();
-    const int job = sh.job;
+    const int job = uni(sh.job);
     if (job >= a.count) return;
     const BatchDesc d = a.d[job];
     const int n = d.n, m = d.m, Mw = (m + 63) >> 6, kmin = n < m ? n : m;
@@ -199,7 +207,7 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
       __syncthreads();
       uint64_t F = 0ull;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) F |= sh.fb[w];
+      for (int w = 0; w < NW; ++w) F |= uni64(sh.fb[w]);
 
       // ---- pivot search over the bits of word q.  Wave 0 decides from the
       // window alone while it holds a candidate for the current bit; the beyond
@@ -207,62 +215,69 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
       // only when the window has none (then the whole workgroup takes part).
       int t = 0, k = 0, lstart = 0, xfer = -1;
       uint64_t K = 0ull;
+      // pivot log of wave 0, lane i = pivot i: its word as found, bit, row
+      uint64_t lgw = 0ull;
+      int lgk = 0, lgo = 0;
+      const int tmax = nrest < 64 ? nrest : 64;
+      const uint64_t wbits = nbits == 64 ? ~0ull : ((1ull << nbits) - 1ull);
       for (;;) {
         if (wv == 0) {
           int need = -1;
-          while (k < nbits && R + t < n) {
-            if (!((F >> k) & 1ull)) {
-              ++k;
-              continue;
-            }
-            const uint32_t b0 = (uint32_t)(xw0 >> k) & 1u, b1 = (uint32_t)(xw1 >> k) & 1u;
-            const uint64_t bal0 = __ballot(b0 && lane >= t);
-            const uint64_t bal1 = __ballot(b1);
-            if (!(bal0 | bal1)) {
-              if (nslb > 0) {
-                need = k;
-                break;
+          // bits still to examine, in increasing order
+          uint64_t Fr = F & wbits & (k >= 64 ? 0ull : (~0ull << k));
+          while (Fr && t < tmax) {
+            t = uni(t);
+            k = (int)__builtin_ctzll(Fr);
+            Fr &= Fr - 1ull;
+            const uint64_t kb = 1ull << k;
+            bool c0 = (xw0 & kb) != 0ull, c1 = (xw1 & kb) != 0ull;
+            const uint64_t bal0 = __ballot(c0) & (~0ull << t);  // positions t.. of slot 0
+            int p = (int)__builtin_ctzll(bal0);
+            if (__builtin_expect(bal0 == 0ull, 0)) {
+              const uint64_t bal1 = __ballot(c1);
+              if (!bal1) {
+                if (nslb > 0) {
+                  need = k;
+                  break;
+                }
+                continue;  // the window is every remaining row: not a pivot column
               }
-              ++k;  // the window is every remaining row: not a pivot column
-              continue;
+              // the first candidate is in slot 1: exchange it with position t
+              const int p1 = (int)__builtin_ctzll(bal1);
+              const uint64_t xp = rdl64b(xw1, p1), xt = rdl64b(xw0, t);
+              const int op = __builtin_amdgcn_readlane(ow1, p1), ot = __builtin_amdgcn_readlane(ow0, t);
+              xw1 = wrl64b(xw1, xt, p1);
+              ow1 = wrlane(ot, p1, ow1);
+              xw0 = wrl64b(xw0, xp, t);
+              ow0 = wrlane(op, t, ow0);
+              c0 = (xw0 & kb) != 0ull;
+              c1 = (xw1 & kb) != 0ull;
+              p = t;
             }
-            int p;
-            uint64_t pw;
-            int porg;
-            if (bal0) {
-              p = (int)__builtin_ctzll(bal0);
-              pw = rdl64b(xw0, p);
-              porg = __builtin_amdgcn_readlane(ow0, p);
-            } else {
-              p = 64 + (int)__builtin_ctzll(bal1);
-              pw = rdl64b(xw1, p - 64);
-              porg = __builtin_amdgcn_readlane(ow1, p - 64);
-            }
-            // every later row with bit k is reduced in the bits above k (rows
-            // between t and p have no bit k; the pivot row itself is kept)
-            const uint64_t ph = (k == 63) ? 0ull : (pw & (~0ull << (k + 1)));
-            if (b0 && lane > p) xw0 ^= ph;
-            if (b1 && 64 + lane > p) xw1 ^= ph;
-            if (p != t) {  // exchange positions R + t and R + p (t < 64)
-              const uint64_t xt = rdl64b(xw0, t);
-              const int ot = __builtin_amdgcn_readlane(ow0, t);
-              if (p < 64) {
-                xw0 = wrl64b(xw0, xt, p);
-                ow0 = wrlane(ot, p, ow0);
-              } else {
-                xw1 = wrl64b(xw1, xt, p - 64);
-                ow1 = wrlane(ot, p - 64, ow1);
-              }
-              xw0 = wrl64b(xw0, pw, t);
-              ow0 = wrlane(porg, t, ow0);
-            }
-            if (lane == 0) {
-              sh.pivw[t] = pw;
-              sh.prow[t] = k;
-            }
-            K |= 1ull << k;
+            p = uni(p);
+            const uint64_t pw = rdl64b(xw0, p);
+            const int porg = __builtin_amdgcn_readlane(ow0, p);
+            // every row with bit k is reduced in the bits above k.  Lanes
+            // before t are finished positions (their rows are in the log) and
+            // lane p is the pivot, overwritten below or finished itself.
+            const uint64_t ph = pw & ~((kb << 1) - 1ull);  // zero for k = 63
+            if (c0) xw0 ^= ph;
+            if (c1) xw1 ^= ph;
+            // the row at position t moves to position p (nothing moves if p = t)
+            const uint64_t xt = rdl64b(xw0, t);
+            const int ot = __builtin_amdgcn_readlane(ow0, t);
+            xw0 = wrl64b(xw0, xt, p);
+            ow0 = wrlane(ot, p, ow0);
+            lgw = wrl64b(lgw, pw, t);
+            lgk = wrlane(k, t, lgk);
+            lgo = wrlane(porg, t, lgo);
+            K |= kb;
             ++t;
-            ++k;
+          }
+          k = need >= 0 ? need : 64;
+          if (lane < t) {
+            sh.pivw[lane] = lgw;
+            sh.prow[lane] = lgk;
           }
           if (lane == 0) {
             sh.cmd = need;
@@ -271,7 +286,7 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
           }
         }
         __syncthreads();
-        const int cmd = sh.cmd, tt = sh.tcnt;
+        const int cmd = uni(sh.cmd), tt = uni(sh.tcnt);
         if (xfer >= 0) {  // the row that left the window for beyond position xfer
           const int j = xfer - R - kWin, jt = j % NT, ju = j / NT;
           if (tid == jt) {
@@ -287,8 +302,8 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
         if (cmd < 0) break;
         // catch the beyond rows up with the pivots found since their last one
         for (int i = lstart; i < tt; ++i) {
-          const int kk = sh.prow[i];
-          const uint64_t P = (kk == 63) ? 0ull : (sh.pivw[i] & (~0ull << (kk + 1)));
+          const int kk = uni(sh.prow[i]);
+          const uint64_t P = (kk == 63) ? 0ull : (uni64(sh.pivw[i]) & (~0ull << (kk + 1)));
 #pragma unroll
           for (int u = 0; u < RB; ++u)
             if (u < nslb) xb[u] ^= P & (0ull - ((xb[u] >> kk) & 1ull));
@@ -318,18 +333,20 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
           sh.fb[wv] = fo;
         }
         __syncthreads();
-        int p = sh.cand[0], wb = 0;
+        int p = uni(sh.cand[0]), wb = 0;
 #pragma unroll
-        for (int w = 1; w < NW; ++w)
-          if (sh.cand[w] < p) {
-            p = sh.cand[w];
+        for (int w = 1; w < NW; ++w) {
+          const int c = uni(sh.cand[w]);
+          if (c < p) {
+            p = c;
             wb = w;
           }
+        }
         if (p != INT_MAX) xfer = p;
         if (wv == 0) {
-          uint64_t fw = wave_or64((lane >= t ? xw0 : 0ull) | xw1);
+          uint64_t fw = uni64(wave_or64((lane >= t ? xw0 : 0ull) | xw1));
 #pragma unroll
-          for (int w = 0; w < NW; ++w) fw |= sh.fb[w];
+          for (int w = 0; w < NW; ++w) fw |= uni64(sh.fb[w]);
           F = (cmd == 63) ? 0ull : (fw & (~0ull << (cmd + 1)));
           k = cmd + 1;
           if (p != INT_MAX) {  // the candidate enters the window at position t
@@ -339,15 +356,15 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
               sh.xfer_x = xt;
               sh.xfer_o = ot;
             }
-            xw0 = wrl64b(xw0, sh.candw[wb], t);
-            ow0 = wrlane(sh.cando[wb], t, ow0);
+            xw0 = wrl64b(xw0, uni64(sh.candw[wb]), t);
+            ow0 = wrlane(uni(sh.cando[wb]), t, ow0);
             F |= 1ull << cmd;
             k = cmd;
           }
         }
       }
-      const int r = sh.tcnt;
-      K = sh.kmask;
+      const int r = uni(sh.tcnt);
+      K = uni64(sh.kmask);
       if (tid == 0) {
         sh.pK[q] = K;
         sh.pR[q] = R;
@@ -420,16 +437,18 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
       // unreduced pivot rows); words, positions written back
       if (wv == 0) {
         if (lane < nrest) {
-          uint64_t c;
-          if (lane < r) {
-            const int kk = sh.prow[lane];
-            c = sh.tinv[kk] & ~(1ull << kk);
+          uint64_t c, xo = xw0;
+          int oo = ow0;
+          if (lane < r) {  // pivot lane: its row as found, from the log
+            c = sh.tinv[lgk] & ~(1ull << lgk);
+            xo = lgw;
+            oo = lgo;
           } else {
             c = apply16(sh.Tt, xw0 & K);
           }
           sh.cvec[lane] = c;
-          sh.map[R + lane] = ow0;
-          W[(size_t)ow0 * Mw + q] = xw0;
+          sh.map[R + lane] = oo;
+          W[(size_t)oo * Mw + q] = xo;
         }
         if (64 + lane < nrest) {
           sh.cvec[64 + lane] = apply16(sh.Tt, xw1 & K);
