@@ -917,6 +917,10 @@ int stage_descs(const std::vector<BatchDesc> &v, BatchDesc *dev, hipStream_t s) 
   return GF2_OK;
 }
 
+// Words of one batched worker slot for an n x m item: the working copy with
+// rows padded to 64-byte segments.
+int64_t batch_slot_words(int64_t n, int64_t m) { return n * ((ceil_div(m, 64) + 7) / 8 * 8); }
+
 // Validate the items and order them by decreasing work (n * m * min(n, m)),
 // so that a persistent launch starts the largest matrices first.
 int batch_descs(const gf2_batch_item *items, int64_t count, bool solve, std::vector<BatchDesc> &out,
@@ -934,7 +938,7 @@ int batch_descs(const gf2_batch_item *items, int64_t count, bool solve, std::vec
       return fail(GF2_EINVAL, "batch item " + std::to_string(i) + ": negative offset");
     const double n = (double)it.rows, m = (double)it.cols;
     key[(size_t)i] = std::make_pair(n * m * (n < m ? n : m) + n + m, (int32_t)i);
-    mw = std::max(mw, it.rows * ceil_div(it.cols, 64));
+    mw = std::max(mw, batch_slot_words(it.rows, it.cols));
   }
   std::stable_sort(key.begin(), key.end(),
                    [](const std::pair<double, int32_t> &x, const std::pair<double, int32_t> &y) {
@@ -1420,7 +1424,7 @@ size_t gf2_workspace_bytes(int op, int64_t rows, int64_t cols, int64_t k) {
       if (cols > GF2_BATCH_MAX_DIM || k > GF2_BATCH_MAX_DIM) break;
       int workers = 1;
       if (batch_workers_for(rows, &workers)) return SIZE_MAX;
-      return batch_dec_need(rows, k * ceil_div(cols, 64), workers);
+      return batch_dec_need(rows, batch_slot_words(k, cols), workers);
     }
     case GF2_OP_SOLVE_BATCHED:
       return rows > 0 ? align256((size_t)rows * sizeof(BatchDesc)) : 0;

@@ -38,7 +38,9 @@ constexpr int NT = kBatchThreads;          // threads per workgroup
 constexpr int NW = NT / 64;                // waves per workgroup
 constexpr int kWin = 128;                  // window rows of the pivot search, two per lane of wave 0
 constexpr int RB = (kBatchMaxDim - kWin + NT - 1) / NT;  // rows beyond the window per thread
-constexpr int kChunk = 8;                  // later words per table build
+constexpr int kChunk = 8;                  // later words per table build (one 64-byte segment)
+constexpr int kRU = 2;                     // rows per thread in each stage of the row update
+constexpr int kCp = 8;                     // rows per thread in flight in the working copy
 
 __device__ inline uint64_t rdl64b(uint64_t v, int l) {
   const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
@@ -111,8 +113,8 @@ struct BatchShared {
   union {
     struct {
       uint64_t T[16][16][kChunk];     // 4-bit tables of the current chunk
-      uint64_t U[64][kChunk];         // pivot rows' chunk words, by pivot bit position
     } up;
+    uint64_t rowq[NT / 8][kBatchMaxPanels];  // outputs: panel words of the rows in flight
     struct {
       uint64_t ninv[64];              // row k of (I + N)^-1 (bit-position space)
       uint64_t Nt[16][16];            // its 4-bit tables
@@ -139,7 +141,7 @@ struct BatchShared {
   int32_t job;
 };
 
-__global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
+__global__ __launch_bounds__(NT, kBatchWGPerCU) void k_batch_dec(BatchArgs a) {
   __shared__ BatchShared sh;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -154,19 +156,39 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
     const BatchDesc d = a.d[job];
     const int n = d.n, m = d.m, Mw = (m + 63) >> 6, kmin = n < m ? n : m;
 
-    // ---- working copy (padding bits cleared) and identity map
+    // ---- working copy (row stride ld words, a multiple of one 64-byte
+    // segment, so that a chunk of kChunk words is one aligned segment; padding
+    // bits cleared) and identity map.  A row is read by the next power of two
+    // lanes at or above Mw; each thread moves kCp rows at a time.
+    const int ld = (Mw + kChunk - 1) & ~(kChunk - 1);
     {
       const uint64_t *A = a.A + d.a;
-      const int nwords = n * Mw;
-      for (int e = tid; e < nwords; e += NT) W[e] = A[e] & pad_mask(m, e % Mw);
+      const int lsh = Mw <= 1 ? 0 : 32 - __builtin_clz(Mw - 1);
+      const int rows_it = NT >> lsh, w = tid & ((1 << lsh) - 1);
+      const uint64_t pm = pad_mask(m, w);
+      for (int i0 = tid >> lsh; i0 < n; i0 += kCp * rows_it) {
+        uint64_t v[kCp];
+#pragma unroll
+        for (int j = 0; j < kCp; ++j) {
+          const int i = i0 + j * rows_it;
+          v[j] = (i < n && w < Mw) ? A[(size_t)i * Mw + w] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < kCp; ++j) {
+          const int i = i0 + j * rows_it;
+          if (i < n && w < Mw) W[(uint32_t)(i * ld + w)] = v[j] & pm;
+        }
+      }
       for (int i = tid; i < n; i += NT) sh.map[i] = i;
     }
     __syncthreads();
+    auto rd = [&](int row, int w) -> uint64_t { return W[(uint32_t)(row * ld + w)]; };
 
     int R = 0, nq = 0;
     for (int q = 0; q < Mw && R < n; ++q) {
       nq = q + 1;
       const int nbits = (m - 64 * q) < 64 ? (m - 64 * q) : 64;
+
       const int nrest = n - R;  // rows at or below the next free position
       // Positions R .. R + kWin - 1 form the window: position R + 64 * s + l is
       // slot s of lane l of wave 0.  Position R + kWin + NT * u + tid is slot u
@@ -178,11 +200,11 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
       if (wv == 0) {
         if (lane < nrest) {
           ow0 = sh.map[R + lane];
-          xw0 = W[(size_t)ow0 * Mw + q];
+          xw0 = rd(ow0, q);
         }
         if (64 + lane < nrest) {
           ow1 = sh.map[R + 64 + lane];
-          xw1 = W[(size_t)ow1 * Mw + q];
+          xw1 = rd(ow1, q);
         }
         f = xw0 | xw1;
       }
@@ -195,7 +217,7 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
         const int pos = R + kWin + NT * u + tid;
         if (u < nslb && pos < n) {
           ob[u] = sh.map[pos];
-          xb[u] = W[(size_t)ob[u] * Mw + q];
+          xb[u] = rd(ob[u], q);
         }
         f |= xb[u];
       }
@@ -435,6 +457,7 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
       __syncthreads();
       // ---- canonical multipliers c (the trailing update applies c to the
       // unreduced pivot rows); words, positions written back
+      auto put_q = [&](int row, uint64_t v) { W[(size_t)row * ld + q] = v; };
       if (wv == 0) {
         if (lane < nrest) {
           uint64_t c, xo = xw0;
@@ -448,12 +471,12 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
           }
           sh.cvec[lane] = c;
           sh.map[R + lane] = oo;
-          W[(size_t)oo * Mw + q] = xo;
+          put_q(oo, xo);
         }
         if (64 + lane < nrest) {
           sh.cvec[64 + lane] = apply16(sh.Tt, xw1 & K);
           sh.map[R + 64 + lane] = ow1;
-          W[(size_t)ow1 * Mw + q] = xw1;
+          put_q(ow1, xw1);
         }
       }
 #pragma unroll
@@ -463,57 +486,89 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
           const uint64_t mm = apply16(sh.tr.fin.Nt, xb[u] & K);
           sh.cvec[pos - R] = apply16(sh.Tt, mm);
           sh.map[pos] = ob[u];
-          W[(size_t)ob[u] * Mw + q] = mm;
+          put_q(ob[u], mm);
         }
       }
 
-      // ---- trailing update, chunks of kChunk later words
-      for (int c0 = q + 1; c0 < Mw; c0 += kChunk) {
-        const int nw = (Mw - c0) < kChunk ? (Mw - c0) : kChunk;
-        __syncthreads();  // multipliers written; the previous chunk's tables are no longer read
-        for (int e = tid; e < 64 * kChunk; e += NT) {
-          const int k = e / kChunk, w = e % kChunk;
-          uint64_t v = 0ull;
-          if (((K >> k) & 1ull) && w < nw) {
-            const int s = __popcll(K & ((1ull << k) - 1ull));
-            v = W[(size_t)sh.map[R + s] * Mw + c0 + w];
-          }
-          sh.tr.up.U[k][w] = v;
-        }
-        __syncthreads();
-        for (int e = tid; e < 16 * 16 * kChunk; e += NT) {
-          const int g = e / (16 * kChunk), v = (e / kChunk) & 15, w = e % kChunk;
-          uint64_t acc = 0ull;
+      // ---- trailing update (eq. (Aj)) over 64-byte aligned chunks of kChunk
+      // words.  Thread (g, w, h) builds entries v = 8h .. 8h+7 of table g for
+      // chunk word w from the four pivot rows of bit positions 4g .. 4g+3,
+      // whose words it loads one chunk ahead; the row update keeps two stages
+      // of kRU rows per thread in flight.
+      {
+        const int tg = tid >> 4, tw = (tid >> 1) & 7, th = tid & 1;
+        const int c_first = (q + 1) & ~(kChunk - 1);
+        __syncthreads();  // positions, multipliers and panel words written above
+        // offsets of the pivot rows of bit positions 4 tg .. 4 tg + 3 (-1: no pivot)
+        int urow[4];
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
-            if ((v >> b) & 1) acc ^= sh.tr.up.U[4 * g + b][w];
-          sh.tr.up.T[g][v][w] = acc;
+        for (int b = 0; b < 4; ++b) {
+          const int kp = 4 * tg + b;
+          urow[b] = ((K >> kp) & 1ull) ? sh.map[R + __popcll(K & ((1ull << kp) - 1ull))] : -1;
         }
-        __syncthreads();
-        const int grp = tid / kChunk, w = tid % kChunk;
+        auto load_u = [&](int c0, uint64_t (&u)[4]) {
+          const int cw = c0 + tw;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) u[b] = (urow[b] >= 0 && cw > q && cw < Mw) ? rd(urow[b], cw) : 0ull;
+        };
+        uint64_t u[4];
+        if (c_first < Mw) load_u(c_first, u);
+        const int grp = tid >> 3, w = tid & 7;
         constexpr int G = NT / kChunk;  // row groups
-        if (w < nw) {
-          for (int i0 = R + grp; i0 < n; i0 += 4 * G) {
-            size_t off[4];
-            uint64_t old[4], cc[4];
+        const int nst = (n - R + G * kRU - 1) / (G * kRU);
+        for (int c0 = c_first; c0 < Mw; c0 += kChunk) {
+          if (c0 != c_first) __syncthreads();  // the previous chunk's tables are no longer read
+          {
+            const uint64_t base = th ? u[3] : 0ull;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int i = i0 + j * G;
-              off[j] = 0;
-              old[j] = 0ull;
-              cc[j] = 0ull;
-              if (i < n) {
-                off[j] = (size_t)sh.map[i] * Mw + c0 + w;
-                old[j] = W[off[j]];
-                cc[j] = sh.cvec[i - R];
+            for (int j = 0; j < 8; ++j)
+              sh.tr.up.T[tg][8 * th + j][tw] =
+                  base ^ ((j & 1) ? u[0] : 0ull) ^ ((j & 2) ? u[1] : 0ull) ^ ((j & 4) ? u[2] : 0ull);
+          }
+          __syncthreads();
+          if (c0 + kChunk < Mw) load_u(c0 + kChunk, u);
+          const int cw = c0 + w;
+          if (cw > q && cw < Mw) {
+            int rowA[kRU], rowB[kRU];
+            uint64_t oldA[kRU], oldB[kRU];
+            auto load_stage = [&](int st, int (&rw)[kRU], uint64_t (&old)[kRU]) {
+#pragma unroll
+              for (int j = 0; j < kRU; ++j) {
+                const int i = R + grp + G * (kRU * st + j);
+                rw[j] = 0;
+                old[j] = 0ull;
+                if (i < n) {
+                  rw[j] = sh.map[i];
+                  old[j] = rd(rw[j], cw);
+                }
               }
-            }
+            };
+            auto update_stage = [&](int st, const int (&rw)[kRU], const uint64_t (&old)[kRU]) {
+              uint64_t acc[kRU], cc[kRU];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              uint64_t acc = 0ull;
+              for (int j = 0; j < kRU; ++j) {
+                const int i = R + grp + G * (kRU * st + j);
+                cc[j] = i < n ? sh.cvec[i - R] : 0ull;
+                acc[j] = old[j];
+              }
+#pragma unroll 4
+              for (int g = 0; g < 16; ++g)
 #pragma unroll
-              for (int g = 0; g < 16; ++g) acc ^= sh.tr.up.T[g][(cc[j] >> (4 * g)) & 15u][w];
-              if (i0 + j * G < n) W[off[j]] = old[j] ^ acc;
+                for (int j = 0; j < kRU; ++j) acc[j] ^= sh.tr.up.T[g][(cc[j] >> (4 * g)) & 15u][w];
+#pragma unroll
+              for (int j = 0; j < kRU; ++j) {
+                const int i = R + grp + G * (kRU * st + j);
+                if (i < n) W[(size_t)rw[j] * ld + cw] = acc[j];
+              }
+            };
+            load_stage(0, rowA, oldA);
+            for (int st = 0; st < nst; st += 2) {
+              if (st + 1 < nst) load_stage(st + 1, rowB, oldB);
+              update_stage(st, rowA, oldA);
+              if (st + 1 < nst) {
+                if (st + 2 < nst) load_stage(st + 2, rowA, oldA);
+                update_stage(st + 1, rowB, oldB);
+              }
             }
           }
         }
@@ -539,54 +594,84 @@ __global__ __launch_bounds__(NT) void k_batch_dec(BatchArgs a) {
       for (int t = tid; t < kmin; t += NT) a.pivcols[d.c + t] = t < rank ? pcol[t] : -1;
     if (a.perm)
       for (int i = tid; i < n; i += NT) a.perm[d.p + i] = sh.map[i];
-    // 8 lanes per output row, lane w8 writing words w8, w8 + 8, ...
-    const int w8 = tid & 7;
-    if (a.E) {
-      uint64_t *E = a.E + d.e;
-      for (int t = tid >> 3; t < kmin; t += NT / 8) {
-        const int pc = t < rank ? pcol[t] : 0, qt = pc >> 6;
-        const size_t src = (size_t)sh.map[t] * Mw;
-        for (int w = w8; w < Mw; w += 8) {
-          uint64_t v = 0ull;
-          if (t < rank && w >= qt) {
-            v = W[src + w];
-            if (w == qt) v &= ~0ull << (pc & 63);
-          }
-          E[(size_t)t * Mw + w] = v;
-        }
-      }
+    // One pass over the positions, 8 lanes per row (lane w8 holds words w8,
+    // w8 + 8, ...): each row's words are read once (the next rows' while the
+    // current ones are written); position t < kmin writes its E row, and the
+    // row's panel words are staged in LDS so that each lane forms its L words.
+    const int w8 = tid & 7, rg = tid >> 3;
+    constexpr int kOW = kBatchMaxPanels / 8;  // words per lane
+    const int Lw = (kmin + 63) >> 6;
+    if (a.L && tid < Lw) {  // first panel whose pivot range reaches past column 64 * lw
+      int j = 0;
+      while (j < nq && sh.pR[j] + sh.pr[j] <= 64 * tid) ++j;
+      sh.lj0[tid] = j;
     }
-    if (a.L) {
-      uint64_t *L = a.L + d.l;
-      const int Lw = (kmin + 63) >> 6;
-      // first panel whose pivot range reaches past column 64 * lw
-      if (tid < Lw) {
-        int j = 0;
-        while (j < nq && sh.pR[j] + sh.pr[j] <= 64 * tid) ++j;
-        sh.lj0[tid] = j;
-      }
-      __syncthreads();
-      for (int i = tid >> 3; i < n; i += NT / 8) {
-        const size_t src = (size_t)sh.map[i] * Mw;
-        for (int lw = w8; lw < Lw; lw += 8) {
-          const int c_lo = 64 * lw;
-          uint64_t v = 0ull;
-          for (int j = sh.lj0[lw]; j < nq && sh.pR[j] < c_lo + 64; ++j) {
-            const int Rj = sh.pR[j], rj = sh.pr[j];
-            if (rj == 0 || i < Rj) continue;
-            const uint64_t xw = W[src + j];
-            uint64_t bits;
-            if (i < Rj + rj) {
-              const int s = i - Rj, kk = pcol[i] & 63;
-              bits = compress(xw & ((1ull << kk) - 1ull), sh.pK[j], sh.pmv[j]) | (1ull << s);
-            } else {
-              bits = compress(xw, sh.pK[j], sh.pmv[j]);
-            }
-            const int shf = Rj - c_lo;
-            v |= shf >= 0 ? (bits << shf) : (bits >> (-shf));
-          }
-          L[(size_t)i * Lw + lw] = v;
+    __syncthreads();
+    if (a.E || a.L) {
+      uint64_t *E = a.E ? a.E + d.e : nullptr;
+      uint64_t *L = a.L ? a.L + d.l : nullptr;
+      auto load_row = [&](int i, uint64_t (&x)[kOW]) {
+        const size_t src = i < n ? (size_t)sh.map[i] * ld : 0;
+#pragma unroll
+        for (int jj = 0; jj < kOW; ++jj) {
+          const int w = w8 + 8 * jj;
+          x[jj] = (i < n && w < Mw) ? W[src + w] : 0ull;
         }
+      };
+      uint64_t x[kOW], xn[kOW];
+      load_row(rg, x);
+      for (int i0 = 0; i0 < n; i0 += NT / 8) {
+        const int i = i0 + rg;
+        load_row(i + NT / 8, xn);
+        if (E && i < kmin) {
+          const int pc = i < rank ? pcol[i] : 0, qt = pc >> 6;
+#pragma unroll
+          for (int jj = 0; jj < kOW; ++jj) {
+            const int w = w8 + 8 * jj;
+            if (w < Mw) {
+              uint64_t v = (i < rank && w >= qt) ? x[jj] : 0ull;
+              if (w == qt) v &= ~0ull << (pc & 63);
+              if (w == Mw - 1) v &= pad_mask(m, w);
+              E[(size_t)i * Mw + w] = v;
+            }
+          }
+        }
+        if (L) {
+#pragma unroll
+          for (int jj = 0; jj < kOW; ++jj) {
+            const int w = w8 + 8 * jj;
+            if (w < nq) sh.tr.rowq[rg][w] = x[jj];
+          }
+          __syncthreads();
+          if (i < n) {
+#pragma unroll
+            for (int jj = 0; jj < kOW; ++jj) {
+              const int lw = w8 + 8 * jj;
+              if (lw < Lw) {
+                const int c_lo = 64 * lw;
+                uint64_t v = 0ull;
+                for (int j = sh.lj0[lw]; j < nq && sh.pR[j] < c_lo + 64; ++j) {
+                  const int Rj = sh.pR[j], rj = sh.pr[j];
+                  if (rj == 0 || i < Rj) continue;
+                  const uint64_t xw = sh.tr.rowq[rg][j];
+                  uint64_t bits;
+                  if (i < Rj + rj) {
+                    const int s = i - Rj, kk = pcol[i] & 63;
+                    bits = compress(xw & ((1ull << kk) - 1ull), sh.pK[j], sh.pmv[j]) | (1ull << s);
+                  } else {
+                    bits = compress(xw, sh.pK[j], sh.pmv[j]);
+                  }
+                  const int shf = Rj - c_lo;
+                  v |= shf >= 0 ? (bits << shf) : (bits >> (-shf));
+                }
+                L[(size_t)i * Lw + lw] = v;
+              }
+            }
+          }
+          __syncthreads();
+        }
+#pragma unroll
+        for (int jj = 0; jj < kOW; ++jj) x[jj] = xn[jj];
       }
     }
   }

@@ -181,6 +181,13 @@ def edge_inputs(orc):
     shapes = [(n, m) for _, n, m in cases]
     mats = [A for A, _, _ in cases]
     omats = list(mats)
+    # padding bits set in the input: ignored (the oracle gets the clean matrix)
+    clean = synth.dense(3, 15, 300, 130)
+    dirty = clean.copy()
+    dirty[:, 2] |= ~synth.pad_mask(130)
+    shapes.append((300, 130))
+    mats.append(dirty)
+    omats.append(clean)
     # planted rank 37: the GPU forms X*Y with gf2_matmul, the oracle with its product
     n, m, r = 1500, 1700, 37
     X, Y = synth.planted(3, 9, n, m, r, 0.5)
