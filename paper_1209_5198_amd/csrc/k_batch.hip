@@ -112,7 +112,7 @@ struct BatchShared {
   uint64_t cvec[kBatchMaxDim];        // canonical multipliers of positions R.. (then pivot columns)
   union {
     struct {
-      uint64_t T[16][16][kChunk];     // 4-bit tables of the current chunk
+      uint64_t T[16][16][kChunk + 1]; // 4-bit tables of the current chunk (rows padded: fewer bank conflicts)
     } up;
     uint64_t rowq[NT / 8][kBatchMaxPanels];  // outputs: panel words of the rows in flight
     struct {
@@ -689,6 +689,7 @@ __global__ void k_batch_reset(uint32_t *counter) {
 // triangular recurrences run on lane-indexed registers; across blocks they are
 // parities of staged rows against the finished part.
 constexpr int kSolveNT = 64;
+constexpr int kSolveU = 8;  // words (or row groups) whose loads one lane issues together
 
 __global__ __launch_bounds__(kSolveNT) void k_batch_solve(BatchSolveArgs a) {
   __shared__ uint64_t pb[kBatchMaxDim / 64], y[kBatchMaxDim / 64], xs[kBatchMaxDim / 64];
@@ -708,16 +709,26 @@ __global__ __launch_bounds__(kSolveNT) void k_batch_solve(BatchSolveArgs a) {
     pb[lane] = 0ull;
   }
   __syncthreads();
-  for (int c = 0; c < nbw; ++c) {
-    const int i = 64 * c + lane;
-    uint32_t bit = 0u;
-    if (i < n) {
-      int64_t pi = perm[i];
-      pi = pi < 0 ? 0 : (pi >= n ? n - 1 : pi);
-      bit = (uint32_t)((B[pi >> 6] >> (pi & 63)) & 1ull);
+  // (P b): bit i is bit perm[i] of b; eight 64-row groups per round, their
+  // loads issued together
+  for (int c0 = 0; c0 < nbw; c0 += kSolveU) {
+    int64_t pi[kSolveU];
+#pragma unroll
+    for (int j = 0; j < kSolveU; ++j) {
+      const int i = 64 * (c0 + j) + lane;
+      pi[j] = i < n ? perm[i] : 0;
     }
-    const uint64_t wbits = __ballot(bit);
-    if (lane == 0) pb[c] = wbits;
+    uint64_t bw[kSolveU];
+#pragma unroll
+    for (int j = 0; j < kSolveU; ++j) {
+      pi[j] = pi[j] < 0 ? 0 : (pi[j] >= n ? n - 1 : pi[j]);
+      bw[j] = (64 * (c0 + j) + lane < n) ? B[pi[j] >> 6] : 0ull;
+    }
+#pragma unroll
+    for (int j = 0; j < kSolveU; ++j) {
+      const uint64_t wbits = __ballot((bw[j] >> (pi[j] & 63)) & 1ull);
+      if (lane == 0 && c0 + j < nbw) pb[c0 + j] = wbits;
+    }
   }
   __syncthreads();
 
@@ -725,14 +736,21 @@ __global__ __launch_bounds__(kSolveNT) void k_batch_solve(BatchSolveArgs a) {
   const int nblk = (r + 63) >> 6;
   for (int b = 0; b < nblk; ++b) {
     const int t0 = 64 * b, nb = (r - t0) < 64 ? (r - t0) : 64;
-    for (int e = lane; e < 64 * (b + 1); e += kSolveNT) {
-      const int row = e / (b + 1), w = e - row * (b + 1);
-      blk[row][w] = row < nb ? L[(size_t)(t0 + row) * Lw + w] : 0ull;
-    }
-    __syncthreads();
+    // lane = row t0 + lane: the parity of its words before b with y, and its
+    // diagonal word b, read kSolveU words at a time
     uint32_t acc = (uint32_t)((pb[b] >> lane) & 1ull);
-    for (int w = 0; w < b; ++w) acc ^= (uint32_t)__popcll(blk[lane][w] & y[w]) & 1u;
-    const uint64_t dw = blk[lane][b] & ((1ull << lane) - 1ull);
+    uint64_t dw = 0ull;
+    const uint64_t *Lrow = L + (size_t)(t0 + lane) * Lw;
+    for (int w0 = 0; w0 <= b; w0 += kSolveU) {
+      uint64_t v[kSolveU];
+#pragma unroll
+      for (int j = 0; j < kSolveU; ++j) v[j] = (lane < nb && w0 + j <= b) ? Lrow[w0 + j] : 0ull;
+#pragma unroll
+      for (int j = 0; j < kSolveU; ++j) {
+        if (w0 + j < b) acc ^= (uint32_t)__popcll(v[j] & y[w0 + j]) & 1u;
+        if (w0 + j == b) dw = v[j] & ((1ull << lane) - 1ull);
+      }
+    }
     uint64_t yb = 0ull;
     for (int s = 0; s < nb; ++s) {
       const uint64_t ds = rdl64b(dw, s);
@@ -751,7 +769,15 @@ __global__ __launch_bounds__(kSolveNT) void k_batch_solve(BatchSolveArgs a) {
     uint32_t v = 0u;
     if (i < n) {
       v = (uint32_t)((pb[i >> 6] >> (i & 63)) & 1ull);
-      for (int w = 0; w < nblk; ++w) v ^= (uint32_t)__popcll(L[(size_t)i * Lw + w] & y[w]) & 1u;
+      const uint64_t *Lrow = L + (size_t)i * Lw;
+      for (int w0 = 0; w0 < nblk; w0 += kSolveU) {
+        uint64_t lv[kSolveU];
+#pragma unroll
+        for (int j = 0; j < kSolveU; ++j) lv[j] = w0 + j < nblk ? Lrow[w0 + j] : 0ull;
+#pragma unroll
+        for (int j = 0; j < kSolveU; ++j)
+          if (w0 + j < nblk) v ^= (uint32_t)__popcll(lv[j] & y[w0 + j]) & 1u;
+      }
     }
     bad |= __ballot(v);
   }
@@ -761,20 +787,29 @@ __global__ __launch_bounds__(kSolveNT) void k_batch_solve(BatchSolveArgs a) {
   if (ok) {
     for (int b = nblk - 1; b >= 0; --b) {
       const int t0 = 64 * b, nb = (r - t0) < 64 ? (r - t0) : 64;
-      __syncthreads();
-      for (int e = lane; e < 64 * Mw; e += kSolveNT) {
-        const int row = e / Mw, w = e - row * Mw;
-        blk[row][w] = row < nb ? E[(size_t)(t0 + row) * Mw + w] : 0ull;
-      }
-      __syncthreads();
+      __syncthreads();  // xs holds the solved blocks after b
       const bool valid = lane < nb;
       int pc = 0;
       if (valid) {
         const int64_t v = pivcols[t0 + lane];
         pc = v < 0 ? 0 : (v >= m ? m - 1 : (int)v);
       }
+      // lane = row t0 + lane of E: its parity with the solved part, and the row
+      // itself staged in the lane's own slot of blk for the bits at this
+      // block's pivot columns
       uint32_t acc = valid ? (uint32_t)((y[b] >> lane) & 1ull) : 0u;
-      for (int w = 0; w < Mw; ++w) acc ^= (uint32_t)__popcll(blk[lane][w] & xs[w]) & 1u;
+      const uint64_t *Erow = E + (size_t)(t0 + lane) * Mw;
+      for (int w0 = 0; w0 < Mw; w0 += kSolveU) {
+        uint64_t v[kSolveU];
+#pragma unroll
+        for (int j = 0; j < kSolveU; ++j) v[j] = (valid && w0 + j < Mw) ? Erow[w0 + j] : 0ull;
+#pragma unroll
+        for (int j = 0; j < kSolveU; ++j)
+          if (w0 + j < Mw) {
+            acc ^= (uint32_t)__popcll(v[j] & xs[w0 + j]) & 1u;
+            blk[lane][w0 + j] = v[j];
+          }
+      }
       uint64_t dm = 0ull;
       for (int u = 0; u < nb; ++u) {
         const int pu = __builtin_amdgcn_readlane(pc, u);
