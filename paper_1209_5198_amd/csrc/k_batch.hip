@@ -654,12 +654,14 @@ __global__ __launch_bounds__(NT, kBatchWGPerCU) void k_batch_dec(BatchArgs a) {
                   const int Rj = sh.pR[j], rj = sh.pr[j];
                   if (rj == 0 || i < Rj) continue;
                   const uint64_t xw = sh.tr.rowq[rg][j];
+                  const uint64_t Kj = sh.pK[j];
                   uint64_t bits;
                   if (i < Rj + rj) {
                     const int s = i - Rj, kk = pcol[i] & 63;
-                    bits = compress(xw & ((1ull << kk) - 1ull), sh.pK[j], sh.pmv[j]) | (1ull << s);
+                    const uint64_t lo = xw & ((1ull << kk) - 1ull);
+                    bits = (Kj == ~0ull ? lo : compress(lo, Kj, sh.pmv[j])) | (1ull << s);
                   } else {
-                    bits = compress(xw, sh.pK[j], sh.pmv[j]);
+                    bits = Kj == ~0ull ? xw : compress(xw, Kj, sh.pmv[j]);  // a full panel needs no compression
                   }
                   const int shf = Rj - c_lo;
                   v |= shf >= 0 ? (bits << shf) : (bits >> (-shf));
