@@ -12,6 +12,12 @@ Cases:
   planted      A = X*Y, X 32768 x 20000, Y 20000 x 65536 Bernoulli(1/2),
                seed 20000 (factors from synth.planted stream 9); the product is
                formed by the oracle's matmul
+  matmul16384  C = A*B, A and B 16384 x 16384 Bernoulli(1/2), seed 16384
+               streams 2 and 3
+  matmul32768  C = A*B, A and B 32768 x 32768 Bernoulli(1/2), seed 32768
+               streams 2 and 3 (the GPU test runs it with one Strassen level)
+  planted_rref the planted matrix above: its reduced row echelon form R and
+               null-space basis N (oracle Gauss-Jordan)
 
 Usage: python tests/golden/make_fullsize_hashes.py [case ...]
 """
@@ -74,7 +80,39 @@ def case_planted():
     return out
 
 
-CASES = {"dense16384": case_dense16384, "planted": case_planted, "dense65536": case_dense65536}
+def product_case(seed, n):
+    A = synth.dense(seed, 2, n, n)
+    B = synth.dense(seed, 3, n, n)
+    t0 = time.time()
+    C = oracle.matmul(A, B, n, n, n)
+    dt = time.time() - t0
+    return {"n": n, "k": n, "m": n, "seed": seed, "streams": [2, 3], "C": digest(C),
+            "oracle_seconds": round(dt, 1), "oracle_threads": oracle.num_threads()}
+
+
+def case_matmul16384():
+    return product_case(16384, 16384)
+
+
+def case_matmul32768():
+    return product_case(32768, 32768)
+
+
+def case_planted_rref():
+    n, r, m = 32768, 20000, 65536
+    X, Y = synth.planted(20000, 9, n, m, r)
+    A = oracle.matmul(X, Y, n, r, m)
+    del X, Y
+    t0 = time.time()
+    res = oracle.nullspace(A, n, m)
+    dt = time.time() - t0
+    return {"n": n, "m": m, "seed": 20000, "stream": 9, "r_planted": r, "nullity": res["nullity"],
+            "R": digest(res["R"]), "N": digest(res["N"]), "oracle_seconds": round(dt, 1),
+            "oracle_threads": oracle.num_threads()}
+
+
+CASES = {"dense16384": case_dense16384, "planted": case_planted, "dense65536": case_dense65536,
+         "matmul16384": case_matmul16384, "matmul32768": case_matmul32768, "planted_rref": case_planted_rref}
 
 
 def main(argv):

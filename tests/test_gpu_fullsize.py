@@ -7,8 +7,8 @@
 * planted rank: X (32768 x 20000) and Y (20000 x 65536) from the generator; the
   GPU forms A = X*Y with gf2_matmul (its digest must equal the oracle product's)
   and decomposes it: rank 20000 and every output digest equal.
-* 16384^3 product: 64 sampled rows recomputed by the oracle one by one, plus the
-  Freivalds identity C*x = A*(B*x) for 64 random columns x (oracle products).
+* 16384^3 product, and a 32768^3 product with one Strassen-Winograd level
+  (cutoff 16384): SHA-256 of C equals the oracle product's digest.
 """
 import hashlib
 import json
@@ -108,19 +108,34 @@ def test_fullsize_planted_rank(g, gold):
     check_decomposition(g, A, n, m, ref)
 
 
-def test_fullsize_matmul_16384(g, orc):
+def fullsize_product(g, gold, name, cutoff=None):
+    """C = A*B at a full size: SHA-256 of C equals the oracle product's digest."""
     import torch
 
-    n = k = m = 16384
-    say("fullsize matmul", n)
-    A = synth.dense(16384, 2, n, k)
-    B = synth.dense(16384, 3, k, m)
-    C = g.matmul(g.Mat.from_rowmajor(A, n, k), g.Mat.from_rowmajor(B, k, m)).to_rowmajor()
-    torch.cuda.synchronize()
-    rows = np.random.default_rng(7).choice(n, size=64, replace=False)
-    ref_rows = orc.matmul(A[rows], B, 64, k, m)
-    assert np.array_equal(C[rows], ref_rows)
-    x = synth.dense(16384, 4, m, 64)
-    Cx = orc.matmul(C, x, n, m, 64)
-    ABx = orc.matmul(A, orc.matmul(B, x, k, m, 64), n, k, 64)
-    assert np.array_equal(Cx, ABx)
+    ref = gold.get(name)
+    if ref is None:
+        pytest.skip("no golden digest for " + name)
+    n, seed = ref["n"], ref["seed"]
+    say("fullsize matmul", n, "strassen_cutoff", cutoff)
+    A = synth.dense(seed, ref["streams"][0], n, n)
+    B = synth.dense(seed, ref["streams"][1], n, n)
+    Ag, Bg = g.Mat.from_rowmajor(A, n, n), g.Mat.from_rowmajor(B, n, n)
+    del A, B
+    if cutoff is not None:
+        g.gf2_set_param("strassen_cutoff", cutoff)
+    try:
+        C = g.matmul(Ag, Bg)
+        torch.cuda.synchronize()
+    finally:
+        if cutoff is not None:
+            g.gf2_set_param("strassen_cutoff", 65536)
+    assert digest(C.to_rowmajor()) == ref["C"]
+
+
+def test_fullsize_matmul_16384(g, gold):
+    fullsize_product(g, gold, "matmul16384")
+
+
+def test_fullsize_matmul_32768_strassen(g, gold):
+    # one Strassen-Winograd level (32768 > 16384), leaves of 16384^3
+    fullsize_product(g, gold, "matmul32768", cutoff=16384)

@@ -93,8 +93,9 @@ def test_nullspace_fullsize_planted(g, orc):
     import torch
 
     with open(GOLD) as f:
-        ref = json.load(f).get("planted")
-    if ref is None:
+        golds = json.load(f)
+    ref, rref = golds.get("planted"), golds.get("planted_rref")
+    if ref is None or rref is None:
         pytest.skip("no golden digests for planted")
     n, m, r = ref["n"], ref["m"], ref["r_planted"]
     say("nullspace fullsize planted", n, m, r)
@@ -102,22 +103,27 @@ def test_nullspace_fullsize_planted(g, orc):
     Am = g.matmul(g.Mat.from_rowmajor(X, n, r), g.Mat.from_rowmajor(Y, r, m))
     del X, Y
     N = g.Mat.zeros(m, m)
+    R = g.Mat.zeros(min(n, m), m)
     nul = torch.empty(1, dtype=torch.int64, device="cuda")
     piv = torch.empty(min(n, m), dtype=torch.int64, device="cuda")
     rank = torch.empty(1, dtype=torch.int64, device="cuda")
-    g.gf2_rref(Am, None, piv, rank)
+    g.gf2_rref(Am, R, piv, rank)
     g.gf2_nullspace(Am, N, nul)
     torch.cuda.synchronize()
     pv = piv.cpu().numpy()
     assert int(rank.item()) == ref["rank"] and digest(pv) == ref["pivcols"]
     k = int(nul.item())
-    assert k == m - ref["rank"]
+    assert k == m - ref["rank"] == rref["nullity"]
+    # the reduced row echelon form and the basis, bit for bit
+    assert digest(R.to_rowmajor()) == rref["R"]
+    del R
     free = np.setdiff1d(np.arange(m), pv[:ref["rank"]])
     A = Am.to_rowmajor()
     del Am
     Nh = N.to_rowmajor()[:k]
     del N
     torch.cuda.empty_cache()
+    assert digest(Nh) == rref["N"]
     # unit matrix on the free columns, sampled rows
     rows = np.random.default_rng(3).choice(k, size=64, replace=False)
     for j in rows:
