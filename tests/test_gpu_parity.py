@@ -316,6 +316,21 @@ def test_decompose_spread_pivots(g, orc, s):
     assert_same_ple(got, ref, s)
 
 
+def test_decompose_paired_columns(g, orc):
+    """Columns in identical pairs: every 64-column sub-panel holds exactly 32
+    pivots, so each product's inner words have rows 0..31 only and the table
+    steps of rows 32..63 are skipped."""
+    n, m = 3000, 5000
+    say("paired columns")
+    bits = orc.unpack_bits(synth.dense(61, 1, n, m), m)
+    bits[:, 1::2] = bits[:, 0::2][:, :bits[:, 1::2].shape[1]]
+    A = orc.pack_bits(bits)
+    ref = orc.ple(A, n, m)
+    assert ref["rank"] == m // 2
+    got = gpu_decompose(g, A, n, m)
+    assert_same_ple(got, ref, "paired")
+
+
 @pytest.mark.parametrize("w", [1, 2, 5])
 def test_decompose_input_layouts(g, orc, w):
     n, m = 900, 1000
