@@ -200,9 +200,12 @@ int gf2_solve_batched(const gf2_batch_item *items, int64_t count, const uint64_t
  * product at 32768^3 and 65536^3 (up to max_size); afterwards the trailing
  * update and gf2_matmul use the fastest tile of each class and the measured
  * cutoff (the smallest size where one level paid, else twice the largest size
- * compared).  No result of any call depends on it.  Allocates its operands
- * with hipMalloc (up to about 3.5 GB at max_size >= 65536) and synchronises
- * `stream`.  GF2_EINVAL for max_size < 256.
+ * compared).  Then it times one decomposition of a random square matrix of
+ * 2048, 16384 and 32768 bits (up to max_size) for each panel width W = 2, 4,
+ * 8; the fastest becomes the width of the size class (see
+ * gf2_autotune_params).  No result of any call depends on it.  Allocates its
+ * operands with hipMalloc (up to about 3.5 GB at max_size >= 65536) and
+ * synchronises `stream`.  GF2_EINVAL for max_size < 256.
  */
 int gf2_autotune(int64_t max_size, void *stream);
 
@@ -214,8 +217,34 @@ int gf2_autotune(int64_t max_size, void *stream);
 int gf2_autotune_table(int32_t *variants, int64_t *strassen_cutoff);
 
 /*
+ * The parameters an n x m decomposition uses now, beside Section 6's analytic
+ * choices (host pointers, each may be NULL):
+ *   panel_words          W, sub-panels of 64 columns per trailing-update panel:
+ *                        the "panel_words" knob when set, else the width
+ *                        gf2_autotune measured for the size class of max(n, m)
+ *                        (<= 4096, <= 16384, larger) while "autotuned" is 1,
+ *                        else 8;
+ *   table_bits           c of the trailing-update product's tables (8: 2^8
+ *                        entries per 8 inner bits; the batched kernel uses
+ *                        c = 4 and one-word panels);
+ *   analytic_table_bits  the c minimising C(b, c, n) = (b/c)(2^c - 1 + n) for
+ *                        that product (b = 64 W inner bits, n = rows), the
+ *                        paper's choice of table size;
+ *   analytic_strassen    44c + 6(2^c - 1) at c = table_bits, the size from
+ *                        which the paper's cost model makes one Strassen-
+ *                        Winograd level pay (the measured cutoff is reported
+ *                        by gf2_autotune_table).
+ * GF2_EINVAL for negative sizes.
+ */
+int gf2_autotune_params(int64_t rows, int64_t cols, int32_t *panel_words, int32_t *table_bits,
+                        int32_t *analytic_table_bits, int64_t *analytic_strassen);
+
+/*
  * Tuning knobs, process-wide (no knob changes any result):
- *   "panel_words"        : s, sub-panels of 64 columns per trailing-update panel (1..8)
+ *   "panel_words"        : W, sub-panels of 64 columns per trailing-update panel
+ *                          (1..8; 0 = automatic, the default: the width measured by
+ *                          gf2_autotune for the size class while "autotuned" is 1,
+ *                          else 8)
  *   "strassen_cutoff"    : gf2_matmul recurses with Strassen-Winograd (one level
  *                          per halving) while every dimension of the current
  *                          product is at least this many bits (default 65536; 0 = never)

@@ -18,6 +18,7 @@
 #include <limits.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <string>
@@ -32,7 +33,7 @@ namespace {
 thread_local std::string g_err;
 // set for the duration of an allocation-free call: no profiling events
 thread_local bool g_noalloc = false;
-int g_panel_words = 8;
+int g_panel_words = 0;  // 0: automatic (the tuned width of the size class, else 8)
 // Strassen-Winograd recursion while every dimension of the current product is
 // at least this many bits (0: never).  Measured on MI355X: one level pays at
 // 65536^3 (56 ms against 62 ms), none at 32768^3 (10.3 ms against 8 ms).
@@ -64,8 +65,28 @@ double g_post_follow_lookups = 1.5e9;
 // (1, 2-3, 4-15, 16+ blocks of 16 words); -1 = the built-in rule.
 constexpr int kTuneRows = 9, kTuneBlocks = 4;
 int g_tuned[kTuneRows][kTuneBlocks];
+// Panel width (sub-panels of 64 columns) per decomposition size class
+// (max(n, m) <= 4096, <= 16384, larger), written by gf2_autotune.
+constexpr int kWClasses = 3;
+constexpr int64_t kWClassMax[kWClasses] = {4096, 16384, INT64_MAX};
+constexpr int64_t kWClassProbe[kWClasses] = {2048, 16384, 32768};  // the size each class is timed at
+int g_tuned_W[kWClasses] = {0, 0, 0};
+int w_class(int64_t n, int64_t m) {
+  const int64_t s = n > m ? n : m;
+  int c = 0;
+  while (c + 1 < kWClasses && s > kWClassMax[c]) ++c;
+  return c;
+}
 bool g_tuned_valid = false;  // a table was measured
 bool g_tuned_on = false;     // ... and is used
+
+// Panel width of an n x m decomposition: the knob when set, else the tuned
+// width of its size class while the tuned table is in use, else 8.
+int panel_words_for(int64_t n, int64_t m) {
+  if (g_panel_words > 0) return g_panel_words;
+  const int t = g_tuned_W[w_class(n, m)];
+  return (g_tuned_on && t > 0) ? t : kMaxPanelWords;
+}
 int tune_row_class(int64_t rows) {
   int r = 0;
   while (r + 1 < kTuneRows && rows >= ((int64_t)512 << r)) ++r;
@@ -470,7 +491,7 @@ int factor_panels(const gf2_mat *A, DecWork &w, const Exec &x, Pack pack) {
     HIPCHK(launch_pack(*A, w.W, w.ldw, w.n, A->cols, w.NB, G));
     if (pack == Pack::kIdentityRight) HIPCHK(launch_set_identity(w.W, w.ldw, w.n, A->cols, G));
   }
-  const int S = g_panel_words;
+  const int S = panel_words_for(w.n, A->cols);
   int prev = -1;
   // Main stream G: post(J), next panel's columns, chain(J+1), in order (no
   // stream hop before the chain).  Bulk stream Cs: the rest of panel J's
@@ -526,7 +547,7 @@ int factor(const gf2_mat *A, DecWork &w, const Exec &x, Pack pack = Pack::kPlain
     HIPCHK(launch_pack(*A, w.W, w.ldw, w.n, A->cols, w.NB, G));
     if (pack == Pack::kIdentityRight) HIPCHK(launch_set_identity(w.W, w.ldw, w.n, A->cols, G));
   }
-  const int S = g_panel_words;
+  const int S = panel_words_for(w.n, A->cols);
   int P = g_sp_panels;
   if (P * S > kSpSubMax) P = kSpSubMax / S;
   const int SPW = P * S;
@@ -709,7 +730,7 @@ const char *gf2_last_error(void) { return g_err.c_str(); }
 int gf2_set_param(const char *name, int64_t value) {
   if (!name) return fail(GF2_EINVAL, "null parameter name");
   if (!strcmp(name, "panel_words")) {
-    if (value < 1 || value > kMaxPanelWords) return fail(GF2_EINVAL, "panel_words must be in 1..8");
+    if (value < 0 || value > kMaxPanelWords) return fail(GF2_EINVAL, "panel_words must be in 0..8");
     g_panel_words = (int)value;
     return GF2_OK;
   }
@@ -1736,10 +1757,79 @@ int gf2_autotune(int64_t max_size, void *stream) {
       break;
     }
   }
+  if (rc) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return rc; }
+  if (largest > 0) g_strassen_cutoff = cutoff > 0 ? cutoff : 2 * largest;
+
+  // ---- panel width (sub-panels of 64 columns, W) per decomposition size
+  // class: one decomposition of a random square matrix at the class's probe
+  // size (up to max_size) for W = 2, 4, 8; the fastest becomes the class's
+  // width.  Classes above max_size keep the default (8).
+  const int saved_w = g_panel_words;
+  const bool saved_on = g_tuned_on;
+  g_tuned_on = false;
+  for (int c = 0; c < kWClasses && !rc; ++c) {
+    const int64_t n = kWClassProbe[c];
+    if (n > max_size) {
+      g_tuned_W[c] = 0;
+      continue;
+    }
+    const int64_t nw = n / 64;
+    const size_t words = (size_t)n * (size_t)nw;
+    char *mem = nullptr;
+    if (hipMalloc(&mem, 3 * words * 8 + (size_t)(2 * n + 1) * 8) != hipSuccess) {
+      (void)hipGetLastError();
+      g_tuned_W[c] = 0;
+      break;  // not enough memory at this size: the larger classes keep the default
+    }
+    uint64_t *dA = (uint64_t *)mem, *dL = dA + words, *dE = dL + words;
+    int64_t *perm = (int64_t *)(dE + words), *piv = perm + n, *rk = piv + n;
+    const gf2_mat Am{dA, n, n, nw, n}, Lm{dL, n, n, nw, n}, Em{dE, n, n, nw, n};
+    float best_ms = 1e30f;
+    int best = 0;
+    if (launch_fill_bits(dA, words, 0x7a11 + c, s) != hipSuccess) rc = fail(GF2_EHIP, "fill");
+    for (int W : {2, 4, 8}) {
+      if (rc) break;
+      g_panel_words = W;
+      float ms = 0.f;
+      rc = timed([&]() -> int { return gf2_decompose(&Am, &Lm, &Em, perm, piv, rk, stream); }, &ms);
+      if (!rc && ms < best_ms) {
+        best_ms = ms;
+        best = W;
+      }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(mem);
+    g_tuned_W[c] = best;
+  }
+  g_panel_words = saved_w;
+  g_tuned_on = saved_on;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (rc) return rc;
-  if (largest > 0) g_strassen_cutoff = cutoff > 0 ? cutoff : 2 * largest;
+  return rc;
+}
+
+int gf2_autotune_params(int64_t rows, int64_t cols, int32_t *panel_words, int32_t *table_bits,
+                        int32_t *analytic_table_bits, int64_t *analytic_strassen) {
+  if (rows < 0 || cols < 0) return fail(GF2_EINVAL, "gf2_autotune_params: rows and cols must be >= 0");
+  const int W = panel_words_for(rows, cols);
+  if (panel_words) *panel_words = W;
+  if (table_bits) *table_bits = 8;  // the trailing-update product's tables: 2^8 entries per 8 inner bits
+  if (analytic_table_bits) {
+    // Section 6: the table size minimising C(b, c, n) = (b / c)(2^c - 1 + n)
+    // for the panel's product, b = 64 W inner bits and n = rows output rows
+    double best = 1e300;
+    int bc = 1;
+    for (int c = 1; c <= 24; ++c) {
+      const double cost = (64.0 * W / c) * (std::ldexp(1.0, c) - 1.0 + (double)rows);
+      if (cost < best) {
+        best = cost;
+        bc = c;
+      }
+    }
+    *analytic_table_bits = bc;
+  }
+  // Section 6: Strassen-Winograd pays on the CPU model from n >= 44c + 6(2^c - 1)
+  if (analytic_strassen) *analytic_strassen = 44 * 8 + 6 * ((1 << 8) - 1);
   return GF2_OK;
 }
 

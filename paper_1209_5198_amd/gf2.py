@@ -29,7 +29,7 @@ GF2_EHIP = -3
 
 EXPORTED = ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_decompose_batched",
             "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_inverse", "gf2_autotune", "gf2_autotune_table",
-            "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_microbench", "gf2_workspace_bytes",
+            "gf2_autotune_params", "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_microbench", "gf2_workspace_bytes",
             "gf2_matmul_ws", "gf2_decompose_ws", "gf2_rank_ws", "gf2_solve_ws", "gf2_decompose_batched_ws",
             "gf2_solve_batched_ws", "gf2_decompose_noalloc", "gf2_decompose_graph", "gf2_graph_launch",
             "gf2_graph_destroy", "gf2_release", "gf2_last_error", "gf2_version")
@@ -80,6 +80,8 @@ def load():
         lib.gf2_inverse.argtypes = [P, P, vp, vp]
         lib.gf2_autotune.argtypes = [i64, vp]
         lib.gf2_autotune_table.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(i64)]
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        lib.gf2_autotune_params.argtypes = [i64, i64, i32p, i32p, i32p, ctypes.POINTER(i64)]
         lib.gf2_set_param.argtypes = [ctypes.c_char_p, i64]
         lib.gf2_profile.argtypes = [ctypes.c_int]
         lib.gf2_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
@@ -104,7 +106,7 @@ def load():
         lib.gf2_version.restype = ctypes.c_char_p
         for name in ("gf2_matmul", "gf2_decompose", "gf2_rank", "gf2_solve", "gf2_decompose_batched",
                      "gf2_solve_batched", "gf2_rref", "gf2_nullspace", "gf2_inverse", "gf2_autotune",
-                     "gf2_autotune_table", "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_microbench",
+                     "gf2_autotune_table", "gf2_autotune_params", "gf2_set_param", "gf2_profile", "gf2_profile_read", "gf2_microbench",
                      "gf2_matmul_ws", "gf2_decompose_ws", "gf2_rank_ws", "gf2_solve_ws", "gf2_decompose_batched_ws",
                      "gf2_solve_batched_ws", "gf2_decompose_noalloc", "gf2_decompose_graph", "gf2_graph_launch",
                      "gf2_graph_destroy", "gf2_release"):
@@ -261,6 +263,17 @@ def gf2_autotune_table():
     c = ctypes.c_int64()
     _check(load().gf2_autotune_table(v, ctypes.byref(c)))
     return [list(v[4 * r:4 * r + 4]) for r in range(9)], c.value
+
+
+def gf2_autotune_params(rows: int, cols: int) -> dict:
+    """The panel width and table size an n x m decomposition uses, beside the
+    paper's analytic table size and Strassen point (Section 6)."""
+    w, c, ca = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    st = ctypes.c_int64()
+    _check(load().gf2_autotune_params(int(rows), int(cols), ctypes.byref(w), ctypes.byref(c), ctypes.byref(ca),
+                                      ctypes.byref(st)))
+    return {"panel_words": w.value, "table_bits": c.value, "analytic_table_bits": ca.value,
+            "analytic_strassen": st.value}
 
 
 def gf2_set_param(name: str, value: int) -> None:

@@ -41,10 +41,12 @@ def test_set_param_validation_without_gpu():
     from paper_1209_5198_amd import gf2
 
     gf2.load()
-    assert gf2.load().gf2_set_param(b"panel_words", 0) == gf2.GF2_EINVAL
+    assert gf2.load().gf2_set_param(b"panel_words", -1) == gf2.GF2_EINVAL
+    assert gf2.load().gf2_set_param(b"panel_words", 9) == gf2.GF2_EINVAL
     assert gf2.load().gf2_set_param(b"no_such_knob", 1) == gf2.GF2_EINVAL
     assert b"unknown" in gf2.load().gf2_last_error()
     assert gf2.load().gf2_set_param(b"panel_words", 8) == gf2.GF2_OK
+    assert gf2.load().gf2_set_param(b"panel_words", 0) == gf2.GF2_OK  # automatic (the default)
 
 
 def test_null_descriptor_rejected_without_gpu():
@@ -249,3 +251,28 @@ def test_caller_workspace_validation_without_gpu():
         assert lib.gf2_rank_ws(ctypes.byref(A), fake, ws, nb, None) == gf2.GF2_EINVAL
     assert lib.gf2_set_param(b"chain_cus", 8) == gf2.GF2_EINVAL
     assert lib.gf2_set_param(b"chain_cus", 0) == gf2.GF2_OK
+
+
+def test_autotune_params_analytic_choices():
+    """gf2_autotune_params reports the paper's analytic choices (Section 6): the
+    table size minimising C(b, c, n) = (b/c)(2^c - 1 + n) -- the Remark there
+    puts the continuous minimum of C(64, c, 64) near 4.77 and of C(128, c,
+    128) near 5.5 -- and the Strassen point 44c + 6(2^c - 1) = 1882 at c = 8."""
+    from paper_1209_5198_amd import gf2
+
+    lib = gf2.load()
+    try:
+        assert lib.gf2_set_param(b"panel_words", 1) == gf2.GF2_OK  # b = 64
+        p = gf2.gf2_autotune_params(64, 64)
+        assert p["panel_words"] == 1 and p["table_bits"] == 8 and p["analytic_strassen"] == 1882
+        assert p["analytic_table_bits"] == 5  # integer neighbour of 4.77
+        assert lib.gf2_set_param(b"panel_words", 2) == gf2.GF2_OK  # b = 128
+        assert gf2.gf2_autotune_params(128, 128)["analytic_table_bits"] in (5, 6)  # either side of 5.5
+        # larger products: the minimum moves up like log2(n)
+        assert gf2.gf2_autotune_params(65536, 65536)["analytic_table_bits"] > \
+            gf2.gf2_autotune_params(2048, 2048)["analytic_table_bits"]
+        assert lib.gf2_set_param(b"panel_words", 0) == gf2.GF2_OK
+        assert gf2.gf2_autotune_params(2048, 2048)["panel_words"] == 8  # untuned default
+        assert lib.gf2_autotune_params(-1, 5, None, None, None, None) == gf2.GF2_EINVAL
+    finally:
+        lib.gf2_set_param(b"panel_words", 0)

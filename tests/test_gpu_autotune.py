@@ -1,6 +1,7 @@
-"""The autotuner: it measures a tile for every size class and a Strassen
-cutoff, and no result depends on it (decomposition and product stay
-bit-identical to the oracle with the tuned table in use)."""
+"""The autotuner: it measures a tile for every size class, a Strassen cutoff
+and a panel width per decomposition size class, and no result depends on it
+(decompositions in two size classes and a product stay bit-identical to the
+oracle with the tuned choices in use)."""
 import numpy as np
 import pytest
 
@@ -41,6 +42,21 @@ def test_autotune_table_and_invariance(g, orc):
         assert np.array_equal(out["perm"].cpu().numpy(), ref["perm"])
         assert np.array_equal(out["E"].to_rowmajor(), ref["E"])
         assert np.array_equal(out["L"].to_rowmajor(), ref["L"])
+        # the measured panel widths, and a decomposition in the second size
+        # class with its width equal to the oracle too
+        for n_c in (2048, 16384, 32768):
+            p = g.gf2_autotune_params(n_c, n_c)
+            print("class", n_c, p, flush=True)
+            assert p["panel_words"] in (2, 4, 8)
+        n2, m2 = 5000, 4500
+        A2 = synth.dense(91, 4, n2, m2)
+        out2 = g.decompose(g.Mat.from_rowmajor(A2, n2, m2))
+        torch.cuda.synchronize()
+        ref2 = orc.ple(A2, n2, m2)
+        assert int(out2["rank"].item()) == ref2["rank"]
+        assert np.array_equal(out2["perm"].cpu().numpy(), ref2["perm"])
+        assert np.array_equal(out2["E"].to_rowmajor(), ref2["E"])
+        assert np.array_equal(out2["L"].to_rowmajor(), ref2["L"])
         X, Y = synth.dense(91, 2, 2100, 1500), synth.dense(91, 3, 1500, 2500)
         C = g.matmul(g.Mat.from_rowmajor(X, 2100, 1500), g.Mat.from_rowmajor(Y, 1500, 2500)).to_rowmajor()
         assert np.array_equal(C, orc.matmul(X, Y, 2100, 1500, 2500))

@@ -125,12 +125,12 @@ def test_decompose_panel_width_invariant(g, orc, panel_words):
     try:
         got = gpu_decompose(g, A, n, m)
     finally:
-        g.gf2_set_param("panel_words", 8)
+        g.gf2_set_param("panel_words", 0)
     assert_same_ple(got, ref, panel_words)
 
 
 KNOB_DEFAULTS = {"panel_gemm_variant": -1, "overlap_lookups": 300000000, "post_follow_lookups": 1500000000,
-                 "sp_panels": 0, "panel_words": 8}
+                 "sp_panels": 0, "panel_words": 0}
 
 
 @pytest.mark.parametrize("knobs", [{"panel_gemm_variant": v} for v in range(6)] + [
