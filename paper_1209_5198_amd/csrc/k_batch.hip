@@ -252,7 +252,16 @@ __global__ __launch_bounds__(NT, kBatchWGPerCU) void k_batch_dec(BatchArgs a) {
             k = (int)__builtin_ctzll(Fr);
             Fr &= Fr - 1ull;
             const uint64_t kb = 1ull << k;
-            bool c0 = (xw0 & kb) != 0ull, c1 = (xw1 & kb) != 0ull;
+            // all ones in the lanes whose row has bit k: the one-bit field of
+            // the word half holding bit k, sign-extended
+            const int ks = 31 - (k & 31);
+            auto bitmask = [&](uint64_t x) -> uint64_t {
+              const uint32_t h = k < 32 ? (uint32_t)x : (uint32_t)(x >> 32);
+              const uint32_t mk = (uint32_t)((int32_t)(h << ks) >> 31);
+              return ((uint64_t)mk << 32) | mk;
+            };
+            uint64_t m0 = bitmask(xw0), m1 = bitmask(xw1);
+            bool c0 = (uint32_t)m0 != 0u, c1 = (uint32_t)m1 != 0u;
             const uint64_t bal0 = __ballot(c0) & (~0ull << t);  // positions t.. of slot 0
             int p = (int)__builtin_ctzll(bal0);
             if (__builtin_expect(bal0 == 0ull, 0)) {
@@ -272,8 +281,8 @@ __global__ __launch_bounds__(NT, kBatchWGPerCU) void k_batch_dec(BatchArgs a) {
               ow1 = wrlane(ot, p1, ow1);
               xw0 = wrl64b(xw0, xp, t);
               ow0 = wrlane(op, t, ow0);
-              c0 = (xw0 & kb) != 0ull;
-              c1 = (xw1 & kb) != 0ull;
+              m0 = bitmask(xw0);
+              m1 = bitmask(xw1);
               p = t;
             }
             p = uni(p);
@@ -283,8 +292,8 @@ __global__ __launch_bounds__(NT, kBatchWGPerCU) void k_batch_dec(BatchArgs a) {
             // before t are finished positions (their rows are in the log) and
             // lane p is the pivot, overwritten below or finished itself.
             const uint64_t ph = pw & ~((kb << 1) - 1ull);  // zero for k = 63
-            if (c0) xw0 ^= ph;
-            if (c1) xw1 ^= ph;
+            xw0 ^= ph & m0;
+            xw1 ^= ph & m1;
             // the row at position t moves to position p (nothing moves if p = t)
             const uint64_t xt = rdl64b(xw0, t);
             const int ot = __builtin_amdgcn_readlane(ow0, t);
