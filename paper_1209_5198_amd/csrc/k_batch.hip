@@ -237,9 +237,9 @@ __global__ __launch_bounds__(NT, kBatchWGPerCU) void k_batch_dec(BatchArgs a) {
       // only when the window has none (then the whole workgroup takes part).
       int t = 0, k = 0, lstart = 0, xfer = -1;
       uint64_t K = 0ull;
-      // pivot log of wave 0, lane i = pivot i: its word as found, bit, row
+      // pivot log of wave 0, lane i = pivot i: its word as found and its row
       uint64_t lgw = 0ull;
-      int lgk = 0, lgo = 0;
+      int lgo = 0;
       const int tmax = nrest < 64 ? nrest : 64;
       const uint64_t wbits = nbits == 64 ? ~0ull : ((1ull << nbits) - 1ull);
       for (;;) {
@@ -294,22 +294,21 @@ __global__ __launch_bounds__(NT, kBatchWGPerCU) void k_batch_dec(BatchArgs a) {
             const uint64_t ph = pw & ~((kb << 1) - 1ull);  // zero for k = 63
             xw0 ^= ph & m0;
             xw1 ^= ph & m1;
-            // the row at position t moves to position p (nothing moves if p = t)
-            const uint64_t xt = rdl64b(xw0, t);
-            const int ot = __builtin_amdgcn_readlane(ow0, t);
-            xw0 = wrl64b(xw0, xt, p);
-            ow0 = wrlane(ot, p, ow0);
+            if (p != t) {  // the row at position t moves to position p
+              const uint64_t xt = rdl64b(xw0, t);
+              const int ot = __builtin_amdgcn_readlane(ow0, t);
+              xw0 = wrl64b(xw0, xt, p);
+              ow0 = wrlane(ot, p, ow0);
+            }
             lgw = wrl64b(lgw, pw, t);
-            lgk = wrlane(k, t, lgk);
             lgo = wrlane(porg, t, lgo);
             K |= kb;
             ++t;
           }
           k = need >= 0 ? need : 64;
-          if (lane < t) {
-            sh.pivw[lane] = lgw;
-            sh.prow[lane] = lgk;
-          }
+          if (lane < t) sh.pivw[lane] = lgw;
+          // pivot i sits at the i-th set bit of K (bits are taken in order)
+          if ((K >> lane) & 1ull) sh.prow[__popcll(K & ((1ull << lane) - 1ull))] = lane;
           if (lane == 0) {
             sh.cmd = need;
             sh.tcnt = t;
@@ -472,7 +471,8 @@ __global__ __launch_bounds__(NT, kBatchWGPerCU) void k_batch_dec(BatchArgs a) {
           uint64_t c, xo = xw0;
           int oo = ow0;
           if (lane < r) {  // pivot lane: its row as found, from the log
-            c = sh.tinv[lgk] & ~(1ull << lgk);
+            const int kk = sh.prow[lane];
+            c = sh.tinv[kk] & ~(1ull << kk);
             xo = lgw;
             oo = lgo;
           } else {
