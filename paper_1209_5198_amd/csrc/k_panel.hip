@@ -264,10 +264,11 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
     // ---- pivot-wave state.  Slot s of the window is position Rb + s; the
     // first half (slots 0..63) is kept reduced by every pivot, the second half
     // holds rows that are reduced on demand (Proj) when the first half has no
-    // candidate.
-    uint32_t a_lo = 0u, a_hi = 0u, b_lo = 0u, b_hi = 0u;
+    // candidate.  A pivot leaves the first half: its slot reads zero there
+    // (so it is never a candidate again) and lane t of e holds pivot t.
+    uint32_t a_lo = 0u, a_hi = 0u, b_lo = 0u, b_hi = 0u, e_lo = 0u, e_hi = 0u;
     int org0 = lane, org1 = 64 + lane;
-    uint64_t act0 = 0ull, act1 = 0ull;
+    uint64_t act1 = 0ull;
     uint32_t m_lo = 0u, m_hi = 0u, y_lo = 0u, y_hi = 0u;  // M_j and Zc row j (lane j)
     uint64_t pivmask = 0ull, F = 0ull;
     bool Fknown = false;
@@ -276,29 +277,29 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
       const bool v0 = wb + lane < nblk, v1 = wb + 64 + lane < nblk;
       if (v0) { const uint64_t x = sh.blk[wb + lane][b]; a_lo = (uint32_t)x; a_hi = (uint32_t)(x >> 32); }
       if (v1) { const uint64_t x = sh.blk[wb + 64 + lane][b]; b_lo = (uint32_t)x; b_hi = (uint32_t)(x >> 32); }
-      act0 = __ballot(v0);
       act1 = __ballot(v1);
     }
 
+    // all ones in the lanes whose x has bit s (s < 32), zero elsewhere
+    auto bit_lanes = [](uint32_t x, int s) -> uint32_t { return (uint32_t)__builtin_amdgcn_sbfe((int)x, s, 1); };
     // pivot t = ib for bit k with reduced row (p_lo, p_hi): bookkeeping rows M
-    // (RREF of the pivots so far) and the coefficient map, free slots.
-    // mm: lanes j of earlier pivots whose M_j has bit k.
-    auto commit = [&](int k, uint32_t p_lo, uint32_t p_hi, uint64_t mm) {
+    // (RREF of the pivots so far), the coefficient map and the pivot row.
+    // mm: all ones in the lanes j of earlier pivots whose M_j has bit k.
+    auto commit = [&](int k, uint32_t p_lo, uint32_t p_hi, uint32_t mm) {
       const uint64_t tb = 1ull << ib;
       const uint32_t t_lo = (uint32_t)tb, t_hi = (uint32_t)(tb >> 32);
-      if (__builtin_amdgcn_inverse_ballot_w64(mm)) {  // (exec-masked XORs)
-        m_lo ^= p_lo;
-        m_hi ^= p_hi;
-        y_lo ^= t_lo;
-        y_hi ^= t_hi;
-      }
+      m_lo ^= p_lo & mm;
+      m_hi ^= p_hi & mm;
+      y_lo ^= t_lo & mm;
+      y_hi ^= t_hi & mm;
       m_lo = wrlane(p_lo, k, m_lo);
       m_hi = wrlane(p_hi, k, m_hi);
       y_lo = wrlane(t_lo, k, y_lo);
       y_hi = wrlane(t_hi, k, y_hi);
+      e_lo = wrlane(p_lo, ib, e_lo);
+      e_hi = wrlane(p_hi, ib, e_hi);
       const uint64_t kb = 1ull << k;
       pivmask |= kb;
-      act0 &= ~tb;
       if (Fknown) {
         if (F & kb) F |= ((uint64_t)p_hi << 32) | p_lo;
         F &= ~kb;
@@ -308,33 +309,29 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
 
     // Bits [k, kend) whose word half is fixed, while the first half of the
     // window has a candidate (the common case); returns at the first bit where
-    // it has none.  The candidates other than the pivot are reduced by it, then
-    // the pivot moves to slot ib and the row of slot ib to the pivot's slot.
+    // it has none.  Every candidate is reduced by the pivot (which empties the
+    // pivot's own slot), then the row of slot ib moves to the pivot's slot.
     auto run_bits = [&](auto hi_tag, int &k, int kend) {
       constexpr bool HI = decltype(hi_tag)::value;
       for (; k < kend; ++k) {
-        const uint32_t bit = 1u << (k & 31);
-        const uint64_t c0 = __ballot(((HI ? a_hi : a_lo) & bit) != 0u) & act0;
+        const uint32_t vc = bit_lanes(HI ? a_hi : a_lo, k & 31);
+        const uint64_t c0 = __ballot(vc != 0u);
         if (c0 == 0ull) return;
         const int sp = __builtin_ctzll(c0);
         const uint32_t p_lo = __builtin_amdgcn_readlane(a_lo, sp), p_hi = __builtin_amdgcn_readlane(a_hi, sp);
-        const int p_org = __builtin_amdgcn_readlane(org0, sp);
-        const uint32_t i_lo = __builtin_amdgcn_readlane(a_lo, ib), i_hi = __builtin_amdgcn_readlane(a_hi, ib);
-        const int i_org = __builtin_amdgcn_readlane(org0, ib);
-        if (__builtin_amdgcn_inverse_ballot_w64(c0 & ~(1ull << sp))) {  // (exec-masked XORs)
-          a_lo ^= p_lo;
-          a_hi ^= p_hi;
+        a_lo ^= p_lo & vc;
+        a_hi ^= p_hi & vc;
+        if (sp != ib) {  // slot ib holds no candidate: its row moves to slot sp
+          const uint32_t i_lo = __builtin_amdgcn_readlane(a_lo, ib), i_hi = __builtin_amdgcn_readlane(a_hi, ib);
+          const int p_org = __builtin_amdgcn_readlane(org0, sp), i_org = __builtin_amdgcn_readlane(org0, ib);
+          a_lo = wrlane(i_lo, sp, a_lo);
+          a_hi = wrlane(i_hi, sp, a_hi);
+          org0 = wrlane(i_org, sp, org0);
+          a_lo = wrlane(0u, ib, a_lo);
+          a_hi = wrlane(0u, ib, a_hi);
+          org0 = wrlane(p_org, ib, org0);
         }
-        // (slot ib holds no candidate unless ib == sp; then both writes store
-        // the pivot); the writes are grouped by lane so the lane register is
-        // set twice
-        a_lo = wrlane(i_lo, sp, a_lo);
-        a_hi = wrlane(i_hi, sp, a_hi);
-        org0 = wrlane(i_org, sp, org0);
-        a_lo = wrlane(p_lo, ib, a_lo);
-        a_hi = wrlane(p_hi, ib, a_hi);
-        org0 = wrlane(p_org, ib, org0);
-        commit(k, p_lo, p_hi, __ballot(((HI ? m_hi : m_lo) & bit) != 0u));
+        commit(k, p_lo, p_hi, bit_lanes(HI ? m_hi : m_lo, k & 31));
       }
     };
 
@@ -369,10 +366,10 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
           b_lo = wrlane(i_lo, sp, b_lo);
           b_hi = wrlane(i_hi, sp, b_hi);
           org1 = wrlane(i_org, sp, org1);
-          a_lo = wrlane(p_lo, ib, a_lo);
-          a_hi = wrlane(p_hi, ib, a_hi);
+          a_lo = wrlane(0u, ib, a_lo);
+          a_hi = wrlane(0u, ib, a_hi);
           org0 = wrlane(p_org, ib, org0);
-          commit(k, p_lo, p_hi, __ballot(((k < 32 ? m_lo : m_hi) & bit) != 0u));
+          commit(k, p_lo, p_hi, bit_lanes(k < 32 ? m_lo : m_hi, k & 31));
           ++k;
           continue;
         }
@@ -497,11 +494,10 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
                                (uint32_t)__builtin_amdgcn_readlane(a_lo, ib);
           const uint64_t xin = sh.blk[si][b];
           const uint64_t xrp = xin ^ proj4(sh.Tp, xin);
-          a_lo = wrlane((uint32_t)xrp, ib, a_lo);
-          a_hi = wrlane((uint32_t)(xrp >> 32), ib, a_hi);
+          a_lo = wrlane(0u, ib, a_lo);
+          a_hi = wrlane(0u, ib, a_hi);
           F |= xro;
-          commit(k, (uint32_t)xrp, (uint32_t)(xrp >> 32),
-                 __ballot(((k < 32 ? m_lo : m_hi) & (1u << (k & 31))) != 0u));
+          commit(k, (uint32_t)xrp, (uint32_t)(xrp >> 32), bit_lanes(k < 32 ? m_lo : m_hi, k & 31));
         }
         ++k;
       }
@@ -510,7 +506,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
     const int r = sh.ctl_ib;
     // (pivot wave) lane t < r: word q of E_t, the coefficient map yM
     const uint64_t yM = ((uint64_t)y_hi << 32) | y_lo;
-    const uint64_t xr0 = ((uint64_t)a_hi << 32) | a_lo;
+    const uint64_t xr0 = ((uint64_t)e_hi << 32) | e_lo;
     materialize(wb);
 
     // ---- multipliers of the pivot rows (unit lower block L_pp) from the
