@@ -313,10 +313,11 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
     // pivot's own slot), then the row of slot ib moves to the pivot's slot.
     auto run_bits = [&](auto hi_tag, int &k, int kend) {
       constexpr bool HI = decltype(hi_tag)::value;
-      for (; k < kend; ++k) {
-        const uint32_t vc = bit_lanes(HI ? a_hi : a_lo, k & 31);
+      // bit kk; false when the first half has no candidate for it
+      auto step = [&](int kk) __attribute__((always_inline)) -> bool {
+        const uint32_t vc = bit_lanes(HI ? a_hi : a_lo, kk & 31);
         const uint64_t c0 = __ballot(vc != 0u);
-        if (c0 == 0ull) return;
+        if (c0 == 0ull) return false;
         const int sp = __builtin_ctzll(c0);
         const uint32_t p_lo = __builtin_amdgcn_readlane(a_lo, sp), p_hi = __builtin_amdgcn_readlane(a_hi, sp);
         a_lo ^= p_lo & vc;
@@ -331,8 +332,32 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
           a_hi = wrlane(0u, ib, a_hi);
           org0 = wrlane(p_org, ib, org0);
         }
-        commit(k, p_lo, p_hi, bit_lanes(HI ? m_hi : m_lo, k & 31));
+        commit(kk, p_lo, p_hi, bit_lanes(HI ? m_hi : m_lo, kk & 31));
+        return true;
+      };
+      constexpr int k0 = HI ? 32 : 0;
+      if (kend == k0 + 32) {  // a whole half: the bit positions are constants
+        switch (k - k0) {
+#define GF2_BIT(i)                  \
+  case i:                           \
+    if (!step(k0 + i)) {            \
+      k = k0 + i;                   \
+      return;                       \
+    }                               \
+    [[fallthrough]];
+          GF2_BIT(0) GF2_BIT(1) GF2_BIT(2) GF2_BIT(3) GF2_BIT(4) GF2_BIT(5) GF2_BIT(6) GF2_BIT(7)
+          GF2_BIT(8) GF2_BIT(9) GF2_BIT(10) GF2_BIT(11) GF2_BIT(12) GF2_BIT(13) GF2_BIT(14) GF2_BIT(15)
+          GF2_BIT(16) GF2_BIT(17) GF2_BIT(18) GF2_BIT(19) GF2_BIT(20) GF2_BIT(21) GF2_BIT(22) GF2_BIT(23)
+          GF2_BIT(24) GF2_BIT(25) GF2_BIT(26) GF2_BIT(27) GF2_BIT(28) GF2_BIT(29) GF2_BIT(30) GF2_BIT(31)
+#undef GF2_BIT
+          default:
+            break;
+        }
+        k = kend;
+        return;
       }
+      for (; k < kend; ++k)
+        if (!step(k)) return;
     };
 
     // Pivot wave: bits from k on, until the end of the sub-panel or a bit that
