@@ -554,15 +554,23 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
     if (wv == 0) {
       if (lane < r) yx = proj4(sh.Tp, sh.blk[wb + lane][b]);
       // Linv = L_pp^{-1} by forward substitution over t: every row s > t whose
-      // multipliers include pivot t XORs in the finished row t.  The rows
-      // that take row t are lane t of the transposed strictly lower part,
-      // so each step is two lane reads and one masked XOR.
-      uint64_t li = lane < r ? (1ull << lane) : 0ull;
-      const uint64_t ycol = transpose64(lane < r ? (yx & ((1ull << lane) - 1ull)) : 0ull, lane);
-      for (int t = 0; t < r; ++t) {
-        const uint64_t row = rdl64(li, t);
-        if (__builtin_amdgcn_inverse_ballot_w64(rdl64(ycol, t))) li ^= row;
+      // multipliers include pivot t XORs in the finished row t (a lane read
+      // and a masked XOR per step).  Rows and multipliers past r are zero, so
+      // all 64 steps run; rows t < 32 have no bits in the high half.
+      const uint64_t ylow = lane < r ? (yx & ((1ull << lane) - 1ull)) : 0ull;
+      const uint32_t yl_lo = (uint32_t)ylow, yl_hi = (uint32_t)(ylow >> 32);
+      uint32_t li_lo = lane < r && lane < 32 ? 1u << lane : 0u;
+      uint32_t li_hi = lane < r && lane >= 32 ? 1u << (lane - 32) : 0u;
+#pragma unroll
+      for (int t = 0; t < 32; ++t) li_lo ^= (uint32_t)__builtin_amdgcn_readlane(li_lo, t) & bit_lanes(yl_lo, t);
+#pragma unroll
+      for (int t = 32; t < 64; ++t) {
+        const uint32_t mt = bit_lanes(yl_hi, t - 32);
+        const uint32_t r_lo = __builtin_amdgcn_readlane(li_lo, t), r_hi = __builtin_amdgcn_readlane(li_hi, t);
+        li_lo ^= r_lo & mt;
+        li_hi ^= r_hi & mt;
       }
+      const uint64_t li = ((uint64_t)li_hi << 32) | li_lo;
       sh.Li[lane] = li;
       w.Zc[(size_t)q * 64 + lane] = yM;
       w.Linv[(size_t)q * 64 + lane] = li;
