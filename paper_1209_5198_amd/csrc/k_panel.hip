@@ -133,11 +133,11 @@ struct ChainShared {
   PanelTables pt;                            // tables of the panel's finished sub-panels
   uint64_t blk[kBlkMax][kMaxPanelWords];     // block rows: panel words, level = current sub-panel
   int bsrc[kBlkMax];                         // panel-start position of the row at block index i
-  uint64_t win[kWin][kMaxPanelWords];        // staging for window permutations and pivot rows
+  uint64_t win[kWin][kMaxPanelWords];        // staging for window permutations
   uint64_t Pt[kMaxPanelWords - 1][16][16];   // 4-bit tables of the pivot rows before the solve
   int wsrc[kWin];
   int sorg[kWin];
-  uint64_t Tp[16][16];                       // 4-bit tables: Proj during a scan, then y = x * Zc
+  uint64_t Tp[16][16];                       // 4-bit tables of M: Proj during a scan
   uint64_t Tw[16][16];                       // Proj tables private to the pivot wave
   uint64_t Ms[64];
   uint64_t Li[64];
@@ -311,12 +311,14 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
     // window has a candidate (the common case); returns at the first bit where
     // it has none.  Every candidate is reduced by the pivot (which empties the
     // pivot's own slot), then the row of slot ib moves to the pivot's slot.
+    // The next bit's candidates are taken before the pivot's bookkeeping, so
+    // that the ballot's latency overlaps it.
     auto run_bits = [&](auto hi_tag, int &k, int kend) {
       constexpr bool HI = decltype(hi_tag)::value;
+      uint32_t vc = bit_lanes(HI ? a_hi : a_lo, k & 31);  // candidates of bit k (lane masks)
+      uint64_t c0 = __ballot(vc != 0u);
       // bit kk; false when the first half has no candidate for it
       auto step = [&](int kk) __attribute__((always_inline)) -> bool {
-        const uint32_t vc = bit_lanes(HI ? a_hi : a_lo, kk & 31);
-        const uint64_t c0 = __ballot(vc != 0u);
         if (c0 == 0ull) return false;
         const int sp = __builtin_ctzll(c0);
         const uint32_t p_lo = __builtin_amdgcn_readlane(a_lo, sp), p_hi = __builtin_amdgcn_readlane(a_hi, sp);
@@ -331,6 +333,10 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
           a_lo = wrlane(0u, ib, a_lo);
           a_hi = wrlane(0u, ib, a_hi);
           org0 = wrlane(p_org, ib, org0);
+        }
+        if ((kk & 31) != 31) {
+          vc = bit_lanes(HI ? a_hi : a_lo, (kk & 31) + 1);
+          c0 = __ballot(vc != 0u);
         }
         commit(kk, p_lo, p_hi, bit_lanes(HI ? m_hi : m_lo, kk & 31));
         return true;
@@ -429,7 +435,8 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
         }
         sh.sorg[lane] = org0;
         sh.sorg[64 + lane] = org1;
-        sh.Ms[lane] = ((uint64_t)m_hi << 32) | m_lo;
+        // M for a scan below the window; at the end the coefficient map
+        sh.Ms[lane] = need ? ((uint64_t)m_hi << 32) | m_lo : ((uint64_t)y_hi << 32) | y_lo;
       }
       __syncthreads();
       if (!sh.ctl_need) break;
@@ -535,12 +542,11 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
     materialize(wb);
 
     // ---- multipliers of the pivot rows (unit lower block L_pp) from the
-    // coefficient map: word q of pivot row t at level b lies in the span of
-    // E_0..E_t, so y = word * Zc lists its multipliers (bit t set).  Then the
-    // block's inverse.  The pivot rows' later words get 4-bit tables.
-    if (wv == 0) sh.Ms[lane] = yM;
-    __syncthreads();
-    if (tid < 256) sh.Tp[tid >> 4][tid & 15] = table4_entry(sh.Ms, tid);
+    // coefficient map (in Ms since the search ended): word q of pivot row t
+    // at level b lies in the span of E_0..E_t, so y = word * Zc lists its
+    // multipliers (bit t set).  Then the block's inverse.  The pivot rows'
+    // later words get 4-bit tables.
+    if (tid < 256) sh.pt.Tz[b][tid >> 4][tid & 15] = table4_entry(sh.Ms, tid);
     for (int e = tid; e < (s_eff - 1 - b) * 256; e += NT) {
       const int wd = b + 1 + (e >> 8), g = (e >> 4) & 15, v = e & 15;
       uint64_t acc = 0ull;
@@ -552,7 +558,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
     __syncthreads();
     uint64_t yx = 0ull;
     if (wv == 0) {
-      if (lane < r) yx = proj4(sh.Tp, sh.blk[wb + lane][b]);
+      if (lane < r) yx = proj4(sh.pt.Tz[b], sh.blk[wb + lane][b]);
       // Linv = L_pp^{-1} by forward substitution over t: every row s > t whose
       // multipliers include pivot t XORs in the finished row t (a lane read
       // and a masked XOR per step).  Rows and multipliers past r are zero, so
@@ -586,23 +592,19 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
     }
     __syncthreads();
     // ---- pivot rows in final form: word q = E_t | L_pp bits left of t; later
-    // panel words = L_pp^{-1} * (pivot rows at level b)
+    // panel words = L_pp^{-1} * (pivot rows at level b), from the tables of
+    // those words built before the last barrier
     {
       const int nw = s_eff - 1 - b;
       for (int e = tid; e < r * nw; e += NT) {
         const int t = e / nw, wd = b + 1 + (e - t * nw);
-        sh.win[t][wd] = proj4(sh.Pt[wd - b - 1], sh.Li[t]);
+        sh.blk[wb + t][wd] = proj4(sh.Pt[wd - b - 1], sh.Li[t]);
       }
-    }
-    __syncthreads();
-    for (int e = tid; e < r * kMaxPanelWords; e += NT) {
-      const int t = e >> 3, j = e & 7;
-      if (j > b && j < s_eff) sh.blk[wb + t][j] = sh.win[t][j];
     }
     if (wv == 0 && lane < r) sh.blk[wb + lane][b] = xr0 | (yx & ((1ull << lane) - 1ull));
     __syncthreads();
-    // ---- tables of sub-panel b, then every block row below its pivots gets it
-    if (tid < 256) sh.pt.Tz[b][tid >> 4][tid & 15] = table4_entry(sh.Ms, tid);
+    // ---- tables of sub-panel b (Tz built above), then every block row below
+    // its pivots gets it
     for (int e = tid; e < (s_eff - 1 - b) * 256; e += NT) {
       const int wd = b + 1 + (e >> 8), g = (e >> 4) & 15, v = e & 15;
       uint64_t acc = 0ull;
