@@ -96,7 +96,11 @@ __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
   constexpr int UB = NT >= 1024 ? 1 : 2;  // rows per lane looked up together (registers: 4 waves per SIMD at 1024)
   constexpr int NW = NT / 64;          // waves
   constexpr int RPL = TM / (8 * NW);   // rows per lane
-  constexpr int JOBS = NT / 8;         // table-build jobs (8 threads each, one word pair per thread)
+  // Table builds: jobs of 8 threads (one word pair per thread).  At 1024
+  // threads half of them build, 16 entries each: the staged B rows are then
+  // read half as often (512 build threads measured faster than 1024, 256 or 128).
+  constexpr int BT = NT >= 1024 ? 512 : NT;
+  constexpr int JOBS = BT / 8;
   constexpr int EPJ = 4 * 256 / JOBS;  // entries per job
   constexpr int LOGE = EPJ == 8 ? 3 : (EPJ == 16 ? 4 : (EPJ == 32 ? 5 : 6));
   static_assert(RPL * 8 * NW == TM && RPL % (2 * UB) == 0, "tile");
@@ -219,7 +223,7 @@ __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
         As[2 * (tid + j * NT) + 1] = hi;
       }
     }
-    {
+    if (tid < BT) {
       ulonglong2 bv[8];
 #pragma unroll
       for (int b = 0; b < 8; ++b) bv[b] = Bs[half][8 * g_b + b][w2];
