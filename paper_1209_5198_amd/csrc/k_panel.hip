@@ -300,10 +300,9 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
       e_hi = wrlane(p_hi, ib, e_hi);
       const uint64_t kb = 1ull << k;
       pivmask |= kb;
-      if (Fknown) {
-        if (F & kb) F |= ((uint64_t)p_hi << 32) | p_lo;
-        F &= ~kb;
-      }
+      // (F is read only once a scan has set it, so it is kept up to date
+      // without a branch)
+      F = ((F & kb) ? F | (((uint64_t)p_hi << 32) | p_lo) : F) & ~kb;
       ++ib;
     };
 
@@ -319,7 +318,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
       uint64_t c0 = __ballot(vc != 0u);
       // bit kk; false when the first half has no candidate for it
       auto step = [&](int kk) __attribute__((always_inline)) -> bool {
-        if (c0 == 0ull) return false;
+        if (__builtin_expect(c0 == 0ull, 0)) return false;
         const int sp = __builtin_ctzll(c0);
         const uint32_t p_lo = __builtin_amdgcn_readlane(a_lo, sp), p_hi = __builtin_amdgcn_readlane(a_hi, sp);
         a_lo ^= p_lo & vc;
@@ -342,23 +341,13 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
         return true;
       };
       constexpr int k0 = HI ? 32 : 0;
-      if (kend == k0 + 32) {  // a whole half: the bit positions are constants
-        switch (k - k0) {
-#define GF2_BIT(i)                  \
-  case i:                           \
-    if (!step(k0 + i)) {            \
-      k = k0 + i;                   \
-      return;                       \
-    }                               \
-    [[fallthrough]];
-          GF2_BIT(0) GF2_BIT(1) GF2_BIT(2) GF2_BIT(3) GF2_BIT(4) GF2_BIT(5) GF2_BIT(6) GF2_BIT(7)
-          GF2_BIT(8) GF2_BIT(9) GF2_BIT(10) GF2_BIT(11) GF2_BIT(12) GF2_BIT(13) GF2_BIT(14) GF2_BIT(15)
-          GF2_BIT(16) GF2_BIT(17) GF2_BIT(18) GF2_BIT(19) GF2_BIT(20) GF2_BIT(21) GF2_BIT(22) GF2_BIT(23)
-          GF2_BIT(24) GF2_BIT(25) GF2_BIT(26) GF2_BIT(27) GF2_BIT(28) GF2_BIT(29) GF2_BIT(30) GF2_BIT(31)
-#undef GF2_BIT
-          default:
-            break;
-        }
+      if (k == k0 && kend == k0 + 32) {  // a whole half from its first bit: constant bit positions
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+          if (!step(k0 + i)) {
+            k = k0 + i;
+            return;
+          }
         k = kend;
         return;
       }
