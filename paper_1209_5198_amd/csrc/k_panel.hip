@@ -141,6 +141,7 @@ struct ChainShared {
   uint64_t Tw[16][16];                       // Proj tables private to the pivot wave
   uint64_t Ms[64];
   uint64_t Li[64];
+  uint64_t ynext[kWin];                      // y = (word b) * Zc of the next window's rows
   int mb_pos[kMbMax], mb_src[kMbMax];        // positions below the block that received a block row
   int mb_n;
   int scan_best;
@@ -546,6 +547,11 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
     }
     __syncthreads();
     uint64_t yx = 0ull;
+    const int we = wb + r + kWin < nblk ? wb + r + kWin : nblk;  // end of the next window
+    if (wv != 0 && b + 1 < s_eff) {
+      // meanwhile, the first half of the next window's word b + 1: y = (word b) * Zc
+      for (int i = wb + r + tid - 64; i < we; i += NT - 64) sh.ynext[i - wb - r] = proj4(sh.pt.Tz[b], sh.blk[i][b]);
+    }
     if (wv == 0) {
       if (lane < r) yx = proj4(sh.pt.Tz[b], sh.blk[wb + lane][b]);
       // Linv = L_pp^{-1} by forward substitution over t: every row s > t whose
@@ -604,13 +610,11 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
     }
     __syncthreads();
     if (b + 1 < s_eff) {
-      // word b + 1 of the next window's rows: y = (word b) * Zc_b, then
-      // word b + 1 ^= y * E_b[b + 1] (4-bit tables); the rest is deferred
-      const int we = wb + r + kWin < nblk ? wb + r + kWin : nblk;
+      // word b + 1 of the next window's rows: word b + 1 ^= y * E_b[b + 1]
+      // (4-bit tables; y = (word b) * Zc_b was formed beside the inverse);
+      // the rest is deferred
       for (int i = wb + r + tid; i < we; i += NT) {
-        uint64_t y = 0ull;
-#pragma unroll
-        for (int g = 0; g < 16; ++g) y ^= sh.pt.Tz[b][g][(sh.blk[i][b] >> (4 * g)) & 15u];
+        const uint64_t y = sh.ynext[i - wb - r];
         uint64_t v = 0ull;
 #pragma unroll
         for (int g = 0; g < 16; ++g) v ^= sh.pt.Te[pidx(b, b + 1)][g][(y >> (4 * g)) & 15u];
