@@ -103,8 +103,9 @@ int tune_block_class(int blocks) { return blocks <= 1 ? 0 : (blocks <= 3 ? 1 : (
 // gf2_release() destroys them.
 struct Pipe {
   hipStream_t gemm = nullptr, chain = nullptr;
-  std::vector<hipEvent_t> ring;
-  size_t next = 0;
+  std::vector<hipEvent_t> ring;      // links that involve the caller's stream
+  std::vector<hipEvent_t> ring_dev;  // links between the pipe's own two streams
+  size_t next = 0, next_dev = 0;
 };
 std::map<std::pair<int, hipStream_t>, Pipe> g_pipes;
 
@@ -336,6 +337,12 @@ int get_pipe(hipStream_t user, Pipe **out) {
     HIPCHK(hipStreamCreateWithFlags(&p.chain, hipStreamNonBlocking));
     p.ring.assign(64, nullptr);
     for (auto &e : p.ring) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // Both ends of these links are kernels of this device, so the events skip
+    // the system-scope fence (the caller's stream, which may hand results to
+    // the host or another device, is linked through the ring above).
+    p.ring_dev.assign(64, nullptr);
+    for (auto &e : p.ring_dev)
+      HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence));
   }
   *out = &p;
   return GF2_OK;
@@ -363,11 +370,13 @@ int make_exec(hipStream_t user, bool single, Exec &x) {
   return GF2_OK;
 }
 
-// an event marking everything enqueued so far on s (null on a single stream)
-int mark(const Exec &x, hipStream_t s, hipEvent_t *e) {
+// an event marking everything enqueued so far on s (null on a single stream);
+// device_only: its waiter is the pipe's other stream
+int mark(const Exec &x, hipStream_t s, hipEvent_t *e, bool device_only = false) {
   *e = nullptr;
   if (!x.P) return GF2_OK;
-  *e = x.P->ring[x.P->next++ % x.P->ring.size()];
+  *e = device_only ? x.P->ring_dev[x.P->next_dev++ % x.P->ring_dev.size()]
+                   : x.P->ring[x.P->next++ % x.P->ring.size()];
   HIPCHK(hipEventRecord(*e, s));
   return GF2_OK;
 }
@@ -382,7 +391,8 @@ int wait_mark(hipStream_t waiter, hipEvent_t e) {
 int link(const Exec &x, hipStream_t signaller, hipStream_t waiter) {
   if (signaller == waiter) return GF2_OK;
   hipEvent_t e = nullptr;
-  int rc = mark(x, signaller, &e);
+  const bool device_only = signaller != x.user && waiter != x.user;
+  int rc = mark(x, signaller, &e, device_only);
   return rc ? rc : wait_mark(waiter, e);
 }
 
@@ -888,6 +898,8 @@ int gf2_release(void) {
     HIPCHK(hipSetDevice(kv.first.first));
     for (hipEvent_t e : kv.second.ring)
       if (e) HIPCHK(hipEventDestroy(e));
+    for (hipEvent_t e : kv.second.ring_dev)
+      if (e) HIPCHK(hipEventDestroy(e));
     if (kv.second.gemm) HIPCHK(hipStreamDestroy(kv.second.gemm));
     if (kv.second.chain) HIPCHK(hipStreamDestroy(kv.second.chain));
   }
@@ -1214,7 +1226,8 @@ int decompose_body(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t
   if (E && L && x.P) {
     // both outputs are HBM-bound copies of disjoint parts of the working
     // matrix: E on the pipe's main stream beside L on the caller's stream
-    if ((rc = link(x, s, x.G))) return rc;
+    // (the main stream already follows every launch of the factorization,
+    // and the caller's stream holds nothing newer)
     HIPCHK(launch_extract_E(w, *E, x.G));
     HIPCHK(launch_extract_L(w, *L, s));
     if ((rc = link(x, x.G, s))) return rc;
