@@ -370,6 +370,15 @@ int make_exec(hipStream_t user, bool single, Exec &x) {
   return GF2_OK;
 }
 
+// At most two panels: the event links of the look-ahead streams cost more than
+// the overlap they buy (one stream: 0.283 against 0.336 ms at 1024^2, equal at
+// 2048^2, slower from 4096^2 on), so such factorizations run on the caller's
+// stream alone.  S as in the panel loop.
+bool few_panels(const DecWork &w, const gf2_mat *A) {
+  const int S = panel_words_for(w.n, A->cols);
+  return (w.Mw + S - 1) / S <= 2;
+}
+
 // an event marking everything enqueued so far on s (null on a single stream);
 // device_only: its waiter is the pipe's other stream
 int mark(const Exec &x, hipStream_t s, hipEvent_t *e, bool device_only = false) {
@@ -690,7 +699,7 @@ int rref_run(const gf2_mat *A, hipStream_t s, RrefWork &rw, bool augment = false
   void *extra = nullptr;
   prepare_decomp(n, m, ws, w, extra_bytes, &extra);
   Exec x;
-  if ((rc = make_exec(s, false, x))) return rc;
+  if ((rc = make_exec(s, few_panels(w, A), x))) return rc;
   char *p = (char *)extra;
   rw.E = (uint64_t *)p; p += bE;
   rw.G = (uint64_t *)p; p += bG;
@@ -1221,7 +1230,7 @@ int decompose_body(const gf2_mat *A, const gf2_mat *L, const gf2_mat *E, int64_t
   DecWork w;
   prepare_decomp(n, m, ws, w, 0, nullptr);
   Exec x;
-  if ((rc = make_exec(s, single, x))) return rc;
+  if ((rc = make_exec(s, single || few_panels(w, A), x))) return rc;
   if ((rc = factor(A, w, x))) return rc;
   if (E && L && x.P) {
     // both outputs are HBM-bound copies of disjoint parts of the working
@@ -1300,7 +1309,7 @@ int rank_body(const gf2_mat *A, int64_t *rank, void *ws, hipStream_t s) {
   if (wide) prepare_decomp(A->cols, A->rows, ws, w, 0, nullptr);
   else prepare_decomp(A->rows, A->cols, ws, w, 0, nullptr);
   Exec x;
-  if ((rc = make_exec(s, false, x))) return rc;
+  if ((rc = make_exec(s, few_panels(w, A), x))) return rc;
   if ((rc = factor(A, w, x, wide ? Pack::kTransposed : Pack::kPlain))) return rc;
   HIPCHK(launch_finish(w, nullptr, nullptr, rank, s));
   return GF2_OK;
@@ -1334,7 +1343,7 @@ int solve_body(const gf2_mat *A, const gf2_mat *B, const gf2_mat *X, uint64_t *c
   void *extra = nullptr;
   prepare_decomp(n, m, ws, w, solve_extra(n, k), &extra);
   Exec x;
-  if ((rc = make_exec(s, false, x))) return rc;
+  if ((rc = make_exec(s, few_panels(w, A), x))) return rc;
   if ((rc = factor(A, w, x))) return rc;
   SolveWork sw;
   sw.Y = (uint64_t *)extra;
