@@ -273,6 +273,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
     uint32_t m_lo = 0u, m_hi = 0u, y_lo = 0u, y_hi = 0u;  // M_j and Zc row j (lane j)
     uint64_t pivmask = 0ull, F = 0ull;
     bool Fknown = false;
+    uint64_t Fdone = 0ull;  // pivots (their bits) already folded into F
     int ib = 0;
     if (wv == 0) {
       const bool v0 = wb + lane < nblk, v1 = wb + 64 + lane < nblk;
@@ -301,9 +302,6 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
       e_hi = wrlane(p_hi, ib, e_hi);
       const uint64_t kb = 1ull << k;
       pivmask |= kb;
-      // (F is read only once a scan has set it, so it is kept up to date
-      // without a branch)
-      F = ((F & kb) ? F | (((uint64_t)p_hi << 32) | p_lo) : F) & ~kb;
       ++ib;
     };
 
@@ -394,9 +392,25 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
           ++k;
           continue;
         }
-        if (Fknown && !((F >> k) & 1ull)) {  // no row below the window can have bit k
-          ++k;
-          continue;
+        if (Fknown) {
+          // F is brought up to date only here, where it is read: the pivots
+          // taken since, in order, from their rows in e (pivot t is the t-th
+          // set bit of pivmask)
+          for (uint64_t todo = pivmask & ~Fdone; todo; todo &= todo - 1ull) {
+            const int kf = __builtin_ctzll(todo);
+            const uint64_t fb = 1ull << kf;
+            if (F & fb) {
+              const int t = __popcll(pivmask & (fb - 1ull));
+              F |= ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(e_hi, t) << 32) |
+                   (uint32_t)__builtin_amdgcn_readlane(e_lo, t);
+            }
+            F &= ~fb;
+          }
+          Fdone = pivmask;
+          if (!((F >> k) & 1ull)) {  // no row below the window can have bit k
+            ++k;
+            continue;
+          }
         }
         return true;
       }
@@ -511,6 +525,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(DecWork w, int q0, int 
               (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)fv);
         }
         Fknown = true;
+        Fdone = pivmask;  // (F is the rows' state now)
         if (best != 0x7fffffff) {
           const uint64_t xro = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(a_hi, ib) << 32) |
                                (uint32_t)__builtin_amdgcn_readlane(a_lo, ib);
