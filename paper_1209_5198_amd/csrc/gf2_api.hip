@@ -527,10 +527,10 @@ int factor_panels(const gf2_mat *A, DecWork &w, const Exec &x, Pack pack) {
     if (post_on_cs) {
       // Cs already follows the previous bulk update; wait for this chain
       if ((rc = link(x, G, Cs))) return rc;
-      HIPCHK(launch_post(w, q0, s_eff, 0, w.Mw, Cs));
+      HIPCHK(launch_post(w, q0, s_eff, 0, w.Mw, gf2::device_cus(), Cs));
       if ((rc = link(x, Cs, G))) return rc;
     } else {
-      HIPCHK(launch_post(w, q0, s_eff, 0, w.Mw, G));  // row exchanges, multipliers, pivot rows in echelon form
+      HIPCHK(launch_post(w, q0, s_eff, 0, w.Mw, gf2::device_cus(), G));  // row exchanges, multipliers, pivot rows in echelon form
     }
     const int nq0 = q0 + s_eff;
     bool next_on_cs = false;
@@ -584,7 +584,7 @@ int factor(const gf2_mat *A, DecWork &w, const Exec &x, Pack pack = Pack::kPlain
       const int s_eff = sp1 - q0 < S ? sp1 - q0 : S;
       const bool last = q0 + s_eff == sp1;
       if ((rc = link(x, Cs, G))) return rc;  // the previous bulk work
-      HIPCHK(launch_post(w, q0, s_eff, sp0, n1, G));
+      HIPCHK(launch_post(w, q0, s_eff, sp0, n1, gf2::device_cus(), G));
       const int nq0 = q0 + s_eff;
       if (nq0 < Mw) {
         const int ns = Mw - nq0 < S ? Mw - nq0 : S;

@@ -161,7 +161,7 @@ int gemm_wall_variant(int64_t active_rows, int qc0, int qc1, int ncu);  // ... m
 extern int g_wide_threads;  // threads of the 2048-row product tile (512 or 1024)
 
 hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, int spb, hipStream_t s);
-hipError_t launch_post(const DecWork &w, int q0, int s_eff, int wlo, int whi, hipStream_t s);
+hipError_t launch_post(const DecWork &w, int q0, int s_eff, int wlo, int whi, int ncu, hipStream_t s);
 // closing a super-panel (k_super.hip): net permutation on the words outside
 // [lo, hi), list reset, pivot rows in echelon form on the far words [qa, qb)
 hipError_t launch_sp_swap(const DecWork &w, int buf, int lo, int hi, hipStream_t s);

@@ -735,7 +735,7 @@ hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, int sp
 
 // ---------------------------------------------------------------- after the chain
 // One launch per panel, two kinds of workgroups (1024 threads each):
-//   * one per half (8 words) of a 16-word column block: the panel's net row
+//   * one per part (2, 4 or 8 words) of a 16-word column block: the panel's net row
 //     permutation applied to its words outside the panel (P^(j) applied to all
 //     columns), then, for trailing words, the pivot rows in echelon form
 //     E = L_pp^{-1} * rows (block forward substitution over the sub-panels).
@@ -746,22 +746,26 @@ hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, int sp
 //     eq. (Aj) restricted to the panel).  These touch only panel words.
 constexpr int kPostThreads = 1024;
 constexpr int kRowsPerWG = kPostThreads / 2;
-constexpr int kPW = TW / 2;  // words per column workgroup
 
+// PW: words per column workgroup (2, 4 or 8 of a 16-word block)
+template <int PW>
 struct TrsmShared {
-  uint64_t X[kMaxPanelWords * 64][kPW];             // 32 KB: pivot rows, this half block
-  uint64_t T[16][16][kPW];                          // 16 KB: 4-bit tables
+  uint64_t X[kMaxPanelWords * 64][PW];              // up to 32 KB: pivot rows, this part of the block
+  uint64_t T[16][16][PW];                           // up to 16 KB: 4-bit tables
   uint64_t Cf[kMaxPanelWords * 64][kMaxPanelWords]; // 32 KB: multipliers L_cb
   uint64_t Li[kMaxPanelWords][64];                  // 4 KB: Linv_b
   SubInfo Sb[kMaxPanelWords];
 };
+template <int PW>
 union PostShared {
-  TrsmShared t;
+  TrsmShared<PW> t;
   PanelTables pt;
 };
 
 // the row now at listed position p comes from position bp_src[p] at the panel start
+template <int PW>
 __device__ void post_swap(const DecWork &w, int q0, int s_eff, int blk, int half, int wlo, int whi) {
+  constexpr int kPW = PW;
   const int cnt = w.st->bp_count;
   if (cnt == 0) return;
   const int tid = threadIdx.x, wl = tid % kPW, e0 = tid / kPW;
@@ -783,12 +787,14 @@ __device__ void post_swap(const DecWork &w, int q0, int s_eff, int blk, int half
   __syncthreads();
 }
 
-// Pivot rows of the panel, words of half `half` of column block blk right of
-// the panel:
+// Pivot rows of the panel, words of part `half` (PW words) of column block blk
+// right of the panel:
 //   E_b = Linv_b * X_b, then X_c ^= L_cb * E_b for later sub-panels c,
 // with L_cb = word q0+b of the pivot rows of sub-panel c (their multipliers for
-// the pivots of sub-panel b).  8-lane groups over the half block, 4-bit tables.
-__device__ void post_trsm(const DecWork &w, int q0, int s_eff, int blk, int half, int whi, TrsmShared &sh) {
+// the pivots of sub-panel b).  PW-lane groups over the part, 4-bit tables.
+template <int PW>
+__device__ void post_trsm(const DecWork &w, int q0, int s_eff, int blk, int half, int whi, TrsmShared<PW> &sh) {
+  constexpr int kPW = PW;
   constexpr int G = kPostThreads / kPW;  // row groups
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, h = lane / kPW, wl = lane % kPW;
   const int qc0 = q0 + s_eff;
@@ -890,25 +896,40 @@ __device__ void post_rows(const DecWork &w, int q0, int s_eff, int64_t blk0, Pan
 
 // Words [wlo, whi) (wlo <= q0, whi <= Mw): the column workgroups cover the
 // blocks that meet them.
+template <int PW>
 __global__ __launch_bounds__(kPostThreads) void k_post(DecWork w, int q0, int s_eff, int wlo, int whi) {
-  __shared__ PostShared sh;
-  constexpr int kParts = TW / kPW;
+  __shared__ PostShared<PW> sh;
+  constexpr int kPW = PW, kParts = TW / kPW;
   const int blk0 = wlo / TW;
   const int nc = kParts * ((whi - 1) / TW - blk0 + 1);  // column workgroups: kParts per 16-word block
   if ((int)blockIdx.x < nc) {
     const int blk = blk0 + (int)blockIdx.x / kParts, half = blockIdx.x % kParts;
-    post_swap(w, q0, s_eff, blk, half, wlo, whi);
+    post_swap<PW>(w, q0, s_eff, blk, half, wlo, whi);
     const int qc0 = q0 + s_eff;
-    if (qc0 < whi && blk * TW + kPW * half + kPW - 1 >= qc0) post_trsm(w, q0, s_eff, blk, half, whi, sh.t);
+    if (qc0 < whi && blk * TW + kPW * half + kPW - 1 >= qc0) post_trsm<PW>(w, q0, s_eff, blk, half, whi, sh.t);
   } else {
     post_rows(w, q0, s_eff, (int64_t)(blockIdx.x - nc) * kRowsPerWG, sh.pt);
   }
 }
 
-hipError_t launch_post(const DecWork &w, int q0, int s_eff, int wlo, int whi, hipStream_t s) {
+// The column workgroups take the narrowest part of a block (2, 4 or 8 words)
+// for which the whole launch still fits the device's CUs in one round: each
+// workgroup's solve is a chain of dependent steps, so narrower parts finish
+// sooner, until a second round of workgroups costs more (2048^2 and 16384^2
+// take 2 words, 32768^2 4, 65536^2 8).
+hipError_t launch_post(const DecWork &w, int q0, int s_eff, int wlo, int whi, int ncu, hipStream_t s) {
   const int64_t rows_wg = (w.n + kRowsPerWG - 1) / kRowsPerWG;
-  const int64_t blocks = (int64_t)(TW / kPW) * ((whi - 1) / TW - wlo / TW + 1) + rows_wg;
-  hipLaunchKernelGGL(k_post, dim3((unsigned)blocks), dim3(kPostThreads), 0, s, w, q0, s_eff, wlo, whi);
+  const int64_t nblk = (whi - 1) / TW - wlo / TW + 1;
+  if ((TW / 2) * nblk + rows_wg <= ncu) {
+    hipLaunchKernelGGL(k_post<2>, dim3((unsigned)((TW / 2) * nblk + rows_wg)), dim3(kPostThreads), 0, s, w, q0,
+                       s_eff, wlo, whi);
+  } else if ((TW / 4) * nblk + rows_wg <= ncu) {
+    hipLaunchKernelGGL(k_post<4>, dim3((unsigned)((TW / 4) * nblk + rows_wg)), dim3(kPostThreads), 0, s, w, q0,
+                       s_eff, wlo, whi);
+  } else {
+    hipLaunchKernelGGL(k_post<8>, dim3((unsigned)((TW / 8) * nblk + rows_wg)), dim3(kPostThreads), 0, s, w, q0,
+                       s_eff, wlo, whi);
+  }
   return hipGetLastError();
 }
 
