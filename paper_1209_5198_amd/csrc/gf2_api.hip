@@ -300,6 +300,17 @@ int run_gemm(GemmArgs &a, int64_t nrows_max, int variant, int64_t active_rows, h
     variant = g_tuned[tune_row_class(active_rows)][tune_block_class(blocks)];
   }
   if (variant < 0 || variant >= kGemmVariants) variant = gemm_auto_variant(active_rows, a.qc0, a.qc1, gf2::device_cus());
+  // A narrow accumulating product that runs alone (kparts = -1 on entry) and
+  // whose workgroups leave CUs idle is split over its inner words (up to 8
+  // parts, the launch still one round): each workgroup's chain of dependent
+  // table steps is what it waits for.
+  const bool may_split = a.kparts < 0;
+  a.kparts = 1;
+  if (may_split && (variant == 4 || variant == 5) && a.accumulate) {
+    const int tm = gemm_tile_rows(variant);
+    const int64_t wgs = ((active_rows + tm - 1) / tm) * (((a.qc1 - 1) >> 3) - (a.qc0 >> 3) + 1);
+    while (a.kparts < 8 && 2 * a.kparts <= a.kwords && wgs * 2 * a.kparts <= gf2::device_cus()) a.kparts *= 2;
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool prof = prof_on();
   if (prof) {  // the launch records the kernel's own start and end
@@ -410,7 +421,10 @@ int link(const Exec &x, hipStream_t signaller, hipStream_t waiter) {
 // eq. (Aj) for those sub-panels.  nz: flag slot ORed with "a written word is
 // nonzero"; skip: flag slot whose zero means the Schur complement is zero
 // (-1: none).
-int trailing_gemm(DecWork &w, int q0, int nsub, int nz, int skip, int qc0, int qc1, hipStream_t s) {
+// split_ok: nothing runs beside this launch (the inner dimension of a narrow
+// product may then be split over idle CUs)
+int trailing_gemm(DecWork &w, int q0, int nsub, int nz, int skip, int qc0, int qc1, hipStream_t s,
+                  bool split_ok = false) {
   if (qc1 <= qc0) return GF2_OK;
   GemmArgs a;
   memset(&a, 0, sizeof(a));
@@ -423,6 +437,7 @@ int trailing_gemm(DecWork &w, int q0, int nsub, int nz, int skip, int qc0, int q
   a.accumulate = 1;
   a.nzflag = w.nzflag + nz;
   a.skip_flag = skip >= 0 ? w.nzflag + skip : nullptr;
+  a.kparts = split_ok ? -1 : 1;
   // at most 64 pivots per sub-panel so far: a lower bound on the rows left
   int64_t active = w.n - 64ll * (q0 + nsub);
   if (active < 1) active = 1;
@@ -541,7 +556,8 @@ int factor_panels(const gf2_mat *A, DecWork &w, const Exec &x, Pack pack) {
       const double bulk = (double)(rows_left > 0 ? rows_left : 0) * (double)(w.Mw - nq0 - ns) * 8.0 * s_eff;
       const bool early = bulk >= g_overlap_lookups;
       if (early && !post_on_cs && (rc = link(x, G, Cs))) return rc;
-      if ((rc = trailing_gemm(w, q0, s_eff, q0, prev, nq0, nq0 + ns, G))) return rc;  // next panel's columns
+      // next panel's columns (alone on the chip unless the bulk update started early)
+      if ((rc = trailing_gemm(w, q0, s_eff, q0, prev, nq0, nq0 + ns, G, !early))) return rc;
       if (!early && (rc = link(x, G, Cs))) return rc;
       if ((rc = chain(w, nq0, ns, prev, -1, G))) return rc;                           // look-ahead
       if ((rc = trailing_gemm(w, q0, s_eff, q0, prev, nq0 + ns, w.Mw, Cs))) return rc; // the rest

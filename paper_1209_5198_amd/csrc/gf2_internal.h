@@ -135,6 +135,9 @@ struct GemmArgs {
   uint32_t *nzflag;                                  // optional: OR of all written words != 0
   const uint32_t *skip_flag;                         // optional: skip the launch when *skip_flag == 0
   unsigned long long *work;                          // optional: += table lookups performed
+  int32_t kparts;                                    // narrow kernels, accumulate only: parts of the inner
+                                                     // words (blockIdx.z), each XORed into C atomically;
+                                                     // 0 or 1: one part (-1 on entry to run_gemm: may split)
 };
 
 // ---------------------------------------------------------------- launchers (one per kernel file)
@@ -158,6 +161,7 @@ hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int variant, hipStr
                        hipEvent_t e1 = nullptr);
 int gemm_auto_variant(int64_t active_rows, int qc0, int qc1, int ncu);  // variant for a launch shape
 int gemm_wall_variant(int64_t active_rows, int qc0, int qc1, int ncu);  // ... minimising its wall time
+int gemm_tile_rows(int v);                                               // rows of a variant's tile
 extern int g_wide_threads;  // threads of the 2048-row product tile (512 or 1024)
 
 hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, int spb, hipStream_t s);

@@ -84,6 +84,25 @@ __device__ inline uint64_t store_acc2(const uint64_t (&acc)[RPL][2], uint64_t *C
   return any;
 }
 
+// The same rows XORed into C with 64-bit atomics (one part of a product split
+// over its inner dimension).  Every word gets its atomic, a zero one included,
+// so that the last part to reach a word sees its final value: `any` is then
+// nonzero whenever some written word ends nonzero (it may also be nonzero when
+// none does, which only costs a zero-tail exit).
+template <int RPL, int S>
+__device__ inline uint64_t xor_acc2(const uint64_t (&acc)[RPL][2], uint64_t *Cl, bool ok0, bool ok1, int ulo,
+                                    int uhi) {
+  uint64_t any = 0;
+#pragma unroll
+  for (int u = 0; u < RPL; ++u)
+    if (u >= ulo && u < uhi) {
+      unsigned long long *p = (unsigned long long *)(Cl + (int64_t)u * S * TW);
+      if (ok0) any |= atomicXor(p, (unsigned long long)acc[u][0]) ^ acc[u][0];
+      if (ok1) any |= atomicXor(p + 1, (unsigned long long)acc[u][1]) ^ acc[u][1];
+    }
+  return any;
+}
+
 // Four tables (32 inner bits) per step.  The B rows of a step are staged
 // through LDS (two 4 KB buffers): 256 threads load the 32 rows x 16 words of a
 // later step with one 16-byte load each, store them (masked) into the free
@@ -356,11 +375,17 @@ __global__ __launch_bounds__(NT) void k_gemm_narrow(GemmArgs a) {
   int ulo, uhi;
   lane_rows<RPL, 16 * NW>(tile0, 16 * wv + G, rb, re, ulo, uhi);
   const size_t cbase = widx(a.ldC, tile0 + 16 * wv + G, q8) + 2 * w4;  // (q8 % 16) + 2*w4 stays in the block
+  // inner words [kw0, kw1) of part blockIdx.z; with several parts each one
+  // starts from zero and XORs its partial product into C
+  const int nparts = a.kparts > 1 ? a.kparts : 1;
+  const int kw0 = (int)(((int64_t)blockIdx.z * a.kwords) / nparts);
+  const int kw1 = (int)(((int64_t)(blockIdx.z + 1) * a.kwords) / nparts);
   uint64_t acc[RPL][2];
   {
     uint64_t *C = a.C;
     asm volatile("" : "+s"(C));
-    load_acc2<RPL, 16 * NW>(acc, C + cbase, a.accumulate && ok0, a.accumulate && ok1, ulo, uhi);
+    const bool ld = a.accumulate && nparts == 1;
+    load_acc2<RPL, 16 * NW>(acc, C + cbase, ld && ok0, ld && ok1, ulo, uhi);
   }
 
   const int bw4 = tid & 3;
@@ -398,8 +423,8 @@ __global__ __launch_bounds__(NT) void k_gemm_narrow(GemmArgs a) {
   };
 
   uint64_t bv[8][2], av[APT];
-  load_b(0, bv);
-  load_a(0, av);
+  load_b(kw0, bv);
+  load_a(kw0, av);
   const char *Tb = (const char *)&T[0][0][0][0];
   uint32_t lbase[4], sel[4];
 #pragma unroll
@@ -408,7 +433,7 @@ __global__ __launch_bounds__(NT) void k_gemm_narrow(GemmArgs a) {
     lbase[i] = ((uint32_t)s << 6) | ((uint32_t)w4 << 4);
     sel[i] = 0x0C0C0000u | ((4u + (uint32_t)s) << 8);  // [lane base | byte s of the A half | 0 | 0]
   }
-  for (int kw = 0; kw < a.kwords; ++kw) {
+  for (int kw = kw0; kw < kw1; ++kw) {
     __syncthreads();  // previous lookups finished: T and As are free
 #pragma unroll
     for (int j = 0; j < APT; ++j) As[tid + j * NT] = av[j];
@@ -430,7 +455,7 @@ __global__ __launch_bounds__(NT) void k_gemm_narrow(GemmArgs a) {
         }
       }
     }
-    if (kw + 1 < a.kwords) {  // in flight during the lookups
+    if (kw + 1 < kw1) {  // in flight during the lookups
       load_b(kw + 1, bv);
       load_a(kw + 1, av);
     }
@@ -463,7 +488,8 @@ __global__ __launch_bounds__(NT) void k_gemm_narrow(GemmArgs a) {
   {
     uint64_t *C = a.C;
     asm volatile("" : "+s"(C));
-    any = store_acc2<RPL, 16 * NW>(acc, C + cbase, ok0, ok1, ulo, uhi);
+    any = nparts == 1 ? store_acc2<RPL, 16 * NW>(acc, C + cbase, ok0, ok1, ulo, uhi)
+                      : xor_acc2<RPL, 16 * NW>(acc, C + cbase, ok0, ok1, ulo, uhi);
   }
   if (a.nzflag) {
     if (__ballot(any != 0ull) != 0ull && lane == 0) atomicOr(a.nzflag, 1u);
@@ -473,7 +499,7 @@ __global__ __launch_bounds__(NT) void k_gemm_narrow(GemmArgs a) {
     if (lo < a.qc0) lo = a.qc0;
     if (hi > a.qc1) hi = a.qc1;
     const unsigned long long words = hi > lo ? (unsigned long long)(hi - lo) : 0ull;
-    atomicAdd(a.work, (unsigned long long)(re - rb) * words * (unsigned long long)a.kwords * 8ull);
+    atomicAdd(a.work, (unsigned long long)(re - rb) * words * (unsigned long long)(kw1 - kw0) * 8ull);
   }
 }
 
@@ -556,7 +582,7 @@ hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t 
   const int blocks_y = ((a.qc1 - 1) >> 4) - (a.qc0 >> 4) + 1;
   const dim3 grid((unsigned)tiles, (unsigned)blocks_y);
   const int chunks = ((a.qc1 - 1) >> 3) - (a.qc0 >> 3) + 1;  // 8-word chunks (narrow kernels)
-  const dim3 gridn((unsigned)tiles, (unsigned)chunks);
+  const dim3 gridn((unsigned)tiles, (unsigned)chunks, (unsigned)(a.kparts > 1 ? a.kparts : 1));
 #define GF2_LAUNCH(K, GRID, NT)                                              \
   do {                                                                       \
     if (e0 && e1)                                                            \
