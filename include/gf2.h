@@ -30,8 +30,11 @@
  * calls use a workspace per (device, stream) that the library grows on demand
  * with hipMalloc and releases in gf2_release(); the *_ws forms take a
  * caller-owned workspace instead (sizes from gf2_workspace_bytes) and never
- * allocate.  Calls that share a device must not run concurrently from several
- * host threads.
+ * allocate.  A factorization of more than two 512-column panels runs on two
+ * internal look-ahead streams per (device, stream), ordered after the work
+ * already on `stream` and before work enqueued on it later; smaller ones run
+ * on `stream` itself.  Calls that share a device must not run concurrently
+ * from several host threads.
  *
  * Return value: 0 on success, or a negative GF2_E* code; gf2_last_error()
  * then returns a message (thread-local, valid until the next call).  An
