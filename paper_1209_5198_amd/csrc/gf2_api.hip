@@ -48,7 +48,15 @@ int g_panel_gemm_variant = -1;  // product-kernel variant for the trailing updat
 int g_sp_panels = 0;
 // one-level schedule: product tiles by the wall-time rule instead of the
 // largest tile that still gives every CU a workgroup
-bool g_wall_tiles = false;
+// Trailing-update tiles by the wall-time rule (rounds x fitted step time)
+// instead of the largest tile that fills the CUs: 0 never, 1 always, 2 (the
+// default) for launches of at most 16384 active rows whose wall-rule tile fits
+// the CUs in one round.  There it avoids a partly filled second round (16384^2:
+// 4.76 against 4.88 ms).  Elsewhere its model is off: always, 32768^2 12.6
+// against 12.4 ms; with the row limit alone, a planted rank-20000 32768 x 65536
+// matrix 19.9 against 19.35 ms (tiles of several rounds); with the one-round
+// limit alone, 65536^2 51.2 against 50.5 ms.
+int g_wall_tiles = 2;
 // near-update size (table lookups) from which a panel's update of the near
 // words beyond the next panel starts right after the row exchanges, beside
 // the next panel's columns and its pivot chain, instead of after them
@@ -442,8 +450,16 @@ int trailing_gemm(DecWork &w, int q0, int nsub, int nz, int skip, int qc0, int q
   int64_t active = w.n - 64ll * (q0 + nsub);
   if (active < 1) active = 1;
   int v = g_panel_gemm_variant;
-  if (v < 0 && !g_tuned_on && (g_sp_panels > 0 || g_wall_tiles))
-    v = gemm_wall_variant(active, qc0, qc1, gf2::device_cus());
+  if (v < 0 && !g_tuned_on) {
+    const int ncu = gf2::device_cus();
+    if (g_sp_panels > 0 || g_wall_tiles == 1) {
+      v = gemm_wall_variant(active, qc0, qc1, ncu);
+    } else if (g_wall_tiles == 2 && active <= 16384 && !gemm_narrow_ok(qc0, qc1)) {
+      const int vw = gemm_wall_variant(active, qc0, qc1, ncu), tm = gemm_tile_rows(vw);
+      const int64_t wgs = ((active + tm - 1) / tm) * (int64_t)(((qc1 - 1) >> 4) - (qc0 >> 4) + 1);
+      if (wgs <= ncu) v = vw;
+    }
+  }
   return run_gemm(a, w.n, v, active, s);
 }
 
@@ -790,8 +806,8 @@ int gf2_set_param(const char *name, int64_t value) {
     return GF2_OK;
   }
   if (!strcmp(name, "wall_tiles")) {
-    if (value < 0 || value > 1) return fail(GF2_EINVAL, "wall_tiles must be 0 or 1");
-    g_wall_tiles = value == 1;
+    if (value < 0 || value > 2) return fail(GF2_EINVAL, "wall_tiles must be 0, 1 or 2");
+    g_wall_tiles = (int)value;
     return GF2_OK;
   }
   if (!strcmp(name, "wide_threads")) {

@@ -162,6 +162,7 @@ hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int variant, hipStr
 int gemm_auto_variant(int64_t active_rows, int qc0, int qc1, int ncu);  // variant for a launch shape
 int gemm_wall_variant(int64_t active_rows, int qc0, int qc1, int ncu);  // ... minimising its wall time
 int gemm_tile_rows(int v);                                               // rows of a variant's tile
+bool gemm_narrow_ok(int qc0, int qc1);                                   // an 8-aligned range of <= 8 words
 extern int g_wide_threads;  // threads of the 2048-row product tile (512 or 1024)
 
 hipError_t launch_panel(const DecWork &w, int q0, int s_eff, int flag_q0, int spb, hipStream_t s);
