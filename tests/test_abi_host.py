@@ -47,6 +47,11 @@ def test_set_param_validation_without_gpu():
     assert b"unknown" in gf2.load().gf2_last_error()
     assert gf2.load().gf2_set_param(b"panel_words", 8) == gf2.GF2_OK
     assert gf2.load().gf2_set_param(b"panel_words", 0) == gf2.GF2_OK  # automatic (the default)
+    # tile rule of the trailing update: 0 plain, 1 wall-time always, 2 limited (the default)
+    for v in (-1, 3):
+        assert gf2.load().gf2_set_param(b"wall_tiles", v) == gf2.GF2_EINVAL
+    for v in (0, 1, 2):
+        assert gf2.load().gf2_set_param(b"wall_tiles", v) == gf2.GF2_OK
 
 
 def test_null_descriptor_rejected_without_gpu():
