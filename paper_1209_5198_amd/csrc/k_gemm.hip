@@ -139,16 +139,25 @@ __global__ __launch_bounds__(NT) void k_gemm_wide(GemmArgs a) {
   if (a.skip_flag && *a.skip_flag == 0u) return;  // the Schur complement is already zero
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6, G = lane >> 3, w2 = lane & 7;
-  const int blk = blockIdx.y + (a.qc0 >> 4);
+  // A trailing update (mapped B) has its grid as (column block, tile), the
+  // tiles counted from the one holding d, the first row below the panel's
+  // pivots: the grid still has a tile for every row of the matrix, and the
+  // workgroups past the last row, one row of tiles per tile of pivots so far,
+  // come last in dispatch order (a 1024-thread workgroup takes a whole CU even
+  // to find it has no rows).  A plain product keeps (tile, column block).
+  const bool mapped = a.bsub != nullptr;
+  const int blk = (mapped ? blockIdx.x : blockIdx.y) + (a.qc0 >> 4);
   const int64_t qw = (int64_t)blk * TW + 2 * w2;
   const bool ok0 = qw >= a.qc0 && qw < a.qc1, ok1 = qw + 1 >= a.qc0 && qw + 1 < a.qc1;
 
-  const int64_t tile0 = a.row_tile0 + (int64_t)blockIdx.x * TM;
-  int64_t rb = tile0;
-  if (a.bsub) {  // rows below the panel's pivots: first row after the last sub-panel's pivots
-    const int64_t d = a.bsub[a.kwords - 1].R + a.bsub[a.kwords - 1].r;
-    if (d > rb) rb = d;
+  int64_t d = a.row_tile0;
+  if (mapped) {
+    const int64_t dd = a.bsub[a.kwords - 1].R + a.bsub[a.kwords - 1].r;
+    if (dd > d) d = dd;
   }
+  const int64_t tile0 =
+      a.row_tile0 + (mapped ? (d - a.row_tile0) / TM + (int64_t)blockIdx.y : (int64_t)blockIdx.x) * TM;
+  int64_t rb = d > tile0 ? d : tile0;
   int64_t re = tile0 + TM < a.row_end ? tile0 + TM : a.row_end;
   if (rb >= re) return;
 
@@ -584,7 +593,7 @@ hipError_t launch_gemm(const GemmArgs &a, int64_t nrows_max, int v, hipStream_t 
   const int TM = gemm_tile_rows(v);
   const int64_t tiles = (nrows_max + TM - 1) / TM;
   const int blocks_y = ((a.qc1 - 1) >> 4) - (a.qc0 >> 4) + 1;
-  const dim3 grid((unsigned)tiles, (unsigned)blocks_y);
+  const dim3 grid = a.bsub ? dim3((unsigned)blocks_y, (unsigned)tiles) : dim3((unsigned)tiles, (unsigned)blocks_y);
   const int chunks = ((a.qc1 - 1) >> 3) - (a.qc0 >> 3) + 1;  // 8-word chunks (narrow kernels)
   const dim3 gridn((unsigned)tiles, (unsigned)chunks, (unsigned)(a.kparts > 1 ? a.kparts : 1));
 #define GF2_LAUNCH(K, GRID, NT)                                              \
