@@ -75,7 +75,7 @@ LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12   # 157.3 TB/s: 256 CUs x 256 B/clk x 2.
 # product launches of one 65536^2 decomposition (four decompositions counted).
 # Valid only for the product kernel source they were measured on.
 TRAFFIC = {"kernel_source_sha256": "33e40c7051b76f206a87d0ce4e69bc76b0ed3b66db79e5eb967367a223cd5711",
-           "fetch_bytes": 62892.63 * 2 * 1024, "write_bytes": 93339.50 * 1024}
+           "fetch_bytes": 62864.12 * 2 * 1024, "write_bytes": 93206.40 * 1024}
 SEED = 65536
 # The oracle on the bench's own 65536^2 input (seed 65536), run once on the
 # whole matrix (about 7e11 word operations, minutes of CPU time, so this script

@@ -270,9 +270,9 @@ int gf2_autotune_params(int64_t rows, int64_t cols, int32_t *panel_words, int32_
  *                          (default 1.5e9; -1 = never, 0 = always)
  *   "wall_tiles"         : trailing-update tiles that minimise rounds x a fitted
  *                          step time instead of the largest tile filling the CUs:
- *                          0 = never, 1 = always, 2 = for launches of at most
- *                          16384 active rows where that tile fits the CUs in
- *                          one round (default)
+ *                          0 = never, 1 = always (default), 2 = for launches
+ *                          of at most 16384 active rows where that tile fits
+ *                          the CUs in one round
  * Returns 0, or GF2_EINVAL for an unknown name or out-of-range value.
  */
 int gf2_set_param(const char *name, int64_t value);

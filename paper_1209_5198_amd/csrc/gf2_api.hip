@@ -49,14 +49,15 @@ int g_sp_panels = 0;
 // one-level schedule: product tiles by the wall-time rule instead of the
 // largest tile that still gives every CU a workgroup
 // Trailing-update tiles by the wall-time rule (rounds x fitted step time)
-// instead of the largest tile that fills the CUs: 0 never, 1 always, 2 (the
-// default) for launches of at most 16384 active rows whose wall-rule tile fits
-// the CUs in one round.  There it avoids a partly filled second round (16384^2:
-// 4.76 against 4.88 ms).  Elsewhere its model is off: always, 32768^2 12.6
-// against 12.4 ms; with the row limit alone, a planted rank-20000 32768 x 65536
-// matrix 19.9 against 19.35 ms (tiles of several rounds); with the one-round
-// limit alone, 65536^2 51.2 against 50.5 ms.
-int g_wall_tiles = 2;
+// instead of the largest tile that fills the CUs: 0 never, 1 always (the
+// default), 2 for launches of at most 16384 active rows whose wall-rule tile
+// fits the CUs in one round.  Since a trailing update's workgroups without rows
+// come last in its grid, "always" is the fastest: 65536^2 43.7-43.9 against
+// 44.3-44.4 ms for 2, 32768^2 11.54-11.57 against 11.87-12.16 ms, the planted
+// rank-20000 32768 x 65536 matrix 18.00-18.06 against 18.08-18.13 ms, 16384^2
+// and 2048^2 unchanged.  (With those workgroups first, 2 was the best: always
+// cost 32768^2 12.6 against 12.4 ms.)
+int g_wall_tiles = 1;
 // near-update size (table lookups) from which a panel's update of the near
 // words beyond the next panel starts right after the row exchanges, beside
 // the next panel's columns and its pivot chain, instead of after them
